@@ -1,0 +1,282 @@
+/*
+ * l2t.h -- C ABI of the MI355X (gfx950) electronic-temperature sub-step
+ * library for the meshless two-temperature MD scheme of Ullah & Ponga,
+ * "A new approach for electronic heat conduction in molecular dynamics
+ * simulations" (arXiv 1810.12357).
+ *
+ * What the library computes (every step runs in the library's HIP kernels):
+ *   - neighbour sets within a user cut-off (Section 2.1: the electronic
+ *     temperature of each atom is evaluated inside a fixed cut-off radius
+ *     given by the user; Section 2, the cut-off of Eq. 4);
+ *   - the local lattice temperature of Eq. 4 from neighbour velocities with
+ *     the centre-of-mass velocity removed, and the kinetic-energy gate of the
+ *     remark after Eq. 8 (no electron-phonon exchange where K_i < epsilon);
+ *   - explicit sub-steps (Section 2.1) of the master equation Eq. 2 with the
+ *     normalisation of Section 2, theta = (T - T_min)/(T_max - T_min):
+ *       dT_i/dt = (T_max - T_min) K sum_{j in N(i)} f(theta_i, theta_j)
+ *                 - g_i (T_i - T_i^lat)/c_i + q_i(t)/c_i
+ *     where f is the pair term of Eq. 2, K the exchange rate of Eq. 3 (one
+ *     value per system, so K_ij is symmetric), g = G V_atom and c = C_e V_atom
+ *     the per-atom coupling and heat capacity (Section 2, C_e = lambda T_e),
+ *     and q_i the laser source of Eq. 9 taken as energy per unit time per
+ *     atom;
+ *   - the per-system energy ledger: the exchange rate of Eq. 6 integrated
+ *     over each sub-step, the source energy, and the electronic energy;
+ *   - the discrete adjoint of the sub-step map, for gradients of a loss on
+ *     the final T_e with respect to K, G and the initial field.
+ *
+ * Units: Angstrom, femtosecond, eV, Kelvin, amu.
+ *
+ * Conventions that hold for every entry point:
+ *   - Every function returns an int status (L2T_OK = 0; negative values are
+ *     errors; positive values are warnings).  No C++ exception crosses the
+ *     ABI.  After an error, l2t_last_error() holds a message.
+ *   - A context owns all device buffers it allocates; the caller owns every
+ *     pointer it passes in.  Caller pointers are borrowed for the duration of
+ *     the call only: host buffers are copied before the call returns; device
+ *     buffers are read or written in order on the context's stream.
+ *   - Per-atom arrays are in the caller's atom order of one system, FP64.
+ *     Internally the library reorders atoms by cell; the order never leaks.
+ *   - mem = L2T_HOST for host pointers, L2T_DEVICE for device pointers on the
+ *     context's device.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - All work runs on the HIP stream passed to l2t_create (0 = the null
+ *     stream) and is asynchronous unless the function says it synchronises.
+ */
+#ifndef L2T_H
+#define L2T_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define L2T_OK         0
+#define L2T_WUNSTABLE  1   /* warning: explicit step may be unstable (see l2t_set_params) */
+#define L2T_EINVAL    -1   /* bad argument (sizes, ranges, box, unknown enum) */
+#define L2T_ENOMEM    -2   /* device allocation failed */
+#define L2T_EHIP      -3   /* HIP runtime error (message in l2t_last_error) */
+#define L2T_ESTATE    -4   /* call out of order (e.g. advance before neighbours) */
+#define L2T_ERANGE    -5   /* theta left [0,1] or T became non-finite (sticky) */
+#define L2T_ENOTIMPL  -6   /* combination not supported */
+
+/* ---- precision of the sub-step path ---------------------------------------- */
+#define L2T_FP64   0   /* plain: literal Eq. 2 pair term in FP64, one launch per sub-step per system */
+#define L2T_FP32C  1   /* FP32 fluxes, Kahan-compensated sums, compensated (hi+lo) state */
+
+/* ---- memory space of a caller pointer -------------------------------------- */
+#define L2T_HOST    0
+#define L2T_DEVICE  1
+
+/* ---- per-atom fields (FP64 in the caller's atom order) --------------------- */
+#define L2T_FIELD_TE    0   /* electronic temperature T_e, K (read/write) */
+#define L2T_FIELD_TL    1   /* lattice temperature T^lat, K (read/write; >= 0) */
+#define L2T_FIELD_GATE  2   /* 1.0 where the kinetic-energy gate holds, else 0.0 (read/write) */
+#define L2T_FIELD_NBRS  3   /* neighbour count |N(i)| as a double (read only) */
+
+/* ---- electronic heat capacity models (per atom) ---------------------------- */
+#define L2T_CE_CONST   0   /* c = ce_const */
+#define L2T_CE_LINEAR  1   /* c = gamma T (C_e = lambda T_e, Section 2) */
+#define L2T_CE_CAPPED  2   /* c = min(gamma T, ce_cap) */
+
+/* ---- tuning options (l2t_set_option) ---------------------------------------- */
+#define L2T_OPT_PERSISTENT     0   /* FP32C: 1 = fuse sub-steps in one persistent launch (default 1) */
+#define L2T_OPT_BLOCK          1   /* FP32C: threads per workgroup, multiple of 64 (0 = autotune) */
+#define L2T_OPT_RESIDENT_MAX   2   /* FP32C: largest system kept whole in LDS (atoms; 0 = autotune, -1 = never) */
+#define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
+#define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
+
+typedef struct l2t_ctx l2t_ctx;
+
+/* One independent system.  Periodic axes use the minimum image convention
+ * and need box_len >= 2 r_cut; atoms on a free axis must lie inside
+ * [box_lo, box_lo + box_len]. */
+typedef struct {
+    int32_t n_atoms;        /* > 0 */
+    int32_t periodic[3];    /* 1 = periodic along x, y, z */
+    double box_lo[3];       /* Angstrom */
+    double box_len[3];      /* Angstrom, > 0 */
+} l2t_system_desc;
+
+/* Per-system parameters of Eq. 2, Eq. 4 gate and Eq. 9. */
+typedef struct {
+    double T_min, T_max;    /* normalisation range of Section 2, K (T_max > T_min) */
+    double K;               /* exchange rate K_ij of Eq. 3, 1/fs (>= 0) */
+    double dt;              /* electronic sub-step, fs (> 0) */
+    double g;               /* G V_atom, eV/(fs K) per atom (>= 0) */
+    int32_t ce_model;       /* L2T_CE_* */
+    int32_t laser_on;       /* 1 = add the Eq. 9 source */
+    double ce_const;        /* eV/K per atom (L2T_CE_CONST) */
+    double gamma;           /* eV/K^2 per atom (L2T_CE_LINEAR, L2T_CE_CAPPED) */
+    double ce_cap;          /* eV/K per atom (L2T_CE_CAPPED) */
+    double ke_eps;          /* kinetic-energy gate epsilon, eV (1e-5 in the paper) */
+    double laser_fluence;   /* absorbed fluence F, eV/A^2 */
+    double laser_lp;        /* penetration length l_p, A (> 0 when laser_on) */
+    double laser_t0;        /* pulse centre t_0, fs */
+    double laser_sigma;     /* pulse standard deviation sigma, fs (> 0 when laser_on) */
+    double laser_x0;        /* x of the irradiated free surface x_0, A */
+    double v_atom;          /* atomic volume V_atom = V/N, A^3 */
+} l2t_params;
+
+/* Per-system ledger, FP64.  With any heat capacity model,
+ * sum_T + T_ledger_acc is conserved by the sub-step (the exchange term sums
+ * to zero over the system); with a constant uniform c,
+ * E_e + E_e_to_l - E_src is conserved too. */
+typedef struct {
+    double t;               /* time of the current state, fs */
+    int64_t step;           /* sub-steps taken since the last l2t_set_field(TE) */
+    double E_e;             /* sum_i integral_0^{T_i} c dT, eV */
+    double sum_T;           /* sum_i T_i, K */
+    double E_e_to_l;        /* sum over sub-steps of sum_i g_i (T_i - T_i^lat) dt, eV (Eq. 6) */
+    double E_src;           /* sum over sub-steps of sum_i q_i dt, eV */
+    double T_ledger_acc;    /* sum over sub-steps of sum_i dt (g_i (T_i - T_i^lat) - q_i)/c_i, K */
+    double T_max_atom;      /* largest T_i, K */
+    double T_min_atom;      /* smallest T_i, K */
+} l2t_energy_report;
+
+/* ---- lifecycle -------------------------------------------------------------- */
+
+/* Create a context holding n_systems independent systems (Section 2.1: one
+ * electronic temperature per atom).  descs[n_systems] is copied.  precision is
+ * L2T_FP64 or L2T_FP32C.  hip_stream is a hipStream_t (may be NULL).
+ * Errors: EINVAL (n_systems < 1, n_atoms < 1, box_len <= 0, bad precision),
+ * ENOMEM, EHIP (no device). */
+int l2t_create(l2t_ctx **out, int32_t n_systems, const l2t_system_desc *descs,
+               int32_t precision, void *hip_stream);
+
+/* Release every buffer owned by the context (synchronises its stream). */
+void l2t_destroy(l2t_ctx *ctx);
+
+/* ---- geometry --------------------------------------------------------------- */
+
+/* Atom positions of system sys, SoA xyz[3*n]: x[0..n), y[0..n), z[0..n), A.
+ * Positions on periodic axes are wrapped into the box.  Invalidates the
+ * neighbour sets.  Errors: EINVAL (sys out of range, NULL). */
+int l2t_set_positions(l2t_ctx *ctx, int32_t sys, const double *xyz, int32_t mem);
+
+/* Build the neighbour sets N(i) = { j != i : |x_j - x_i| <= r_cut } of every
+ * system (Section 2.1, user-given cut-off; minimum image on periodic axes,
+ * distances in FP64, inclusive).  Atoms are binned into cells of edge >=
+ * r_cut and reordered by cell.  Synchronises.  Outputs (nullable): the
+ * largest and the mean neighbour count over all atoms.
+ * Errors: ESTATE (positions missing), EINVAL (r_cut <= 0, periodic box_len <
+ * 2 r_cut, atom outside the box on a free axis). */
+int l2t_build_neighbors(l2t_ctx *ctx, double r_cut, int32_t *max_nbrs, double *mean_nbrs);
+
+/* Copy the neighbour sets of system sys to host arrays in the caller's atom
+ * order, each row sorted by ascending j: row_ptr[n+1], col[cap].  With
+ * col == NULL only row_ptr is written.  Synchronises.
+ * Errors: ESTATE (no neighbours), EINVAL (cap < entries). */
+int l2t_get_neighbors(l2t_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *col, int64_t cap);
+
+/* ---- parameters and fields -------------------------------------------------- */
+
+/* Parameters of system sys (Eq. 2, Eq. 3 value K, Eq. 4 gate epsilon,
+ * Eq. 9 source).  Returns L2T_WUNSTABLE (a warning, parameters are still set)
+ * when the neighbour sets exist and the Gershgorin bound of the linearised
+ * explicit step, 2 K dt max_i |N(i)|, exceeds 2.
+ * Errors: EINVAL (T_max <= T_min, dt <= 0, K < 0, g < 0, unknown ce_model,
+ * non-positive heat capacity constants, laser_lp or laser_sigma <= 0). */
+int l2t_set_params(l2t_ctx *ctx, int32_t sys, const l2t_params *p);
+
+/* Write a per-atom field of system sys from src[n] (FP64, caller order).
+ * Writing L2T_FIELD_TE restarts the system's ledger and step counter.
+ * Synchronises.  Errors: ESTATE (neighbours not built), EINVAL (unknown or
+ * read-only field, T^lat < 0), ERANGE (a T_e outside [T_min, T_max] or
+ * non-finite; nothing is written). */
+int l2t_set_field(l2t_ctx *ctx, int32_t sys, int32_t field, const double *src, int32_t mem);
+
+/* Read a per-atom field of system sys into dst[n] (FP64, caller order).
+ * FP32C temperatures are returned as (double)hi + (double)lo.
+ * Synchronises when mem == L2T_HOST. */
+int l2t_get_field(l2t_ctx *ctx, int32_t sys, int32_t field, double *dst, int32_t mem);
+
+/* Eq. 4: local lattice temperature from velocities v[3*n] (SoA, A/fs) and
+ * masses m[n] (amu) over {i} U N(i) with the centre-of-mass velocity of that
+ * set removed (global_com = 1: the system's centre of mass instead), and the
+ * gate of the remark after Eq. 8: K_i = 1/2 m_i |v_i - v_com|^2 < ke_eps
+ * switches the coupling of atom i off.  Uses ke_eps of the system's
+ * parameters.  Synchronises.  Errors: ESTATE (neighbours or parameters
+ * missing), EINVAL (mass <= 0). */
+int l2t_set_velocities(l2t_ctx *ctx, int32_t sys, const double *v, const double *mass,
+                       int32_t mem, int32_t global_com);
+
+/* ---- time stepping ---------------------------------------------------------- */
+
+/* Advance every system by n_substeps explicit forward-Euler sub-steps of
+ * Eq. 2 (Section 2.1), Jacobi-synchronous: every read in sub-step n sees the
+ * step-n state.  L2T_FP64: one launch per sub-step per system, the systems
+ * one after another.  L2T_FP32C: all systems together; with
+ * L2T_OPT_PERSISTENT, all sub-steps in one persistent launch.  Asynchronous;
+ * a range violation is reported by the next synchronising call as ERANGE.
+ * Errors: ESTATE (neighbours, parameters or T_e missing), EINVAL. */
+int l2t_advance(l2t_ctx *ctx, int32_t n_substeps);
+
+/* Advance system sys alone (same arithmetic as l2t_advance). */
+int l2t_advance_system(l2t_ctx *ctx, int32_t sys, int32_t n_substeps);
+
+/* As l2t_advance, and record the forward trajectory for l2t_adjoint: the
+ * state is stored every ckpt_every sub-steps (device memory, about
+ * ceil(n/ckpt) * 8 bytes per atom) and the sub-steps in between are recomputed
+ * by the adjoint with the same kernels, so the recomputation is bitwise equal
+ * to the forward.  Errors: as l2t_advance; EINVAL (ckpt_every < 1); ENOMEM. */
+int l2t_advance_recorded(l2t_ctx *ctx, int32_t n_substeps, int32_t ckpt_every);
+
+/* Discrete adjoint of the last recorded advance (derived from Eq. 2 by
+ * differentiating the forward-Euler map).  Given dL_dTN = dL/dT^N for all
+ * atoms of all systems (FP64, systems concatenated in order, caller order
+ * inside each), writes dL/dK and dL/dg per system (host arrays
+ * [n_systems], FP64) and, if dL_dT0 is not NULL, dL/dT^0 (same layout as
+ * dL_dTN, memory space mem).  The reverse sub-step is a gather over the same
+ * neighbour sets (no atomics): (J^T lambda)_k = K sum_{j in N(k)}
+ * d1f(theta_k, theta_j) (lambda_k - lambda_j) + local terms.  Synchronises.
+ * Errors: ESTATE (no recorded advance), EINVAL. */
+int l2t_adjoint(l2t_ctx *ctx, const double *dL_dTN, int32_t mem, double *dL_dK,
+                double *dL_dg, double *dL_dT0);
+
+/* Per-system ledger (FP64 reductions on the device).  Synchronises; returns
+ * ERANGE if any sub-step since the last check produced theta outside [0,1]
+ * or a non-finite T (the ledger is still written). */
+int l2t_energies(l2t_ctx *ctx, int32_t sys, l2t_energy_report *out);
+
+/* Wait for the context's stream; reports a pending ERANGE. */
+int l2t_sync(l2t_ctx *ctx);
+
+/* Set a tuning option L2T_OPT_* (see above). */
+int l2t_set_option(l2t_ctx *ctx, int32_t option, int64_t value);
+
+/* Read a tuning choice the autotuner or the caller made. */
+int l2t_get_option(l2t_ctx *ctx, int32_t option, int64_t *value);
+
+/* ---- helpers ------------------------------------------------------------------ */
+
+/* Eq. 3 for a multi-shell cut-off: K = 2 kappa_e d / (C_e S) with S the lattice
+ * sum of |r_ij|^2 over one atom's neighbour set (S = Z b^2 for a single
+ * shell).  SI inputs (W/m/K, J/m^3/K, m^2) give 1/s.  Returns NaN for
+ * non-positive inputs. */
+double l2t_exchange_rate(double kappa_e, double C_e, int32_t dim, double lattice_sum);
+
+/* FP32 pair term of Eq. 2 as the FP32C path evaluates it, for n pairs of
+ * normalised temperatures on the device (ti, tj, out are device pointers,
+ * FP32): out[k] = f(ti[k], tj[k]).  The cancellation-free product form
+ * f = d h(m, d^2) with d = theta_j - theta_i and m = (theta_i + theta_j)/2 is
+ * used, so f(a, b) = -f(b, a) holds bitwise.  Asynchronous on hip_stream.
+ * Errors: EINVAL (n < 0, NULL with n > 0). */
+int l2t_pair_fp32(const float *ti, const float *tj, float *out, int64_t n, void *hip_stream);
+
+/* Static text of a status code. */
+const char *l2t_strerror(int status);
+
+/* Message of the last error on this context ("" if none). */
+const char *l2t_last_error(const l2t_ctx *ctx);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int l2t_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* L2T_H */

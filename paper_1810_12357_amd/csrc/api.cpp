@@ -1,0 +1,605 @@
+// Host side of the C ABI declared in include/l2t.h: argument validation,
+// device buffers, call-order state, error reporting.  All arithmetic of the
+// method runs in the kernels of k_geometry.hip, k_step.hip and k_adjoint.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "l2t_internal.h"
+
+using l2t::SystemState;
+
+namespace l2t {
+
+int fail(l2t_ctx *c, int status, const std::string &msg) {
+    if (c) c->last_error = msg;
+    return status;
+}
+
+int hip_fail(l2t_ctx *c, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return fail(c, L2T_ENOMEM, m);
+    return fail(c, L2T_EHIP, m);
+}
+
+int ensure_scratch(l2t_ctx *c, size_t bytes) {
+    if (bytes <= c->scratch_bytes) return L2T_OK;
+    if (c->scratch) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->scratch);
+    }
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    if (hipMalloc(&c->scratch, bytes) != hipSuccess)
+        return fail(c, L2T_ENOMEM, "scratch allocation failed");
+    c->scratch_bytes = bytes;
+    return L2T_OK;
+}
+
+}  // namespace l2t
+
+namespace {
+
+template <typename T>
+int dalloc(l2t_ctx *c, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) return l2t::hip_fail(c, e, "hipMalloc");
+    e = hipMemsetAsync(*p, 0, sizeof(T) * count, c->stream);
+    if (e != hipSuccess) return l2t::hip_fail(c, e, "hipMemsetAsync");
+    return L2T_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+bool bad_sys(const l2t_ctx *c, int32_t sys) {
+    return !c || sys < 0 || sys >= (int32_t)c->sys.size();
+}
+
+// copy a caller buffer to device memory if it lives on the host
+int stage_in(l2t_ctx *c, const double *src, size_t count, int32_t mem, double *staging,
+             const double **dev) {
+    if (mem == L2T_DEVICE) {
+        *dev = src;
+        return L2T_OK;
+    }
+    if (mem != L2T_HOST) return l2t::fail(c, L2T_EINVAL, "mem must be L2T_HOST or L2T_DEVICE");
+    L2T_HIP(c, hipMemcpyAsync(staging, src, sizeof(double) * count, hipMemcpyHostToDevice,
+                              c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    *dev = staging;
+    return L2T_OK;
+}
+
+int check_err(l2t_ctx *c) {
+    unsigned h = 0;
+    L2T_HIP(c, hipMemcpyAsync(&h, c->derr, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    if (h) L2T_HIP(c, hipMemsetAsync(c->derr, 0, sizeof(unsigned), c->stream));
+    if (h & l2t::kErrBarrier)
+        return l2t::fail(c, L2T_EHIP, "persistent sub-step launch: grid barrier spin limit reached");
+    if (h & l2t::kErrRange)
+        return l2t::fail(c, L2T_ERANGE,
+                         "a sub-step produced theta outside [0,1] or a non-finite temperature");
+    return L2T_OK;
+}
+
+bool ready_to_advance(l2t_ctx *c, int32_t s0, int32_t s1, std::string *why) {
+    if (!c->nbrs_built) {
+        *why = "neighbour sets not built";
+        return false;
+    }
+    for (int32_t s = s0; s < s1; ++s) {
+        const SystemState &st = c->sys[s];
+        if (!st.has_params) {
+            *why = "parameters of system " + std::to_string(s) + " not set";
+            return false;
+        }
+        if (!st.has_te) {
+            *why = "T_e of system " + std::to_string(s) + " not set";
+            return false;
+        }
+        if (st.params.g > 0.0 && !st.has_tl) {
+            *why = "T_lat of system " + std::to_string(s) + " not set (G > 0)";
+            return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int l2t_version(void) { return 10000; }
+
+const char *l2t_strerror(int status) {
+    switch (status) {
+        case L2T_OK: return "ok";
+        case L2T_WUNSTABLE: return "warning: explicit sub-step may be unstable";
+        case L2T_EINVAL: return "invalid argument";
+        case L2T_ENOMEM: return "out of device memory";
+        case L2T_EHIP: return "HIP runtime error";
+        case L2T_ESTATE: return "call out of order";
+        case L2T_ERANGE: return "temperature outside [T_min, T_max] or non-finite";
+        case L2T_ENOTIMPL: return "not implemented";
+        default: return "unknown status";
+    }
+}
+
+const char *l2t_last_error(const l2t_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+double l2t_exchange_rate(double kappa_e, double C_e, int32_t dim, double lattice_sum) {
+    if (!(kappa_e > 0.0) || !(C_e > 0.0) || dim < 1 || !(lattice_sum > 0.0)) return NAN;
+    return 2.0 * kappa_e * (double)dim / (C_e * lattice_sum);
+}
+
+void l2t_destroy(l2t_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    l2t::drop_graphs(c);
+    dfree(c->pos);
+    dfree(c->pos_int);
+    dfree(c->perm);
+    dfree(c->inv);
+    dfree(c->cell_start);
+    dfree(c->cell_scratch);
+    dfree(c->cell_of);
+    dfree(c->cell_int);
+    dfree(c->sorted_local);
+    dfree(c->cnt);
+    dfree(c->slices);
+    dfree(c->col);
+    for (int b = 0; b < 2; ++b) {
+        dfree(c->T64[b]);
+        dfree(c->Thi[b]);
+    }
+    dfree(c->Tl64);
+    dfree(c->srcw64);
+    dfree(c->Tlo);
+    dfree(c->Tl32);
+    dfree(c->srcw32);
+    dfree(c->ledger);
+    dfree(c->slice_red);
+    dfree(c->energy_out);
+    dfree(c->dparams);
+    dfree(c->dstep);
+    dfree(c->derr);
+    dfree(c->dbar);
+    dfree(c->stage);
+    if (c->scratch) (void)hipFree(c->scratch);
+    if (c->rec.buf) (void)hipFree(c->rec.buf);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int l2t_create(l2t_ctx **out, int32_t n_systems, const l2t_system_desc *descs, int32_t precision,
+               void *hip_stream) {
+    if (!out) return L2T_EINVAL;
+    *out = nullptr;
+    if (n_systems < 1 || !descs) return L2T_EINVAL;
+    if (precision != L2T_FP64 && precision != L2T_FP32C) return L2T_EINVAL;
+    int64_t n_tot = 0, n_int = 0;
+    for (int32_t s = 0; s < n_systems; ++s) {
+        const l2t_system_desc &d = descs[s];
+        if (d.n_atoms < 1) return L2T_EINVAL;
+        for (int k = 0; k < 3; ++k)
+            if (!(d.box_len[k] > 0.0) || !std::isfinite(d.box_lo[k]) || !std::isfinite(d.box_len[k]))
+                return L2T_EINVAL;
+        n_tot += d.n_atoms;
+        n_int += (d.n_atoms + l2t::kWave - 1) / l2t::kWave * l2t::kWave;
+    }
+    if (n_tot > INT32_MAX / 4 || n_int > INT32_MAX / 4) return L2T_EINVAL;
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return L2T_EHIP;
+    if (hipGetDevice(&dev) != hipSuccess) return L2T_EHIP;
+    l2t_ctx *c = new (std::nothrow) l2t_ctx();
+    if (!c) return L2T_ENOMEM;
+    c->precision = precision;
+    c->stream = (hipStream_t)hip_stream;
+    c->device = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        c->n_cu = prop.multiProcessorCount;
+        c->lds_per_block = prop.sharedMemPerBlock;
+    }
+    c->sys.resize(n_systems);
+    int64_t coff = 0;
+    int32_t aoff = 0;
+    for (int32_t s = 0; s < n_systems; ++s) {
+        SystemState &st = c->sys[s];
+        st.desc = descs[s];
+        st.caller_off = coff;
+        st.atom_off = aoff;
+        st.n_pad = (descs[s].n_atoms + l2t::kWave - 1) / l2t::kWave * l2t::kWave;
+        st.slice0 = aoff / l2t::kWave;
+        st.n_slices = st.n_pad / l2t::kWave;
+        coff += descs[s].n_atoms;
+        aoff += st.n_pad;
+        c->max_n = std::max(c->max_n, descs[s].n_atoms);
+    }
+    c->n_tot = n_tot;
+    c->n_int = (int32_t)n_int;
+    c->n_slices = (int32_t)(n_int / l2t::kWave);
+    const size_t S = (size_t)n_systems, NT = (size_t)n_tot, NI = (size_t)n_int,
+                 NS = (size_t)c->n_slices;
+    int rc = L2T_OK;
+#define ALLOC(p, n)                                    \
+    if (rc == L2T_OK) rc = dalloc(c, &(p), (size_t)(n));
+    ALLOC(c->pos, 3 * NT);
+    ALLOC(c->pos_int, 3 * NI);
+    ALLOC(c->perm, NI);
+    ALLOC(c->inv, NT);
+    ALLOC(c->cell_of, NT);
+    ALLOC(c->cell_int, NI);
+    ALLOC(c->sorted_local, NT);
+    ALLOC(c->cnt, NI);
+    ALLOC(c->slices, NS);
+    if (precision == L2T_FP64) {
+        ALLOC(c->T64[0], NI);
+        ALLOC(c->T64[1], NI);
+        ALLOC(c->Tl64, NI);
+        ALLOC(c->srcw64, NI);
+    } else {
+        ALLOC(c->Thi[0], NI);
+        ALLOC(c->Thi[1], NI);
+        ALLOC(c->Tlo, NI);
+        ALLOC(c->Tl32, NI);
+        ALLOC(c->srcw32, NI);
+    }
+    ALLOC(c->ledger, 3 * NS);
+    ALLOC(c->slice_red, 4 * NS);
+    ALLOC(c->energy_out, 8);
+    ALLOC(c->dparams, S);
+    ALLOC(c->dstep, S);
+    ALLOC(c->derr, 4);
+    ALLOC(c->dbar, 4);
+    ALLOC(c->stage, std::max<size_t>(NT, 4 * (size_t)c->max_n));
+#undef ALLOC
+    if (rc == L2T_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = L2T_EHIP;
+    if (rc != L2T_OK) {
+        l2t_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return L2T_OK;
+}
+
+int l2t_set_positions(l2t_ctx *c, int32_t sys, const double *xyz, int32_t mem) {
+    if (bad_sys(c, sys) || !xyz) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
+    SystemState &st = c->sys[sys];
+    const int32_t n = st.desc.n_atoms;
+    const hipMemcpyKind kind = mem == L2T_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    for (int d = 0; d < 3; ++d)
+        L2T_HIP(c, hipMemcpyAsync(c->pos + (size_t)d * c->n_tot + st.caller_off,
+                                  xyz + (size_t)d * n, sizeof(double) * n, kind, c->stream));
+    if (mem == L2T_HOST) L2T_HIP(c, hipStreamSynchronize(c->stream));
+    st.has_pos = true;
+    c->nbrs_built = false;
+    return L2T_OK;
+}
+
+int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mean_nbrs) {
+    if (!c) return L2T_EINVAL;
+    if (!(r_cut > 0.0) || !std::isfinite(r_cut)) return l2t::fail(c, L2T_EINVAL, "r_cut <= 0");
+    for (size_t s = 0; s < c->sys.size(); ++s)
+        if (!c->sys[s].has_pos)
+            return l2t::fail(c, L2T_ESTATE, "positions of system " + std::to_string(s) + " not set");
+    l2t::drop_graphs(c);
+    c->rec.valid = false;
+    int rc = l2t::build_neighbors(c, r_cut);
+    if (rc != L2T_OK) return rc;
+    c->nbrs_built = true;
+    c->tune.tuned = false;
+    for (auto &st : c->sys) {
+        st.has_te = false;   // internal order changed: fields must be written again
+        st.has_tl = false;
+    }
+    // per-atom fields start at zero (T^lat = 0, no gate)
+    if (c->precision == L2T_FP64) {
+        L2T_HIP(c, hipMemsetAsync(c->Tl64, 0, sizeof(double) * c->n_int, c->stream));
+    } else {
+        L2T_HIP(c, hipMemsetAsync(c->Tl32, 0, sizeof(float) * c->n_int, c->stream));
+    }
+    for (int32_t s = 0; s < (int32_t)c->sys.size(); ++s)
+        if (c->sys[s].has_params) {
+            rc = l2t::source_weights(c, s);
+            if (rc != L2T_OK) return rc;
+        }
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    if (max_nbrs) *max_nbrs = c->max_nbrs;
+    if (mean_nbrs) *mean_nbrs = c->mean_nbrs;
+    return L2T_OK;
+}
+
+int l2t_get_neighbors(l2t_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *col, int64_t cap) {
+    if (bad_sys(c, sys) || !row_ptr) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
+    return l2t::neighbors_to_host(c, sys, row_ptr, col, cap);
+}
+
+int l2t_set_params(l2t_ctx *c, int32_t sys, const l2t_params *p) {
+    if (bad_sys(c, sys) || !p) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    const l2t_params &q = *p;
+    auto fin = [](double v) { return std::isfinite(v); };
+    if (!fin(q.T_min) || !fin(q.T_max) || !(q.T_max > q.T_min) || q.T_min < 0.0)
+        return l2t::fail(c, L2T_EINVAL, "need 0 <= T_min < T_max");
+    if (!(q.dt > 0.0) || !fin(q.dt)) return l2t::fail(c, L2T_EINVAL, "dt must be > 0");
+    if (!(q.K >= 0.0) || !fin(q.K)) return l2t::fail(c, L2T_EINVAL, "K must be >= 0");
+    if (!(q.g >= 0.0) || !fin(q.g)) return l2t::fail(c, L2T_EINVAL, "g must be >= 0");
+    if (q.ce_model == L2T_CE_CONST) {
+        if (!(q.ce_const > 0.0)) return l2t::fail(c, L2T_EINVAL, "ce_const must be > 0");
+    } else if (q.ce_model == L2T_CE_LINEAR) {
+        if (!(q.gamma > 0.0)) return l2t::fail(c, L2T_EINVAL, "gamma must be > 0");
+    } else if (q.ce_model == L2T_CE_CAPPED) {
+        if (!(q.gamma > 0.0) || !(q.ce_cap > 0.0))
+            return l2t::fail(c, L2T_EINVAL, "gamma and ce_cap must be > 0");
+    } else {
+        return l2t::fail(c, L2T_EINVAL, "unknown ce_model");
+    }
+    if (q.laser_on) {
+        if (!(q.laser_lp > 0.0) || !(q.laser_sigma > 0.0) || !(q.laser_fluence >= 0.0) ||
+            !(q.v_atom > 0.0) || !fin(q.laser_t0) || !fin(q.laser_x0))
+            return l2t::fail(c, L2T_EINVAL, "laser needs l_p, sigma, V_atom > 0 and F >= 0");
+    }
+    if (!(q.ke_eps >= 0.0)) return l2t::fail(c, L2T_EINVAL, "ke_eps must be >= 0");
+    SystemState &st = c->sys[sys];
+    st.params = q;
+    st.has_params = true;
+    int rc = l2t::upload_params(c);
+    if (rc != L2T_OK) return rc;
+    if (c->nbrs_built) {
+        rc = l2t::source_weights(c, sys);
+        if (rc != L2T_OK) return rc;
+    }
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    // Gershgorin: the linearised exchange operator has eigenvalues in
+    // [-2 K c max|N(i)|, 0] with c <= 1, so forward Euler is stable if
+    // 2 K dt max|N(i)| <= 2.
+    if (c->nbrs_built && q.K * q.dt * (double)st.max_nbrs > 1.0) {
+        c->last_error = "Gershgorin bound 2 K dt max|N(i)| exceeds 2";
+        return L2T_WUNSTABLE;
+    }
+    return L2T_OK;
+}
+
+int l2t_set_field(l2t_ctx *c, int32_t sys, int32_t field, const double *src, int32_t mem) {
+    if (bad_sys(c, sys) || !src) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (field != L2T_FIELD_TE && field != L2T_FIELD_TL && field != L2T_FIELD_GATE)
+        return l2t::fail(c, L2T_EINVAL, "unknown or read-only field");
+    if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
+    SystemState &st = c->sys[sys];
+    if (field == L2T_FIELD_TE && !st.has_params)
+        return l2t::fail(c, L2T_ESTATE, "set parameters before T_e");
+    const double *dsrc = nullptr;
+    int rc = stage_in(c, src, st.desc.n_atoms, mem, c->stage, &dsrc);
+    if (rc != L2T_OK) return rc;
+    bool ok = true;
+    if (field == L2T_FIELD_TE) {
+        rc = l2t::check_field_range(c, dsrc, st.desc.n_atoms, st.params.T_min, st.params.T_max, &ok);
+        if (rc != L2T_OK) return rc;
+        if (!ok) return l2t::fail(c, L2T_ERANGE, "T_e outside [T_min, T_max] or non-finite");
+    } else if (field == L2T_FIELD_TL) {
+        rc = l2t::check_field_range(c, dsrc, st.desc.n_atoms, 0.0, HUGE_VAL, &ok);
+        if (rc != L2T_OK) return rc;
+        if (!ok) return l2t::fail(c, L2T_EINVAL, "T_lat must be finite and >= 0");
+    }
+    rc = l2t::permute_in(c, sys, dsrc, field);
+    if (rc != L2T_OK) return rc;
+    if (field == L2T_FIELD_TE) {
+        rc = l2t::reset_ledger(c, sys);
+        if (rc != L2T_OK) return rc;
+        L2T_HIP(c, hipMemsetAsync(c->dstep + sys, 0, sizeof(int64_t), c->stream));
+        st.step = 0;
+        st.has_te = true;
+        c->rec.valid = false;
+    } else if (field == L2T_FIELD_TL) {
+        st.has_tl = true;
+    }
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    return L2T_OK;
+}
+
+int l2t_get_field(l2t_ctx *c, int32_t sys, int32_t field, double *dst, int32_t mem) {
+    if (bad_sys(c, sys) || !dst) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (field < L2T_FIELD_TE || field > L2T_FIELD_NBRS)
+        return l2t::fail(c, L2T_EINVAL, "unknown field");
+    if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
+    if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
+    const SystemState &st = c->sys[sys];
+    double *d = mem == L2T_DEVICE ? dst : c->stage;
+    int rc = l2t::permute_out(c, sys, field, d);
+    if (rc != L2T_OK) return rc;
+    if (mem == L2T_HOST) {
+        L2T_HIP(c, hipMemcpyAsync(dst, c->stage, sizeof(double) * st.desc.n_atoms,
+                                  hipMemcpyDeviceToHost, c->stream));
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return L2T_OK;
+}
+
+int l2t_set_velocities(l2t_ctx *c, int32_t sys, const double *v, const double *mass, int32_t mem,
+                       int32_t global_com) {
+    if (bad_sys(c, sys) || !v || !mass) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
+    if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
+    SystemState &st = c->sys[sys];
+    if (!st.has_params) return l2t::fail(c, L2T_ESTATE, "set parameters before velocities");
+    const int32_t n = st.desc.n_atoms;
+    const double *dv = v, *dm = mass;
+    if (mem == L2T_HOST) {
+        L2T_HIP(c, hipMemcpyAsync(c->stage, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice,
+                                  c->stream));
+        L2T_HIP(c, hipMemcpyAsync(c->stage + 3 * (size_t)n, mass, sizeof(double) * n,
+                                  hipMemcpyHostToDevice, c->stream));
+        dv = c->stage;
+        dm = c->stage + 3 * (size_t)n;
+    }
+    bool ok = true;
+    int rc = l2t::check_field_range(c, dm, n, 1e-300, HUGE_VAL, &ok);
+    if (rc != L2T_OK) return rc;
+    if (!ok) return l2t::fail(c, L2T_EINVAL, "masses must be finite and > 0");
+    rc = l2t::lattice_temperature(c, sys, dv, dm, global_com);
+    if (rc != L2T_OK) return rc;
+    st.has_tl = true;
+    return L2T_OK;
+}
+
+int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
+    if (!c) return L2T_EINVAL;
+    l2t::Tuning &t = c->tune;
+    switch (option) {
+        case L2T_OPT_PERSISTENT: t.persistent = value ? 1 : 0; break;
+        case L2T_OPT_BLOCK:
+            if (value != 0 && (value < 64 || value > 256 || value % 64))
+                return l2t::fail(c, L2T_EINVAL, "block must be 0 or one of 64, 128, 192, 256");
+            if (value == 0) {
+                t.block = 256;
+                t.tuned = false;
+                l2t::drop_graphs(c);
+                return L2T_OK;
+            }
+            t.block = (int)value;
+            break;
+        case L2T_OPT_RESIDENT_MAX: t.resident_max = (int)value; break;
+        case L2T_OPT_GRAPH: t.graph = value ? 1 : 0; break;
+        case L2T_OPT_AUTOTUNE:
+            t.autotune = value ? 1 : 0;
+            if (value) t.tuned = false;
+            break;
+        default: return l2t::fail(c, L2T_EINVAL, "unknown option");
+    }
+    if (option != L2T_OPT_AUTOTUNE) t.tuned = true;   // an explicit choice overrides tuning
+    l2t::drop_graphs(c);
+    return L2T_OK;
+}
+
+int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
+    if (!c || !value) return L2T_EINVAL;
+    const l2t::Tuning &t = c->tune;
+    switch (option) {
+        case L2T_OPT_PERSISTENT: *value = t.persistent; break;
+        case L2T_OPT_BLOCK: *value = t.block; break;
+        case L2T_OPT_RESIDENT_MAX: *value = t.resident_max; break;
+        case L2T_OPT_GRAPH: *value = t.graph; break;
+        case L2T_OPT_AUTOTUNE: *value = t.autotune; break;
+        default: return l2t::fail(c, L2T_EINVAL, "unknown option");
+    }
+    return L2T_OK;
+}
+
+int l2t_advance(l2t_ctx *c, int32_t n) {
+    if (!c || n < 0) return l2t::fail(c, L2T_EINVAL, "n_substeps must be >= 0");
+    std::string why;
+    if (!ready_to_advance(c, 0, (int32_t)c->sys.size(), &why)) return l2t::fail(c, L2T_ESTATE, why);
+    c->rec.valid = false;
+    if (n == 0) return L2T_OK;
+    if (c->precision == L2T_FP64) {
+        for (int32_t s = 0; s < (int32_t)c->sys.size(); ++s) {
+            int rc = l2t::advance_plain(c, s, n);
+            if (rc != L2T_OK) return rc;
+        }
+        return L2T_OK;
+    }
+    if (c->tune.autotune && !c->tune.tuned) {
+        int rc = l2t::autotune(c);
+        if (rc != L2T_OK) return rc;
+    }
+    return l2t::advance_fp32c(c, n);
+}
+
+int l2t_advance_system(l2t_ctx *c, int32_t sys, int32_t n) {
+    if (bad_sys(c, sys) || n < 0) return l2t::fail(c, L2T_EINVAL, "bad system index or n < 0");
+    std::string why;
+    if (!ready_to_advance(c, sys, sys + 1, &why)) return l2t::fail(c, L2T_ESTATE, why);
+    c->rec.valid = false;
+    if (n == 0) return L2T_OK;
+    return l2t::advance_plain(c, sys, n);
+}
+
+int l2t_advance_recorded(l2t_ctx *c, int32_t n, int32_t ckpt_every) {
+    if (!c || n < 1 || ckpt_every < 1) return l2t::fail(c, L2T_EINVAL, "need n >= 1, ckpt >= 1");
+    if (c->precision != L2T_FP32C)
+        return l2t::fail(c, L2T_ENOTIMPL, "the adjoint is provided for the FP32C path");
+    std::string why;
+    if (!ready_to_advance(c, 0, (int32_t)c->sys.size(), &why)) return l2t::fail(c, L2T_ESTATE, why);
+    l2t::Recording &r = c->rec;
+    r.valid = false;
+    r.n_steps = n;
+    r.ckpt = ckpt_every;
+    r.n_ckpt = (n + ckpt_every - 1) / ckpt_every;
+    size_t need = (size_t)r.n_ckpt * 2 * sizeof(float) * (size_t)c->n_int;
+    if (need > r.bytes) {
+        if (r.buf) (void)hipFree(r.buf);
+        r.buf = nullptr;
+        r.bytes = 0;
+        if (hipMalloc(&r.buf, need) != hipSuccess)
+            return l2t::fail(c, L2T_ENOMEM, "checkpoint allocation failed");
+        r.bytes = need;
+    }
+    r.step0.resize(c->sys.size());
+    for (size_t s = 0; s < c->sys.size(); ++s) r.step0[s] = c->sys[s].step;
+    for (int64_t k = 0; k < r.n_ckpt; ++k) {
+        int rc = l2t::record_checkpoint(c, k);
+        if (rc != L2T_OK) return rc;
+        int32_t len = (int32_t)std::min<int64_t>(ckpt_every, n - k * ckpt_every);
+        rc = l2t::advance_plain(c, -1, len);
+        if (rc != L2T_OK) return rc;
+    }
+    r.valid = true;
+    return L2T_OK;
+}
+
+int l2t_adjoint(l2t_ctx *c, const double *dL_dTN, int32_t mem, double *dL_dK, double *dL_dg,
+                double *dL_dT0) {
+    if (!c || !dL_dTN || !dL_dK || !dL_dg) return l2t::fail(c, L2T_EINVAL, "NULL argument");
+    if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
+    if (!c->rec.valid) return l2t::fail(c, L2T_ESTATE, "no recorded advance");
+    const double *dw = nullptr;
+    int rc = stage_in(c, dL_dTN, (size_t)c->n_tot, mem, c->stage, &dw);
+    if (rc != L2T_OK) return rc;
+    // dL/dT^0 goes straight to a device destination, else through the
+    // staging buffer (free again once the adjoint has read dL/dT^N)
+    double *d0 = dL_dT0 ? (mem == L2T_DEVICE ? dL_dT0 : c->stage) : nullptr;
+    rc = l2t::adjoint(c, dw, dL_dK, dL_dg, d0);
+    if (rc != L2T_OK) return rc;
+    if (dL_dT0 && mem == L2T_HOST) {
+        L2T_HIP(c, hipMemcpyAsync(dL_dT0, d0, sizeof(double) * (size_t)c->n_tot,
+                                  hipMemcpyDeviceToHost, c->stream));
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return check_err(c);
+}
+
+int l2t_energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out) {
+    if (bad_sys(c, sys) || !out) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (!c->nbrs_built || !c->sys[sys].has_params || !c->sys[sys].has_te)
+        return l2t::fail(c, L2T_ESTATE, "neighbours, parameters and T_e must be set");
+    int rc = l2t::energies(c, sys, out);
+    if (rc != L2T_OK) return rc;
+    out->t = (double)c->sys[sys].step * c->sys[sys].params.dt;
+    return check_err(c);
+}
+
+int l2t_sync(l2t_ctx *c) {
+    if (!c) return L2T_EINVAL;
+    return check_err(c);
+}
+
+int l2t_pair_fp32(const float *ti, const float *tj, float *out, int64_t n, void *hip_stream) {
+    if (n < 0 || (n > 0 && (!ti || !tj || !out))) return L2T_EINVAL;
+    return l2t::pair_fp32(ti, tj, out, n, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

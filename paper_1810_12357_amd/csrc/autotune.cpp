@@ -1,0 +1,164 @@
+// Autotuner for the FP32C sub-step launch: times the candidate launch
+// shapes (persistent launch with a grid barrier vs one launch per sub-step,
+// workgroup size) on a short probe from the current state, restores the
+// state, and keeps the fastest.  Results are cached per problem shape in
+// memory and, when L2T_AUTOTUNE_CACHE names a file, on disk.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "l2t_internal.h"
+
+namespace l2t {
+namespace {
+
+struct Choice {
+    int persistent, block;
+};
+
+std::map<std::string, Choice> &mem_cache() {
+    static std::map<std::string, Choice> m;
+    return m;
+}
+
+std::string shape_key(const l2t_ctx *c) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "n_int=%d slices=%d sys=%zu nbr=%d cu=%d", c->n_int,
+                  c->n_slices, c->sys.size(), c->max_nbrs, c->n_cu);
+    return buf;
+}
+
+bool file_lookup(const std::string &key, Choice *ch) {
+    const char *path = std::getenv("L2T_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char *bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = '\0';
+        if (key == line) {
+            int p = 0, b = 0;
+            if (std::sscanf(bar + 1, "%d %d", &p, &b) == 2) {
+                ch->persistent = p;
+                ch->block = b;
+                found = true;
+            }
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void file_store(const std::string &key, const Choice &ch) {
+    const char *path = std::getenv("L2T_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s|%d %d\n", key.c_str(), ch.persistent, ch.block);
+    std::fclose(f);
+}
+
+}  // namespace
+
+int autotune(l2t_ctx *c) {
+    Tuning &t = c->tune;
+    const std::string key = shape_key(c);
+    Choice best{t.persistent, t.block};
+    auto it = mem_cache().find(key);
+    if (it != mem_cache().end() || file_lookup(key, &best)) {
+        if (it != mem_cache().end()) best = it->second;
+        t.persistent = best.persistent;
+        t.block = best.block;
+        t.tuned = true;
+        return L2T_OK;
+    }
+    // snapshot of everything a probe changes
+    const size_t NI = (size_t)c->n_int, NS = (size_t)c->n_slices, S = c->sys.size();
+    const size_t bytes = sizeof(float) * 2 * NI + sizeof(double) * 3 * NS + sizeof(int64_t) * S;
+    if (ensure_scratch(c, bytes) != L2T_OK) return L2T_ENOMEM;
+    char *p = (char *)c->scratch;
+    float *s_hi = (float *)p;
+    float *s_lo = s_hi + NI;
+    double *s_led = (double *)(s_lo + NI);
+    int64_t *s_step = (int64_t *)(s_led + 3 * NS);
+    const int cur = c->cur;
+    auto save = [&]() -> int {
+        L2T_HIP(c, hipMemcpyAsync(s_hi, c->Thi[cur], sizeof(float) * NI, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        L2T_HIP(c, hipMemcpyAsync(s_lo, c->Tlo, sizeof(float) * NI, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        L2T_HIP(c, hipMemcpyAsync(s_led, c->ledger, sizeof(double) * 3 * NS,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        L2T_HIP(c, hipMemcpyAsync(s_step, c->dstep, sizeof(int64_t) * S, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        return L2T_OK;
+    };
+    auto restore = [&]() -> int {
+        L2T_HIP(c, hipMemcpyAsync(c->Thi[cur], s_hi, sizeof(float) * NI, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        L2T_HIP(c, hipMemcpyAsync(c->Tlo, s_lo, sizeof(float) * NI, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        L2T_HIP(c, hipMemcpyAsync(c->ledger, s_led, sizeof(double) * 3 * NS,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        L2T_HIP(c, hipMemcpyAsync(c->dstep, s_step, sizeof(int64_t) * S, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        return L2T_OK;
+    };
+    int rc = save();
+    if (rc != L2T_OK) return rc;
+    hipEvent_t e0, e1;
+    L2T_HIP(c, hipEventCreate(&e0));
+    L2T_HIP(c, hipEventCreate(&e1));
+    const int probe = 16;   // even: the probe leaves the state in buffer `cur`
+    float best_ms = 1e30f;
+    const std::vector<Choice> cand = {{1, 256}, {1, 128}, {1, 64}, {0, 256}, {0, 128}};
+    for (const Choice &ch : cand) {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 2 && rc == L2T_OK; ++rep) {
+            L2T_HIP(c, hipEventRecord(e0, c->stream));
+            rc = fp32c_launch(c, probe, ch.persistent, ch.block, 0, 0);
+            L2T_HIP(c, hipEventRecord(e1, c->stream));
+            L2T_HIP(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            L2T_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+            ms_min = std::min(ms_min, ms);
+            if (rc == L2T_OK) rc = restore();
+        }
+        if (rc != L2T_OK) break;
+        unsigned err = 0;
+        L2T_HIP(c, hipMemcpyAsync(&err, c->derr, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                  c->stream));
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+        if (err & kErrBarrier) {
+            // a persistent shape that did not get all its workgroups resident
+            L2T_HIP(c, hipMemsetAsync(c->derr, 0, sizeof(unsigned), c->stream));
+            continue;
+        }
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = ch;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != L2T_OK) return rc;
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    t.persistent = best.persistent;
+    t.block = best.block;
+    t.tuned = true;
+    mem_cache()[key] = best;
+    file_store(key, best);
+    drop_graphs(c);
+    return L2T_OK;
+}
+
+}  // namespace l2t

@@ -1,0 +1,662 @@
+// Geometry kernels: cell binning, cell-sorted internal order, neighbour sets
+// in wavefront-sliced column-major layout, per-atom field permutation, the
+// local lattice temperature (Eq. 4) with the kinetic-energy gate, and the
+// per-atom depth weights of the laser source (Eq. 9).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "l2t_internal.h"
+
+namespace l2t {
+namespace {
+
+struct Grid {
+    int32_t nc[3];
+    int32_t periodic[3];
+    double lo[3], len[3];
+};
+
+__device__ inline double wrap_coord(double x, double lo, double len, int32_t periodic) {
+    double s = x - lo;
+    if (periodic) s -= len * floor(s / len);
+    return s;
+}
+
+__device__ inline int32_t cell_coord(double s, double len, int32_t nc) {
+    int32_t k = (int32_t)floor(s / len * (double)nc);
+    return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+}
+
+// distinct cell coordinates c-1, c, c+1 along one axis (wrapped or clipped)
+__device__ inline int axis_cells(int32_t c, int32_t nc, int32_t periodic, int32_t out[3]) {
+    int m = 0;
+    for (int o = -1; o <= 1; ++o) {
+        int32_t k = c + o;
+        if (periodic) {
+            k = (k % nc + nc) % nc;
+        } else if (k < 0 || k >= nc) {
+            continue;
+        }
+        bool dup = false;
+        for (int q = 0; q < m; ++q) dup |= (out[q] == k);
+        if (!dup) out[m++] = k;
+    }
+    return m;
+}
+
+__device__ inline double min_image(double d, double len, int32_t periodic) {
+    return periodic ? d - len * rint(d / len) : d;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// bin the atoms of one system (caller order) into cells of edge >= r_cut
+__global__ void k_bin(const double *px, const double *py, const double *pz, int32_t n, Grid g,
+                      int32_t *cell_of, int32_t *count, unsigned *err) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double p[3] = {px[i], py[i], pz[i]};
+    int32_t ic[3];
+    for (int d = 0; d < 3; ++d) {
+        double s = wrap_coord(p[d], g.lo[d], g.len[d], g.periodic[d]);
+        if (!g.periodic[d] && !(s >= 0.0 && s <= g.len[d])) atomicOr(err, kErrBox);
+        ic[d] = cell_coord(s, g.len[d], g.nc[d]);
+    }
+    int32_t cell = (ic[0] * g.nc[1] + ic[1]) * g.nc[2] + ic[2];
+    cell_of[i] = cell;
+    atomicAdd(&count[cell], 1);
+}
+
+// exclusive prefix sum of n int32 values with out[n] = total; one workgroup,
+// fixed chunking, so the result is deterministic
+__global__ void k_scan_excl(const int32_t *in, int32_t *out, int64_t n) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x, T = blockDim.x;
+    int64_t chunk = (n + T - 1) / T;
+    int64_t b = (int64_t)t * chunk, e = b + chunk < n ? b + chunk : n;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += in[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int k = 0; k < T; ++k) {
+            int64_t v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        out[n] = (int32_t)acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t i = b; i < e; ++i) {
+        int32_t v = in[i];
+        out[i] = (int32_t)acc;
+        acc += v;
+    }
+}
+
+__global__ void k_scatter(const int32_t *cell_of, int32_t n, const int32_t *start, int32_t *fill,
+                          int32_t *sorted) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = cell_of[i];
+    int32_t pos = start[c] + atomicAdd(&fill[c], 1);
+    sorted[pos] = i;
+}
+
+// order the atoms inside every cell by caller index (makes the order
+// independent of the atomic scatter)
+__global__ void k_sort_cells(const int32_t *start, int64_t ncell, int32_t *sorted) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int32_t b = start[c], e = start[c + 1];
+    for (int32_t i = b + 1; i < e; ++i) {
+        int32_t v = sorted[i];
+        int32_t j = i - 1;
+        while (j >= b && sorted[j] > v) {
+            sorted[j + 1] = sorted[j];
+            --j;
+        }
+        sorted[j + 1] = v;
+    }
+}
+
+// internal slots of one system: slot = atom_off + position in cell order
+__global__ void k_assign(const int32_t *sorted, int32_t n, int32_t n_pad, int32_t atom_off,
+                         int64_t caller_off, const double *px, const double *py, const double *pz,
+                         const int32_t *cell_of, Grid g, int32_t *perm, int32_t *inv,
+                         int32_t *cell_int, double *qx, double *qy, double *qz) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_pad) return;
+    int32_t slot = atom_off + k;
+    if (k < n) {
+        int32_t i = sorted[k];
+        perm[slot] = (int32_t)(caller_off + i);
+        inv[caller_off + i] = slot;
+        cell_int[slot] = cell_of[i];
+        qx[slot] = g.lo[0] + wrap_coord(px[i], g.lo[0], g.len[0], g.periodic[0]);
+        qy[slot] = g.lo[1] + wrap_coord(py[i], g.lo[1], g.len[1], g.periodic[1]);
+        qz[slot] = g.lo[2] + wrap_coord(pz[i], g.lo[2], g.len[2], g.periodic[2]);
+    } else {
+        perm[slot] = -1;
+        cell_int[slot] = -1;
+        qx[slot] = qy[slot] = qz[slot] = 0.0;
+    }
+}
+
+// count (FILL = false) or write (FILL = true) the neighbour set of every atom
+// of one system; rows visit the distinct cells of the 3x3x3 stencil in a
+// fixed order and each cell's atoms in cell order
+template <bool FILL>
+__global__ void k_neighbors(int32_t n, int32_t atom_off, const double *qx, const double *qy,
+                            const double *qz, const int32_t *cell_int, const int32_t *start,
+                            Grid g, double rc2, int32_t *cnt, const SliceInfo *slices,
+                            int32_t *col) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int32_t slot = atom_off + k;
+    const double xi = qx[slot], yi = qy[slot], zi = qz[slot];
+    const int32_t cell0 = cell_int[slot];
+    int32_t ic[3] = {cell0 / (g.nc[1] * g.nc[2]), (cell0 / g.nc[2]) % g.nc[1], cell0 % g.nc[2]};
+    int32_t sx[3], sy[3], sz[3];
+    int mx = axis_cells(ic[0], g.nc[0], g.periodic[0], sx);
+    int my = axis_cells(ic[1], g.nc[1], g.periodic[1], sy);
+    int mz = axis_cells(ic[2], g.nc[2], g.periodic[2], sz);
+    int32_t m = 0;
+    int64_t base = 0;
+    int lane = slot & (kWave - 1);
+    int32_t width = 0;
+    if (FILL) {
+        const SliceInfo si = slices[slot / kWave];
+        base = (int64_t)si.col_base64 * kWave + lane;
+        width = si.width;
+    }
+    for (int a = 0; a < mx; ++a)
+        for (int b = 0; b < my; ++b)
+            for (int e = 0; e < mz; ++e) {
+                int32_t cell = (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[e];
+                for (int32_t q = start[cell]; q < start[cell + 1]; ++q) {
+                    int32_t j = atom_off + q;
+                    if (j == slot) continue;
+                    double dx = min_image(qx[j] - xi, g.len[0], g.periodic[0]);
+                    double dy = min_image(qy[j] - yi, g.len[1], g.periodic[1]);
+                    double dz = min_image(qz[j] - zi, g.len[2], g.periodic[2]);
+                    if (dx * dx + dy * dy + dz * dz <= rc2) {
+                        if (FILL) col[base + (int64_t)m * kWave] = j;
+                        ++m;
+                    }
+                }
+            }
+    if (FILL) {
+        for (int32_t q = m; q < width; ++q) col[base + (int64_t)q * kWave] = slot;
+    } else {
+        cnt[slot] = m;
+    }
+}
+
+__global__ void k_slice_width(const int32_t *cnt, const int32_t *perm, int32_t n_slices,
+                              int32_t *width, int32_t *nvalid) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slices) return;
+    int32_t w = 0, v = 0;
+    for (int l = 0; l < kWave; ++l) {
+        int32_t slot = s * kWave + l;
+        if (perm[slot] >= 0) {
+            w = max(w, cnt[slot]);
+            ++v;
+        }
+    }
+    width[s] = w;
+    nvalid[s] = v;
+}
+
+// pad slots carry no atom: zero count
+__global__ void k_zero_pad_counts(const int32_t *perm, int32_t *cnt, int32_t n_int) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_int && perm[s] < 0) cnt[s] = 0;
+}
+
+// pad slots still run the neighbour loop of their slice: every entry of
+// their row points at the slot itself (pair term zero, always in bounds)
+__global__ void k_pad_rows(const int32_t *perm, const SliceInfo *slices, int32_t n_int,
+                           int32_t *col) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_int || perm[s] >= 0) return;
+    const SliceInfo si = slices[s / kWave];
+    const int64_t base = (int64_t)si.col_base64 * kWave + (s & (kWave - 1));
+    for (int32_t q = 0; q < si.width; ++q) col[base + (int64_t)q * kWave] = s;
+}
+
+// ---- per-atom fields -------------------------------------------------------
+__global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
+                           const double *src, int32_t field, int32_t precision, double *T64,
+                           float *Thi, float *Tlo, double *Tl64, float *Tl32) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_pad) return;
+    int32_t slot = atom_off + k;
+    int32_t g = perm[slot];
+    double v = (g >= 0) ? src[g - caller_off] : 0.0;
+    if (field == L2T_FIELD_TE) {
+        if (precision == L2T_FP64) {
+            T64[slot] = v;
+        } else {
+            float hi = (float)v;
+            Thi[slot] = hi;
+            Tlo[slot] = (float)(v - (double)hi);
+        }
+    } else if (field == L2T_FIELD_TL) {
+        if (precision == L2T_FP64) {
+            Tl64[slot] = copysign(v, signbit(Tl64[slot]) ? -1.0 : 1.0);
+        } else {
+            Tl32[slot] = copysignf((float)v, signbit(Tl32[slot]) ? -1.0f : 1.0f);
+        }
+    } else if (field == L2T_FIELD_GATE) {
+        bool gated = (g >= 0) && v != 0.0;
+        if (precision == L2T_FP64) {
+            Tl64[slot] = gated ? -fabs(Tl64[slot]) : fabs(Tl64[slot]);
+        } else {
+            Tl32[slot] = gated ? -fabsf(Tl32[slot]) : fabsf(Tl32[slot]);
+        }
+    }
+}
+
+__global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
+                            int32_t field, int32_t precision, const double *T64, const float *Thi,
+                            const float *Tlo, const double *Tl64, const float *Tl32,
+                            const int32_t *cnt, double *dst) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_pad) return;
+    int32_t slot = atom_off + k;
+    int32_t g = perm[slot];
+    if (g < 0) return;
+    double v = 0.0;
+    if (field == L2T_FIELD_TE) {
+        v = (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+    } else if (field == L2T_FIELD_TL) {
+        v = (precision == L2T_FP64) ? fabs(Tl64[slot]) : (double)fabsf(Tl32[slot]);
+    } else if (field == L2T_FIELD_GATE) {
+        bool s = (precision == L2T_FP64) ? signbit(Tl64[slot]) : signbit(Tl32[slot]);
+        v = s ? 1.0 : 0.0;
+    } else if (field == L2T_FIELD_NBRS) {
+        v = (double)cnt[slot];
+    }
+    dst[g - caller_off] = v;
+}
+
+__global__ void k_range_count(const double *v, int64_t n, double lo, double hi, unsigned *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = v[i];
+    if (!(x >= lo && x <= hi)) atomicAdd(bad, 1u);
+}
+
+// ---- Eq. 4 lattice temperature -----------------------------------------------
+// gather velocities and masses of one system into internal order
+__global__ void k_gather_vm(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
+                            int32_t n, const double *v, const double *m, double *out /*[4][n_pad]*/) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_pad) return;
+    int32_t g = perm[atom_off + k];
+    if (g < 0) {
+        out[k] = out[n_pad + k] = out[2 * n_pad + k] = out[3 * n_pad + k] = 0.0;
+        return;
+    }
+    int64_t i = g - caller_off;
+    out[k] = v[i];
+    out[n_pad + k] = v[n + i];
+    out[2 * n_pad + k] = v[2 * n + i];
+    out[3 * n_pad + k] = m[i];
+}
+
+// system-wide momentum and mass (one workgroup, fixed reduction order)
+__global__ void k_momentum(const double *vm, int32_t n_pad, double *out /*[4]*/) {
+    __shared__ double red[4][256];
+    const int t = threadIdx.x;
+    double a[4] = {0, 0, 0, 0};
+    for (int32_t k = t; k < n_pad; k += blockDim.x) {
+        double m = vm[3 * n_pad + k];
+        a[0] += m * vm[k];
+        a[1] += m * vm[n_pad + k];
+        a[2] += m * vm[2 * n_pad + k];
+        a[3] += m;
+    }
+    for (int q = 0; q < 4; ++q) red[q][t] = a[q];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int q = 0; q < 4; ++q) out[q] = red[q][0];
+}
+
+// T_i^lat = sum_{j in {i} U N(i)} 1/2 m_j |v_j - v_com|^2 / (3/2 k_B N_j); the
+// coupling of atom i is gated off where 1/2 m_i |v_i - v_com|^2 < ke_eps.  The
+// gate is stored in the sign bit of T^lat.
+__global__ void k_lattice_temp(int32_t atom_off, int32_t n_pad, const int32_t *perm,
+                               const SliceInfo *slices, const int32_t *col, const double *vm,
+                               const double *gmom, int32_t global_com, double ke_eps,
+                               int32_t precision, double *Tl64, float *Tl32) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_pad) return;
+    int32_t slot = atom_off + k;
+    if (perm[slot] < 0) return;
+    const double *vx = vm, *vy = vm + n_pad, *vz = vm + 2 * n_pad, *ms = vm + 3 * n_pad;
+    const SliceInfo si = slices[slot / kWave];
+    const int64_t base = (int64_t)si.col_base64 * kWave + (slot & (kWave - 1));
+    double vc[3];
+    if (global_com) {
+        vc[0] = gmom[0] / gmom[3];
+        vc[1] = gmom[1] / gmom[3];
+        vc[2] = gmom[2] / gmom[3];
+    } else {
+        double P[3] = {ms[k] * vx[k], ms[k] * vy[k], ms[k] * vz[k]}, M = ms[k];
+        for (int32_t q = 0; q < si.width; ++q) {
+            int32_t j = col[base + (int64_t)q * kWave];
+            if (j == slot) continue;
+            int32_t l = j - atom_off;
+            P[0] += ms[l] * vx[l];
+            P[1] += ms[l] * vy[l];
+            P[2] += ms[l] * vz[l];
+            M += ms[l];
+        }
+        vc[0] = P[0] / M;
+        vc[1] = P[1] / M;
+        vc[2] = P[2] / M;
+    }
+    double ux = vx[k] - vc[0], uy = vy[k] - vc[1], uz = vz[k] - vc[2];
+    double Ki = 0.5 * ms[k] * (ux * ux + uy * uy + uz * uz) * kMvv2e;
+    double KE = Ki;
+    int32_t nj = 1;
+    for (int32_t q = 0; q < si.width; ++q) {
+        int32_t j = col[base + (int64_t)q * kWave];
+        if (j == slot) continue;
+        int32_t l = j - atom_off;
+        double wx = vx[l] - vc[0], wy = vy[l] - vc[1], wz = vz[l] - vc[2];
+        KE += 0.5 * ms[l] * (wx * wx + wy * wy + wz * wz) * kMvv2e;
+        ++nj;
+    }
+    double T = KE / (1.5 * kBoltzmann * (double)nj);
+    bool gated = Ki < ke_eps;
+    if (precision == L2T_FP64) {
+        Tl64[slot] = gated ? -T : T;
+        if (gated && T == 0.0) Tl64[slot] = -0.0;
+    } else {
+        float f = (float)T;
+        Tl32[slot] = gated ? -f : f;
+        if (gated && f == 0.0f) Tl32[slot] = -0.0f;
+    }
+}
+
+// depth weight of the Eq. 9 source: exp(-(x_i - x_0)/l_p)
+__global__ void k_source_weights(int32_t atom_off, int32_t n_pad, const int32_t *perm,
+                                 const double *qx, double x0, double lp, double *w64, float *w32) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_pad) return;
+    int32_t slot = atom_off + k;
+    double w = (perm[slot] >= 0) ? exp(-(qx[slot] - x0) / lp) : 0.0;
+    if (w64) w64[slot] = w;
+    if (w32) w32[slot] = (float)w;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int build_neighbors(l2t_ctx *c, double r_cut) {
+    const int S = (int)c->sys.size();
+    // cell grids
+    int64_t cells_total = 0;
+    std::vector<int64_t> cstart_off(S);
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
+        st.ncell = 1;
+        for (int d = 0; d < 3; ++d) {
+            if (st.desc.periodic[d] && st.desc.box_len[d] < 2.0 * r_cut)
+                return fail(c, L2T_EINVAL, "system " + std::to_string(s) +
+                                               ": periodic box length below 2 r_cut");
+            double k = std::floor(st.desc.box_len[d] / r_cut);
+            st.nc[d] = (int32_t)std::max(1.0, std::min(k, 1.0e6));
+            st.ncell *= st.nc[d];
+        }
+        if (st.ncell > (int64_t)1 << 30) return fail(c, L2T_EINVAL, "cell grid too large");
+        cstart_off[s] = cells_total;
+        st.cell_off = cells_total;
+        cells_total += st.ncell + 1;
+    }
+    if (cells_total > c->cells_total) {
+        if (c->cell_start) (void)hipFree(c->cell_start);
+        if (c->cell_scratch) (void)hipFree(c->cell_scratch);
+        c->cell_start = nullptr;
+        c->cell_scratch = nullptr;
+        if (hipMalloc(&c->cell_start, sizeof(int32_t) * cells_total) != hipSuccess ||
+            hipMalloc(&c->cell_scratch, sizeof(int32_t) * cells_total) != hipSuccess)
+            return fail(c, L2T_ENOMEM, "cell list allocation failed");
+        c->cells_total = cells_total;
+    }
+    const hipStream_t st_ = c->stream;
+    L2T_HIP(c, hipMemsetAsync(c->derr, 0, sizeof(unsigned), st_));
+    const double rc2 = r_cut * r_cut;
+    std::vector<Grid> grids(S);
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
+        Grid &g = grids[s];
+        for (int d = 0; d < 3; ++d) {
+            g.nc[d] = st.nc[d];
+            g.periodic[d] = st.desc.periodic[d];
+            g.lo[d] = st.desc.box_lo[d];
+            g.len[d] = st.desc.box_len[d];
+        }
+        const int32_t n = st.desc.n_atoms;
+        const double *px = c->pos + st.caller_off, *py = px + c->n_tot, *pz = py + c->n_tot;
+        int32_t *count = c->cell_scratch + cstart_off[s];
+        int32_t *start = c->cell_start + cstart_off[s];
+        int32_t *cell_of = c->cell_of + st.caller_off;
+        int32_t *sorted = c->sorted_local + st.caller_off;
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, count,
+                           st.ncell, 0);
+        hipLaunchKernelGGL(k_bin, dim3(nblk(n, 256)), dim3(256), 0, st_, px, py, pz, n, g, cell_of,
+                           count, c->derr);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st_, count, start, st.ncell);
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, count,
+                           st.ncell, 0);
+        hipLaunchKernelGGL(k_scatter, dim3(nblk(n, 256)), dim3(256), 0, st_, cell_of, n, start,
+                           count, sorted);
+        hipLaunchKernelGGL(k_sort_cells, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, start,
+                           st.ncell, sorted);
+        hipLaunchKernelGGL(k_assign, dim3(nblk(st.n_pad, 256)), dim3(256), 0, st_, sorted, n,
+                           st.n_pad, st.atom_off, st.caller_off, px, py, pz, cell_of, g, c->perm,
+                           c->inv, c->cell_int, c->pos_int, c->pos_int + c->n_int,
+                           c->pos_int + 2 * (int64_t)c->n_int);
+        hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
+                           st.atom_off, c->pos_int, c->pos_int + c->n_int,
+                           c->pos_int + 2 * (int64_t)c->n_int, c->cell_int, start, g, rc2, c->cnt,
+                           nullptr, nullptr);
+    }
+    L2T_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_zero_pad_counts, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
+                       c->cnt, c->n_int);
+    // slice widths -> column offsets (host scan)
+    int32_t *dw = c->cell_scratch;   // reuse: needs 2 * n_slices ints
+    if ((int64_t)2 * c->n_slices > c->cells_total) {
+        if (ensure_scratch(c, sizeof(int32_t) * 2 * (size_t)c->n_slices) != L2T_OK) return L2T_ENOMEM;
+        dw = (int32_t *)c->scratch;
+    }
+    hipLaunchKernelGGL(k_slice_width, dim3(nblk(c->n_slices, 256)), dim3(256), 0, st_, c->cnt,
+                       c->perm, c->n_slices, dw, dw + c->n_slices);
+    std::vector<int32_t> hw(2 * (size_t)c->n_slices);
+    L2T_HIP(c, hipMemcpyAsync(hw.data(), dw, sizeof(int32_t) * hw.size(), hipMemcpyDeviceToHost,
+                              st_));
+    unsigned herr = 0;
+    L2T_HIP(c, hipMemcpyAsync(&herr, c->derr, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
+    L2T_HIP(c, hipStreamSynchronize(st_));
+    if (herr & kErrBox) return fail(c, L2T_EINVAL, "an atom lies outside the box on a free axis");
+    std::vector<SliceInfo> hs(c->n_slices);
+    int64_t total64 = 0;
+    int32_t wmax = 0;
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
+        st.max_nbrs = 0;
+        for (int32_t q = 0; q < st.n_slices; ++q) {
+            int32_t sl = st.slice0 + q;
+            hs[sl].sys = s;
+            hs[sl].width = hw[sl];
+            hs[sl].n_valid = hw[c->n_slices + sl];
+            if (total64 > INT32_MAX) return fail(c, L2T_ENOMEM, "neighbour table too large");
+            hs[sl].col_base64 = (int32_t)total64;
+            total64 += hw[sl];
+            st.max_nbrs = std::max(st.max_nbrs, hw[sl]);
+        }
+        wmax = std::max(wmax, st.max_nbrs);
+    }
+    int64_t col_len = std::max<int64_t>(total64 * kWave, 1);
+    if (col_len > c->col_len) {
+        if (c->col) (void)hipFree(c->col);
+        c->col = nullptr;
+        if (hipMalloc(&c->col, sizeof(int32_t) * col_len) != hipSuccess)
+            return fail(c, L2T_ENOMEM, "neighbour table allocation failed");
+        c->col_len = col_len;
+    }
+    L2T_HIP(c, hipMemcpyAsync(c->slices, hs.data(), sizeof(SliceInfo) * hs.size(),
+                              hipMemcpyHostToDevice, st_));
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
+        const int32_t n = st.desc.n_atoms;
+        hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n, st.atom_off,
+                           c->pos_int, c->pos_int + c->n_int, c->pos_int + 2 * (int64_t)c->n_int,
+                           c->cell_int, c->cell_start + cstart_off[s], grids[s], rc2, c->cnt,
+                           c->slices, c->col);
+    }
+    hipLaunchKernelGGL(k_pad_rows, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
+                       c->slices, c->n_int, c->col);
+    L2T_HIP(c, hipGetLastError());
+    // statistics
+    std::vector<int32_t> hc(c->n_int);
+    L2T_HIP(c, hipMemcpyAsync(hc.data(), c->cnt, sizeof(int32_t) * hc.size(), hipMemcpyDeviceToHost,
+                              st_));
+    L2T_HIP(c, hipStreamSynchronize(st_));
+    int64_t sum = 0;
+    int32_t mx = 0;
+    for (int32_t v : hc) {
+        sum += v;
+        mx = std::max(mx, v);
+    }
+    c->max_nbrs = mx;
+    c->mean_nbrs = c->n_tot > 0 ? (double)sum / (double)c->n_tot : 0.0;
+    c->r_cut = r_cut;
+    (void)wmax;
+    return L2T_OK;
+}
+
+int permute_in(l2t_ctx *c, int32_t sys, const double *src_dev, int32_t field) {
+    const SystemState &st = c->sys[sys];
+    hipLaunchKernelGGL(k_field_in, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream, st.atom_off,
+                       st.n_pad, c->perm, st.caller_off, src_dev, field, c->precision,
+                       c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+int permute_out(l2t_ctx *c, int32_t sys, int32_t field, double *dst_dev) {
+    const SystemState &st = c->sys[sys];
+    hipLaunchKernelGGL(k_field_out, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream,
+                       st.atom_off, st.n_pad, c->perm, st.caller_off, field, c->precision,
+                       c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32, c->cnt, dst_dev);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+int check_field_range(l2t_ctx *c, const double *src_dev, int64_t n, double lo, double hi,
+                      bool *ok) {
+    unsigned *bad = c->derr + 1;
+    L2T_HIP(c, hipMemsetAsync(bad, 0, sizeof(unsigned), c->stream));
+    hipLaunchKernelGGL(k_range_count, dim3(nblk(n, 256)), dim3(256), 0, c->stream, src_dev, n, lo,
+                       hi, bad);
+    unsigned h = 0;
+    L2T_HIP(c, hipMemcpyAsync(&h, bad, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    *ok = (h == 0);
+    return L2T_OK;
+}
+
+int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_dev, const double *m_dev,
+                        int32_t global_com) {
+    const SystemState &st = c->sys[sys];
+    size_t need = sizeof(double) * (4 * (size_t)st.n_pad + 4);
+    if (ensure_scratch(c, need) != L2T_OK) return L2T_ENOMEM;
+    double *vm = (double *)c->scratch;
+    double *gm = vm + 4 * (size_t)st.n_pad;
+    hipLaunchKernelGGL(k_gather_vm, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream,
+                       st.atom_off, st.n_pad, c->perm, st.caller_off, st.desc.n_atoms, v_dev, m_dev,
+                       vm);
+    if (global_com)
+        hipLaunchKernelGGL(k_momentum, dim3(1), dim3(256), 0, c->stream, vm, st.n_pad, gm);
+    hipLaunchKernelGGL(k_lattice_temp, dim3(nblk(st.n_pad, 128)), dim3(128), 0, c->stream,
+                       st.atom_off, st.n_pad, c->perm, c->slices, c->col, vm, gm, global_com,
+                       st.params.ke_eps, c->precision, c->Tl64, c->Tl32);
+    L2T_HIP(c, hipGetLastError());
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    return L2T_OK;
+}
+
+int source_weights(l2t_ctx *c, int32_t sys) {
+    const SystemState &st = c->sys[sys];
+    if (!st.params.laser_on) return L2T_OK;
+    hipLaunchKernelGGL(k_source_weights, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream,
+                       st.atom_off, st.n_pad, c->perm, c->pos_int, st.params.laser_x0,
+                       st.params.laser_lp, c->precision == L2T_FP64 ? c->srcw64 : nullptr,
+                       c->precision == L2T_FP32C ? c->srcw32 : nullptr);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+int neighbors_to_host(l2t_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *col, int64_t cap) {
+    const SystemState &st = c->sys[sys];
+    const int32_t n = st.desc.n_atoms;
+    std::vector<SliceInfo> hs(st.n_slices);
+    std::vector<int32_t> perm(st.n_pad), cnt(st.n_pad), inv(n);
+    L2T_HIP(c, hipMemcpyAsync(hs.data(), c->slices + st.slice0, sizeof(SliceInfo) * hs.size(),
+                              hipMemcpyDeviceToHost, c->stream));
+    L2T_HIP(c, hipMemcpyAsync(perm.data(), c->perm + st.atom_off, sizeof(int32_t) * st.n_pad,
+                              hipMemcpyDeviceToHost, c->stream));
+    L2T_HIP(c, hipMemcpyAsync(cnt.data(), c->cnt + st.atom_off, sizeof(int32_t) * st.n_pad,
+                              hipMemcpyDeviceToHost, c->stream));
+    int64_t c0 = (int64_t)hs.empty() ? 0 : (int64_t)hs[0].col_base64 * kWave;
+    int64_t c1 = c0;
+    for (const SliceInfo &si : hs) c1 = std::max<int64_t>(c1, ((int64_t)si.col_base64 + si.width) * kWave);
+    std::vector<int32_t> hcol(std::max<int64_t>(c1 - c0, 1));
+    if (c1 > c0)
+        L2T_HIP(c, hipMemcpyAsync(hcol.data(), c->col + c0, sizeof(int32_t) * (c1 - c0),
+                                  hipMemcpyDeviceToHost, c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    // row lengths in caller order
+    for (int32_t k = 0; k < st.n_pad; ++k)
+        if (perm[k] >= 0) inv[perm[k] - st.caller_off] = k;
+    row_ptr[0] = 0;
+    for (int32_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[inv[i]];
+    if (!col) return L2T_OK;
+    if (row_ptr[n] > cap) return fail(c, L2T_EINVAL, "col capacity below the neighbour count");
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t k = inv[i];
+        const SliceInfo &si = hs[k / kWave];
+        int64_t base = (int64_t)si.col_base64 * kWave - c0 + (k % kWave);
+        int32_t *dst = col + row_ptr[i];
+        for (int32_t q = 0; q < cnt[k]; ++q) {
+            int32_t j = hcol[base + (int64_t)q * kWave];
+            dst[q] = (int32_t)(perm[j - st.atom_off] - st.caller_off);
+        }
+        std::sort(dst, dst + cnt[k]);
+    }
+    return L2T_OK;
+}
+
+}  // namespace l2t

@@ -1,0 +1,437 @@
+// Sub-step kernels of the master equation (Eq. 2) with electron-phonon
+// coupling and the laser source (Eq. 9), forward Euler (Section 2.1), plus the
+// per-system FP64 energy / ledger reductions.
+//
+// Layout: one wavefront owns one slice of 64 consecutive cell-sorted atoms;
+// lane l of the wave owns atom 64*slice + l.  Neighbour indices of a slice are
+// column-major (entry k of all 64 lanes is one coalesced 256-byte read) and
+// short rows are padded with the atom's own index, whose pair term is zero.
+//
+//  * FP64 plain: literal two-exponential pair term, one launch per sub-step.
+//  * FP32C: cancellation-free product form of the pair term evaluated in
+//    FP32 from the hi part of the neighbour temperatures, Kahan-compensated
+//    per-atom sum, state kept as an unevaluated FP32 pair hi + lo and updated
+//    with an error-free transformation; FP64 only in the ledger reductions.
+//    Either one launch per sub-step, or a persistent launch that runs all
+//    sub-steps with a grid barrier between them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "l2t_internal.h"
+#include "step_device.h"
+
+namespace l2t {
+namespace {
+
+using namespace dev;
+
+// ---- kernels ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_step_fp64(const SliceInfo *slices, int32_t slice0,
+                                                   int32_t n_slices, const int32_t *col,
+                                                   const double *T, double *Tn, const double *Tl,
+                                                   const double *srcw, const DevParams *P,
+                                                   const int64_t *dstep, int32_t rel,
+                                                   double *ledger, unsigned *err) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (q >= n_slices) return;
+    const int32_t sl = slice0 + q;
+    const SliceInfo si = slices[sl];
+    const DevParams &p = P[si.sys];
+    slice_step_fp64(si, sl, lane, p, col, T, Tn, Tl, srcw, dstep[si.sys] + rel, ledger, err);
+}
+
+__global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int32_t slice0,
+                                                    int32_t n_slices, const int32_t *col,
+                                                    const float *Thi, float *Thi_n, float *Tlo,
+                                                    const float *Tl, const float *srcw,
+                                                    const DevParams *P, const int64_t *dstep,
+                                                    int32_t rel, double *ledger, unsigned *err) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (q >= n_slices) return;
+    const int32_t sl = slice0 + q;
+    const SliceInfo si = slices[sl];
+    const DevParams &p = P[si.sys];
+    slice_step_fp32c(si, sl, lane, p, col, Thi, Thi_n, Tlo, Tl, srcw, dstep[si.sys] + rel, ledger,
+                     err);
+}
+
+// Grid-wide barrier for the persistent kernel.  bar[0] counts arrivals over
+// the whole launch (barrier k completes at k * nblocks arrivals); bar[1] is an
+// abort word raised when a block spins past the limit, so every block leaves
+// instead of waiting forever.  Release / acquire at agent scope make the
+// sub-step's writes visible across the XCDs.
+__device__ inline bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned k, unsigned *err) {
+    __syncthreads();
+    __shared__ int abort_flag;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = k * nblocks;
+        int ab = 0;
+        unsigned long long spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1ull << 25)) {
+                atomicOr(err, kErrBarrier);
+                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+        }
+        __threadfence();
+        abort_flag = ab;
+    }
+    __syncthreads();
+    return abort_flag == 0;
+}
+
+// Persistent FP32C launch: every workgroup owns a fixed contiguous range of
+// slices, runs n_steps sub-steps over it, and meets the others at a grid
+// barrier after each sub-step.  Workgroup b runs on XCD b mod 8; it takes
+// logical range (b mod 8) * (G/8) + b/8 so that each XCD sweeps one
+// contiguous eighth of the atoms and its L2 serves the neighbour gathers.
+__global__ __launch_bounds__(256) void k_persistent_fp32c(
+    const SliceInfo *slices, int32_t n_slices, const int32_t *col, float *Thi0, float *Thi1,
+    float *Tlo, const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep,
+    int32_t n_steps, double *ledger, unsigned *err, unsigned *bar) {
+    const unsigned G = gridDim.x;
+    const unsigned b = blockIdx.x;
+    const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+    const int32_t per = (n_slices + (int32_t)G - 1) / (int32_t)G;
+    const int32_t s_lo = min(n_slices, (int32_t)logical * per);
+    const int32_t s_hi = min(n_slices, s_lo + per);
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    for (int32_t st = 0; st < n_steps; ++st) {
+        const float *Tin = (st & 1) ? Thi1 : Thi0;
+        float *Tout = (st & 1) ? Thi0 : Thi1;
+        for (int32_t sl = s_lo + wave; sl < s_hi; sl += nw) {
+            const SliceInfo si = slices[sl];
+            slice_step_fp32c(si, sl, lane, P[si.sys], col, Tin, Tout, Tlo, Tl, srcw,
+                             dstep[si.sys] + st, ledger, err);
+        }
+        if (!grid_barrier(bar, G, (unsigned)st + 1u, err)) return;
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+__global__ void k_bump(int64_t *dstep, int32_t s0, int32_t s1, int32_t n) {
+    int32_t s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < s1) dstep[s] += n;
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_copy_range_f64(const double *a, double *b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+__global__ void k_copy_range_f32(const float *a, float *b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// per-slice E_e, sum T, max T, min T (one wave per slice)
+__global__ void k_slice_energy(const SliceInfo *slices, int32_t slice0, int32_t n_slices,
+                               int32_t precision, const double *T64, const float *Thi,
+                               const float *Tlo, const DevParams *P, double *red) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (q >= n_slices) return;
+    const int32_t sl = slice0 + q;
+    const SliceInfo si = slices[sl];
+    const DevParams &p = P[si.sys];
+    const int32_t slot = sl * kWave + lane;
+    const bool valid = lane < si.n_valid;
+    double T = 0.0;
+    if (valid) T = (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+    double e = valid ? energy_of(p, T) : 0.0;
+    double s = valid ? T : 0.0;
+    double mx = valid ? T : -INFINITY, mn = valid ? T : INFINITY;
+    e = wave_sum(e);
+    s = wave_sum(s);
+    mx = wave_max(mx);
+    mn = wave_min(mn);
+    if (lane == 0) {
+        red[4 * (int64_t)sl + 0] = e;
+        red[4 * (int64_t)sl + 1] = s;
+        red[4 * (int64_t)sl + 2] = mx;
+        red[4 * (int64_t)sl + 3] = mn;
+    }
+}
+
+// per-system sums over its slices in a fixed order (one workgroup)
+__global__ void k_system_reduce(int32_t slice0, int32_t n_slices, const double *red,
+                                const double *ledger, double *out) {
+    __shared__ double acc[7][256];
+    const int t = threadIdx.x;
+    double a[7] = {0, 0, 0, 0, 0, -INFINITY, INFINITY};
+    for (int32_t q = t; q < n_slices; q += blockDim.x) {
+        const int64_t sl = slice0 + q;
+        a[0] += red[4 * sl + 0];
+        a[1] += red[4 * sl + 1];
+        a[2] += ledger[3 * sl + 0];
+        a[3] += ledger[3 * sl + 1];
+        a[4] += ledger[3 * sl + 2];
+        a[5] = fmax(a[5], red[4 * sl + 2]);
+        a[6] = fmin(a[6], red[4 * sl + 3]);
+    }
+    for (int k = 0; k < 7; ++k) acc[k][t] = a[k];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            for (int k = 0; k < 5; ++k) acc[k][t] += acc[k][t + w];
+            acc[5][t] = fmax(acc[5][t], acc[5][t + w]);
+            acc[6][t] = fmin(acc[6][t], acc[6][t + w]);
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < 7; ++k) out[k] = acc[k][0];
+}
+
+__global__ void k_pair(const float *ti, const float *tj, float *out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = pair32(ti[i], tj[i], 1.0f, 0.5f, 0.0f);
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int upload_params(l2t_ctx *c) {
+    const int S = (int)c->sys.size();
+    c->hparams.assign(S, DevParams{});
+    for (int s = 0; s < S; ++s) {
+        const SystemState &st = c->sys[s];
+        const l2t_params &q = st.params;
+        DevParams &p = c->hparams[s];
+        p.T_min = q.T_min;
+        p.span = q.T_max - q.T_min;
+        p.inv_span = 1.0 / p.span;
+        p.K = q.K;
+        p.A = p.span * q.K;
+        p.dt = q.dt;
+        p.g = q.g;
+        p.ce_const = q.ce_const;
+        p.gamma = q.gamma;
+        p.ce_cap = q.ce_cap;
+        p.ce_model = q.ce_model;
+        p.laser_on = q.laser_on;
+        p.lp = q.laser_lp;
+        p.t0 = q.laser_t0;
+        p.sigma = q.laser_sigma;
+        p.inv_sigma = q.laser_on ? 1.0 / q.laser_sigma : 0.0;
+        p.x0 = q.laser_x0;
+        p.i0 = q.laser_on ? q.laser_fluence * q.v_atom /
+                                (q.laser_lp * std::sqrt(2.0 * M_PI) * q.laser_sigma)
+                          : 0.0;
+        p.atom_off = st.atom_off;
+        p.n_pad = st.n_pad;
+        p.slice0 = st.slice0;
+        p.n_slices = st.n_slices;
+        p.f_inv_span = (float)p.inv_span;
+        p.f_half_inv_span = (float)(0.5 * p.inv_span);
+        p.f_m_off = (float)(-q.T_min * p.inv_span);
+        p.f_A = (float)p.A;
+        p.f_K = (float)q.K;
+        p.f_dt = (float)q.dt;
+        p.f_g = (float)q.g;
+        p.f_ce_const = (float)q.ce_const;
+        p.f_gamma = (float)q.gamma;
+        p.f_ce_cap = (float)q.ce_cap;
+        p.f_T_min = (float)q.T_min;
+        p.f_T_max = (float)q.T_max;
+        p.f_i0 = (float)p.i0;
+    }
+    L2T_HIP(c, hipMemcpyAsync(c->dparams, c->hparams.data(), sizeof(DevParams) * S,
+                              hipMemcpyHostToDevice, c->stream));
+    return L2T_OK;
+}
+
+int bump_steps(l2t_ctx *c, int32_t sys, int32_t n) {
+    int32_t s0 = sys < 0 ? 0 : sys, s1 = sys < 0 ? (int32_t)c->sys.size() : sys + 1;
+    hipLaunchKernelGGL(k_bump, dim3(nblk(s1 - s0, 256)), dim3(256), 0, c->stream, c->dstep, s0, s1,
+                       n);
+    L2T_HIP(c, hipGetLastError());
+    for (int32_t s = s0; s < s1; ++s) c->sys[s].step += n;
+    return L2T_OK;
+}
+
+int reset_ledger(l2t_ctx *c, int32_t sys) {
+    const SystemState &st = c->sys[sys];
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblk(3 * (int64_t)st.n_slices, 256)), dim3(256), 0,
+                       c->stream, c->ledger + 3 * (int64_t)st.slice0, 3 * (int64_t)st.n_slices);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+// One system (sys >= 0) or all systems (sys < 0), one launch per sub-step.
+int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
+    const int32_t s0 = sys < 0 ? 0 : c->sys[sys].slice0;
+    const int32_t ns = sys < 0 ? c->n_slices : c->sys[sys].n_slices;
+    const int wpb = 4;
+    const dim3 grid(nblk(ns, wpb)), block(wpb * kWave);
+    int cur = c->cur;
+    for (int32_t k = 0; k < n; ++k) {
+        if (c->precision == L2T_FP64) {
+            hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
+                               c->T64[cur], c->T64[cur ^ 1], c->Tl64, c->srcw64, c->dparams,
+                               c->dstep, k, c->ledger, c->derr);
+        } else {
+            hipLaunchKernelGGL(k_step_fp32c, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
+                               c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32,
+                               c->dparams, c->dstep, k, c->ledger, c->derr);
+        }
+        cur ^= 1;
+    }
+    L2T_HIP(c, hipGetLastError());
+    if (n & 1) {
+        if (sys < 0) {
+            c->cur ^= 1;
+        } else {
+            // keep every system's state in the same buffer: copy this one back
+            const SystemState &st = c->sys[sys];
+            if (c->precision == L2T_FP64)
+                hipLaunchKernelGGL(k_copy_range_f64, dim3(nblk(st.n_pad, 256)), dim3(256), 0,
+                                   c->stream, c->T64[c->cur ^ 1] + st.atom_off,
+                                   c->T64[c->cur] + st.atom_off, (int64_t)st.n_pad);
+            else
+                hipLaunchKernelGGL(k_copy_range_f32, dim3(nblk(st.n_pad, 256)), dim3(256), 0,
+                                   c->stream, c->Thi[c->cur ^ 1] + st.atom_off,
+                                   c->Thi[c->cur] + st.atom_off, (int64_t)st.n_pad);
+            L2T_HIP(c, hipGetLastError());
+        }
+    }
+    return bump_steps(c, sys, n);
+}
+
+// Largest co-resident grid of the persistent kernel at this block size.
+static int persistent_grid(l2t_ctx *c, int block) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent_fp32c, block, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int slices_per_block_min = std::max(1, block / kWave);
+    int want = (c->n_slices + slices_per_block_min - 1) / slices_per_block_min;
+    int g = std::min(per_cu * c->n_cu, want);
+    if (g >= 8) g -= g % 8;
+    return std::max(1, g);
+}
+
+// FP32C, all systems, n sub-steps starting at the current state.
+int fp32c_launch(l2t_ctx *c, int32_t n, int persistent, int block, int /*resident_max*/,
+                 int /*rel_step0*/) {
+    int cur = c->cur;
+    if (persistent) {
+        const int grid = persistent_grid(c, block);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->dbar, 2);
+        hipLaunchKernelGGL(k_persistent_fp32c, dim3(grid), dim3(block), 0, c->stream, c->slices,
+                           c->n_slices, c->col, c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32,
+                           c->srcw32, c->dparams, c->dstep, n, c->ledger, c->derr, c->dbar);
+    } else {
+        const int wpb = block / kWave;
+        const dim3 g(nblk(c->n_slices, wpb)), b(block);
+        for (int32_t k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(k_step_fp32c, g, b, 0, c->stream, c->slices, 0, c->n_slices, c->col,
+                               c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32,
+                               c->dparams, c->dstep, k, c->ledger, c->derr);
+            cur ^= 1;
+        }
+    }
+    L2T_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_bump, dim3(nblk((int64_t)c->sys.size(), 256)), dim3(256), 0, c->stream,
+                       c->dstep, 0, (int32_t)c->sys.size(), n);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+void drop_graphs(l2t_ctx *c) {
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+// FP32C advance of all systems with the tuned configuration, captured once
+// per (n, buffer parity, configuration) in a hipGraph and replayed.
+int advance_fp32c(l2t_ctx *c, int32_t n) {
+    const Tuning &t = c->tune;
+    if (!t.graph) {
+        int rc = fp32c_launch(c, n, t.persistent, t.block, t.resident_max, 0);
+        if (rc != L2T_OK) return rc;
+    } else {
+        GraphKey key{n, (c->cur << 8) | (t.persistent << 4) | 0, t.block};
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            // capture on a private stream (the caller's may be the legacy null
+            // stream, which cannot be captured), replay on the caller's
+            if (!c->cap_stream)
+                L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipStream_t user = c->stream;
+            L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+            c->stream = c->cap_stream;
+            int rc = fp32c_launch(c, n, t.persistent, t.block, t.resident_max, 0);
+            c->stream = user;
+            hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc != L2T_OK) return rc;
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+            hipGraphExec_t ge = nullptr;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+            it = c->graphs.emplace(key, ge).first;
+        }
+        L2T_HIP(c, hipGraphLaunch(it->second, c->stream));
+    }
+    if (n & 1) c->cur ^= 1;
+    for (auto &st : c->sys) st.step += n;
+    return L2T_OK;
+}
+
+int energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out) {
+    const SystemState &st = c->sys[sys];
+    hipLaunchKernelGGL(k_slice_energy, dim3(nblk(st.n_slices, 4)), dim3(256), 0, c->stream,
+                       c->slices, st.slice0, st.n_slices, c->precision, c->T64[c->cur],
+                       c->Thi[c->cur], c->Tlo, c->dparams, c->slice_red);
+    hipLaunchKernelGGL(k_system_reduce, dim3(1), dim3(256), 0, c->stream, st.slice0, st.n_slices,
+                       c->slice_red, c->ledger, c->energy_out);
+    L2T_HIP(c, hipGetLastError());
+    double h[8] = {0};
+    L2T_HIP(c, hipMemcpyAsync(h, c->energy_out, sizeof(double) * 7, hipMemcpyDeviceToHost,
+                              c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    out->step = st.step;
+    out->t = 0.0;
+    out->E_e = h[0];
+    out->sum_T = h[1];
+    out->E_e_to_l = h[2];
+    out->E_src = h[3];
+    out->T_ledger_acc = h[4];
+    out->T_max_atom = h[5];
+    out->T_min_atom = h[6];
+    return L2T_OK;
+}
+
+int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream_t s) {
+    if (n == 0) return L2T_OK;
+    hipLaunchKernelGGL(k_pair, dim3(nblk(n, 256)), dim3(256), 0, s, ti, tj, out, n);
+    return hipGetLastError() == hipSuccess ? L2T_OK : L2T_EHIP;
+}
+
+}  // namespace l2t

@@ -1,0 +1,199 @@
+// Internal declarations shared by the library's own sources (host API, kernel
+// launchers, autotuner).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "l2t.h"
+
+namespace l2t {
+
+constexpr int kWave = 64;                          // CDNA wavefront width
+constexpr double kBoltzmann = 8.617333262e-5;      // eV/K
+constexpr double kMvv2e = 103.64269652680505;      // 1 amu*A^2/fs^2 in eV
+
+// error bits of the device-side sticky flag
+constexpr unsigned kErrRange = 1u;      // theta outside [0,1] or non-finite T
+constexpr unsigned kErrBox = 2u;        // atom outside the box on a free axis
+constexpr unsigned kErrBarrier = 4u;    // persistent-kernel barrier spin limit hit
+constexpr unsigned kErrCellOverflow = 8u;
+
+// One wavefront-sized slice of 64 consecutive internal atoms.  The neighbour
+// indices of the slice are stored column-major: entry k of lane l lives at
+// col[64 * col_base64 + 64 * k + l]; lanes with fewer than `width` neighbours
+// are padded with their own index, whose pair term is exactly zero.
+struct SliceInfo {
+    int32_t sys;
+    int32_t width;
+    int32_t col_base64;
+    int32_t n_valid;
+};
+
+// Per-system constants as the kernels read them.
+struct DevParams {
+    double T_min, span, inv_span, K, A, dt, g;
+    double ce_const, gamma, ce_cap;
+    double i0, lp, t0, sigma, inv_sigma, x0;
+    int32_t ce_model, laser_on;
+    int32_t atom_off, n_pad;
+    int32_t slice0, n_slices;
+    // FP32 copies for the compensated path
+    float f_inv_span, f_half_inv_span, f_m_off, f_A, f_K, f_dt, f_g;
+    float f_ce_const, f_gamma, f_ce_cap, f_T_min, f_T_max, f_i0;
+};
+
+struct SystemState {
+    l2t_system_desc desc{};
+    l2t_params params{};
+    bool has_pos = false, has_params = false, has_te = false, has_tl = false;
+    int64_t caller_off = 0;      // offset of this system in concatenated caller arrays
+    int32_t atom_off = 0;        // first internal slot
+    int32_t n_pad = 0;           // internal slots (multiple of 64)
+    int32_t slice0 = 0, n_slices = 0;
+    int32_t nc[3] = {1, 1, 1};
+    int64_t cell_off = 0, ncell = 0;
+    int64_t step = 0;            // sub-steps since the last T_e write
+    int32_t max_nbrs = 0;
+};
+
+struct GraphKey {
+    int32_t n, mode, sys;
+    bool operator<(const GraphKey &o) const {
+        if (n != o.n) return n < o.n;
+        if (mode != o.mode) return mode < o.mode;
+        return sys < o.sys;
+    }
+};
+
+struct Tuning {
+    int persistent = 1;
+    int block = 256;
+    int resident_max = 0;    // 0 = autotune
+    int graph = 1;
+    int autotune = 1;
+    bool tuned = false;
+};
+
+struct Recording {
+    bool valid = false;
+    int32_t n_steps = 0, ckpt = 0;
+    int64_t n_ckpt = 0;
+    std::vector<int64_t> step0;   // per-system step index at the start
+    void *buf = nullptr;          // checkpoints [n_ckpt][state words per atom][n_int]
+    size_t bytes = 0;
+};
+
+}  // namespace l2t
+
+struct l2t_ctx {
+    int precision = L2T_FP32C;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+    int device = 0;
+    int n_cu = 256;
+    size_t lds_per_block = 65536;
+    std::vector<l2t::SystemState> sys;
+    int64_t n_tot = 0;           // sum of caller atoms
+    int32_t n_int = 0;           // internal slots (systems padded to 64)
+    int32_t n_slices = 0;
+    int32_t max_n = 0;
+    double r_cut = 0.0;
+    bool nbrs_built = false;
+    int32_t max_nbrs = 0;
+    double mean_nbrs = 0.0;
+
+    // device buffers (owned)
+    double *pos = nullptr;       // caller order SoA [3][n_tot]
+    double *pos_int = nullptr;   // internal order SoA [3][n_int]
+    int32_t *perm = nullptr;     // internal slot -> caller-global index (-1 = padding)
+    int32_t *inv = nullptr;      // caller-global index -> internal slot
+    int32_t *cell_start = nullptr;
+    int32_t *cell_scratch = nullptr;
+    int32_t *cell_of = nullptr;  // caller order [n_tot]
+    int32_t *cell_int = nullptr; // internal order [n_int]
+    int32_t *sorted_local = nullptr;
+    int32_t *cnt = nullptr;      // internal [n_int]
+    l2t::SliceInfo *slices = nullptr;
+    int32_t *col = nullptr;
+    int64_t col_len = 0;
+    int64_t cells_total = 0;
+
+    double *T64[2] = {nullptr, nullptr};
+    double *Tl64 = nullptr;
+    double *srcw64 = nullptr;
+    float *Thi[2] = {nullptr, nullptr};
+    float *Tlo = nullptr;
+    float *Tl32 = nullptr;
+    float *srcw32 = nullptr;
+    int cur = 0;
+
+    double *ledger = nullptr;    // [n_slices][3]
+    double *slice_red = nullptr; // [n_slices][4]
+    double *energy_out = nullptr;// [n_sys][8]
+    l2t::DevParams *dparams = nullptr;
+    int64_t *dstep = nullptr;    // per-system step index
+    unsigned *derr = nullptr;
+    unsigned *dbar = nullptr;    // grid barrier words
+    double *stage = nullptr;     // staging [max(n_tot, 3 * max_n)]
+    void *scratch = nullptr;     // temporary (autotune snapshot, velocities)
+    size_t scratch_bytes = 0;
+
+    std::vector<l2t::DevParams> hparams;
+    l2t::Tuning tune;
+    std::map<l2t::GraphKey, hipGraphExec_t> graphs;
+    l2t::Recording rec;
+    std::string last_error;
+};
+
+namespace l2t {
+
+// ---- status helpers (api.cpp) ---------------------------------------------
+int fail(l2t_ctx *c, int status, const std::string &msg);
+int hip_fail(l2t_ctx *c, hipError_t e, const char *what);
+
+#define L2T_HIP(ctx, expr)                                              \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess) return ::l2t::hip_fail((ctx), e_, #expr); \
+    } while (0)
+
+// ---- geometry (k_geometry.hip) ---------------------------------------------
+int build_neighbors(l2t_ctx *c, double r_cut);
+int permute_in(l2t_ctx *c, int32_t sys, const double *src_dev, int32_t field);
+int permute_out(l2t_ctx *c, int32_t sys, int32_t field, double *dst_dev);
+int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_caller, const double *m_caller,
+                        int32_t global_com);
+int neighbors_to_host(l2t_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *col, int64_t cap);
+int source_weights(l2t_ctx *c, int32_t sys);
+int check_field_range(l2t_ctx *c, const double *src_dev, int64_t n, double lo, double hi,
+                      bool *ok);
+
+// ---- sub-steps (k_step.hip) ------------------------------------------------
+int upload_params(l2t_ctx *c);
+int advance_plain(l2t_ctx *c, int32_t sys, int32_t n);    // FP64 or FP32C, one launch per sub-step
+int advance_fp32c(l2t_ctx *c, int32_t n);                 // all systems, tuned path
+int reset_ledger(l2t_ctx *c, int32_t sys);
+int energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out);
+int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream_t s);
+int fp32c_launch(l2t_ctx *c, int32_t n, int persistent, int block, int resident_max,
+                 int rel_step0);
+int bump_steps(l2t_ctx *c, int32_t sys, int32_t n);
+void drop_graphs(l2t_ctx *c);
+
+// ---- adjoint (k_adjoint.hip) ------------------------------------------------
+int record_checkpoint(l2t_ctx *c, int64_t slot);
+int adjoint(l2t_ctx *c, const double *dL_dTN_dev, double *dL_dK, double *dL_dg,
+            double *dL_dT0_dev);
+
+// ---- autotuner (autotune.cpp) ------------------------------------------------
+int autotune(l2t_ctx *c);
+
+// ---- buffers ---------------------------------------------------------------
+int ensure_scratch(l2t_ctx *c, size_t bytes);
+
+}  // namespace l2t

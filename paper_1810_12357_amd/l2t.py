@@ -1,0 +1,343 @@
+"""ctypes binding of libl2t.so (declared in include/l2t.h).
+
+Argument marshalling only: every step of the electronic-temperature path runs
+in the library's HIP kernels.  Functions carry the C names; ``Context`` is a
+small convenience wrapper over them.  Arrays may be numpy arrays (host) or
+torch tensors on the GPU (device); torch is used for device memory and the
+current HIP stream only.
+
+Loading fails loudly when the library has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libl2t.so")
+
+L2T_OK, L2T_WUNSTABLE = 0, 1
+L2T_EINVAL, L2T_ENOMEM, L2T_EHIP, L2T_ESTATE, L2T_ERANGE, L2T_ENOTIMPL = -1, -2, -3, -4, -5, -6
+L2T_FP64, L2T_FP32C = 0, 1
+L2T_HOST, L2T_DEVICE = 0, 1
+L2T_FIELD_TE, L2T_FIELD_TL, L2T_FIELD_GATE, L2T_FIELD_NBRS = 0, 1, 2, 3
+L2T_CE_CONST, L2T_CE_LINEAR, L2T_CE_CAPPED = 0, 1, 2
+L2T_OPT_PERSISTENT, L2T_OPT_BLOCK, L2T_OPT_RESIDENT_MAX, L2T_OPT_GRAPH, L2T_OPT_AUTOTUNE = 0, 1, 2, 3, 4
+
+# every symbol the header declares (checked by the CPU test suite)
+EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbors",
+           "l2t_get_neighbors", "l2t_set_params", "l2t_set_field", "l2t_get_field",
+           "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
+           "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
+           "l2t_exchange_rate", "l2t_pair_fp32", "l2t_strerror", "l2t_last_error",
+           "l2t_version")
+
+
+class l2t_system_desc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("periodic", C.c_int32 * 3),
+                ("box_lo", C.c_double * 3), ("box_len", C.c_double * 3)]
+
+
+class l2t_params(C.Structure):
+    _fields_ = [("T_min", C.c_double), ("T_max", C.c_double), ("K", C.c_double),
+                ("dt", C.c_double), ("g", C.c_double),
+                ("ce_model", C.c_int32), ("laser_on", C.c_int32),
+                ("ce_const", C.c_double), ("gamma", C.c_double), ("ce_cap", C.c_double),
+                ("ke_eps", C.c_double),
+                ("laser_fluence", C.c_double), ("laser_lp", C.c_double),
+                ("laser_t0", C.c_double), ("laser_sigma", C.c_double),
+                ("laser_x0", C.c_double), ("v_atom", C.c_double)]
+
+
+class l2t_energy_report(C.Structure):
+    _fields_ = [("t", C.c_double), ("step", C.c_int64), ("E_e", C.c_double),
+                ("sum_T", C.c_double), ("E_e_to_l", C.c_double), ("E_src", C.c_double),
+                ("T_ledger_acc", C.c_double), ("T_max_atom", C.c_double),
+                ("T_min_atom", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class L2TError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"l2t status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libl2t.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "paper_1810_12357_amd.build.build() (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "l2t_create": (C.c_int, [P(vp), i32, P(l2t_system_desc), i32, vp]),
+        "l2t_destroy": (None, [vp]),
+        "l2t_set_positions": (C.c_int, [vp, i32, vp, i32]),
+        "l2t_build_neighbors": (C.c_int, [vp, d, P(i32), P(d)]),
+        "l2t_get_neighbors": (C.c_int, [vp, i32, vp, vp, i64]),
+        "l2t_set_params": (C.c_int, [vp, i32, P(l2t_params)]),
+        "l2t_set_field": (C.c_int, [vp, i32, i32, vp, i32]),
+        "l2t_get_field": (C.c_int, [vp, i32, i32, vp, i32]),
+        "l2t_set_velocities": (C.c_int, [vp, i32, vp, vp, i32, i32]),
+        "l2t_advance": (C.c_int, [vp, i32]),
+        "l2t_advance_system": (C.c_int, [vp, i32, i32]),
+        "l2t_advance_recorded": (C.c_int, [vp, i32, i32]),
+        "l2t_adjoint": (C.c_int, [vp, vp, i32, vp, vp, vp]),
+        "l2t_energies": (C.c_int, [vp, i32, P(l2t_energy_report)]),
+        "l2t_sync": (C.c_int, [vp]),
+        "l2t_set_option": (C.c_int, [vp, i32, i64]),
+        "l2t_get_option": (C.c_int, [vp, i32, P(i64)]),
+        "l2t_exchange_rate": (d, [d, d, i32, d]),
+        "l2t_pair_fp32": (C.c_int, [vp, vp, vp, i64, vp]),
+        "l2t_strerror": (C.c_char_p, [C.c_int]),
+        "l2t_last_error": (C.c_char_p, [vp]),
+        "l2t_version": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ---- argument marshalling ----------------------------------------------------
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, dtype=np.float64):
+    """(pointer, mem, keepalive) for a numpy array or a torch tensor."""
+    if _is_torch(a):
+        import torch
+        want = {np.float64: torch.float64, np.float32: torch.float32,
+                np.int32: torch.int32, np.int64: torch.int64}[dtype]
+        if a.dtype != want or not a.is_contiguous():
+            raise TypeError(f"tensor must be contiguous {want}")
+        return C.c_void_p(a.data_ptr()), (L2T_DEVICE if a.is_cuda else L2T_HOST), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return C.c_void_p(arr.ctypes.data), L2T_HOST, arr
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(0)
+
+
+def make_params(p: dict) -> l2t_params:
+    return l2t_params(**{k: p[k] for k, _ in l2t_params._fields_})
+
+
+def _check(ctx, rc: int, allow_warn: bool = True) -> int:
+    if rc == L2T_OK or (allow_warn and rc > 0):
+        return rc
+    lib = load()
+    msg = lib.l2t_last_error(ctx).decode() if ctx else ""
+    if not msg:
+        msg = lib.l2t_strerror(rc).decode()
+    raise L2TError(rc, msg)
+
+
+# ---- functions with the C names ----------------------------------------------
+def l2t_version() -> int:
+    return load().l2t_version()
+
+
+def l2t_strerror(status: int) -> str:
+    return load().l2t_strerror(status).decode()
+
+
+def l2t_exchange_rate(kappa_e: float, C_e: float, dim: int, lattice_sum: float) -> float:
+    return load().l2t_exchange_rate(kappa_e, C_e, dim, lattice_sum)
+
+
+def l2t_create(descs, precision: int, stream=None):
+    arr = (l2t_system_desc * len(descs))(*descs)
+    h = C.c_void_p()
+    _check(None, load().l2t_create(C.byref(h), len(descs), arr, precision, _stream(stream)))
+    return h
+
+
+def l2t_destroy(ctx) -> None:
+    load().l2t_destroy(ctx)
+
+
+def l2t_set_positions(ctx, sys: int, xyz) -> int:
+    p, mem, keep = _ptr(xyz)
+    return _check(ctx, load().l2t_set_positions(ctx, sys, p, mem))
+
+
+def l2t_build_neighbors(ctx, r_cut: float):
+    mx = C.c_int32()
+    mean = C.c_double()
+    _check(ctx, load().l2t_build_neighbors(ctx, r_cut, C.byref(mx), C.byref(mean)))
+    return mx.value, mean.value
+
+
+def l2t_get_neighbors(ctx, sys: int, n: int):
+    row = np.zeros(n + 1, dtype=np.int64)
+    lib = load()
+    _check(ctx, lib.l2t_get_neighbors(ctx, sys, row.ctypes.data, None, 0))
+    col = np.zeros(max(int(row[-1]), 1), dtype=np.int32)
+    _check(ctx, lib.l2t_get_neighbors(ctx, sys, row.ctypes.data, col.ctypes.data, col.size))
+    return row, col[:int(row[-1])]
+
+
+def l2t_set_params(ctx, sys: int, params: dict) -> int:
+    pp = make_params(params)
+    return _check(ctx, load().l2t_set_params(ctx, sys, C.byref(pp)))
+
+
+def l2t_set_field(ctx, sys: int, field: int, src) -> int:
+    p, mem, keep = _ptr(src)
+    return _check(ctx, load().l2t_set_field(ctx, sys, field, p, mem))
+
+
+def l2t_get_field(ctx, sys: int, field: int, dst):
+    p, mem, keep = _ptr(dst)
+    _check(ctx, load().l2t_get_field(ctx, sys, field, p, mem))
+    return dst
+
+
+def l2t_set_velocities(ctx, sys: int, v, mass, global_com: bool = False) -> int:
+    pv, mem, kv = _ptr(v)
+    pm, mem2, km = _ptr(mass)
+    if mem != mem2:
+        raise TypeError("velocities and masses must live in the same memory space")
+    return _check(ctx, load().l2t_set_velocities(ctx, sys, pv, pm, mem, int(bool(global_com))))
+
+
+def l2t_advance(ctx, n_substeps: int) -> int:
+    return _check(ctx, load().l2t_advance(ctx, n_substeps))
+
+
+def l2t_advance_system(ctx, sys: int, n_substeps: int) -> int:
+    return _check(ctx, load().l2t_advance_system(ctx, sys, n_substeps))
+
+
+def l2t_advance_recorded(ctx, n_substeps: int, ckpt_every: int) -> int:
+    return _check(ctx, load().l2t_advance_recorded(ctx, n_substeps, ckpt_every))
+
+
+def l2t_adjoint(ctx, dL_dTN, n_systems: int, dL_dT0=None):
+    pw, mem, kw = _ptr(dL_dTN)
+    dK = np.zeros(n_systems)
+    dg = np.zeros(n_systems)
+    p0 = None
+    if dL_dT0 is not None:
+        p0, mem0, k0 = _ptr(dL_dT0)
+        if mem0 != mem:
+            raise TypeError("dL_dTN and dL_dT0 must live in the same memory space")
+    _check(ctx, load().l2t_adjoint(ctx, pw, mem, dK.ctypes.data, dg.ctypes.data, p0))
+    return dK, dg
+
+
+def l2t_energies(ctx, sys: int, check: bool = True) -> dict:
+    e = l2t_energy_report()
+    rc = load().l2t_energies(ctx, sys, C.byref(e))
+    if check:
+        _check(ctx, rc)
+    d = e.as_dict()
+    d["status"] = rc
+    return d
+
+
+def l2t_sync(ctx) -> int:
+    return _check(ctx, load().l2t_sync(ctx))
+
+
+def l2t_set_option(ctx, option: int, value: int) -> int:
+    return _check(ctx, load().l2t_set_option(ctx, option, value))
+
+
+def l2t_get_option(ctx, option: int) -> int:
+    v = C.c_int64()
+    _check(ctx, load().l2t_get_option(ctx, option, C.byref(v)))
+    return v.value
+
+
+def l2t_pair_fp32(ti, tj, out, stream=None) -> None:
+    """Device FP32 tensors ti, tj, out of equal length."""
+    for t in (ti, tj, out):
+        if not (_is_torch(t) and t.is_cuda):
+            raise TypeError("l2t_pair_fp32 takes device tensors")
+    n = out.numel()
+    _check(None, load().l2t_pair_fp32(C.c_void_p(ti.data_ptr()), C.c_void_p(tj.data_ptr()),
+                                      C.c_void_p(out.data_ptr()), n, _stream(stream)))
+
+
+# ---- convenience wrapper -------------------------------------------------------
+def desc_of(system) -> l2t_system_desc:
+    d = l2t_system_desc()
+    d.n_atoms = system.n
+    for k in range(3):
+        d.periodic[k] = int(system.periodic[k])
+        d.box_lo[k] = float(system.box_lo[k])
+        d.box_len[k] = float(system.box_len[k])
+    return d
+
+
+class Context:
+    """Owns one l2t context holding a list of independent systems."""
+
+    def __init__(self, systems, precision: int = L2T_FP32C, stream=None):
+        self.systems = list(systems)
+        self.precision = precision
+        self.h = l2t_create([desc_of(s) for s in self.systems], precision, stream)
+
+    def close(self):
+        if self.h:
+            l2t_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def setup(self, r_cut: float, use_velocities: bool = True):
+        """Positions, neighbours, parameters, T_e and T_lat of every system."""
+        for s, sy in enumerate(self.systems):
+            l2t_set_positions(self.h, s, sy.pos.reshape(-1))
+        mx, mean = l2t_build_neighbors(self.h, r_cut)
+        warn = 0
+        for s, sy in enumerate(self.systems):
+            warn |= l2t_set_params(self.h, s, sy.params)
+            l2t_set_field(self.h, s, L2T_FIELD_TE, sy.T_e0)
+            if use_velocities and sy.vel is not None:
+                l2t_set_velocities(self.h, s, sy.vel.reshape(-1), sy.mass)
+            elif sy.T_l is not None:
+                l2t_set_field(self.h, s, L2T_FIELD_TL, sy.T_l)
+        return mx, mean, warn
+
+    def get(self, sys: int, field: int = L2T_FIELD_TE) -> np.ndarray:
+        out = np.empty(self.systems[sys].n)
+        l2t_get_field(self.h, sys, field, out)
+        return out
+
+    def advance(self, n: int) -> int:
+        return l2t_advance(self.h, n)
+
+    def energies(self, sys: int, check: bool = True) -> dict:
+        return l2t_energies(self.h, sys, check)

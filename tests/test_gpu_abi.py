@@ -1,0 +1,144 @@
+"""GPU-side contract of the C ABI: call order, range errors, stability
+warning, determinism, memory-space round trips."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import gpu_context, max_rel, oracle_trajectory
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1810_12357_amd.l2t")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_call_order_errors():
+    w = W.c1(n_cells=4)
+    sy = w.systems[0]
+    ctx = L.Context(w.systems, L.L2T_FP32C)
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_build_neighbors(ctx.h, w.r_cut)           # no positions
+    assert e.value.status == L.L2T_ESTATE
+    L.l2t_set_positions(ctx.h, 0, sy.pos.reshape(-1))
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TE, sy.T_e0)   # no neighbours
+    assert e.value.status == L.L2T_ESTATE
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_build_neighbors(ctx.h, 0.6 * sy.box_len[0])    # box < 2 r_cut
+    assert e.value.status == L.L2T_EINVAL
+    L.l2t_build_neighbors(ctx.h, w.r_cut)
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_advance(ctx.h, 10)                         # no parameters / T_e
+    assert e.value.status == L.L2T_ESTATE
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_set_params(ctx.h, 0, dict(sy.params, dt=-1.0))
+    assert e.value.status == L.L2T_EINVAL
+    L.l2t_set_params(ctx.h, 0, sy.params)
+    bad = sy.T_e0.copy()
+    bad[7] = np.nan
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TE, bad)
+    assert e.value.status == L.L2T_ERANGE
+    bad[7] = 1.5 * sy.params["T_max"]
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TE, bad)
+    assert e.value.status == L.L2T_ERANGE
+    L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TE, sy.T_e0)
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_advance(ctx.h, 10)                         # G > 0 and no T_lat
+    assert e.value.status == L.L2T_ESTATE
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TL, -np.ones(sy.n))
+    assert e.value.status == L.L2T_EINVAL
+    L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TL, sy.T_l)
+    L.l2t_advance(ctx.h, 10)
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_adjoint(ctx.h, np.ones(sy.n), 1)           # nothing recorded
+    assert e.value.status == L.L2T_ESTATE
+
+
+def test_range_error_after_advance_is_reported():
+    s = W.c4_slab(800, 0.5)
+    s.params = dict(s.params, laser_fluence=1e6, laser_t0=0.0, laser_sigma=5.0)
+    w = W.Workload("hot", [s], 1.1 * W.A_LAT, 50, "fp32c")
+    for prec in (L.L2T_FP32C, L.L2T_FP64):
+        ctx = gpu_context(w, prec)
+        ctx.advance(50)
+        with pytest.raises(L.L2TError) as e:
+            L.l2t_sync(ctx.h)
+        assert e.value.status == L.L2T_ERANGE
+        L.l2t_sync(ctx.h)                                # cleared once reported
+
+
+def test_stability_warning():
+    w = W.c1(n_cells=4)
+    sy = w.systems[0]
+    ctx = gpu_context(w, L.L2T_FP64)
+    rc = L.l2t_set_params(ctx.h, 0, dict(sy.params, K=2.0 / (18 * sy.params["dt"])))
+    assert rc == L.L2T_WUNSTABLE
+    rc = L.l2t_set_params(ctx.h, 0, dict(sy.params, K=0.9 / (18 * sy.params["dt"])))
+    assert rc == L.L2T_OK
+
+
+def test_bitwise_deterministic_and_device_pointers():
+    import torch
+    w = W.c3(n_cells=8, n_substeps=1)
+    sy = w.systems[0]
+    outs = []
+    for rep in range(2):
+        ctx = L.Context(w.systems, L.L2T_FP32C)
+        d = {k: torch.from_numpy(np.ascontiguousarray(v.reshape(-1))).cuda()
+             for k, v in (("pos", sy.pos), ("vel", sy.vel), ("m", sy.mass), ("T", sy.T_e0))}
+        L.l2t_set_positions(ctx.h, 0, d["pos"])
+        L.l2t_build_neighbors(ctx.h, w.r_cut)
+        L.l2t_set_params(ctx.h, 0, sy.params)
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TE, d["T"])
+        L.l2t_set_velocities(ctx.h, 0, d["vel"], d["m"])
+        ctx.advance(300)
+        out = torch.empty(sy.n, dtype=torch.float64, device="cuda")
+        L.l2t_get_field(ctx.h, 0, L.L2T_FIELD_TE, out)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_pad_rows_initialised_after_device_memory_reuse():
+    """Neighbour rows of the padding lanes are written even when the table
+    lands on recycled device memory full of stale values."""
+    import torch
+    junk = torch.full((64 << 20,), 0x7FFFFFFF, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    w = W.c4(n_systems=5, n_substeps=40, size_lo=500, size_hi=2000)
+    ctx = gpu_context(w, L.L2T_FP32C)
+    ctx.advance(40)
+    L.l2t_sync(ctx.h)
+    for s, sy in enumerate(w.systems):
+        traj, _, _ = oracle_trajectory(sy, w.r_cut, [40])
+        assert max_rel(ctx.get(s), traj[0]) < 1e-5
+
+
+def test_advance_system_and_field_round_trip():
+    w = W.c4(n_systems=3, n_substeps=10, size_lo=500, size_hi=1500)
+    ctx = gpu_context(w, L.L2T_FP32C)
+    before = [ctx.get(s) for s in range(3)]
+    L.l2t_advance_system(ctx.h, 1, 7)
+    assert np.array_equal(ctx.get(0), before[0])
+    assert np.array_equal(ctx.get(2), before[2])
+    e1 = ctx.energies(1)
+    assert e1["step"] == 7 and ctx.energies(0)["step"] == 0
+    traj, _, _ = oracle_trajectory(w.systems[1], w.r_cut, [7])
+    assert max_rel(ctx.get(1), traj[0]) < 1e-6
+    # caller order survives the internal cell ordering
+    vals = np.linspace(300.0, 900.0, w.systems[2].n)
+    L.l2t_set_field(ctx.h, 2, L.L2T_FIELD_TE, vals)
+    assert max_rel(ctx.get(2), vals) < 1e-13        # hi + lo keeps ~48 bits

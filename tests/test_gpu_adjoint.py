@@ -1,0 +1,123 @@
+"""GPU adjoint (reverse sub-step kernel with checkpointed recomputation)
+against the FP64 oracle adjoint, and through torch.autograd."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import oracle_lattice, oracle_neighbors
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1810_12357_amd.l2t")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _targets(sy, r_cut, n, K, g):
+    """Target T^N from the oracle with perturbed parameters."""
+    row, col = oracle_neighbors(sy, r_cut)
+    Tl, gated = oracle_lattice(sy, row, col)
+    T, _, _ = oracle.run(row, col, sy.T_e0, Tl, dict(sy.params, K=K, g=g), n, gated=gated)
+    return T
+
+
+def _oracle_grad(sy, r_cut, n, w, params=None):
+    row, col = oracle_neighbors(sy, r_cut)
+    Tl, gated = oracle_lattice(sy, row, col)
+    p = sy.params if params is None else params
+    x = sy.pos[0] if p["laser_on"] else None
+    return oracle.adjoint(row, col, sy.T_e0, Tl, p, n, w, gated=gated, x=x)
+
+
+@pytest.mark.parametrize("ckpt", [7, 50])
+def test_adjoint_matches_oracle_reduced_c5(ckpt):
+    w = W.c5(n_systems=3, n_cells=7, n_substeps=300)
+    n = w.n_substeps
+    ctx = L.Context(w.systems, L.L2T_FP32C)
+    ctx.setup(w.r_cut)
+    L.l2t_advance_recorded(ctx.h, n, ckpt)
+    TN = [ctx.get(s) for s in range(3)]
+    tgt = [_targets(sy, w.r_cut, n, *w.extra["target_params"][s]) for s, sy in enumerate(w.systems)]
+    N = sum(sy.n for sy in w.systems)
+    dL = np.concatenate([2.0 * (TN[s] - tgt[s]) / N for s in range(3)])
+    dT0 = np.zeros(N)
+    dK, dg = L.l2t_adjoint(ctx.h, dL, 3, dL_dT0=dT0)
+    off = 0
+    for s, sy in enumerate(w.systems):
+        lam, oK, og = _oracle_grad(sy, w.r_cut, n, dL[off:off + sy.n])
+        assert dK[s] == pytest.approx(oK, rel=1e-4)
+        assert dg[s] == pytest.approx(og, rel=1e-4)
+        scale = np.abs(lam).max()
+        assert np.max(np.abs(dT0[off:off + sy.n] - lam)) < 1e-4 * scale
+        off += sy.n
+    # recorded forward equals a plain forward
+    ctx2 = L.Context(w.systems, L.L2T_FP32C)
+    ctx2.setup(w.r_cut)
+    L.l2t_set_option(ctx2.h, L.L2T_OPT_PERSISTENT, 1)
+    ctx2.advance(n)
+    for s in range(3):
+        assert np.array_equal(ctx2.get(s), TN[s])
+
+
+def test_adjoint_linear_c_laser_gate():
+    """Every local term: linear heat capacity, laser source, gated atoms."""
+    s4 = W.c4_slab(1500, 0.4)
+    s4.params = dict(s4.params, laser_t0=20.0, laser_sigma=8.0, g=5e-6)
+    rng = np.random.default_rng(2)
+    s4.T_l = 300.0 + 200 * rng.uniform(0, 1, s4.n)
+    w = W.Workload("slab", [s4], 1.1 * W.A_LAT, 400, "fp32c")
+    ctx = L.Context(w.systems, L.L2T_FP32C)
+    ctx.setup(w.r_cut)
+    gate = (rng.uniform(0, 1, s4.n) < 0.1).astype(np.float64)
+    L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_GATE, gate)
+    L.l2t_advance_recorded(ctx.h, 400, 64)
+    wv = rng.normal(size=s4.n) * 1e-3
+    dT0 = np.zeros(s4.n)
+    dK, dg = L.l2t_adjoint(ctx.h, wv, 1, dL_dT0=dT0)
+    row, col = oracle_neighbors(s4, w.r_cut)
+    lam, oK, og = oracle.adjoint(row, col, s4.T_e0, s4.T_l, s4.params, 400, wv,
+                                 gated=gate.astype(np.int32), x=s4.pos[0])
+    assert dK[0] == pytest.approx(oK, rel=1e-4)
+    assert dg[0] == pytest.approx(og, rel=1e-4)
+    assert np.max(np.abs(dT0 - lam)) < 1e-4 * np.abs(lam).max()
+
+
+def test_autograd_function_gradients():
+    import torch
+    from paper_1810_12357_amd import autograd as A
+    w = W.c5(n_systems=2, n_cells=6, n_substeps=200)
+    ctx = L.Context(w.systems, L.L2T_FP32C)
+    ctx.setup(w.r_cut)
+    T0 = torch.from_numpy(np.concatenate([sy.T_e0 for sy in w.systems])).cuda()
+    K = torch.tensor([W.C5_K0, W.C5_K0 * 1.1], dtype=torch.float64, device="cuda",
+                     requires_grad=True)
+    g = torch.tensor([W.C5_G0, W.C5_G0 * 0.9], dtype=torch.float64, device="cuda",
+                     requires_grad=True)
+    T0.requires_grad_(True)
+    TN = A.advance(T0, K, g, ctx, 200, 50)
+    tgt = torch.full_like(TN, 500.0)
+    loss = ((TN - tgt) ** 2).mean()
+    loss.backward()
+    # finite differences of the same GPU forward in K for system 0
+    def f(Kv):
+        with torch.no_grad():
+            out = A.advance(T0.detach(), torch.tensor([Kv, K[1].item()], dtype=torch.float64,
+                                                      device="cuda"), g.detach(), ctx, 200, 50)
+            return float(((out - tgt) ** 2).mean())
+    eps = 1e-3 * W.C5_K0
+    fd = (f(W.C5_K0 + eps) - f(W.C5_K0 - eps)) / (2 * eps)
+    assert K.grad[0].item() == pytest.approx(fd, rel=2e-3)
+    # and the oracle's adjoint for system 0
+    sy = w.systems[0]
+    n0 = sy.n
+    wv = (2.0 * (TN.detach() - tgt) / TN.numel()).cpu().numpy()[:n0]
+    lam, oK, og = _oracle_grad(sy, w.r_cut, 200, wv, dict(sy.params, K=W.C5_K0, g=W.C5_G0))
+    assert K.grad[0].item() == pytest.approx(oK, rel=1e-4)
+    assert g.grad[0].item() == pytest.approx(og, rel=1e-4)
+    assert np.max(np.abs(T0.grad.cpu().numpy()[:n0] - lam)) < 1e-4 * np.abs(lam).max()

@@ -1,0 +1,267 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances: FP64 plain path 1e-12 relative (the two sides differ only in the
+rounding of exp and of the summation order); FP32C path 1e-5 relative, the
+bound the method's FP32 form is held to.  Neighbour sets, gates and neighbour
+counts are compared exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import (gpu_context, gpu_trajectory, light_cone, max_rel, oracle_lattice,
+                     oracle_neighbors, oracle_trajectory, sub_problem)
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1810_12357_amd.l2t")
+
+
+def _torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    _torch_cuda()
+
+
+# ------------------------------------------------------------------ pair term ----
+def test_pair_fp32_accuracy_and_bitwise_antisymmetry():
+    torch = _torch_cuda()
+    rng = np.random.default_rng(21)
+    g = np.linspace(0, 1, 101, dtype=np.float32)
+    ti = np.concatenate([np.repeat(g, g.size), rng.uniform(0, 1, 20000).astype(np.float32),
+                         np.array([0, 1, 0, 1, 0.5], np.float32)])
+    tj = np.concatenate([np.tile(g, g.size),
+                         (ti[g.size ** 2:g.size ** 2 + 20000] +
+                          rng.normal(0, 1e-3, 20000)).clip(0, 1).astype(np.float32),
+                         np.array([1, 0, 0, 1, 0.5], np.float32)])
+    a = torch.from_numpy(ti).cuda()
+    b = torch.from_numpy(tj).cuda()
+    f = torch.empty_like(a)
+    r = torch.empty_like(a)
+    L.l2t_pair_fp32(a, b, f)
+    L.l2t_pair_fp32(b, a, r)
+    torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    r = r.cpu().numpy()
+    assert np.array_equal(f, -r)                       # bitwise
+    # FP64 product form at the same FP32 inputs
+    d = tj.astype(np.float64) - ti.astype(np.float64)
+    m = 0.5 * (ti.astype(np.float64) + tj.astype(np.float64))
+    ref = d * np.cosh(d) - (2 * m * (1 - m) + d * d / 2) * np.sinh(d)
+    err = np.abs(f.astype(np.float64) - ref)
+    assert np.all(err <= 4 * 2.0 ** -24 * np.abs(ref) + 1e-37)
+    # and the oracle's literal FP64 evaluation agrees with that reference
+    lit = oracle.pair(ti.astype(np.float64), tj.astype(np.float64))
+    assert np.max(np.abs(lit - ref)) < 1e-15
+
+
+# ------------------------------------------------------------------ neighbours ----
+@pytest.mark.parametrize("case", ["fcc_periodic", "jitter_1.2a", "slab_free_x", "multi"])
+def test_neighbor_sets_equal_oracle(case):
+    if case == "fcc_periodic":
+        systems, rc = W.c1(n_cells=6).systems, 1.1 * W.A_LAT
+    elif case == "jitter_1.2a":
+        w = W.c3(n_cells=7, n_substeps=1)
+        systems, rc = w.systems, w.r_cut
+    elif case == "slab_free_x":
+        systems, rc = [W.c4_slab(3000, 0.2)], 1.1 * W.A_LAT
+    else:
+        systems = [W.c4_slab(n, 0.1) for n in (500, 777, 2600)] + W.c1(n_cells=4).systems
+        rc = 1.1 * W.A_LAT
+    ctx = L.Context(systems, L.L2T_FP64)
+    for s, sy in enumerate(systems):
+        L.l2t_set_positions(ctx.h, s, sy.pos.reshape(-1))
+    mx, mean = L.l2t_build_neighbors(ctx.h, rc)
+    tot = 0
+    for s, sy in enumerate(systems):
+        row, col = L.l2t_get_neighbors(ctx.h, s, sy.n)
+        r0, c0 = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, rc)
+        assert np.array_equal(row, r0)
+        assert np.array_equal(col, c0)
+        tot += int(row[-1])
+        assert mx >= int(np.diff(row).max())
+    assert mean == pytest.approx(tot / sum(sy.n for sy in systems))
+
+
+# ------------------------------------------------------------ lattice temperature ----
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_lattice_temperature_and_gate_equal_oracle(precision):
+    w = W.c3(n_cells=8, n_substeps=1)
+    sy = w.systems[0]
+    # push a few atoms onto the centre-of-mass velocity of their neighbourhood
+    row, col = oracle_neighbors(sy, w.r_cut)
+    vel = sy.vel.copy()
+    for i in (5, 77, 1234):
+        nb = col[row[i]:row[i + 1]]
+        vel[:, i] = vel[:, nb].mean(axis=1) + 1e-9
+    sy.vel = vel
+    prec = L.L2T_FP64 if precision == "fp64" else L.L2T_FP32C
+    ctx = gpu_context(w, prec)
+    Tl = ctx.get(0, L.L2T_FIELD_TL)
+    gate = ctx.get(0, L.L2T_FIELD_GATE)
+    T0, g0 = oracle_lattice(sy, row, col)
+    assert np.array_equal(gate.astype(np.int32), g0)
+    assert g0[[5, 77, 1234]].all()
+    tol = 1e-13 if precision == "fp64" else 6e-8
+    assert max_rel(Tl, T0) < tol
+    nb = ctx.get(0, L.L2T_FIELD_NBRS)
+    assert np.array_equal(nb, np.diff(row).astype(np.float64))
+
+
+# -------------------------------------------------------------- C1: FP64 plain ----
+@pytest.fixture(scope="module")
+def c1_oracle():
+    w = W.c1()
+    cps = list(range(50, 1001, 50))
+    traj, led, bad = oracle_trajectory(w.systems[0], w.r_cut, cps)
+    assert bad == 0
+    return w, cps, traj, led
+
+
+def test_c1_fp64_plain_matches_oracle(c1_oracle):
+    w, cps, traj, led = c1_oracle
+    ctx = gpu_context(w, L.L2T_FP64)
+    got = gpu_trajectory(ctx, cps)
+    errs = [max_rel(g[0], o) for g, o in zip(got, traj)]
+    assert max(errs) < 1e-12, errs
+    e = ctx.energies(0)
+    assert e["step"] == 1000
+    assert e["E_e_to_l"] == pytest.approx(led[0], rel=1e-10)
+    assert e["T_ledger_acc"] == pytest.approx(led[2], rel=1e-10)
+    assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(w.systems[0].T_e0.sum(), rel=1e-13)
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_c1_fp32c_matches_oracle(c1_oracle, persistent):
+    w, cps, traj, led = c1_oracle
+    ctx = gpu_context(w, L.L2T_FP32C, persistent=persistent)
+    got = gpu_trajectory(ctx, cps)
+    errs = [max_rel(g[0], o) for g, o in zip(got, traj)]
+    assert max(errs) < 1e-5, errs
+    e = ctx.energies(0)
+    assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(w.systems[0].T_e0.sum(), rel=1e-9)
+
+
+def test_fp32c_persistent_equals_per_step_bitwise():
+    w = W.c3(n_cells=9, n_substeps=1)
+    runs = []
+    for persistent, graph in ((0, 0), (1, 0), (1, 1)):
+        ctx = gpu_context(w, L.L2T_FP32C, persistent=persistent, graph=graph)
+        ctx.advance(37)
+        ctx.advance(64)
+        runs.append(ctx.get(0))
+        ctx.close()
+    assert np.array_equal(runs[0], runs[1])
+    assert np.array_equal(runs[0], runs[2])
+
+
+# ---------------------------------------------------------- C2: Fourier limit ----
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_c2_reduced_matches_oracle(precision):
+    w = W.c2(nx=200, ny=3, nz=3, amplitude=500.0, n_substeps=5000, precision=precision)
+    cps = [1000, 5000]
+    traj, led, _ = oracle_trajectory(w.systems[0], w.r_cut, cps)
+    ctx = gpu_context(w, L.L2T_FP64 if precision == "fp64" else L.L2T_FP32C)
+    got = gpu_trajectory(ctx, cps)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for g, o in zip(got, traj):
+        assert max_rel(g[0], o) < tol
+
+
+def test_c2_full_size_fp32c_fourier_decay_and_conservation():
+    w = W.c2()                       # 200 x 8 x 8 cells, 51,200 atoms, 5,000 sub-steps
+    sy = w.systems[0]
+    ctx = gpu_context(w, L.L2T_FP32C)
+    ctx.advance(w.n_substeps)
+    T = ctx.get(0)
+    k = 2 * np.pi / sy.box_len[0]
+    amp = 2.0 / T.size * np.sum((T - T.mean()) * np.sin(k * sy.pos[0]))
+    a = W.A_LAT
+    lat = 8 * (1 - np.cos(k * a / 2)) + 2 * (1 - np.cos(k * a))
+    th0 = 1000.0 / sy.params["T_max"]
+    lam = sy.params["K"] * (1 - 2 * th0 * (1 - th0)) * lat
+    assert amp == pytest.approx(500.0 * (1 - sy.params["dt"] * lam) ** 5000, rel=2e-4)
+    e = ctx.energies(0)
+    assert abs(e["sum_T"] - sy.T_e0.sum()) / sy.T_e0.sum() < 1e-8
+
+
+# --------------------------------------------------------- C3 recipe, reduced ----
+def test_c3_reduced_fp32c_matches_oracle():
+    w = W.c3(n_cells=10, n_substeps=2000)
+    sy = w.systems[0]
+    cps = [200, 1000, 2000]
+    traj, led, bad = oracle_trajectory(sy, w.r_cut, cps)
+    assert bad == 0
+    ctx = gpu_context(w, L.L2T_FP32C)
+    got = gpu_trajectory(ctx, cps)
+    for g, o in zip(got, traj):
+        assert max_rel(g[0], o) < 1e-5
+    e = ctx.energies(0)
+    assert e["E_e_to_l"] == pytest.approx(led[0], rel=1e-5)
+
+
+# ------------------------------------------------------ C4: batched, reduced ----
+def test_c4_reduced_batched_fp32c_matches_oracle():
+    w = W.c4(n_systems=6, n_substeps=6000, size_lo=500, size_hi=6000)
+    cps = [3000, 6000]
+    ctx = gpu_context(w, L.L2T_FP32C)
+    got = gpu_trajectory(ctx, cps)
+    for s, sy in enumerate(w.systems):
+        traj, led, bad = oracle_trajectory(sy, w.r_cut, cps)
+        assert bad == 0
+        for k in range(len(cps)):
+            assert max_rel(got[k][s], traj[k]) < 1e-5, (s, k)
+        e = ctx.energies(s)
+        assert e["E_src"] == pytest.approx(led[1], rel=1e-5)
+        assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(sy.T_e0.sum(), rel=1e-9)
+
+
+def test_c4_plain_fp64_systems_one_after_another_matches_oracle():
+    w = W.c4(n_systems=3, n_substeps=3000, size_lo=500, size_hi=3000)
+    ctx = gpu_context(w, L.L2T_FP64)
+    ctx.advance(3000)
+    for s, sy in enumerate(w.systems):
+        traj, led, _ = oracle_trajectory(sy, w.r_cut, [3000])
+        assert max_rel(ctx.get(s), traj[0]) < 1e-12
+
+
+# ---------------------------------------------- C3 at full size, sampled ----
+@pytest.fixture(scope="module")
+def c3_full():
+    w = W.c3()                       # 4,000,000 atoms
+    sy = w.systems[0]
+    row, col = oracle_neighbors(sy, w.r_cut)
+    return w, sy, row, col
+
+
+def test_c3_full_size_sampled_light_cone(c3_full):
+    """4M-atom jittered FCC in the benchmark's launch configuration: after n
+    sub-steps an atom depends only on atoms within n neighbour hops, so the
+    oracle computes sampled atoms exactly on that light cone."""
+    w, sy, row, col = c3_full
+    n = 12
+    ctx = gpu_context(w, L.L2T_FP32C)
+    ctx.advance(n)
+    T = ctx.get(0)
+    Tl_gpu = ctx.get(0, L.L2T_FIELD_TL)
+    r2 = ((sy.pos - (sy.box_len / 2)[:, None]) ** 2).sum(0)
+    rng = np.random.default_rng(0)
+    seeds = np.r_[np.argsort(r2)[:2], np.argmin(np.abs(np.sqrt(r2) - 15.0)),
+                  np.argmin(np.abs(np.sqrt(r2) - 30.0)), rng.integers(0, sy.n, 3)]
+    # the lattice temperature of every atom from its full neighbour set
+    Tl, gated = oracle.lattice_temperature(row, col, sy.vel, sy.mass, sy.params["ke_eps"])
+    for sd in seeds:
+        keep = light_cone(row, col, [sd], n + 1)
+        r, c = sub_problem(row, col, keep)
+        Tk, _, _ = oracle.run(r, c, sy.T_e0[keep], Tl[keep], sy.params, n, gated=gated[keep])
+        i = int(np.searchsorted(keep, sd))
+        assert abs(T[sd] - Tk[i]) / Tk[i] < 1e-5
+        assert abs(Tl_gpu[sd] - Tl[sd]) / Tl[sd] < 1e-6
