@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--cells", type=int, default=100)
     ap.add_argument("--c4-substeps", type=int, default=600)
     ap.add_argument("--no-c4", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -221,7 +221,10 @@ def test_c4_reduced_batched_fp32c_matches_oracle():
             assert max_rel(got[k][s], traj[k]) < 1e-5, (s, k)
         e = ctx.energies(s)
         assert e["E_src"] == pytest.approx(led[1], rel=1e-5)
-        assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(sy.T_e0.sum(), rel=1e-9)
+        # each applied FP32 increment carries a rounding error of up to 2^-24 of
+        # itself that the FP64 ledger does not see; with ~600 K of laser heating
+        # per atom over 6,000 sub-steps that bounds the drift near 1e-7
+        assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(sy.T_e0.sum(), rel=1e-7)
 
 
 def test_c4_plain_fp64_systems_one_after_another_matches_oracle():
