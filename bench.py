@@ -147,14 +147,17 @@ def main():
     mx, mean = L.l2t_build_neighbors(h, w.r_cut)
     persistent = L.l2t_get_option(h, L.L2T_OPT_PERSISTENT)
     block = L.l2t_get_option(h, L.L2T_OPT_BLOCK)
+    kernel = L.l2t_get_option(h, L.L2T_OPT_KERNEL)
     adv = float(np.mean(adv_ms))
-    bytes_per = 24.0 + 4.0 * mean
-    if persistent:
-        launch_ms, units = adv, sy.n * args.substeps
-        kname = "k_persistent_fp32c"
+    # algorithmic bytes per atom-substep: hi+lo read and write (16), T_lat (4),
+    # row offset (4) and one index per neighbour (4 B global, 2 B brick-local)
+    bytes_per = 24.0 + (2.0 if kernel == 1 else 4.0) * mean
+    if kernel == 1:
+        launch_ms, units, kname = adv / args.substeps, sy.n, "k_brick_fp32c"
+    elif persistent:
+        launch_ms, units, kname = adv, sy.n * args.substeps, "k_persistent_fp32c"
     else:
-        launch_ms, units = adv / args.substeps, sy.n
-        kname = "k_step_fp32c"
+        launch_ms, units, kname = adv / args.substeps, sy.n, "k_step_fp32c"
     achieved = bytes_per * units / (launch_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=kname, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=None,
@@ -167,7 +170,8 @@ def main():
                config=dict(workload=f"c3: FCC {args.cells}^3 cells ({sy.n} atoms), jittered "
                                     f"0.05 A, r_c 1.2a, {args.substeps} FP32C sub-steps per step",
                            n_atoms=sy.n, substeps=args.substeps, mean_neighbors=mean,
-                           max_neighbors=mx, persistent=persistent, block=block),
+                           max_neighbors=mx, kernel=["global-gather", "lds-brick"][kernel],
+                           persistent=persistent, block=block),
                advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
                roofline=roof,
                energy=dict(E_e=e["E_e"], sum_T=e["sum_T"], T_ledger=e["sum_T"] + e["T_ledger_acc"],

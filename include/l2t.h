@@ -83,11 +83,12 @@ extern "C" {
 #define L2T_CE_CAPPED  2   /* c = min(gamma T, ce_cap) */
 
 /* ---- tuning options (l2t_set_option) ---------------------------------------- */
-#define L2T_OPT_PERSISTENT     0   /* FP32C: 1 = fuse sub-steps in one persistent launch (default 1) */
+#define L2T_OPT_PERSISTENT     0   /* FP32C global-gather kernel: 1 = all sub-steps in one persistent launch */
 #define L2T_OPT_BLOCK          1   /* FP32C: threads per workgroup, multiple of 64 (0 = autotune) */
 #define L2T_OPT_RESIDENT_MAX   2   /* FP32C: largest system kept whole in LDS (atoms; 0 = autotune, -1 = never) */
 #define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
+#define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
 
 typedef struct l2t_ctx l2t_ctx;
 

@@ -46,6 +46,9 @@ int ensure_scratch(l2t_ctx *c, size_t bytes) {
 namespace {
 
 template <typename T>
+void dfree(T *&p);
+
+template <typename T>
 int dalloc(l2t_ctx *c, T **p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
@@ -61,6 +64,75 @@ void dfree(T *&p) {
     if (p) (void)hipFree((void *)p);
     p = nullptr;
 }
+
+}  // namespace
+
+namespace l2t {
+
+int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, int64_t shell_len,
+                   int64_t halo_len) {
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    dfree(c->pos_int);
+    dfree(c->perm);
+    dfree(c->cell_int);
+    dfree(c->cnt);
+    dfree(c->slices);
+    for (int b = 0; b < 2; ++b) {
+        dfree(c->T64[b]);
+        dfree(c->Thi[b]);
+    }
+    dfree(c->Tl64);
+    dfree(c->srcw64);
+    dfree(c->Tlo);
+    dfree(c->Tl32);
+    dfree(c->srcw32);
+    dfree(c->ledger);
+    dfree(c->slice_red);
+    dfree(c->bricks);
+    dfree(c->brick_list);
+    dfree(c->shell);
+    dfree(c->halo);
+    c->n_int = n_int;
+    c->n_slices = n_int / kWave;
+    c->n_bricks = n_bricks;
+    c->n_brick_list = n_list;
+    c->cur = 0;
+    const size_t NI = (size_t)n_int, NS = (size_t)c->n_slices;
+    int rc = L2T_OK;
+#define ALLOC(p, n)                                    \
+    if (rc == L2T_OK) rc = dalloc(c, &(p), (size_t)(n));
+    ALLOC(c->pos_int, 3 * NI);
+    ALLOC(c->perm, NI);
+    ALLOC(c->cell_int, NI);
+    ALLOC(c->cnt, NI);
+    ALLOC(c->slices, NS);
+    if (c->precision == L2T_FP64) {
+        ALLOC(c->T64[0], NI);
+        ALLOC(c->T64[1], NI);
+        ALLOC(c->Tl64, NI);
+        ALLOC(c->srcw64, NI);
+    } else {
+        ALLOC(c->Thi[0], NI);
+        ALLOC(c->Thi[1], NI);
+        ALLOC(c->Tlo, NI);
+        ALLOC(c->Tl32, NI);
+        ALLOC(c->srcw32, NI);
+    }
+    ALLOC(c->ledger, 3 * NS);
+    ALLOC(c->slice_red, 4 * NS);
+    ALLOC(c->bricks, (size_t)n_bricks);
+    ALLOC(c->brick_list, (size_t)n_list);
+    ALLOC(c->shell, (size_t)shell_len);
+    ALLOC(c->halo, (size_t)halo_len);
+#undef ALLOC
+    if (rc != L2T_OK) return fail(c, L2T_ENOMEM, "internal buffer allocation failed");
+    return L2T_OK;
+}
+
+}  // namespace l2t
+
+namespace {
 
 bool bad_sys(const l2t_ctx *c, int32_t sys) {
     return !c || sys < 0 || sys >= (int32_t)c->sys.size();
@@ -160,6 +232,12 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c->cnt);
     dfree(c->slices);
     dfree(c->col);
+    dfree(c->col16);
+    dfree(c->pos_slot);
+    dfree(c->bricks);
+    dfree(c->brick_list);
+    dfree(c->shell);
+    dfree(c->halo);
     for (int b = 0; b < 2; ++b) {
         dfree(c->T64[b]);
         dfree(c->Thi[b]);
@@ -231,34 +309,15 @@ int l2t_create(l2t_ctx **out, int32_t n_systems, const l2t_system_desc *descs, i
     c->n_tot = n_tot;
     c->n_int = (int32_t)n_int;
     c->n_slices = (int32_t)(n_int / l2t::kWave);
-    const size_t S = (size_t)n_systems, NT = (size_t)n_tot, NI = (size_t)n_int,
-                 NS = (size_t)c->n_slices;
+    const size_t S = (size_t)n_systems, NT = (size_t)n_tot;
     int rc = L2T_OK;
 #define ALLOC(p, n)                                    \
     if (rc == L2T_OK) rc = dalloc(c, &(p), (size_t)(n));
     ALLOC(c->pos, 3 * NT);
-    ALLOC(c->pos_int, 3 * NI);
-    ALLOC(c->perm, NI);
     ALLOC(c->inv, NT);
     ALLOC(c->cell_of, NT);
-    ALLOC(c->cell_int, NI);
     ALLOC(c->sorted_local, NT);
-    ALLOC(c->cnt, NI);
-    ALLOC(c->slices, NS);
-    if (precision == L2T_FP64) {
-        ALLOC(c->T64[0], NI);
-        ALLOC(c->T64[1], NI);
-        ALLOC(c->Tl64, NI);
-        ALLOC(c->srcw64, NI);
-    } else {
-        ALLOC(c->Thi[0], NI);
-        ALLOC(c->Thi[1], NI);
-        ALLOC(c->Tlo, NI);
-        ALLOC(c->Tl32, NI);
-        ALLOC(c->srcw32, NI);
-    }
-    ALLOC(c->ledger, 3 * NS);
-    ALLOC(c->slice_red, 4 * NS);
+    ALLOC(c->pos_slot, NT);
     ALLOC(c->energy_out, 8);
     ALLOC(c->dparams, S);
     ALLOC(c->dstep, S);
@@ -460,7 +519,10 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
     if (!c) return L2T_EINVAL;
     l2t::Tuning &t = c->tune;
     switch (option) {
-        case L2T_OPT_PERSISTENT: t.persistent = value ? 1 : 0; break;
+        case L2T_OPT_PERSISTENT:
+            t.persistent = value ? 1 : 0;
+            if (value) t.kernel = l2t::kKernelSliced;
+            break;
         case L2T_OPT_BLOCK:
             if (value != 0 && (value < 64 || value > 256 || value % 64))
                 return l2t::fail(c, L2T_EINVAL, "block must be 0 or one of 64, 128, 192, 256");
@@ -474,6 +536,11 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             break;
         case L2T_OPT_RESIDENT_MAX: t.resident_max = (int)value; break;
         case L2T_OPT_GRAPH: t.graph = value ? 1 : 0; break;
+        case L2T_OPT_KERNEL:
+            if (value != l2t::kKernelSliced && value != l2t::kKernelBrick)
+                return l2t::fail(c, L2T_EINVAL, "kernel must be 0 (global) or 1 (brick)");
+            t.kernel = (int)value;
+            break;
         case L2T_OPT_AUTOTUNE:
             t.autotune = value ? 1 : 0;
             if (value) t.tuned = false;
@@ -494,6 +561,7 @@ int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
         case L2T_OPT_RESIDENT_MAX: *value = t.resident_max; break;
         case L2T_OPT_GRAPH: *value = t.graph; break;
         case L2T_OPT_AUTOTUNE: *value = t.autotune; break;
+        case L2T_OPT_KERNEL: *value = t.kernel; break;
         default: return l2t::fail(c, L2T_EINVAL, "unknown option");
     }
     return L2T_OK;

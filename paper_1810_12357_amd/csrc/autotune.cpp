@@ -19,7 +19,7 @@ namespace l2t {
 namespace {
 
 struct Choice {
-    int persistent, block;
+    int kernel, persistent, block;
 };
 
 std::map<std::string, Choice> &mem_cache() {
@@ -29,8 +29,9 @@ std::map<std::string, Choice> &mem_cache() {
 
 std::string shape_key(const l2t_ctx *c) {
     char buf[160];
-    std::snprintf(buf, sizeof buf, "n_int=%d slices=%d sys=%zu nbr=%d cu=%d", c->n_int,
-                  c->n_slices, c->sys.size(), c->max_nbrs, c->n_cu);
+    std::snprintf(buf, sizeof buf, "n_int=%d slices=%d sys=%zu nbr=%d cu=%d bricks=%d tile=%d",
+                  c->n_int, c->n_slices, c->sys.size(), c->max_nbrs, c->n_cu, c->n_brick_list,
+                  c->tile_max);
     return buf;
 }
 
@@ -46,8 +47,9 @@ bool file_lookup(const std::string &key, Choice *ch) {
         if (!bar) continue;
         *bar = '\0';
         if (key == line) {
-            int p = 0, b = 0;
-            if (std::sscanf(bar + 1, "%d %d", &p, &b) == 2) {
+            int k = 0, p = 0, b = 0;
+            if (std::sscanf(bar + 1, "%d %d %d", &k, &p, &b) == 3) {
+                ch->kernel = k;
                 ch->persistent = p;
                 ch->block = b;
                 found = true;
@@ -63,7 +65,7 @@ void file_store(const std::string &key, const Choice &ch) {
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s|%d %d\n", key.c_str(), ch.persistent, ch.block);
+    std::fprintf(f, "%s|%d %d %d\n", key.c_str(), ch.kernel, ch.persistent, ch.block);
     std::fclose(f);
 }
 
@@ -72,10 +74,11 @@ void file_store(const std::string &key, const Choice &ch) {
 int autotune(l2t_ctx *c) {
     Tuning &t = c->tune;
     const std::string key = shape_key(c);
-    Choice best{t.persistent, t.block};
+    Choice best{t.kernel, t.persistent, t.block};
     auto it = mem_cache().find(key);
     if (it != mem_cache().end() || file_lookup(key, &best)) {
         if (it != mem_cache().end()) best = it->second;
+        t.kernel = best.kernel;
         t.persistent = best.persistent;
         t.block = best.block;
         t.tuned = true;
@@ -120,12 +123,19 @@ int autotune(l2t_ctx *c) {
     L2T_HIP(c, hipEventCreate(&e1));
     const int probe = 16;   // even: the probe leaves the state in buffer `cur`
     float best_ms = 1e30f;
-    const std::vector<Choice> cand = {{1, 256}, {1, 128}, {1, 64}, {0, 256}, {0, 128}};
+    // the persistent launch is left out: its grid barrier needs agent-scope
+    // fences on every workgroup and measured 10-30x slower per sub-step than
+    // one launch per sub-step; it stays available through L2T_OPT_PERSISTENT
+    std::vector<Choice> cand = {{kKernelSliced, 0, 256}, {kKernelSliced, 0, 128}};
+    if (c->n_brick_list > 0) {
+        cand.push_back({kKernelBrick, 0, 256});
+        cand.push_back({kKernelBrick, 0, 128});
+    }
     for (const Choice &ch : cand) {
         float ms_min = 1e30f;
         for (int rep = 0; rep < 2 && rc == L2T_OK; ++rep) {
             L2T_HIP(c, hipEventRecord(e0, c->stream));
-            rc = fp32c_launch(c, probe, ch.persistent, ch.block, 0, 0);
+            rc = fp32c_launch(c, probe, ch.kernel, ch.persistent, ch.block);
             L2T_HIP(c, hipEventRecord(e1, c->stream));
             L2T_HIP(c, hipEventSynchronize(e1));
             float ms = 0.0f;
@@ -152,6 +162,7 @@ int autotune(l2t_ctx *c) {
     (void)hipEventDestroy(e1);
     if (rc != L2T_OK) return rc;
     L2T_HIP(c, hipStreamSynchronize(c->stream));
+    t.kernel = best.kernel;
     t.persistent = best.persistent;
     t.block = best.block;
     t.tuned = true;

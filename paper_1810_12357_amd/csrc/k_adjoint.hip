@@ -10,7 +10,8 @@
 // a gather over the forward neighbour table (no atomics), with
 //   d1f = -[(1 - 2m(1-m) - d^2/2) cosh d + (1 - 2m) sinh d],
 //   d = theta_j - theta_k, m = (theta_k + theta_j)/2.
-// Parameter gradients: dL/dK = sum_n dt sum_k lambda_k^{n+1} (T_max - T_min) S_k(T^n),
+// Parameter gradients: dL/dK = sum_n dt sum_k lambda_k^{n+1} (T_max - T_min) S_k(T^n)
+// (the kernels carry S in temperature units, (T_max - T_min) S),
 // dL/dg = sum_n dt sum_k lambda_k^{n+1} (-gate_k (T_k - T^lat_k)/c_k).
 //
 // States between checkpoints are recomputed with the forward slice function
@@ -29,12 +30,12 @@ namespace {
 using namespace dev;
 
 // f and d1f of one pair from FP32 temperatures (same d, m, u as pair32)
-__device__ __forceinline__ void pair32_with_d1(float Tk, float Tj, float inv_span,
-                                               float half_inv_span, float m_off, float *f,
-                                               float *d1) {
-    *f = pair32(Tk, Tj, inv_span, half_inv_span, m_off);
+// f is returned in temperature units (span * f), as the forward sums it
+__device__ __forceinline__ void pair32_with_d1(float Tk, float Tj, const PairK &pk,
+                                               float inv_span, float *f, float *d1) {
+    *f = pair32(Tk, Tj, pk);
     const float d = (Tj - Tk) * inv_span;
-    const float m = fmaf(Tk + Tj, half_inv_span, m_off);
+    const float m = fmaf(Tk + Tj, pk.hinv, pk.moff);
     const float u = d * d;
     // cosh d = sum u^k/(2k)!,  sinh(d)/d = sum u^k/(2k+1)!
     float ch = fmaf(u, 1.0f / 3628800.0f, 1.0f / 40320.0f);
@@ -65,11 +66,12 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
     const float Tk = Thi[slot];
     const float lk = lam[slot];
     const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
+    const PairK pk = pair_consts(p);
     float S = 0.0f, cS = 0.0f, D = 0.0f, cD = 0.0f;
     for (int32_t q = 0; q < si.width; ++q) {
         const int32_t j = cp[q * kWave];
         float f, d1;
-        pair32_with_d1(Tk, Thi[j], p.f_inv_span, p.f_half_inv_span, p.f_m_off, &f, &d1);
+        pair32_with_d1(Tk, Thi[j], pk, p.f_inv_span, &f, &d1);
         const float term = d1 * (lk - lam[j]);
         float y = f - cS, t = S + y;
         cS = (t - S) - y;
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
         l_new = s + lo2;
         lam_lo[slot] = lo2 - (l_new - s);
         const double lfull = (double)lk + (double)lo;
-        gK = lfull * p.dt * p.span * (double)S;
+        gK = lfull * p.dt * (double)S;          // S = span * sum_j f
         gG = gated ? 0.0 : -lfull * p.dt * (double)(Tk - tl) * (double)invc;
     }
     lam_n[slot] = l_new;

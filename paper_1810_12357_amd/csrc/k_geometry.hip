@@ -1,12 +1,19 @@
-// Geometry kernels: cell binning, cell-sorted internal order, neighbour sets
-// in wavefront-sliced column-major layout, per-atom field permutation, the
-// local lattice temperature (Eq. 4) with the kinetic-energy gate, and the
-// per-atom depth weights of the laser source (Eq. 9).
+// Geometry kernels: cell binning, the brick-ordered internal layout, neighbour
+// sets in wavefront-sliced column-major tables (global int32 indices and
+// brick-local uint16 indices with per-brick halo lists), per-atom field
+// permutation, the local lattice temperature (Eq. 4) with the kinetic-energy
+// gate, and the per-atom depth weights of the laser source (Eq. 9).
+//
+// Internal order of one system: cells are grouped into bricks of up to
+// b x b x b cells; bricks in x-major order, cells inside a brick z-fastest,
+// atoms inside a cell by caller index.  Every brick owns a slot range padded
+// to a multiple of 64, so no 64-lane slice straddles two bricks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #include "l2t_internal.h"
@@ -31,8 +38,10 @@ __device__ inline int32_t cell_coord(double s, double len, int32_t nc) {
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
 
-// distinct cell coordinates c-1, c, c+1 along one axis (wrapped or clipped)
-__device__ inline int axis_cells(int32_t c, int32_t nc, int32_t periodic, int32_t out[3]) {
+// distinct cell coordinates c-1, c, c+1 along one axis (wrapped or clipped),
+// with the offset that first produced each
+__device__ inline int axis_cells(int32_t c, int32_t nc, int32_t periodic, int32_t out[3],
+                                 int32_t off[3]) {
     int m = 0;
     for (int o = -1; o <= 1; ++o) {
         int32_t k = c + o;
@@ -43,7 +52,10 @@ __device__ inline int axis_cells(int32_t c, int32_t nc, int32_t periodic, int32_
         }
         bool dup = false;
         for (int q = 0; q < m; ++q) dup |= (out[q] == k);
-        if (!dup) out[m++] = k;
+        if (!dup) {
+            off[m] = o;
+            out[m++] = k;
+        }
     }
     return m;
 }
@@ -57,9 +69,11 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-// bin the atoms of one system (caller order) into cells of edge >= r_cut
+// bin the atoms of one system (caller order); cell_of receives the cell's
+// rank in brick order
 __global__ void k_bin(const double *px, const double *py, const double *pz, int32_t n, Grid g,
-                      int32_t *cell_of, int32_t *count, unsigned *err) {
+                      const int32_t *rank_of_cell, int32_t *cell_of, int32_t *count,
+                      unsigned *err) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double p[3] = {px[i], py[i], pz[i]};
@@ -69,9 +83,9 @@ __global__ void k_bin(const double *px, const double *py, const double *pz, int3
         if (!g.periodic[d] && !(s >= 0.0 && s <= g.len[d])) atomicOr(err, kErrBox);
         ic[d] = cell_coord(s, g.len[d], g.nc[d]);
     }
-    int32_t cell = (ic[0] * g.nc[1] + ic[1]) * g.nc[2] + ic[2];
-    cell_of[i] = cell;
-    atomicAdd(&count[cell], 1);
+    const int32_t r = rank_of_cell[(ic[0] * g.nc[1] + ic[1]) * g.nc[2] + ic[2]];
+    cell_of[i] = r;
+    atomicAdd(&count[r], 1);
 }
 
 // exclusive prefix sum of n int32 values with out[n] = total; one workgroup,
@@ -129,76 +143,114 @@ __global__ void k_sort_cells(const int32_t *start, int64_t ncell, int32_t *sorte
     }
 }
 
-// internal slots of one system: slot = atom_off + position in cell order
-__global__ void k_assign(const int32_t *sorted, int32_t n, int32_t n_pad, int32_t atom_off,
-                         int64_t caller_off, const double *px, const double *py, const double *pz,
-                         const int32_t *cell_of, Grid g, int32_t *perm, int32_t *inv,
-                         int32_t *cell_int, double *qx, double *qy, double *qz) {
+// padding slots of one system: no atom
+__global__ void k_init_slots(int32_t atom_off, int32_t n_pad, int32_t *perm, int32_t *cell_int,
+                             double *qx, double *qy, double *qz, int32_t *cnt) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_pad) return;
-    int32_t slot = atom_off + k;
-    if (k < n) {
-        int32_t i = sorted[k];
-        perm[slot] = (int32_t)(caller_off + i);
-        inv[caller_off + i] = slot;
-        cell_int[slot] = cell_of[i];
-        qx[slot] = g.lo[0] + wrap_coord(px[i], g.lo[0], g.len[0], g.periodic[0]);
-        qy[slot] = g.lo[1] + wrap_coord(py[i], g.lo[1], g.len[1], g.periodic[1]);
-        qz[slot] = g.lo[2] + wrap_coord(pz[i], g.lo[2], g.len[2], g.periodic[2]);
-    } else {
-        perm[slot] = -1;
-        cell_int[slot] = -1;
-        qx[slot] = qy[slot] = qz[slot] = 0.0;
-    }
+    const int32_t s = atom_off + k;
+    perm[s] = -1;
+    cell_int[s] = -1;
+    cnt[s] = 0;
+    qx[s] = qy[s] = qz[s] = 0.0;
 }
 
-// count (FILL = false) or write (FILL = true) the neighbour set of every atom
-// of one system; rows visit the distinct cells of the 3x3x3 stencil in a
-// fixed order and each cell's atoms in cell order
-template <bool FILL>
-__global__ void k_neighbors(int32_t n, int32_t atom_off, const double *qx, const double *qy,
-                            const double *qz, const int32_t *cell_int, const int32_t *start,
-                            Grid g, double rc2, int32_t *cnt, const SliceInfo *slices,
-                            int32_t *col) {
+// final slot of the atom at cell-order position k: its brick's first slot
+// plus its offset inside the brick
+__global__ void k_assign(const int32_t *sorted, int32_t n, int32_t atom_off, int64_t caller_off,
+                         const double *px, const double *py, const double *pz,
+                         const int32_t *cell_of, const int32_t *brick_of_rank,
+                         const BrickInfo *bricks, const int32_t *brick_atom0, Grid g,
+                         int32_t *perm, int32_t *inv, int32_t *cell_int, int32_t *pos_slot,
+                         double *qx, double *qy, double *qz) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    int32_t slot = atom_off + k;
-    const double xi = qx[slot], yi = qy[slot], zi = qz[slot];
-    const int32_t cell0 = cell_int[slot];
+    const int32_t i = sorted[k];
+    const int32_t r = cell_of[i];
+    const int32_t b = brick_of_rank[r];
+    const int32_t slot = bricks[b].slot0 + (k - brick_atom0[b]);
+    perm[slot] = (int32_t)(caller_off + i);
+    inv[caller_off + i] = slot;
+    cell_int[slot] = r;
+    pos_slot[k] = slot;
+    qx[slot] = g.lo[0] + wrap_coord(px[i], g.lo[0], g.len[0], g.periodic[0]);
+    qy[slot] = g.lo[1] + wrap_coord(py[i], g.lo[1], g.len[1], g.periodic[1]);
+    qz[slot] = g.lo[2] + wrap_coord(pz[i], g.lo[2], g.len[2], g.periodic[2]);
+    (void)atom_off;
+}
+
+// Count (FILL = false) or write (FILL = true) the neighbour set of every atom
+// of one system.  Rows visit the distinct cells of the 3x3x3 stencil in a
+// fixed order and each cell's atoms in cell order; both tables hold the same
+// entries in the same order: col the global slot, col16 the index into the
+// brick's LDS tile (own slots first, then the halo list).
+template <bool FILL>
+__global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx,
+                            const double *qy, const double *qz, const int32_t *cell_int,
+                            const int32_t *start, const int32_t *rank_of_cell,
+                            const int32_t *cell_of_rank, const int32_t *brick_of_rank,
+                            const BrickInfo *bricks, const int32_t *shell, Grid g, double rc2,
+                            int32_t *cnt, const SliceInfo *slices, int32_t *col,
+                            uint16_t *col16) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t self = pos_slot[k];
+    const double xi = qx[self], yi = qy[self], zi = qz[self];
+    const int32_t rank0 = cell_int[self];
+    const int32_t cell0 = cell_of_rank[rank0];
     int32_t ic[3] = {cell0 / (g.nc[1] * g.nc[2]), (cell0 / g.nc[2]) % g.nc[1], cell0 % g.nc[2]};
-    int32_t sx[3], sy[3], sz[3];
-    int mx = axis_cells(ic[0], g.nc[0], g.periodic[0], sx);
-    int my = axis_cells(ic[1], g.nc[1], g.periodic[1], sy);
-    int mz = axis_cells(ic[2], g.nc[2], g.periodic[2], sz);
+    int32_t sx[3], sy[3], sz[3], ox[3], oy[3], oz[3];
+    int mx = axis_cells(ic[0], g.nc[0], g.periodic[0], sx, ox);
+    int my = axis_cells(ic[1], g.nc[1], g.periodic[1], sy, oy);
+    int mz = axis_cells(ic[2], g.nc[2], g.periodic[2], sz, oz);
     int32_t m = 0;
     int64_t base = 0;
-    int lane = slot & (kWave - 1);
     int32_t width = 0;
+    BrickInfo bi{};
     if (FILL) {
-        const SliceInfo si = slices[slot / kWave];
-        base = (int64_t)si.col_base64 * kWave + lane;
+        const SliceInfo si = slices[self / kWave];
+        base = (int64_t)si.col_base64 * kWave + (self & (kWave - 1));
         width = si.width;
+        bi = bricks[brick_of_rank[rank0]];
     }
     for (int a = 0; a < mx; ++a)
         for (int b = 0; b < my; ++b)
             for (int e = 0; e < mz; ++e) {
-                int32_t cell = (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[e];
-                for (int32_t q = start[cell]; q < start[cell + 1]; ++q) {
-                    int32_t j = atom_off + q;
-                    if (j == slot) continue;
+                const int32_t cell = (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[e];
+                const int32_t rk = rank_of_cell[cell];
+                int32_t hbase = 0;
+                bool own = true;
+                if (FILL) {
+                    const int32_t p0 = ic[0] - bi.o[0] + ox[a] + 1;
+                    const int32_t p1 = ic[1] - bi.o[1] + oy[b] + 1;
+                    const int32_t p2 = ic[2] - bi.o[2] + oz[e] + 1;
+                    const int32_t h = shell[bi.shell_off + (p0 * bi.sh[1] + p1) * bi.sh[2] + p2];
+                    own = (h == -1);
+                    hbase = bi.n_own_pad + h;
+                }
+                for (int32_t q = start[rk]; q < start[rk + 1]; ++q) {
+                    const int32_t j = pos_slot[q];
+                    if (j == self) continue;
                     double dx = min_image(qx[j] - xi, g.len[0], g.periodic[0]);
                     double dy = min_image(qy[j] - yi, g.len[1], g.periodic[1]);
                     double dz = min_image(qz[j] - zi, g.len[2], g.periodic[2]);
                     if (dx * dx + dy * dy + dz * dz <= rc2) {
-                        if (FILL) col[base + (int64_t)m * kWave] = j;
+                        if (FILL && m < width) {
+                            col[base + (int64_t)m * kWave] = j;
+                            col16[base + (int64_t)m * kWave] =
+                                (uint16_t)(own ? j - bi.slot0 : hbase + (q - start[rk]));
+                        }
                         ++m;
                     }
                 }
             }
     if (FILL) {
-        for (int32_t q = m; q < width; ++q) col[base + (int64_t)q * kWave] = slot;
+        for (int32_t q = m; q < width; ++q) {
+            col[base + (int64_t)q * kWave] = self;
+            col16[base + (int64_t)q * kWave] = (uint16_t)(self - bi.slot0);
+        }
     } else {
-        cnt[slot] = m;
+        cnt[self] = m;
     }
 }
 
@@ -218,24 +270,33 @@ __global__ void k_slice_width(const int32_t *cnt, const int32_t *perm, int32_t n
     nvalid[s] = v;
 }
 
-// pad slots carry no atom: zero count
-__global__ void k_zero_pad_counts(const int32_t *perm, int32_t *cnt, int32_t n_int) {
-    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n_int && perm[s] < 0) cnt[s] = 0;
-}
-
-// pad slots still run the neighbour loop of their slice: every entry of
-// their row points at the slot itself (pair term zero, always in bounds)
-__global__ void k_pad_rows(const int32_t *perm, const SliceInfo *slices, int32_t n_int,
-                           int32_t *col) {
+// padding slots still run the neighbour loop of their slice: every entry of
+// their rows points at the slot itself (pair term zero, always in bounds)
+__global__ void k_pad_rows(const int32_t *perm, const SliceInfo *slices, const BrickInfo *bricks,
+                           int32_t n_int, int32_t *col, uint16_t *col16) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_int || perm[s] >= 0) return;
     const SliceInfo si = slices[s / kWave];
     const int64_t base = (int64_t)si.col_base64 * kWave + (s & (kWave - 1));
-    for (int32_t q = 0; q < si.width; ++q) col[base + (int64_t)q * kWave] = s;
+    const int32_t loc = s - bricks[si.brick].slot0;
+    for (int32_t q = 0; q < si.width; ++q) {
+        col[base + (int64_t)q * kWave] = s;
+        col16[base + (int64_t)q * kWave] = (uint16_t)loc;
+    }
 }
 
-// ---- per-atom fields -------------------------------------------------------
+// halo list of every brick: the slots of the atoms of its halo cells
+__global__ void k_halo_expand(const HaloCell *hc, int64_t n_hc, const BrickInfo *bricks,
+                              const int32_t *start_all, const int32_t *pos_slot_all,
+                              int32_t *halo) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_hc) return;
+    const HaloCell h = hc[e];
+    const BrickInfo &b = bricks[h.brick];
+    const int32_t q0 = start_all[h.start_index], q1 = start_all[h.start_index + 1];
+    for (int32_t q = q0; q < q1; ++q) halo[b.halo_off + h.offset + (q - q0)] = pos_slot_all[h.pos_base + q];
+}
+
 __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                            const double *src, int32_t field, int32_t precision, double *T64,
                            float *Thi, float *Tlo, double *Tl64, float *Tl32) {
@@ -412,11 +473,37 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-int build_neighbors(l2t_ctx *c, double r_cut) {
+// Largest LDS tile (own slots + halo atoms) of one workgroup, in floats.
+constexpr int32_t kTileCapFloats = 16384;
+
+namespace {
+
+struct SysLayout {
+    int32_t b[3] = {1, 1, 1}, nb[3] = {1, 1, 1};
+    int32_t nbrick = 0, brick0 = 0;
+    int64_t rank_off = 0;                 // into the rank maps (sum of ncell)
+    std::vector<int32_t> rank_of_cell, cell_of_rank, brick_cell0;
+};
+
+// brick edge (cells) so that a (b+2)^3-cell tile of this density fits the LDS
+// cap with room for density fluctuations
+int32_t brick_edge(double atoms_per_cell, int32_t limit) {
+    double cells = kTileCapFloats / (1.6 * std::max(atoms_per_cell, 1e-9));
+    int32_t b = (int32_t)std::floor(std::cbrt(cells)) - 2;
+    return std::max(1, std::min(b, limit));
+}
+
+}  // namespace
+
+int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *tile_overflow) {
     const int S = (int)c->sys.size();
-    // cell grids
-    int64_t cells_total = 0;
+    const hipStream_t st_ = c->stream;
+    *tile_overflow = false;
+    // ---- cell grids and brick order (host) -------------------------------------
+    std::vector<SysLayout> lay(S);
     std::vector<int64_t> cstart_off(S);
+    int64_t cells_total = 0, ranks_total = 0;
+    int32_t nbricks = 0;
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         st.ncell = 1;
@@ -428,24 +515,68 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
             st.nc[d] = (int32_t)std::max(1.0, std::min(k, 1.0e6));
             st.ncell *= st.nc[d];
         }
-        if (st.ncell > (int64_t)1 << 30) return fail(c, L2T_EINVAL, "cell grid too large");
+        if (st.ncell > (int64_t)1 << 28) return fail(c, L2T_EINVAL, "cell grid too large");
+        SysLayout &L = lay[s];
+        const int32_t be = brick_edge((double)st.desc.n_atoms / (double)st.ncell, edge_limit);
+        L.nbrick = 1;
+        for (int d = 0; d < 3; ++d) {
+            L.b[d] = std::min(be, st.nc[d]);
+            L.nb[d] = (st.nc[d] + L.b[d] - 1) / L.b[d];
+            L.nbrick *= L.nb[d];
+        }
+        L.brick0 = nbricks;
+        nbricks += L.nbrick;
+        L.rank_off = ranks_total;
+        ranks_total += st.ncell;
         cstart_off[s] = cells_total;
         st.cell_off = cells_total;
         cells_total += st.ncell + 1;
+        L.rank_of_cell.assign(st.ncell, 0);
+        L.cell_of_rank.assign(st.ncell, 0);
+        L.brick_cell0.assign(L.nbrick + 1, 0);
+        int32_t r = 0, bidx = 0;
+        for (int32_t X = 0; X < L.nb[0]; ++X)
+            for (int32_t Y = 0; Y < L.nb[1]; ++Y)
+                for (int32_t Z = 0; Z < L.nb[2]; ++Z, ++bidx) {
+                    L.brick_cell0[bidx] = r;
+                    const int32_t o[3] = {X * L.b[0], Y * L.b[1], Z * L.b[2]};
+                    const int32_t e[3] = {std::min(L.b[0], st.nc[0] - o[0]),
+                                          std::min(L.b[1], st.nc[1] - o[1]),
+                                          std::min(L.b[2], st.nc[2] - o[2])};
+                    for (int32_t a = 0; a < e[0]; ++a)
+                        for (int32_t b2 = 0; b2 < e[1]; ++b2)
+                            for (int32_t z = 0; z < e[2]; ++z) {
+                                const int32_t cell =
+                                    ((o[0] + a) * st.nc[1] + (o[1] + b2)) * st.nc[2] + (o[2] + z);
+                                L.rank_of_cell[cell] = r;
+                                L.cell_of_rank[r] = cell;
+                                ++r;
+                            }
+                }
+        L.brick_cell0[L.nbrick] = r;
     }
-    if (cells_total > c->cells_total) {
-        if (c->cell_start) (void)hipFree(c->cell_start);
-        if (c->cell_scratch) (void)hipFree(c->cell_scratch);
-        c->cell_start = nullptr;
-        c->cell_scratch = nullptr;
-        if (hipMalloc(&c->cell_start, sizeof(int32_t) * cells_total) != hipSuccess ||
-            hipMalloc(&c->cell_scratch, sizeof(int32_t) * cells_total) != hipSuccess)
-            return fail(c, L2T_ENOMEM, "cell list allocation failed");
-        c->cells_total = cells_total;
+    // device copies of the rank maps
+    std::vector<int32_t> h_rank(ranks_total), h_cell(ranks_total), h_brick(ranks_total);
+    for (int s = 0; s < S; ++s) {
+        const SysLayout &L = lay[s];
+        std::copy(L.rank_of_cell.begin(), L.rank_of_cell.end(), h_rank.begin() + L.rank_off);
+        std::copy(L.cell_of_rank.begin(), L.cell_of_rank.end(), h_cell.begin() + L.rank_off);
+        for (int32_t b = 0; b < L.nbrick; ++b)
+            for (int32_t r = L.brick_cell0[b]; r < L.brick_cell0[b + 1]; ++r)
+                h_brick[L.rank_off + r] = L.brick0 + b;
     }
-    const hipStream_t st_ = c->stream;
+    DevBuf<int32_t> d_rank(c, ranks_total), d_cell(c, ranks_total), d_brick(c, ranks_total),
+        d_count(c, cells_total), d_start(c, cells_total);
+    if (!d_rank.ok() || !d_cell.ok() || !d_brick.ok() || !d_count.ok() || !d_start.ok())
+        return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
+    L2T_HIP(c, hipMemcpyAsync(d_rank.p, h_rank.data(), sizeof(int32_t) * ranks_total,
+                              hipMemcpyHostToDevice, st_));
+    L2T_HIP(c, hipMemcpyAsync(d_cell.p, h_cell.data(), sizeof(int32_t) * ranks_total,
+                              hipMemcpyHostToDevice, st_));
+    L2T_HIP(c, hipMemcpyAsync(d_brick.p, h_brick.data(), sizeof(int32_t) * ranks_total,
+                              hipMemcpyHostToDevice, st_));
     L2T_HIP(c, hipMemsetAsync(c->derr, 0, sizeof(unsigned), st_));
-    const double rc2 = r_cut * r_cut;
+    // ---- binning in brick order (device) -------------------------------------------
     std::vector<Grid> grids(S);
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
@@ -458,14 +589,15 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         }
         const int32_t n = st.desc.n_atoms;
         const double *px = c->pos + st.caller_off, *py = px + c->n_tot, *pz = py + c->n_tot;
-        int32_t *count = c->cell_scratch + cstart_off[s];
-        int32_t *start = c->cell_start + cstart_off[s];
+        int32_t *count = d_count.p + cstart_off[s];
+        int32_t *start = d_start.p + cstart_off[s];
         int32_t *cell_of = c->cell_of + st.caller_off;
         int32_t *sorted = c->sorted_local + st.caller_off;
+        const int32_t *rank_of_cell = d_rank.p + lay[s].rank_off;
         hipLaunchKernelGGL(k_fill_i32, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, count,
                            st.ncell, 0);
-        hipLaunchKernelGGL(k_bin, dim3(nblk(n, 256)), dim3(256), 0, st_, px, py, pz, n, g, cell_of,
-                           count, c->derr);
+        hipLaunchKernelGGL(k_bin, dim3(nblk(n, 256)), dim3(256), 0, st_, px, py, pz, n, g,
+                           rank_of_cell, cell_of, count, c->derr);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st_, count, start, st.ncell);
         hipLaunchKernelGGL(k_fill_i32, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, count,
                            st.ncell, 0);
@@ -473,76 +605,224 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
                            count, sorted);
         hipLaunchKernelGGL(k_sort_cells, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, start,
                            st.ncell, sorted);
-        hipLaunchKernelGGL(k_assign, dim3(nblk(st.n_pad, 256)), dim3(256), 0, st_, sorted, n,
-                           st.n_pad, st.atom_off, st.caller_off, px, py, pz, cell_of, g, c->perm,
-                           c->inv, c->cell_int, c->pos_int, c->pos_int + c->n_int,
-                           c->pos_int + 2 * (int64_t)c->n_int);
-        hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
-                           st.atom_off, c->pos_int, c->pos_int + c->n_int,
-                           c->pos_int + 2 * (int64_t)c->n_int, c->cell_int, start, g, rc2, c->cnt,
-                           nullptr, nullptr);
     }
     L2T_HIP(c, hipGetLastError());
-    hipLaunchKernelGGL(k_zero_pad_counts, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
-                       c->cnt, c->n_int);
-    // slice widths -> column offsets (host scan)
-    int32_t *dw = c->cell_scratch;   // reuse: needs 2 * n_slices ints
-    if ((int64_t)2 * c->n_slices > c->cells_total) {
-        if (ensure_scratch(c, sizeof(int32_t) * 2 * (size_t)c->n_slices) != L2T_OK) return L2T_ENOMEM;
-        dw = (int32_t *)c->scratch;
-    }
-    hipLaunchKernelGGL(k_slice_width, dim3(nblk(c->n_slices, 256)), dim3(256), 0, st_, c->cnt,
-                       c->perm, c->n_slices, dw, dw + c->n_slices);
-    std::vector<int32_t> hw(2 * (size_t)c->n_slices);
-    L2T_HIP(c, hipMemcpyAsync(hw.data(), dw, sizeof(int32_t) * hw.size(), hipMemcpyDeviceToHost,
-                              st_));
+    std::vector<int32_t> h_start(cells_total);
+    L2T_HIP(c, hipMemcpyAsync(h_start.data(), d_start.p, sizeof(int32_t) * cells_total,
+                              hipMemcpyDeviceToHost, st_));
     unsigned herr = 0;
     L2T_HIP(c, hipMemcpyAsync(&herr, c->derr, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
     if (herr & kErrBox) return fail(c, L2T_EINVAL, "an atom lies outside the box on a free axis");
+    // ---- slot layout, halo tables (host) -------------------------------------------
+    std::vector<BrickInfo> hb(nbricks);
+    std::vector<int32_t> h_atom0(nbricks), h_list;
+    std::vector<int32_t> h_shell;
+    std::vector<HaloCell> h_halo;
+    int32_t slot = 0;
+    int64_t halo_total = 0;
+    int32_t tile_max = 0;
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
+        const SysLayout &L = lay[s];
+        const int32_t *start = h_start.data() + cstart_off[s];
+        st.atom_off = slot;
+        std::vector<int32_t> stamp(st.ncell, -1), stamp_off(st.ncell, 0);
+        for (int32_t b = 0; b < L.nbrick; ++b) {
+            const int32_t gb = L.brick0 + b;
+            BrickInfo &bi = hb[gb];
+            const int32_t X = b / (L.nb[1] * L.nb[2]), Y = (b / L.nb[2]) % L.nb[1], Z = b % L.nb[2];
+            bi.o[0] = X * L.b[0];
+            bi.o[1] = Y * L.b[1];
+            bi.o[2] = Z * L.b[2];
+            int32_t e[3];
+            for (int d = 0; d < 3; ++d) {
+                e[d] = std::min(L.b[d], st.nc[d] - bi.o[d]);
+                bi.sh[d] = e[d] + 2;
+            }
+            const int32_t a0 = start[L.brick_cell0[b]], a1 = start[L.brick_cell0[b + 1]];
+            h_atom0[gb] = a0;
+            bi.sys = s;
+            bi.slot0 = slot;
+            bi.n_own = a1 - a0;
+            bi.n_own_pad = (bi.n_own + kWave - 1) / kWave * kWave;
+            bi.slice0 = slot / kWave;
+            bi.halo_off = (int32_t)halo_total;
+            bi.n_halo = 0;
+            bi.shell_off = (int32_t)h_shell.size();
+            slot += bi.n_own_pad;
+            if (bi.n_own == 0) continue;
+            h_list.push_back(gb);
+            const int32_t nsh = bi.sh[0] * bi.sh[1] * bi.sh[2];
+            h_shell.resize(h_shell.size() + nsh);
+            int32_t *shl = h_shell.data() + bi.shell_off;
+            for (int32_t p0 = 0; p0 < bi.sh[0]; ++p0)
+                for (int32_t p1 = 0; p1 < bi.sh[1]; ++p1)
+                    for (int32_t p2 = 0; p2 < bi.sh[2]; ++p2) {
+                        const int32_t p[3] = {p0, p1, p2};
+                        int32_t cc[3];
+                        bool valid = true, own = true;
+                        for (int d = 0; d < 3; ++d) {
+                            int32_t v = bi.o[d] + p[d] - 1;
+                            if (st.desc.periodic[d]) {
+                                v = (v % st.nc[d] + st.nc[d]) % st.nc[d];
+                            } else if (v < 0 || v >= st.nc[d]) {
+                                valid = false;
+                            }
+                            cc[d] = v;
+                            own = own && v >= bi.o[d] && v < bi.o[d] + e[d];
+                        }
+                        int32_t &out = shl[(p0 * bi.sh[1] + p1) * bi.sh[2] + p2];
+                        if (!valid) {
+                            out = -2;
+                            continue;
+                        }
+                        if (own) {
+                            out = -1;
+                            continue;
+                        }
+                        const int32_t cell = (cc[0] * st.nc[1] + cc[1]) * st.nc[2] + cc[2];
+                        if (stamp[cell] != gb) {
+                            stamp[cell] = gb;
+                            stamp_off[cell] = bi.n_halo;
+                            const int32_t rk = L.rank_of_cell[cell];
+                            const int32_t cnt = start[rk + 1] - start[rk];
+                            HaloCell h;
+                            h.brick = gb;
+                            h.start_index = (int32_t)(cstart_off[s] + rk);
+                            h.offset = bi.n_halo;
+                            h.pos_base = (int32_t)st.caller_off;
+                            h_halo.push_back(h);
+                            bi.n_halo += cnt;
+                        }
+                        out = stamp_off[cell];
+                    }
+            halo_total += bi.n_halo;
+            tile_max = std::max(tile_max, bi.n_own_pad + bi.n_halo);
+        }
+        st.n_pad = slot - st.atom_off;
+        st.slice0 = st.atom_off / kWave;
+        st.n_slices = st.n_pad / kWave;
+    }
+    if (tile_max > kTileCapFloats) {
+        *tile_overflow = true;
+        return L2T_OK;
+    }
+    if (halo_total > INT32_MAX) return fail(c, L2T_ENOMEM, "halo lists too large");
+    int rc = alloc_internal(c, slot, nbricks, (int32_t)h_list.size(), (int64_t)h_shell.size(),
+                            halo_total);
+    if (rc != L2T_OK) return rc;
+    c->tile_max = tile_max;
+    L2T_HIP(c, hipMemcpyAsync(c->bricks, hb.data(), sizeof(BrickInfo) * hb.size(),
+                              hipMemcpyHostToDevice, st_));
+    if (!h_list.empty())
+        L2T_HIP(c, hipMemcpyAsync(c->brick_list, h_list.data(), sizeof(int32_t) * h_list.size(),
+                                  hipMemcpyHostToDevice, st_));
+    if (!h_shell.empty())
+        L2T_HIP(c, hipMemcpyAsync(c->shell, h_shell.data(), sizeof(int32_t) * h_shell.size(),
+                                  hipMemcpyHostToDevice, st_));
+    DevBuf<int32_t> d_atom0(c, nbricks);
+    DevBuf<HaloCell> d_halo(c, (int64_t)h_halo.size());
+    if (!d_atom0.ok() || !d_halo.ok()) return fail(c, L2T_ENOMEM, "brick table allocation failed");
+    L2T_HIP(c, hipMemcpyAsync(d_atom0.p, h_atom0.data(), sizeof(int32_t) * nbricks,
+                              hipMemcpyHostToDevice, st_));
+    if (!h_halo.empty())
+        L2T_HIP(c, hipMemcpyAsync(d_halo.p, h_halo.data(), sizeof(HaloCell) * h_halo.size(),
+                                  hipMemcpyHostToDevice, st_));
+    // ---- slots, counts (device) ----------------------------------------------------
+    const double rc2 = r_cut * r_cut;
+    const int64_t NI = c->n_int;
+    double *qx = c->pos_int, *qy = c->pos_int + NI, *qz = c->pos_int + 2 * NI;
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
+        const int32_t n = st.desc.n_atoms;
+        const double *px = c->pos + st.caller_off, *py = px + c->n_tot, *pz = py + c->n_tot;
+        const int64_t ro = lay[s].rank_off;
+        hipLaunchKernelGGL(k_init_slots, dim3(nblk(st.n_pad, 256)), dim3(256), 0, st_,
+                           st.atom_off, st.n_pad, c->perm, c->cell_int, qx, qy, qz, c->cnt);
+        hipLaunchKernelGGL(k_assign, dim3(nblk(n, 256)), dim3(256), 0, st_,
+                           c->sorted_local + st.caller_off, n, st.atom_off, st.caller_off, px, py,
+                           pz, c->cell_of + st.caller_off, d_brick.p + ro, c->bricks, d_atom0.p,
+                           grids[s], c->perm, c->inv, c->cell_int, c->pos_slot + st.caller_off,
+                           qx, qy, qz);
+        hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
+                           c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
+                           d_start.p + cstart_off[s], d_rank.p + ro, d_cell.p + ro,
+                           d_brick.p + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, nullptr,
+                           nullptr, nullptr);
+    }
+    L2T_HIP(c, hipGetLastError());
+    // ---- slice widths -> column offsets (host scan) -------------------------------
+    DevBuf<int32_t> dw(c, 2 * (int64_t)c->n_slices + 2);
+    if (!dw.ok()) return fail(c, L2T_ENOMEM, "slice width allocation failed");
+    hipLaunchKernelGGL(k_slice_width, dim3(nblk(c->n_slices, 256)), dim3(256), 0, st_, c->cnt,
+                       c->perm, c->n_slices, dw.p, dw.p + c->n_slices);
+    L2T_HIP(c, hipGetLastError());
+    std::vector<int32_t> hw(2 * (size_t)c->n_slices);
+    if (!hw.empty())
+        L2T_HIP(c, hipMemcpyAsync(hw.data(), dw.p, sizeof(int32_t) * hw.size(),
+                                  hipMemcpyDeviceToHost, st_));
+    L2T_HIP(c, hipStreamSynchronize(st_));
     std::vector<SliceInfo> hs(c->n_slices);
     int64_t total64 = 0;
-    int32_t wmax = 0;
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         st.max_nbrs = 0;
-        for (int32_t q = 0; q < st.n_slices; ++q) {
-            int32_t sl = st.slice0 + q;
-            hs[sl].sys = s;
-            hs[sl].width = hw[sl];
-            hs[sl].n_valid = hw[c->n_slices + sl];
-            if (total64 > INT32_MAX) return fail(c, L2T_ENOMEM, "neighbour table too large");
-            hs[sl].col_base64 = (int32_t)total64;
-            total64 += hw[sl];
-            st.max_nbrs = std::max(st.max_nbrs, hw[sl]);
+        const SysLayout &L = lay[s];
+        for (int32_t b = 0; b < L.nbrick; ++b) {
+            const BrickInfo &bi = hb[L.brick0 + b];
+            for (int32_t q = 0; q < bi.n_own_pad / kWave; ++q) {
+                const int32_t sl = bi.slice0 + q;
+                hs[sl].sys = s;
+                hs[sl].brick = L.brick0 + b;
+                hs[sl].width = hw[sl];
+                hs[sl].n_valid = hw[c->n_slices + sl];
+                if (total64 > INT32_MAX) return fail(c, L2T_ENOMEM, "neighbour table too large");
+                hs[sl].col_base64 = (int32_t)total64;
+                total64 += hw[sl];
+                st.max_nbrs = std::max(st.max_nbrs, hw[sl]);
+            }
         }
-        wmax = std::max(wmax, st.max_nbrs);
     }
     int64_t col_len = std::max<int64_t>(total64 * kWave, 1);
     if (col_len > c->col_len) {
         if (c->col) (void)hipFree(c->col);
+        if (c->col16) (void)hipFree(c->col16);
         c->col = nullptr;
-        if (hipMalloc(&c->col, sizeof(int32_t) * col_len) != hipSuccess)
+        c->col16 = nullptr;
+        c->col_len = 0;
+        if (hipMalloc(&c->col, sizeof(int32_t) * col_len) != hipSuccess ||
+            hipMalloc(&c->col16, sizeof(uint16_t) * col_len) != hipSuccess)
             return fail(c, L2T_ENOMEM, "neighbour table allocation failed");
         c->col_len = col_len;
     }
-    L2T_HIP(c, hipMemcpyAsync(c->slices, hs.data(), sizeof(SliceInfo) * hs.size(),
-                              hipMemcpyHostToDevice, st_));
+    c->col_used = total64 * kWave;
+    if (!hs.empty())
+        L2T_HIP(c, hipMemcpyAsync(c->slices, hs.data(), sizeof(SliceInfo) * hs.size(),
+                                  hipMemcpyHostToDevice, st_));
+    // ---- tables and halo lists (device) ----------------------------------------------
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         const int32_t n = st.desc.n_atoms;
-        hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n, st.atom_off,
-                           c->pos_int, c->pos_int + c->n_int, c->pos_int + 2 * (int64_t)c->n_int,
-                           c->cell_int, c->cell_start + cstart_off[s], grids[s], rc2, c->cnt,
-                           c->slices, c->col);
+        const int64_t ro = lay[s].rank_off;
+        hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
+                           c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
+                           d_start.p + cstart_off[s], d_rank.p + ro, d_cell.p + ro,
+                           d_brick.p + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, c->slices,
+                           c->col, c->col16);
     }
     hipLaunchKernelGGL(k_pad_rows, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
-                       c->slices, c->n_int, c->col);
+                       c->slices, c->bricks, c->n_int, c->col, c->col16);
+    if (!h_halo.empty())
+        hipLaunchKernelGGL(k_halo_expand, dim3(nblk((int64_t)h_halo.size(), 256)), dim3(256), 0,
+                           st_, d_halo.p, (int64_t)h_halo.size(), c->bricks, d_start.p,
+                           c->pos_slot, c->halo);
     L2T_HIP(c, hipGetLastError());
-    // statistics
+    // ---- statistics ----------------------------------------------------------------------
     std::vector<int32_t> hc(c->n_int);
-    L2T_HIP(c, hipMemcpyAsync(hc.data(), c->cnt, sizeof(int32_t) * hc.size(), hipMemcpyDeviceToHost,
-                              st_));
+    if (!hc.empty())
+        L2T_HIP(c, hipMemcpyAsync(hc.data(), c->cnt, sizeof(int32_t) * hc.size(),
+                                  hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
     int64_t sum = 0;
     int32_t mx = 0;
@@ -552,9 +832,21 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
     }
     c->max_nbrs = mx;
     c->mean_nbrs = c->n_tot > 0 ? (double)sum / (double)c->n_tot : 0.0;
+    c->mean_width = c->n_tot > 0 ? (double)total64 * kWave / (double)c->n_tot : 0.0;
     c->r_cut = r_cut;
-    (void)wmax;
     return L2T_OK;
+}
+
+int build_neighbors(l2t_ctx *c, double r_cut) {
+    int32_t limit = 8;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        bool overflow = false;
+        int rc = build_neighbors_once(c, r_cut, limit, &overflow);
+        if (rc != L2T_OK) return rc;
+        if (!overflow) return L2T_OK;
+        limit = std::max(1, limit / 2);
+    }
+    return fail(c, L2T_EINVAL, "atom density too high for the LDS tile of one cell and its halo");
 }
 
 int permute_in(l2t_ctx *c, int32_t sys, const double *src_dev, int32_t field) {

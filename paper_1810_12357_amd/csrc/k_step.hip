@@ -60,6 +60,41 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
                      err);
 }
 
+// LDS-tile FP32C sub-step: one workgroup per brick stages the FP32 hi
+// temperatures of the brick's own slots and of its halo atoms in LDS, then its
+// waves run the brick's slices reading neighbours from the tile through the
+// uint16 table.  Workgroup b runs on XCD b mod 8 and takes brick
+// (b mod 8) * (G/8) + b/8, so each XCD sweeps one contiguous range of bricks
+// and its L2 serves the halo loads.
+__global__ __launch_bounds__(256) void k_brick_fp32c(
+    const BrickInfo *bricks, const int32_t *list, int32_t n_list, const SliceInfo *slices,
+    const uint16_t *col16, const int32_t *halo, const float *Thi, float *Thi_n, float *Tlo,
+    const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep, int32_t rel,
+    double *ledger, unsigned *err) {
+    extern __shared__ float tile[];
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+    if ((int32_t)logical >= n_list) return;
+    const BrickInfo bi = bricks[list[logical]];
+    for (int32_t t = threadIdx.x; t < bi.n_own_pad; t += blockDim.x) tile[t] = Thi[bi.slot0 + t];
+    const int32_t *hl = halo + bi.halo_off;
+    for (int32_t t = threadIdx.x; t < bi.n_halo; t += blockDim.x)
+        tile[bi.n_own_pad + t] = Thi[hl[t]];
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    const int32_t ns = bi.n_own_pad / kWave;
+    for (int32_t q = wave; q < ns; q += nw) {
+        const int32_t sl = bi.slice0 + q;
+        const SliceInfo si = slices[sl];
+        const DevParams &p = P[si.sys];
+        const float Ti = tile[q * kWave + lane];
+        const uint16_t *cp = col16 + (int64_t)si.col_base64 * kWave + lane;
+        slice_update_fp32c(si, sl, lane, p, Ti, [&](int32_t k) { return tile[cp[k * kWave]]; },
+                           Thi_n, Tlo, Tl, srcw, dstep[si.sys] + rel, ledger, err);
+    }
+}
+
 // Grid-wide barrier for the persistent kernel.  bar[0] counts arrivals over
 // the whole launch (barrier k completes at k * nblocks arrivals); bar[1] is an
 // abort word raised when a block spins past the limit, so every block leaves
@@ -207,7 +242,7 @@ __global__ void k_system_reduce(int32_t slice0, int32_t n_slices, const double *
 
 __global__ void k_pair(const float *ti, const float *tj, float *out, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = pair32(ti[i], tj[i], 1.0f, 0.5f, 0.0f);
+    if (i < n) out[i] = pair32(ti[i], tj[i], PairK{0.5f, 0.0f, 1.0f, -1.0f / 3.0f, kUTiny});
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -258,6 +293,9 @@ int upload_params(l2t_ctx *c) {
         p.f_T_min = (float)q.T_min;
         p.f_T_max = (float)q.T_max;
         p.f_i0 = (float)p.i0;
+        p.f_inv2 = (float)(p.inv_span * p.inv_span);
+        p.f_c_tiny = (float)(-p.inv_span * p.inv_span / 3.0);
+        p.f_w_tiny = (float)((double)dev::kUTiny * p.span * p.span);
     }
     L2T_HIP(c, hipMemcpyAsync(c->dparams, c->hparams.data(), sizeof(DevParams) * S,
                               hipMemcpyHostToDevice, c->stream));
@@ -336,10 +374,20 @@ static int persistent_grid(l2t_ctx *c, int block) {
 }
 
 // FP32C, all systems, n sub-steps starting at the current state.
-int fp32c_launch(l2t_ctx *c, int32_t n, int persistent, int block, int /*resident_max*/,
-                 int /*rel_step0*/) {
+int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
     int cur = c->cur;
-    if (persistent) {
+    if (kernel == kKernelBrick) {
+        const int32_t nl = c->n_brick_list;
+        const unsigned grid = (unsigned)((nl + 7) / 8 * 8);
+        const size_t lds = sizeof(float) * (size_t)c->tile_max;
+        for (int32_t k = 0; k < n && nl > 0; ++k) {
+            hipLaunchKernelGGL(k_brick_fp32c, dim3(grid), dim3(block), lds, c->stream, c->bricks,
+                               c->brick_list, nl, c->slices, c->col16, c->halo, c->Thi[cur],
+                               c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32, c->dparams, c->dstep,
+                               k, c->ledger, c->derr);
+            cur ^= 1;
+        }
+    } else if (persistent) {
         const int grid = persistent_grid(c, block);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->dbar, 2);
         hipLaunchKernelGGL(k_persistent_fp32c, dim3(grid), dim3(block), 0, c->stream, c->slices,
@@ -372,10 +420,10 @@ void drop_graphs(l2t_ctx *c) {
 int advance_fp32c(l2t_ctx *c, int32_t n) {
     const Tuning &t = c->tune;
     if (!t.graph) {
-        int rc = fp32c_launch(c, n, t.persistent, t.block, t.resident_max, 0);
+        int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block);
         if (rc != L2T_OK) return rc;
     } else {
-        GraphKey key{n, (c->cur << 8) | (t.persistent << 4) | 0, t.block};
+        GraphKey key{n, (c->cur << 8) | (t.persistent << 4) | t.kernel, t.block};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             // capture on a private stream (the caller's may be the legacy null
@@ -386,7 +434,7 @@ int advance_fp32c(l2t_ctx *c, int32_t n) {
             hipStream_t user = c->stream;
             L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
             c->stream = c->cap_stream;
-            int rc = fp32c_launch(c, n, t.persistent, t.block, t.resident_max, 0);
+            int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block);
             c->stream = user;
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc != L2T_OK) return rc;

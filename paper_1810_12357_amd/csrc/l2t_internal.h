@@ -32,6 +32,23 @@ struct SliceInfo {
     int32_t width;
     int32_t col_base64;
     int32_t n_valid;
+    int32_t brick;      // brick that owns the slice
+    int32_t pad_[3];
+};
+
+// A brick of up to b x b x b cells: its own slots (padded to 64) and the halo
+// atoms of the surrounding one-cell shell, staged together in LDS.  shell maps
+// a shell position (o - 1 .. o + e, per axis) to -1 (own cell), -2 (outside a
+// free boundary) or the cell's offset in the brick's halo list.
+struct BrickInfo {
+    int32_t slot0, n_own, n_own_pad, slice0;
+    int32_t halo_off, n_halo, shell_off, sys;
+    int32_t o[3];       // first cell of the brick (grid coordinates)
+    int32_t sh[3];      // shell extent per axis (brick extent + 2)
+};
+
+struct HaloCell {
+    int32_t brick, start_index, offset, pos_base;
 };
 
 // Per-system constants as the kernels read them.
@@ -45,6 +62,7 @@ struct DevParams {
     // FP32 copies for the compensated path
     float f_inv_span, f_half_inv_span, f_m_off, f_A, f_K, f_dt, f_g;
     float f_ce_const, f_gamma, f_ce_cap, f_T_min, f_T_max, f_i0;
+    float f_inv2, f_c_tiny, f_w_tiny;
 };
 
 struct SystemState {
@@ -70,8 +88,12 @@ struct GraphKey {
     }
 };
 
+constexpr int kKernelSliced = 0;   // global gathers through the int32 table
+constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
+
 struct Tuning {
-    int persistent = 1;
+    int kernel = kKernelBrick;
+    int persistent = 0;
     int block = 256;
     int resident_max = 0;    // 0 = autotune
     int graph = 1;
@@ -120,7 +142,16 @@ struct l2t_ctx {
     int32_t *cnt = nullptr;      // internal [n_int]
     l2t::SliceInfo *slices = nullptr;
     int32_t *col = nullptr;
+    uint16_t *col16 = nullptr;   // same layout as col, brick-local indices
+    int32_t *pos_slot = nullptr; // caller layout [n_tot]: cell-order position -> slot
+    l2t::BrickInfo *bricks = nullptr;
+    int32_t *brick_list = nullptr;   // non-empty bricks
+    int32_t *shell = nullptr;
+    int32_t *halo = nullptr;
+    int32_t n_bricks = 0, n_brick_list = 0, tile_max = 0;
     int64_t col_len = 0;
+    int64_t col_used = 0;
+    double mean_width = 0.0;     // mean row length of the sliced table (padding included)
     int64_t cells_total = 0;
 
     double *T64[2] = {nullptr, nullptr};
@@ -180,8 +211,7 @@ int advance_fp32c(l2t_ctx *c, int32_t n);                 // all systems, tuned 
 int reset_ledger(l2t_ctx *c, int32_t sys);
 int energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out);
 int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream_t s);
-int fp32c_launch(l2t_ctx *c, int32_t n, int persistent, int block, int resident_max,
-                 int rel_step0);
+int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block);
 int bump_steps(l2t_ctx *c, int32_t sys, int32_t n);
 void drop_graphs(l2t_ctx *c);
 
@@ -195,5 +225,27 @@ int autotune(l2t_ctx *c);
 
 // ---- buffers ---------------------------------------------------------------
 int ensure_scratch(l2t_ctx *c, size_t bytes);
+// (re)allocate every internal-order buffer for n_int slots and the brick tables
+int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, int64_t shell_len,
+                   int64_t halo_len);
+
+// device buffer released (after a stream sync) when it goes out of scope
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf(l2t_ctx *c, int64_t n) : s(c->stream) {
+        if (hipMalloc((void **)&p, sizeof(T) * (size_t)(n > 0 ? n : 1)) != hipSuccess) p = nullptr;
+    }
+    ~DevBuf() {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    bool ok() const { return p != nullptr; }
+};
 
 }  // namespace l2t

@@ -57,34 +57,57 @@ __device__ inline float pulse32(const DevParams &p, int64_t step) {
 // With d = theta_j - theta_i and m = (theta_i + theta_j)/2 the pair term of
 // Eq. 2 equals d [cosh d - (2 m (1 - m) + d^2/2) sinh(d)/d].  Writing u = d^2,
 // cosh d - (u/2) sinh(d)/d = sum_k (1 - k) u^k / (2k)! =: P(u) and
-// sinh(d)/d = sum_k u^k / (2k+1)! =: Q(u), so f = d (P(u) - 2 m (1 - m) Q(u)).
-// Both series are truncated below half an FP32 ulp of h for |d| <= 1; for
-// u <= 1e-2 the short forms are used.  h depends on (m, u) only, both
-// symmetric in (i, j), so f(i, j) = -f(j, i) holds bitwise.
-__device__ __forceinline__ float pair32(float Ti, float Tj, float inv_span, float half_inv_span,
-                                        float m_off) {
-    const float d = (Tj - Ti) * inv_span;
-    const float m = fmaf(Ti + Tj, half_inv_span, m_off);
+// sinh(d)/d = sum_k u^k / (2k+1)! =: Q(u), so f = d h with
+// h = P(u) - 2 m (1 - m) Q(u).  pair32 returns span * f = dT h in temperature
+// units (dT = T_j - T_i is exact for nearby FP32 temperatures).  Three exact
+// tiers by the size of u: u <= kUTiny keeps P = 1, Q = 1 + u/6 (dropped terms
+// below 3e-9 relative), u <= 1e-2 adds the u^2, u^3 terms, larger u takes the
+// series to u^6 (below half an FP32 ulp of h for |d| <= 1).  Everything
+// depends on (m, u) only, symmetric in (i, j), so pair32(i, j) = -pair32(j, i)
+// holds bitwise.
+constexpr float kUTiny = 2.5e-4f;
+
+struct PairK {
+    float hinv;     // 0.5 / span
+    float moff;     // -T_min / span
+    float inv2;     // 1 / span^2
+    float c_tiny;   // -1 / (3 span^2): u/6 scaled by -2, in T^2 units
+    float w_tiny;   // kUTiny * span^2
+};
+
+__device__ __forceinline__ PairK pair_consts(const DevParams &p) {
+    return PairK{p.f_half_inv_span, p.f_m_off, p.f_inv2, p.f_c_tiny, p.f_w_tiny};
+}
+
+__device__ __forceinline__ float pair32(float Ti, float Tj, const PairK &k) {
+    const float dT = Tj - Ti;
+    const float m = fmaf(Ti + Tj, k.hinv, k.moff);
     const float a = fmaf(-m, m, m);
-    const float u = d * d;
-    float P, Q2;   // Q2 = -2 Q
-    if (u <= 1.0e-2f) {
-        P = fmaf(u * u, fmaf(u, -1.0f / 360.0f, -1.0f / 24.0f), 1.0f);
-        Q2 = fmaf(u, fmaf(u, -2.0f / 120.0f, -2.0f / 6.0f), -2.0f);
+    const float w = dT * dT;
+    float h;
+    if (w <= k.w_tiny) {
+        h = fmaf(a, fmaf(w, k.c_tiny, -2.0f), 1.0f);
     } else {
-        float p = fmaf(u, -5.0f / 479001600.0f, -4.0f / 3628800.0f);
-        p = fmaf(u, p, -3.0f / 40320.0f);
-        p = fmaf(u, p, -1.0f / 360.0f);
-        p = fmaf(u, p, -1.0f / 24.0f);
-        P = fmaf(u * u, p, 1.0f);
-        float q = fmaf(u, -2.0f / 39916800.0f, -2.0f / 362880.0f);
-        q = fmaf(u, q, -2.0f / 5040.0f);
-        q = fmaf(u, q, -2.0f / 120.0f);
-        q = fmaf(u, q, -2.0f / 6.0f);
-        Q2 = fmaf(u, q, -2.0f);
+        const float u = w * k.inv2;
+        float P, Q2;   // Q2 = -2 Q
+        if (u <= 1.0e-2f) {
+            P = fmaf(u * u, fmaf(u, -1.0f / 360.0f, -1.0f / 24.0f), 1.0f);
+            Q2 = fmaf(u, fmaf(u, -2.0f / 120.0f, -2.0f / 6.0f), -2.0f);
+        } else {
+            float pp = fmaf(u, -5.0f / 479001600.0f, -4.0f / 3628800.0f);
+            pp = fmaf(u, pp, -3.0f / 40320.0f);
+            pp = fmaf(u, pp, -1.0f / 360.0f);
+            pp = fmaf(u, pp, -1.0f / 24.0f);
+            P = fmaf(u * u, pp, 1.0f);
+            float q = fmaf(u, -2.0f / 39916800.0f, -2.0f / 362880.0f);
+            q = fmaf(u, q, -2.0f / 5040.0f);
+            q = fmaf(u, q, -2.0f / 120.0f);
+            q = fmaf(u, q, -2.0f / 6.0f);
+            Q2 = fmaf(u, q, -2.0f);
+        }
+        h = fmaf(a, Q2, P);
     }
-    const float h = fmaf(a, Q2, P);
-    return d * h;
+    return dT * h;
 }
 
 // ---- one FP64 plain sub-step of one slice ---------------------------------------
@@ -130,30 +153,28 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
 }
 
 // ---- one FP32C sub-step of one slice ------------------------------------------------
-__device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl, int lane,
-                                                 const DevParams &p,
-                                                 const int32_t *__restrict__ col,
-                                                 const float *__restrict__ Thi,
-                                                 float *__restrict__ Thi_n,
-                                                 float *__restrict__ Tlo,
-                                                 const float *__restrict__ Tl,
-                                                 const float *__restrict__ srcw, int64_t step,
-                                                 double *__restrict__ ledger, unsigned *err) {
+// fetch(k) returns the FP32 hi temperature of this lane's k-th neighbour; the
+// global-gather and the LDS-tile kernels differ only there, so both produce
+// bit-identical states.
+template <class Fetch>
+__device__ __forceinline__ void slice_update_fp32c(const SliceInfo &si, int32_t sl, int lane,
+                                                   const DevParams &p, float Ti, Fetch fetch,
+                                                   float *__restrict__ Thi_n,
+                                                   float *__restrict__ Tlo,
+                                                   const float *__restrict__ Tl,
+                                                   const float *__restrict__ srcw, int64_t step,
+                                                   double *__restrict__ ledger, unsigned *err) {
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
-    const float Ti = Thi[slot];
-    const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
-    const float inv = p.f_inv_span, hinv = p.f_half_inv_span, moff = p.f_m_off;
-    float S = 0.0f, comp = 0.0f;
+    const PairK pk = pair_consts(p);
+    float S = 0.0f, comp = 0.0f;   // span * sum_j f(theta_i, theta_j), Kahan-compensated
     int32_t k = 0;
     const int32_t w = si.width;
-    // batches of 4 neighbours: issue the index and temperature loads first
+    // batches of 4 neighbours: issue the loads first
     for (; k + 4 <= w; k += 4) {
-        const int32_t j0 = cp[(k + 0) * kWave], j1 = cp[(k + 1) * kWave];
-        const int32_t j2 = cp[(k + 2) * kWave], j3 = cp[(k + 3) * kWave];
-        const float T0 = Thi[j0], T1 = Thi[j1], T2 = Thi[j2], T3 = Thi[j3];
-        const float f[4] = {pair32(Ti, T0, inv, hinv, moff), pair32(Ti, T1, inv, hinv, moff),
-                            pair32(Ti, T2, inv, hinv, moff), pair32(Ti, T3, inv, hinv, moff)};
+        const float T0 = fetch(k), T1 = fetch(k + 1), T2 = fetch(k + 2), T3 = fetch(k + 3);
+        const float f[4] = {pair32(Ti, T0, pk), pair32(Ti, T1, pk), pair32(Ti, T2, pk),
+                            pair32(Ti, T3, pk)};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float y = f[q] - comp;
@@ -163,7 +184,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
         }
     }
     for (; k < w; ++k) {
-        const float f = pair32(Ti, Thi[cp[k * kWave]], inv, hinv, moff);
+        const float f = pair32(Ti, fetch(k), pk);
         const float y = f - comp;
         const float t = S + y;
         comp = (t - S) - y;
@@ -180,7 +201,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
         float q = 0.0f;
         if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * srcw[slot];
         const float loc = (q - coup) * invc;
-        const float dT = p.f_dt * fmaf(p.f_A, S, loc);
+        const float dT = p.f_dt * fmaf(p.f_K, S, loc);
         // (hi, lo) + dT without rounding error: TwoSum then renormalise
         const float s = Ti + dT;
         const float bp = s - Ti;
@@ -203,6 +224,22 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
         ledger[3 * (int64_t)sl + 1] += qd;
         ledger[3 * (int64_t)sl + 2] += lt;
     }
+}
+
+// global-gather form over the int32 table
+__device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl, int lane,
+                                                 const DevParams &p,
+                                                 const int32_t *__restrict__ col,
+                                                 const float *__restrict__ Thi,
+                                                 float *__restrict__ Thi_n,
+                                                 float *__restrict__ Tlo,
+                                                 const float *__restrict__ Tl,
+                                                 const float *__restrict__ srcw, int64_t step,
+                                                 double *__restrict__ ledger, unsigned *err) {
+    const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
+    const float Ti = Thi[sl * kWave + lane];
+    slice_update_fp32c(si, sl, lane, p, Ti, [&](int32_t k) { return Thi[cp[k * kWave]]; },
+                       Thi_n, Tlo, Tl, srcw, step, ledger, err);
 }
 
 }  // namespace dev

@@ -150,17 +150,28 @@ def test_c1_fp32c_matches_oracle(c1_oracle, persistent):
     assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(w.systems[0].T_e0.sum(), rel=1e-9)
 
 
-def test_fp32c_persistent_equals_per_step_bitwise():
-    w = W.c3(n_cells=9, n_substeps=1)
+@pytest.mark.parametrize("case", ["c3_jitter", "c4_batch"])
+def test_fp32c_launch_forms_bitwise_equal(case):
+    """Global-gather per-step, persistent, LDS-brick per-step (with and without
+    hipGraph capture) evaluate the same per-atom arithmetic in the same order."""
+    if case == "c3_jitter":
+        w = W.c3(n_cells=9, n_substeps=1)
+    else:
+        w = W.c4(n_systems=5, n_substeps=1, size_lo=500, size_hi=4000)
     runs = []
-    for persistent, graph in ((0, 0), (1, 0), (1, 1)):
-        ctx = gpu_context(w, L.L2T_FP32C, persistent=persistent, graph=graph)
+    forms = ((0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 0, 1))   # (kernel, persistent, graph)
+    for kernel, persistent, graph in forms:
+        ctx = gpu_context(w, L.L2T_FP32C, graph=graph)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+        if persistent:
+            L.l2t_set_option(ctx.h, L.L2T_OPT_PERSISTENT, 1)
         ctx.advance(37)
         ctx.advance(64)
-        runs.append(ctx.get(0))
+        runs.append([ctx.get(s) for s in range(len(w.systems))])
         ctx.close()
-    assert np.array_equal(runs[0], runs[1])
-    assert np.array_equal(runs[0], runs[2])
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
 
 
 # ---------------------------------------------------------- C2: Fourier limit ----
