@@ -109,6 +109,10 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto")
+    ap.add_argument("--brick-edge", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
@@ -121,11 +125,23 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}))
+        return
     w = W.c3(n_cells=args.cells, n_substeps=args.substeps)
     sy = w.systems[0]
     log(f"C3: {sy.n} atoms, r_c = {w.r_cut:.4f} A, {args.substeps} sub-steps per step")
     ctx = L.Context(w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
     h = ctx.h
+    if args.brick_edge:
+        L.l2t_set_option(h, L.L2T_OPT_BRICK_EDGE, args.brick_edge)
+    if args.kernel != "auto":
+        L.l2t_set_option(h, L.L2T_OPT_KERNEL, 1 if args.kernel == "brick" else 0)
     d = setup_system(L, h, sy, dev)
     torch.cuda.synchronize()
     timer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -171,6 +187,7 @@ def main():
                                     f"0.05 A, r_c 1.2a, {args.substeps} FP32C sub-steps per step",
                            n_atoms=sy.n, substeps=args.substeps, mean_neighbors=mean,
                            max_neighbors=mx, kernel=["global-gather", "lds-brick"][kernel],
+                           brick_edge=L.l2t_get_option(h, L.L2T_OPT_BRICK_EDGE),
                            persistent=persistent, block=block),
                advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
                roofline=roof,

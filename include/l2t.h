@@ -89,6 +89,7 @@ extern "C" {
 #define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
 #define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
+#define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells for the next l2t_build_neighbors (0 = automatic) */
 
 typedef struct l2t_ctx l2t_ctx;
 

@@ -360,7 +360,7 @@ int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mea
     int rc = l2t::build_neighbors(c, r_cut);
     if (rc != L2T_OK) return rc;
     c->nbrs_built = true;
-    c->tune.tuned = false;
+    if (!c->tune.pinned) c->tune.tuned = false;   // new layout: tune again unless pinned
     for (auto &st : c->sys) {
         st.has_te = false;   // internal order changed: fields must be written again
         st.has_tl = false;
@@ -536,6 +536,10 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             break;
         case L2T_OPT_RESIDENT_MAX: t.resident_max = (int)value; break;
         case L2T_OPT_GRAPH: t.graph = value ? 1 : 0; break;
+        case L2T_OPT_BRICK_EDGE:
+            if (value < 0 || value > 16) return l2t::fail(c, L2T_EINVAL, "brick edge must be 0..16");
+            t.brick_edge = (int)value;
+            return L2T_OK;
         case L2T_OPT_KERNEL:
             if (value != l2t::kKernelSliced && value != l2t::kKernelBrick)
                 return l2t::fail(c, L2T_EINVAL, "kernel must be 0 (global) or 1 (brick)");
@@ -547,7 +551,12 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             break;
         default: return l2t::fail(c, L2T_EINVAL, "unknown option");
     }
-    if (option != L2T_OPT_AUTOTUNE) t.tuned = true;   // an explicit choice overrides tuning
+    if (option != L2T_OPT_AUTOTUNE) {
+        t.tuned = true;    // an explicit choice overrides tuning, also across rebuilds
+        t.pinned = true;
+    } else {
+        t.pinned = false;
+    }
     l2t::drop_graphs(c);
     return L2T_OK;
 }
@@ -562,6 +571,7 @@ int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
         case L2T_OPT_GRAPH: *value = t.graph; break;
         case L2T_OPT_AUTOTUNE: *value = t.autotune; break;
         case L2T_OPT_KERNEL: *value = t.kernel; break;
+        case L2T_OPT_BRICK_EDGE: *value = c->brick_edge_used; break;
         default: return l2t::fail(c, L2T_EINVAL, "unknown option");
     }
     return L2T_OK;

@@ -254,6 +254,59 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx
     }
 }
 
+// Within each brick, order the atoms by neighbour count (descending, ties in
+// cell order) so the 64 lanes of a slice carry rows of nearly equal length;
+// the brick kernel reads its tile from LDS, so the order inside a brick costs
+// no locality.  One workgroup per non-empty brick; writes new_slot[old slot].
+__global__ void k_brick_rank(const BrickInfo *bricks, const int32_t *list, const int32_t *cnt,
+                             int32_t *new_slot) {
+    extern __shared__ int32_t lc[];
+    __shared__ int32_t hist[256];
+    const BrickInfo bi = bricks[list[blockIdx.x]];
+    for (int32_t t = threadIdx.x; t < 256; t += blockDim.x) hist[t] = 0;
+    for (int32_t t = threadIdx.x; t < bi.n_own; t += blockDim.x)
+        lc[t] = 255 - min(cnt[bi.slot0 + t], 255);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int32_t t = 0; t < bi.n_own; ++t) ++hist[lc[t]];
+        int32_t acc = 0;
+        for (int b = 0; b < 256; ++b) {
+            const int32_t v = hist[b];
+            hist[b] = acc;
+            acc += v;
+        }
+        for (int32_t t = 0; t < bi.n_own; ++t) lc[t] = hist[lc[t]]++;
+    }
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < bi.n_own; t += blockDim.x)
+        new_slot[bi.slot0 + t] = bi.slot0 + lc[t];
+}
+
+__global__ void k_iota(int32_t *p, int32_t n) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) p[s] = s;
+}
+
+__global__ void k_scatter_i32(const int32_t *src, const int32_t *to, int32_t n, int32_t *dst) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[to[s]] = src[s];
+}
+
+__global__ void k_scatter_f64(const double *src, const int32_t *to, int32_t n, double *dst) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[to[s]] = src[s];
+}
+
+__global__ void k_inverse(const int32_t *perm, int32_t n, int32_t *inv) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n && perm[s] >= 0) inv[perm[s]] = s;
+}
+
+__global__ void k_remap(int32_t *p, int64_t n, const int32_t *to) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = to[p[i]];
+}
+
 __global__ void k_slice_width(const int32_t *cnt, const int32_t *perm, int32_t n_slices,
                               int32_t *width, int32_t *nvalid) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -485,12 +538,38 @@ struct SysLayout {
     std::vector<int32_t> rank_of_cell, cell_of_rank, brick_cell0;
 };
 
-// brick edge (cells) so that a (b+2)^3-cell tile of this density fits the LDS
-// cap with room for density fluctuations
-int32_t brick_edge(double atoms_per_cell, int32_t limit) {
-    double cells = kTileCapFloats / (1.6 * std::max(atoms_per_cell, 1e-9));
-    int32_t b = (int32_t)std::floor(std::cbrt(cells)) - 2;
-    return std::max(1, std::min(b, limit));
+// Brick edge (cells), one for all systems of the context.  The (b+2)^3-cell
+// tile at the densest system's density must fit the LDS cap with room for
+// fluctuations; among the edges that fit, take the one with the least
+// estimated time: rounds of resident workgroups over all bricks of all
+// systems (one brick per workgroup; a CU holds as many tiles as its 160 KB of
+// LDS and its 8 workgroups of 4 waves allow) times the work of a full brick
+// (own atoms, plus the halo staging counted at 0.3 of an own atom).
+int32_t brick_edge(const l2t_ctx *c, int32_t limit) {
+    double dens = 1e-9;
+    for (const SystemState &st : c->sys)
+        dens = std::max(dens, (double)st.desc.n_atoms / (double)std::max<int64_t>(1, st.ncell));
+    int32_t best = 1;
+    double best_cost = 1e300;
+    for (int32_t b = 1; b <= limit; ++b) {
+        const double tile = 1.1 * std::pow(b + 2.0, 3) * dens + kWave;
+        if (tile > kTileCapFloats) break;
+        double nbrick = 0.0;
+        for (const SystemState &st : c->sys) {
+            double nb = 1.0;
+            for (int d = 0; d < 3; ++d) nb *= std::ceil((double)st.nc[d] / std::min(b, st.nc[d]));
+            nbrick += nb;
+        }
+        const double per_cu = std::max(1.0, std::min(8.0, std::floor(163840.0 / (4.0 * tile))));
+        const double rounds = std::ceil(nbrick / (per_cu * std::max(1, c->n_cu)));
+        const double work = std::pow((double)b, 3) + 0.3 * (std::pow(b + 2.0, 3) - std::pow(b, 3));
+        const double cost = rounds * work;
+        if (cost < best_cost * 0.999) {
+            best_cost = cost;
+            best = b;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -516,8 +595,13 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
             st.ncell *= st.nc[d];
         }
         if (st.ncell > (int64_t)1 << 28) return fail(c, L2T_EINVAL, "cell grid too large");
+    }
+    const int32_t be = c->tune.brick_edge > 0 ? std::min(c->tune.brick_edge, edge_limit)
+                                              : brick_edge(c, edge_limit);
+    c->brick_edge_used = be;
+    for (int s = 0; s < S; ++s) {
+        SystemState &st = c->sys[s];
         SysLayout &L = lay[s];
-        const int32_t be = brick_edge((double)st.desc.n_atoms / (double)st.ncell, edge_limit);
         L.nbrick = 1;
         for (int d = 0; d < 3; ++d) {
             L.b[d] = std::min(be, st.nc[d]);
@@ -752,6 +836,42 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                            nullptr, nullptr);
     }
     L2T_HIP(c, hipGetLastError());
+    // ---- count order inside every brick --------------------------------------------
+    int32_t own_max_all = 0;
+    for (int32_t gb : h_list) own_max_all = std::max(own_max_all, hb[gb].n_own);
+    if (c->n_brick_list > 0 && own_max_all <= 12288) {   // counts staged in 48 KB of LDS
+        const int64_t NIi = c->n_int;
+        DevBuf<int32_t> to(c, NIi), ti(c, 3 * NIi);
+        DevBuf<double> td(c, 3 * NIi);
+        if (!to.ok() || !ti.ok() || !td.ok())
+            return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
+        int32_t own_max = 0;
+        for (int32_t gb : h_list) own_max = std::max(own_max, hb[gb].n_own);
+        const dim3 gi(nblk(NIi, 256)), bi(256);
+        hipLaunchKernelGGL(k_iota, gi, bi, 0, st_, to.p, c->n_int);
+        hipLaunchKernelGGL(k_brick_rank, dim3(c->n_brick_list), dim3(256),
+                           sizeof(int32_t) * (size_t)own_max, st_, c->bricks, c->brick_list,
+                           c->cnt, to.p);
+        L2T_HIP(c, hipMemcpyAsync(ti.p, c->perm, sizeof(int32_t) * NIi, hipMemcpyDeviceToDevice,
+                                  st_));
+        L2T_HIP(c, hipMemcpyAsync(ti.p + NIi, c->cell_int, sizeof(int32_t) * NIi,
+                                  hipMemcpyDeviceToDevice, st_));
+        L2T_HIP(c, hipMemcpyAsync(ti.p + 2 * NIi, c->cnt, sizeof(int32_t) * NIi,
+                                  hipMemcpyDeviceToDevice, st_));
+        L2T_HIP(c, hipMemcpyAsync(td.p, c->pos_int, sizeof(double) * 3 * NIi,
+                                  hipMemcpyDeviceToDevice, st_));
+        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti.p, to.p, c->n_int, c->perm);
+        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti.p + NIi, to.p, c->n_int, c->cell_int);
+        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti.p + 2 * NIi, to.p, c->n_int, c->cnt);
+        for (int d = 0; d < 3; ++d)
+            hipLaunchKernelGGL(k_scatter_f64, gi, bi, 0, st_, td.p + d * NIi, to.p, c->n_int,
+                               c->pos_int + d * NIi);
+        hipLaunchKernelGGL(k_inverse, gi, bi, 0, st_, c->perm, c->n_int, c->inv);
+        hipLaunchKernelGGL(k_remap, dim3(nblk(c->n_tot, 256)), dim3(256), 0, st_, c->pos_slot,
+                           c->n_tot, to.p);
+        L2T_HIP(c, hipGetLastError());
+        L2T_HIP(c, hipStreamSynchronize(st_));
+    }
     // ---- slice widths -> column offsets (host scan) -------------------------------
     DevBuf<int32_t> dw(c, 2 * (int64_t)c->n_slices + 2);
     if (!dw.ok()) return fail(c, L2T_ENOMEM, "slice width allocation failed");
@@ -839,12 +959,14 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
 
 int build_neighbors(l2t_ctx *c, double r_cut) {
     int32_t limit = 8;
+    c->brick_edge_used = 0;
     for (int attempt = 0; attempt < 4; ++attempt) {
         bool overflow = false;
         int rc = build_neighbors_once(c, r_cut, limit, &overflow);
         if (rc != L2T_OK) return rc;
         if (!overflow) return L2T_OK;
         limit = std::max(1, limit / 2);
+        c->brick_edge_used = 0;
     }
     return fail(c, L2T_EINVAL, "atom density too high for the LDS tile of one cell and its halo");
 }

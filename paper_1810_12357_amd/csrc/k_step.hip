@@ -76,23 +76,62 @@ __global__ __launch_bounds__(256) void k_brick_fp32c(
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
     const BrickInfo bi = bricks[list[logical]];
-    for (int32_t t = threadIdx.x; t < bi.n_own_pad; t += blockDim.x) tile[t] = Thi[bi.slot0 + t];
+    // stage the tile: 8 independent loads in flight per thread
+    constexpr int U = 8;
+    const int32_t B = blockDim.x;
+    for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = t0 + u * B;
+            v[u] = (t < bi.n_own_pad) ? Thi[bi.slot0 + t] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u * B < bi.n_own_pad) tile[t0 + u * B] = v[u];
+    }
     const int32_t *hl = halo + bi.halo_off;
-    for (int32_t t = threadIdx.x; t < bi.n_halo; t += blockDim.x)
-        tile[bi.n_own_pad + t] = Thi[hl[t]];
+    float *ht = tile + bi.n_own_pad;
+    for (int32_t t0 = threadIdx.x; t0 < bi.n_halo; t0 += U * B) {
+        int32_t id[U];
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = t0 + u * B;
+            id[u] = (t < bi.n_halo) ? hl[t] : bi.slot0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = Thi[id[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u * B < bi.n_halo) ht[t0 + u * B] = v[u];
+    }
     __syncthreads();
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
     const int32_t ns = bi.n_own_pad / kWave;
+    if (wave >= ns) return;
+    // every slice of a brick belongs to the brick's system
+    const DevParams &p = P[bi.sys];
+    const int64_t step = dstep[bi.sys] + rel;
+    LedgerAcc acc;
+    SliceInfo si_next = slices[bi.slice0 + wave];
     for (int32_t q = wave; q < ns; q += nw) {
         const int32_t sl = bi.slice0 + q;
-        const SliceInfo si = slices[sl];
-        const DevParams &p = P[si.sys];
+        const SliceInfo si = si_next;
+        if (q + nw < ns) si_next = slices[sl + nw];
+        const int32_t slot = sl * kWave + lane;
+        const float lo = Tlo[slot], tl = Tl[slot];
+        const float sw = p.laser_on ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
         const uint16_t *cp = col16 + (int64_t)si.col_base64 * kWave + lane;
-        slice_update_fp32c(si, sl, lane, p, Ti, [&](int32_t k) { return tile[cp[k * kWave]]; },
-                           Thi_n, Tlo, Tl, srcw, dstep[si.sys] + rel, ledger, err);
+        const LedgerTerms t = slice_core_fp32c(
+            si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
+            [&](uint16_t l) { return tile[l]; }, Thi_n, Tlo, step, err);
+        acc.add(t, p.dt);
     }
+    // the ledger is summed per system, so any slice of the brick can hold it
+    acc.flush(ledger, bi.slice0 + wave, lane);
 }
 
 // Grid-wide barrier for the persistent kernel.  bar[0] counts arrivals over

@@ -98,7 +98,9 @@ struct Tuning {
     int resident_max = 0;    // 0 = autotune
     int graph = 1;
     int autotune = 1;
+    int brick_edge = 0;      // 0 = chosen by the layout builder
     bool tuned = false;
+    bool pinned = false;     // an explicit option was set: keep the choice
 };
 
 struct Recording {
@@ -148,7 +150,7 @@ struct l2t_ctx {
     int32_t *brick_list = nullptr;   // non-empty bricks
     int32_t *shell = nullptr;
     int32_t *halo = nullptr;
-    int32_t n_bricks = 0, n_brick_list = 0, tile_max = 0;
+    int32_t n_bricks = 0, n_brick_list = 0, tile_max = 0, brick_edge_used = 0;
     int64_t col_len = 0;
     int64_t col_used = 0;
     double mean_width = 0.0;     // mean row length of the sliced table (padding included)

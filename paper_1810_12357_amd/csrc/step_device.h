@@ -152,54 +152,80 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
     }
 }
 
+// Sum over the 64 lanes with DPP moves (VALU only, no LDS traffic); the
+// total lands in lane 63 and is broadcast through readlane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    v += dpp_f32<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_f32<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_f32<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_f32<0x118, 0xf>(v);   // row_shr:8   -> lane 15 of each row: row sum
+    v += dpp_f32<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f32<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3 -> lane 63: total
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // ---- one FP32C sub-step of one slice ------------------------------------------------
-// fetch(k) returns the FP32 hi temperature of this lane's k-th neighbour; the
-// global-gather and the LDS-tile kernels differ only there, so both produce
-// bit-identical states.
-template <class Fetch>
-__device__ __forceinline__ void slice_update_fp32c(const SliceInfo &si, int32_t sl, int lane,
-                                                   const DevParams &p, float Ti, Fetch fetch,
-                                                   float *__restrict__ Thi_n,
-                                                   float *__restrict__ Tlo,
-                                                   const float *__restrict__ Tl,
-                                                   const float *__restrict__ srcw, int64_t step,
-                                                   double *__restrict__ ledger, unsigned *err) {
+// idx_at(k) loads this lane's k-th neighbour reference, val_of(ref) returns the
+// FP32 hi temperature it refers to.  The global-gather and LDS-tile kernels
+// differ only in these two, so both produce bit-identical states.  The
+// references of the next chunk of 8 are loaded before the current chunk is
+// evaluated; terms are added in neighbour order.  The caller loads the
+// lane's own lo part, T^lat and source weight ahead of the neighbour loop and
+// receives the lane's ledger terms (energy to the lattice, source, temperature
+// ledger, per unit time) for its wave reduction.
+struct LedgerTerms {
+    float e2l, src, lt;
+};
+
+template <class IdxAt, class ValOf>
+__device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int32_t sl, int lane,
+                                                        const DevParams &p, float Ti, float lo,
+                                                        float tl, float sw, IdxAt idx_at,
+                                                        ValOf val_of, float *__restrict__ Thi_n,
+                                                        float *__restrict__ Tlo, int64_t step,
+                                                        unsigned *err) {
+    constexpr int C = 8;
+    using Ref = decltype(idx_at(0));
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
     const PairK pk = pair_consts(p);
     float S = 0.0f, comp = 0.0f;   // span * sum_j f(theta_i, theta_j), Kahan-compensated
-    int32_t k = 0;
     const int32_t w = si.width;
-    // batches of 4 neighbours: issue the loads first
-    for (; k + 4 <= w; k += 4) {
-        const float T0 = fetch(k), T1 = fetch(k + 1), T2 = fetch(k + 2), T3 = fetch(k + 3);
-        const float f[4] = {pair32(Ti, T0, pk), pair32(Ti, T1, pk), pair32(Ti, T2, pk),
-                            pair32(Ti, T3, pk)};
+    Ref cur[C], nxt[C];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float y = f[q] - comp;
-            const float t = S + y;
-            comp = (t - S) - y;
-            S = t;
+    for (int u = 0; u < C; ++u) cur[u] = (u < w) ? idx_at(u) : Ref{};
+    for (int32_t k0 = 0; k0 < w; k0 += C) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) nxt[u] = (k0 + C + u < w) ? idx_at(k0 + C + u) : Ref{};
+        float Tj[C];
+#pragma unroll
+        for (int u = 0; u < C; ++u) Tj[u] = (k0 + u < w) ? val_of(cur[u]) : Ti;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            if (k0 + u < w) {
+                const float f = pair32(Ti, Tj[u], pk);
+                const float y = f - comp;
+                const float t = S + y;
+                comp = (t - S) - y;
+                S = t;
+            }
         }
-    }
-    for (; k < w; ++k) {
-        const float f = pair32(Ti, fetch(k), pk);
-        const float y = f - comp;
-        const float t = S + y;
-        comp = (t - S) - y;
-        S = t;
+#pragma unroll
+        for (int u = 0; u < C; ++u) cur[u] = nxt[u];
     }
     float hi_new = Ti;
-    double e2l = 0.0, qd = 0.0, lt = 0.0;
+    LedgerTerms r{0.0f, 0.0f, 0.0f};
     if (valid) {
-        const float lo = Tlo[slot];
-        const float tl = Tl[slot];
         const float c = ce32(p, Ti);
         const float invc = 1.0f / c;
         const float coup = signbit(tl) ? 0.0f : p.f_g * (Ti - tl);
         float q = 0.0f;
-        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * srcw[slot];
+        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * sw;
         const float loc = (q - coup) * invc;
         const float dT = p.f_dt * fmaf(p.f_K, S, loc);
         // (hi, lo) + dT without rounding error: TwoSum then renormalise
@@ -210,23 +236,31 @@ __device__ __forceinline__ void slice_update_fp32c(const SliceInfo &si, int32_t 
         hi_new = s + lo2;
         const float lo_new = lo2 - (hi_new - s);
         Tlo[slot] = lo_new;
-        e2l = (double)coup * p.dt;
-        qd = (double)q * p.dt;
-        lt = -(double)loc * p.dt;
+        r = LedgerTerms{coup, q, -loc};
         if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
     }
     Thi_n[slot] = hi_new;
-    e2l = wave_sum(e2l);
-    qd = wave_sum(qd);
-    lt = wave_sum(lt);
-    if (lane == 0) {
-        ledger[3 * (int64_t)sl + 0] += e2l;
-        ledger[3 * (int64_t)sl + 1] += qd;
-        ledger[3 * (int64_t)sl + 2] += lt;
-    }
+    return r;
 }
 
-// global-gather form over the int32 table
+// wave sums of the ledger terms, added in FP64 to a per-slice accumulator
+struct LedgerAcc {
+    double e2l = 0.0, src = 0.0, lt = 0.0;
+    __device__ __forceinline__ void add(const LedgerTerms &t, double dt) {
+        e2l += (double)wave_sum_f32(t.e2l) * dt;
+        src += (double)wave_sum_f32(t.src) * dt;
+        lt += (double)wave_sum_f32(t.lt) * dt;
+    }
+    __device__ __forceinline__ void flush(double *ledger, int32_t sl, int lane) const {
+        if (lane == 0) {
+            ledger[3 * (int64_t)sl + 0] += e2l;
+            ledger[3 * (int64_t)sl + 1] += src;
+            ledger[3 * (int64_t)sl + 2] += lt;
+        }
+    }
+};
+
+// global-gather form over the int32 table (one slice)
 __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl, int lane,
                                                  const DevParams &p,
                                                  const int32_t *__restrict__ col,
@@ -236,10 +270,17 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
                                                  const float *__restrict__ Tl,
                                                  const float *__restrict__ srcw, int64_t step,
                                                  double *__restrict__ ledger, unsigned *err) {
+    const int32_t slot = sl * kWave + lane;
     const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
-    const float Ti = Thi[sl * kWave + lane];
-    slice_update_fp32c(si, sl, lane, p, Ti, [&](int32_t k) { return Thi[cp[k * kWave]]; },
-                       Thi_n, Tlo, Tl, srcw, step, ledger, err);
+    const float Ti = Thi[slot];
+    const float lo = Tlo[slot], tl = Tl[slot];
+    const float sw = p.laser_on ? srcw[slot] : 0.0f;
+    const LedgerTerms t = slice_core_fp32c(
+        si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
+        [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, step, err);
+    LedgerAcc acc;
+    acc.add(t, p.dt);
+    acc.flush(ledger, sl, lane);
 }
 
 }  // namespace dev

@@ -26,7 +26,7 @@ L2T_HOST, L2T_DEVICE = 0, 1
 L2T_FIELD_TE, L2T_FIELD_TL, L2T_FIELD_GATE, L2T_FIELD_NBRS = 0, 1, 2, 3
 L2T_CE_CONST, L2T_CE_LINEAR, L2T_CE_CAPPED = 0, 1, 2
 L2T_OPT_PERSISTENT, L2T_OPT_BLOCK, L2T_OPT_RESIDENT_MAX, L2T_OPT_GRAPH, L2T_OPT_AUTOTUNE = 0, 1, 2, 3, 4
-L2T_OPT_KERNEL = 5
+L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE = 5, 6
 
 # every symbol the header declares (checked by the CPU test suite)
 EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbors",
