@@ -35,6 +35,41 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def library_source_hash() -> str:
+    """sha256 over the library sources (csrc/* and the C header)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1810_12357_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "l2t.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, n_atoms: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the summary is missing, covers another kernel or size, or was
+    taken on other library sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c3_4M_traffic.md")
+    if n_atoms != 4_000_000 or not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", "|", "`")):
+                k, _, v = line.partition(":")
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel") != kernel or vals.get("csrc_sha256") != library_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def setup_system(L, ctx_h, sy, dev):
     """Device copies of the inputs of one system."""
     import torch
@@ -175,8 +210,10 @@ def main():
     else:
         launch_ms, units, kname = adv / args.substeps, sy.n, "k_step_fp32c"
     achieved = bytes_per * units / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kname, sy.n) if units == sy.n else None
     roof = dict(bound="hbm", kernel=kname, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=achieved / HBM_PEAK_GBS, traffic=None,
+                frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 algorithmic_bytes_per_atom_substep=bytes_per,
                 launch_ms=launch_ms, units_per_launch=units)
     out = dict(metric="electron atom-substeps/s (4M-atom FCC, FP32C)", value=value,

@@ -18,7 +18,7 @@
  *     where f is the pair term of Eq. 2, K the exchange rate of Eq. 3 (one
  *     value per system, so K_ij is symmetric), g = G V_atom and c = C_e V_atom
  *     the per-atom coupling and heat capacity (Section 2, C_e = lambda T_e),
- *     and q_i the laser source of Eq. 9 taken as energy per unit time per
+ *     and q_i the laser source of Eq. 10 taken as energy per unit time per
  *     atom;
  *   - the per-system energy ledger: the exchange rate of Eq. 6 integrated
  *     over each sub-step, the source energy, and the electronic energy;
@@ -103,14 +103,14 @@ typedef struct {
     double box_len[3];      /* Angstrom, > 0 */
 } l2t_system_desc;
 
-/* Per-system parameters of Eq. 2, Eq. 4 gate and Eq. 9. */
+/* Per-system parameters of Eq. 2, Eq. 4 gate and Eq. 10. */
 typedef struct {
     double T_min, T_max;    /* normalisation range of Section 2, K (T_max > T_min) */
     double K;               /* exchange rate K_ij of Eq. 3, 1/fs (>= 0) */
     double dt;              /* electronic sub-step, fs (> 0) */
     double g;               /* G V_atom, eV/(fs K) per atom (>= 0) */
     int32_t ce_model;       /* L2T_CE_* */
-    int32_t laser_on;       /* 1 = add the Eq. 9 source */
+    int32_t laser_on;       /* 1 = add the Eq. 10 source */
     double ce_const;        /* eV/K per atom (L2T_CE_CONST) */
     double gamma;           /* eV/K^2 per atom (L2T_CE_LINEAR, L2T_CE_CAPPED) */
     double ce_cap;          /* eV/K per atom (L2T_CE_CAPPED) */
@@ -177,7 +177,7 @@ int l2t_get_neighbors(l2t_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *col,
 /* ---- parameters and fields -------------------------------------------------- */
 
 /* Parameters of system sys (Eq. 2, Eq. 3 value K, Eq. 4 gate epsilon,
- * Eq. 9 source).  Returns L2T_WUNSTABLE (a warning, parameters are still set)
+ * Eq. 10 source).  Returns L2T_WUNSTABLE (a warning, parameters are still set)
  * when the neighbour sets exist and the Gershgorin bound of the linearised
  * explicit step, 2 K dt max_i |N(i)|, exceeds 2.
  * Errors: EINVAL (T_max <= T_min, dt <= 0, K < 0, g < 0, unknown ce_model,

@@ -11,7 +11,7 @@ Function map (paper passages):
   lattice_temperature  Eq. 4 with centre-of-mass removal + the K_i < eps gate
                      (remark after Eq. 8)
   pair               the pair term of Eq. 2, literal two-exponential form
-  run                forward-Euler sub-steps of Eq. 2 with coupling and Eq. 9
+  run                forward-Euler sub-steps of Eq. 2 with coupling and Eq. 10
                      source (Section 2.1), ledgers of Eq. 6
   energies           sum of the per-atom electronic energy and of T
   adjoint            discrete adjoint of ``run`` (derived from Eq. 2)

@@ -18,7 +18,7 @@
  *   - the master equation Eq. 2 with the normalisation theta = (T - T_min) /
  *     (T_max - T_min) of Section 2, integrated with explicit forward Euler
  *     sub-steps (Section 2.1), every read taken from the step-n state;
- *   - the laser source of Eq. 9 as an energy rate per atom divided by the
+ *   - the laser source of Eq. 10 as an energy rate per atom divided by the
  *     atom's heat capacity;
  *   - the energy and temperature ledgers (Eq. 6 rate integrated per step);
  *   - the discrete adjoint of the forward-Euler map (derived from Eq. 2) and
@@ -109,7 +109,7 @@ static double or_energy_of(const or_params *p, double T)
     return 0.5 * p->gamma * Ts * Ts + p->ce_cap * (T - Ts);
 }
 
-/* ---- Eq. 9 source as energy per unit time per atom ------------------------
+/* ---- Eq. 10 source as energy per unit time per atom ------------------------
  * i_0 is taken as F V_atom / (l_p sqrt(2 pi) sigma): the depth profile
  * exp(-(x - x0)/l_p)/l_p integrates to one over depth and the Gaussian in
  * time integrates to sqrt(2 pi) sigma, so a column absorbs fluence F. */

@@ -2,7 +2,7 @@
 // sets in wavefront-sliced column-major tables (global int32 indices and
 // brick-local uint16 indices with per-brick halo lists), per-atom field
 // permutation, the local lattice temperature (Eq. 4) with the kinetic-energy
-// gate, and the per-atom depth weights of the laser source (Eq. 9).
+// gate, and the per-atom depth weights of the laser source (Eq. 10).
 //
 // Internal order of one system: cells are grouped into bricks of up to
 // b x b x b cells; bricks in x-major order, cells inside a brick z-fastest,
@@ -511,7 +511,7 @@ __global__ void k_lattice_temp(int32_t atom_off, int32_t n_pad, const int32_t *p
     }
 }
 
-// depth weight of the Eq. 9 source: exp(-(x_i - x_0)/l_p)
+// depth weight of the Eq. 10 source: exp(-(x_i - x_0)/l_p)
 __global__ void k_source_weights(int32_t atom_off, int32_t n_pad, const int32_t *perm,
                                  const double *qx, double x0, double lp, double *w64, float *w32) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;

@@ -1,5 +1,5 @@
 // Sub-step kernels of the master equation (Eq. 2) with electron-phonon
-// coupling and the laser source (Eq. 9), forward Euler (Section 2.1), plus the
+// coupling and the laser source (Eq. 10), forward Euler (Section 2.1), plus the
 // per-system FP64 energy / ledger reductions.
 //
 // Layout: one wavefront owns one slice of 64 consecutive cell-sorted atoms;

@@ -43,7 +43,7 @@ __device__ inline double energy_of(const DevParams &p, double T) {
     return (T <= Ts) ? 0.5 * p.gamma * T * T : 0.5 * p.gamma * Ts * Ts + p.ce_cap * (T - Ts);
 }
 
-// Gaussian time factor of Eq. 9 at the start of sub-step `step`
+// Gaussian time factor of Eq. 10 at the start of sub-step `step`
 __device__ inline double pulse64(const DevParams &p, int64_t step) {
     double t = (double)step * p.dt - p.t0;
     return exp(-t * t / (2.0 * p.sigma * p.sigma));
