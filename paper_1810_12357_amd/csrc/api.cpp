@@ -232,7 +232,7 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c->cnt);
     dfree(c->slices);
     dfree(c->col);
-    dfree(c->col16);
+    dfree(c->colw);
     dfree(c->pos_slot);
     dfree(c->bricks);
     dfree(c->brick_list);

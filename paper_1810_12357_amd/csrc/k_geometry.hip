@@ -191,7 +191,7 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx
                             const int32_t *cell_of_rank, const int32_t *brick_of_rank,
                             const BrickInfo *bricks, const int32_t *shell, Grid g, double rc2,
                             int32_t *cnt, const SliceInfo *slices, int32_t *col,
-                            uint16_t *col16) {
+                            uint16_t *colh) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int32_t self = pos_slot[k];
@@ -204,12 +204,13 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx
     int my = axis_cells(ic[1], g.nc[1], g.periodic[1], sy, oy);
     int mz = axis_cells(ic[2], g.nc[2], g.periodic[2], sz, oz);
     int32_t m = 0;
-    int64_t base = 0;
+    int64_t base = 0, basew = 0;
     int32_t width = 0;
     BrickInfo bi{};
     if (FILL) {
         const SliceInfo si = slices[self / kWave];
         base = (int64_t)si.col_base64 * kWave + (self & (kWave - 1));
+        basew = (int64_t)si.colw_base64 * kWave + (self & (kWave - 1));
         width = si.width;
         bi = bricks[brick_of_rank[rank0]];
     }
@@ -237,18 +238,19 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx
                     if (dx * dx + dy * dy + dz * dz <= rc2) {
                         if (FILL && m < width) {
                             col[base + (int64_t)m * kWave] = j;
-                            col16[base + (int64_t)m * kWave] =
-                                (uint16_t)(own ? j - bi.slot0 : hbase + (q - start[rk]));
+                            const int32_t loc = own ? j - bi.slot0 : hbase + (q - start[rk]);
+                            colh[2 * (basew + (int64_t)(m >> 1) * kWave) + (m & 1)] =
+                                (uint16_t)(4 * loc);
                         }
                         ++m;
                     }
                 }
             }
     if (FILL) {
-        for (int32_t q = m; q < width; ++q) {
-            col[base + (int64_t)q * kWave] = self;
-            col16[base + (int64_t)q * kWave] = (uint16_t)(self - bi.slot0);
-        }
+        for (int32_t q = m; q < width; ++q) col[base + (int64_t)q * kWave] = self;
+        for (int32_t q = m; q < (width + 1) / 2 * 2; ++q)
+            colh[2 * (basew + (int64_t)(q >> 1) * kWave) + (q & 1)] =
+                (uint16_t)(4 * (self - bi.slot0));
     } else {
         cnt[self] = m;
     }
@@ -326,16 +328,16 @@ __global__ void k_slice_width(const int32_t *cnt, const int32_t *perm, int32_t n
 // padding slots still run the neighbour loop of their slice: every entry of
 // their rows points at the slot itself (pair term zero, always in bounds)
 __global__ void k_pad_rows(const int32_t *perm, const SliceInfo *slices, const BrickInfo *bricks,
-                           int32_t n_int, int32_t *col, uint16_t *col16) {
+                           int32_t n_int, int32_t *col, uint16_t *colh) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_int || perm[s] >= 0) return;
     const SliceInfo si = slices[s / kWave];
     const int64_t base = (int64_t)si.col_base64 * kWave + (s & (kWave - 1));
+    const int64_t basew = (int64_t)si.colw_base64 * kWave + (s & (kWave - 1));
     const int32_t loc = s - bricks[si.brick].slot0;
-    for (int32_t q = 0; q < si.width; ++q) {
-        col[base + (int64_t)q * kWave] = s;
-        col16[base + (int64_t)q * kWave] = (uint16_t)loc;
-    }
+    for (int32_t q = 0; q < si.width; ++q) col[base + (int64_t)q * kWave] = s;
+    for (int32_t q = 0; q < (si.width + 1) / 2 * 2; ++q)
+        colh[2 * (basew + (int64_t)(q >> 1) * kWave) + (q & 1)] = (uint16_t)(4 * loc);
 }
 
 // halo list of every brick: the slots of the atoms of its halo cells
@@ -884,7 +886,7 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                                   hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
     std::vector<SliceInfo> hs(c->n_slices);
-    int64_t total64 = 0;
+    int64_t total64 = 0, totalw64 = 0;
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         st.max_nbrs = 0;
@@ -899,7 +901,9 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                 hs[sl].n_valid = hw[c->n_slices + sl];
                 if (total64 > INT32_MAX) return fail(c, L2T_ENOMEM, "neighbour table too large");
                 hs[sl].col_base64 = (int32_t)total64;
+                hs[sl].colw_base64 = (int32_t)totalw64;
                 total64 += hw[sl];
+                totalw64 += (hw[sl] + 1) / 2;
                 st.max_nbrs = std::max(st.max_nbrs, hw[sl]);
             }
         }
@@ -907,14 +911,20 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     int64_t col_len = std::max<int64_t>(total64 * kWave, 1);
     if (col_len > c->col_len) {
         if (c->col) (void)hipFree(c->col);
-        if (c->col16) (void)hipFree(c->col16);
         c->col = nullptr;
-        c->col16 = nullptr;
         c->col_len = 0;
-        if (hipMalloc(&c->col, sizeof(int32_t) * col_len) != hipSuccess ||
-            hipMalloc(&c->col16, sizeof(uint16_t) * col_len) != hipSuccess)
+        if (hipMalloc(&c->col, sizeof(int32_t) * col_len) != hipSuccess)
             return fail(c, L2T_ENOMEM, "neighbour table allocation failed");
         c->col_len = col_len;
+    }
+    int64_t colw_len = std::max<int64_t>(totalw64 * kWave, 1);
+    if (colw_len > c->colw_len) {
+        if (c->colw) (void)hipFree(c->colw);
+        c->colw = nullptr;
+        c->colw_len = 0;
+        if (hipMalloc(&c->colw, sizeof(uint32_t) * colw_len) != hipSuccess)
+            return fail(c, L2T_ENOMEM, "neighbour table allocation failed");
+        c->colw_len = colw_len;
     }
     c->col_used = total64 * kWave;
     if (!hs.empty())
@@ -929,10 +939,10 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                            c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
                            d_start.p + cstart_off[s], d_rank.p + ro, d_cell.p + ro,
                            d_brick.p + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, c->slices,
-                           c->col, c->col16);
+                           c->col, (uint16_t *)c->colw);
     }
     hipLaunchKernelGGL(k_pad_rows, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
-                       c->slices, c->bricks, c->n_int, c->col, c->col16);
+                       c->slices, c->bricks, c->n_int, c->col, (uint16_t *)c->colw);
     if (!h_halo.empty())
         hipLaunchKernelGGL(k_halo_expand, dim3(nblk((int64_t)h_halo.size(), 256)), dim3(256), 0,
                            st_, d_halo.p, (int64_t)h_halo.size(), c->bricks, d_start.p,

@@ -66,9 +66,9 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
 // uint16 table.  Workgroup b runs on XCD b mod 8 and takes brick
 // (b mod 8) * (G/8) + b/8, so each XCD sweeps one contiguous range of bricks
 // and its L2 serves the halo loads.
-__global__ __launch_bounds__(256) void k_brick_fp32c(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_brick_fp32c(
     const BrickInfo *bricks, const int32_t *list, int32_t n_list, const SliceInfo *slices,
-    const uint16_t *col16, const int32_t *halo, const float *Thi, float *Thi_n, float *Tlo,
+    const uint32_t *colw, const int32_t *halo, const float *Thi, float *Thi_n, float *Tlo,
     const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep, int32_t rel,
     double *ledger, unsigned *err) {
     extern __shared__ float tile[];
@@ -76,8 +76,8 @@ __global__ __launch_bounds__(256) void k_brick_fp32c(
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
     const BrickInfo bi = bricks[list[logical]];
-    // stage the tile: 8 independent loads in flight per thread
-    constexpr int U = 8;
+    // stage the tile: 16 independent loads in flight per thread
+    constexpr int U = 16;
     const int32_t B = blockDim.x;
     for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
         float v[U];
@@ -124,10 +124,9 @@ __global__ __launch_bounds__(256) void k_brick_fp32c(
         const float lo = Tlo[slot], tl = Tl[slot];
         const float sw = p.laser_on ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
-        const uint16_t *cp = col16 + (int64_t)si.col_base64 * kWave + lane;
-        const LedgerTerms t = slice_core_fp32c(
-            si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
-            [&](uint16_t l) { return tile[l]; }, Thi_n, Tlo, step, err);
+        const uint32_t *cw = colw + (int64_t)si.colw_base64 * kWave + lane;
+        const LedgerTerms t =
+            slice_core_brick(si, sl, lane, p, Ti, lo, tl, sw, cw, tile, Thi_n, Tlo, step, err);
         acc.add(t, p.dt);
     }
     // the ledger is summed per system, so any slice of the brick can hold it
@@ -421,7 +420,7 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
         const size_t lds = sizeof(float) * (size_t)c->tile_max;
         for (int32_t k = 0; k < n && nl > 0; ++k) {
             hipLaunchKernelGGL(k_brick_fp32c, dim3(grid), dim3(block), lds, c->stream, c->bricks,
-                               c->brick_list, nl, c->slices, c->col16, c->halo, c->Thi[cur],
+                               c->brick_list, nl, c->slices, c->colw, c->halo, c->Thi[cur],
                                c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32, c->dparams, c->dstep,
                                k, c->ledger, c->derr);
             cur ^= 1;

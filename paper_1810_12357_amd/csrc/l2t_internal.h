@@ -33,7 +33,8 @@ struct SliceInfo {
     int32_t col_base64;
     int32_t n_valid;
     int32_t brick;      // brick that owns the slice
-    int32_t pad_[3];
+    int32_t colw_base64;  // packed brick-local table: word k/2 of lane l at 64*(colw_base64 + k/2) + l
+    int32_t pad_[2];
 };
 
 // A brick of up to b x b x b cells: its own slots (padded to 64) and the halo
@@ -144,7 +145,8 @@ struct l2t_ctx {
     int32_t *cnt = nullptr;      // internal [n_int]
     l2t::SliceInfo *slices = nullptr;
     int32_t *col = nullptr;
-    uint16_t *col16 = nullptr;   // same layout as col, brick-local indices
+    uint32_t *colw = nullptr;    // brick-local table: two LDS byte offsets per word
+    int64_t colw_len = 0;
     int32_t *pos_slot = nullptr; // caller layout [n_tot]: cell-order position -> slot
     l2t::BrickInfo *bricks = nullptr;
     int32_t *brick_list = nullptr;   // non-empty bricks

@@ -182,6 +182,45 @@ struct LedgerTerms {
     float e2l, src, lt;
 };
 
+__device__ __forceinline__ void kahan_add(float &S, float &comp, float f) {
+    const float y = f - comp;
+    const float t = S + y;
+    comp = (t - S) - y;
+    S = t;
+}
+
+// coupling, source, compensated update and range check of one lane, given
+// the neighbour sum S = span * sum_j f(theta_i, theta_j)
+__device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t slot, bool valid,
+                                                    float Ti, float S, float lo, float tl,
+                                                    float sw, float *__restrict__ Thi_n,
+                                                    float *__restrict__ Tlo, int64_t step,
+                                                    unsigned *err) {
+    float hi_new = Ti;
+    LedgerTerms r{0.0f, 0.0f, 0.0f};
+    if (valid) {
+        const float c = ce32(p, Ti);
+        const float invc = 1.0f / c;
+        const float coup = signbit(tl) ? 0.0f : p.f_g * (Ti - tl);
+        float q = 0.0f;
+        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * sw;
+        const float loc = (q - coup) * invc;
+        const float dT = p.f_dt * fmaf(p.f_K, S, loc);
+        // (hi, lo) + dT without rounding error: TwoSum then renormalise
+        const float s = Ti + dT;
+        const float bp = s - Ti;
+        const float er = (Ti - (s - bp)) + (dT - bp);
+        const float lo2 = lo + er;
+        hi_new = s + lo2;
+        const float lo_new = lo2 - (hi_new - s);
+        Tlo[slot] = lo_new;
+        r = LedgerTerms{coup, q, -loc};
+        if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
+    }
+    Thi_n[slot] = hi_new;
+    return r;
+}
+
 template <class IdxAt, class ValOf>
 __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int32_t sl, int lane,
                                                         const DevParams &p, float Ti, float lo,
@@ -206,41 +245,60 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
 #pragma unroll
         for (int u = 0; u < C; ++u) Tj[u] = (k0 + u < w) ? val_of(cur[u]) : Ti;
 #pragma unroll
-        for (int u = 0; u < C; ++u) {
-            if (k0 + u < w) {
-                const float f = pair32(Ti, Tj[u], pk);
-                const float y = f - comp;
-                const float t = S + y;
-                comp = (t - S) - y;
-                S = t;
-            }
-        }
+        for (int u = 0; u < C; ++u)
+            if (k0 + u < w) kahan_add(S, comp, pair32(Ti, Tj[u], pk));
 #pragma unroll
         for (int u = 0; u < C; ++u) cur[u] = nxt[u];
     }
-    float hi_new = Ti;
-    LedgerTerms r{0.0f, 0.0f, 0.0f};
-    if (valid) {
-        const float c = ce32(p, Ti);
-        const float invc = 1.0f / c;
-        const float coup = signbit(tl) ? 0.0f : p.f_g * (Ti - tl);
-        float q = 0.0f;
-        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * sw;
-        const float loc = (q - coup) * invc;
-        const float dT = p.f_dt * fmaf(p.f_K, S, loc);
-        // (hi, lo) + dT without rounding error: TwoSum then renormalise
-        const float s = Ti + dT;
-        const float bp = s - Ti;
-        const float er = (Ti - (s - bp)) + (dT - bp);
-        const float lo2 = lo + er;
-        hi_new = s + lo2;
-        const float lo_new = lo2 - (hi_new - s);
-        Tlo[slot] = lo_new;
-        r = LedgerTerms{coup, q, -loc};
-        if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
+    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, step, err);
+}
+
+// LDS-tile form: the row is read as packed pairs of LDS byte offsets, two
+// chunks of 8 neighbours ahead of their use.  Same terms in the same order
+// as slice_core_fp32c.
+__device__ __forceinline__ LedgerTerms slice_core_brick(const SliceInfo &si, int32_t sl, int lane,
+                                                        const DevParams &p, float Ti, float lo,
+                                                        float tl, float sw,
+                                                        const uint32_t *__restrict__ cw,
+                                                        const float *tile,
+                                                        float *__restrict__ Thi_n,
+                                                        float *__restrict__ Tlo, int64_t step,
+                                                        unsigned *err) {
+    const int32_t slot = sl * kWave + lane;
+    const bool valid = lane < si.n_valid;
+    const PairK pk = pair_consts(p);
+    const char *tb = reinterpret_cast<const char *>(tile);
+    float S = 0.0f, comp = 0.0f;
+    const int32_t w = si.width;
+    const int32_t nwd = (w + 1) >> 1;
+    uint32_t c0[4], c1[4], c2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        c0[u] = (u < nwd) ? cw[u * kWave] : 0u;
+        c1[u] = (4 + u < nwd) ? cw[(4 + u) * kWave] : 0u;
     }
-    Thi_n[slot] = hi_new;
-    return r;
+    for (int32_t k0 = 0; k0 < w; k0 += 8) {
+        const int32_t w0 = k0 >> 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c2[u] = (w0 + 8 + u < nwd) ? cw[(w0 + 8 + u) * kWave] : 0u;
+        float Tj[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            Tj[2 * u] = (k0 + 2 * u < w)
+                            ? *reinterpret_cast<const float *>(tb + (c0[u] & 0xffffu)) : Ti;
+            Tj[2 * u + 1] = (k0 + 2 * u + 1 < w)
+                                ? *reinterpret_cast<const float *>(tb + (c0[u] >> 16)) : Ti;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u < w) kahan_add(S, comp, pair32(Ti, Tj[u], pk));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c0[u] = c1[u];
+            c1[u] = c2[u];
+        }
+    }
+    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, step, err);
 }
 
 // wave sums of the ledger terms, added in FP64 to a per-slice accumulator
