@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto")
     ap.add_argument("--brick-edge", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0,
+                    help="threads per workgroup of the sub-step kernel (0 = autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -177,6 +179,8 @@ def main():
         L.l2t_set_option(h, L.L2T_OPT_BRICK_EDGE, args.brick_edge)
     if args.kernel != "auto":
         L.l2t_set_option(h, L.L2T_OPT_KERNEL, 1 if args.kernel == "brick" else 0)
+    if args.block:
+        L.l2t_set_option(h, L.L2T_OPT_BLOCK, args.block)
     d = setup_system(L, h, sy, dev)
     torch.cuda.synchronize()
     timer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

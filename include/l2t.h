@@ -65,7 +65,7 @@ extern "C" {
 
 /* ---- precision of the sub-step path ---------------------------------------- */
 #define L2T_FP64   0   /* plain: literal Eq. 2 pair term in FP64, one launch per sub-step per system */
-#define L2T_FP32C  1   /* FP32 fluxes, Kahan-compensated sums, compensated (hi+lo) state */
+#define L2T_FP32C  1   /* FP32 pair terms, FP64 neighbour sums, FP32 (hi+lo) state updated in FP64 */
 
 /* ---- memory space of a caller pointer -------------------------------------- */
 #define L2T_HOST    0
@@ -84,7 +84,8 @@ extern "C" {
 
 /* ---- tuning options (l2t_set_option) ---------------------------------------- */
 #define L2T_OPT_PERSISTENT     0   /* FP32C global-gather kernel: 1 = all sub-steps in one persistent launch */
-#define L2T_OPT_BLOCK          1   /* FP32C: threads per workgroup, multiple of 64 (0 = autotune) */
+#define L2T_OPT_BLOCK          1   /* FP32C: threads per workgroup, multiple of 64 up to 512; the
+                                      global-gather kernels use at most 256 (0 = autotune) */
 #define L2T_OPT_RESIDENT_MAX   2   /* FP32C: largest system kept whole in LDS (atoms; 0 = autotune, -1 = never) */
 #define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */

@@ -524,10 +524,10 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             if (value) t.kernel = l2t::kKernelSliced;
             break;
         case L2T_OPT_BLOCK:
-            if (value != 0 && (value < 64 || value > 256 || value % 64))
-                return l2t::fail(c, L2T_EINVAL, "block must be 0 or one of 64, 128, 192, 256");
+            if (value != 0 && (value < 64 || value > l2t::kBrickBlockMax || value % 64))
+                return l2t::fail(c, L2T_EINVAL, "block must be 0 or a multiple of 64 up to 512");
             if (value == 0) {
-                t.block = 256;
+                t.block = l2t::kBrickBlockMax;
                 t.tuned = false;
                 l2t::drop_graphs(c);
                 return L2T_OK;

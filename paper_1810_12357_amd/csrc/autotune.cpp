@@ -128,8 +128,8 @@ int autotune(l2t_ctx *c) {
     // one launch per sub-step; it stays available through L2T_OPT_PERSISTENT
     std::vector<Choice> cand = {{kKernelSliced, 0, 256}, {kKernelSliced, 0, 128}};
     if (c->n_brick_list > 0) {
+        cand.push_back({kKernelBrick, 0, 512});
         cand.push_back({kKernelBrick, 0, 256});
-        cand.push_back({kKernelBrick, 0, 128});
     }
     for (const Choice &ch : cand) {
         float ms_min = 1e30f;

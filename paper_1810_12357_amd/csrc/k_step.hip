@@ -9,11 +9,13 @@
 //
 //  * FP64 plain: literal two-exponential pair term, one launch per sub-step.
 //  * FP32C: cancellation-free product form of the pair term evaluated in
-//    FP32 from the hi part of the neighbour temperatures, Kahan-compensated
-//    per-atom sum, state kept as an unevaluated FP32 pair hi + lo and updated
-//    with an error-free transformation; FP64 only in the ledger reductions.
-//    Either one launch per sub-step, or a persistent launch that runs all
-//    sub-steps with a grid barrier between them.
+//    FP32 from the hi part of the neighbour temperatures, per-atom sum of the
+//    terms in FP64 (one conversion and one FP64 add per term, two vector
+//    instructions where a Kahan step takes four), state kept as an
+//    unevaluated FP32 pair hi + lo whose sum with the increment is formed in
+//    FP64 and split again; ledgers in FP64.  One launch per sub-step (global gathers or LDS brick tiles), or
+//    a persistent launch that runs all sub-steps with a grid barrier between
+//    them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,11 +68,13 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
 // uint16 table.  Workgroup b runs on XCD b mod 8 and takes brick
 // (b mod 8) * (G/8) + b/8, so each XCD sweeps one contiguous range of bricks
 // and its L2 serves the halo loads.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_brick_fp32c(
-    const BrickInfo *bricks, const int32_t *list, int32_t n_list, const SliceInfo *slices,
-    const uint32_t *colw, const int32_t *halo, const float *Thi, float *Thi_n, float *Tlo,
-    const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep, int32_t rel,
-    double *ledger, unsigned *err) {
+__global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(8))) void k_brick_fp32c(
+    const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
+    const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
+    const int32_t *__restrict__ halo, const float *__restrict__ Thi, float *__restrict__ Thi_n,
+    float *__restrict__ Tlo, const float *__restrict__ Tl, const float *__restrict__ srcw,
+    const DevParams *__restrict__ P, const int64_t *__restrict__ dstep, int32_t rel,
+    double *__restrict__ ledger, unsigned *__restrict__ err) {
     extern __shared__ float tile[];
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
@@ -107,30 +111,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             if (t0 + u * B < bi.n_halo) ht[t0 + u * B] = v[u];
     }
     __syncthreads();
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // wave index, slice records and row widths are wave-uniform (scalar registers)
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
     const int32_t ns = bi.n_own_pad / kWave;
     if (wave >= ns) return;
     // every slice of a brick belongs to the brick's system
     const DevParams &p = P[bi.sys];
     const int64_t step = dstep[bi.sys] + rel;
-    LedgerAcc acc;
-    SliceInfo si_next = slices[bi.slice0 + wave];
+    // ledger terms summed per lane over the wave's slices, reduced once per wave
+    // into the row of the wave's first slice (all rows of a system are summed)
+    LedgerTerms acc{0.0f, 0.0f, 0.0f};
     for (int32_t q = wave; q < ns; q += nw) {
         const int32_t sl = bi.slice0 + q;
-        const SliceInfo si = si_next;
-        if (q + nw < ns) si_next = slices[sl + nw];
+        const int32_t w = __builtin_amdgcn_readfirstlane(slices[sl].width);
+        const int32_t nv = __builtin_amdgcn_readfirstlane(slices[sl].n_valid);
+        const int32_t base = __builtin_amdgcn_readfirstlane(slices[sl].colw_base64);
         const int32_t slot = sl * kWave + lane;
         const float lo = Tlo[slot], tl = Tl[slot];
         const float sw = p.laser_on ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
-        const uint32_t *cw = colw + (int64_t)si.colw_base64 * kWave + lane;
-        const LedgerTerms t =
-            slice_core_brick(si, sl, lane, p, Ti, lo, tl, sw, cw, tile, Thi_n, Tlo, step, err);
-        acc.add(t, p.dt);
+        const LedgerTerms t = slice_core_brick(w, slot, lane < nv, p, Ti, lo, tl, sw,
+                                               colw + (int64_t)base * kWave, lane, tile, Thi_n,
+                                               Tlo, step, err);
+        acc.e2l += t.e2l;
+        acc.src += t.src;
+        acc.lt += t.lt;
     }
-    // the ledger is summed per system, so any slice of the brick can hold it
-    acc.flush(ledger, bi.slice0 + wave, lane);
+    ledger_add(ledger, bi.slice0 + wave, lane, acc, p.dt);
 }
 
 // Grid-wide barrier for the persistent kernel.  bar[0] counts arrivals over
@@ -426,12 +435,14 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
             cur ^= 1;
         }
     } else if (persistent) {
+        block = std::min(block, kSlicedBlockMax);
         const int grid = persistent_grid(c, block);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->dbar, 2);
         hipLaunchKernelGGL(k_persistent_fp32c, dim3(grid), dim3(block), 0, c->stream, c->slices,
                            c->n_slices, c->col, c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32,
                            c->srcw32, c->dparams, c->dstep, n, c->ledger, c->derr, c->dbar);
     } else {
+        block = std::min(block, kSlicedBlockMax);
         const int wpb = block / kWave;
         const dim3 g(nblk(c->n_slices, wpb)), b(block);
         for (int32_t k = 0; k < n; ++k) {

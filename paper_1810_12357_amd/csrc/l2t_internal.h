@@ -91,11 +91,13 @@ struct GraphKey {
 
 constexpr int kKernelSliced = 0;   // global gathers through the int32 table
 constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
+constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
+constexpr int kSlicedBlockMax = 256;  // threads per workgroup, global-gather kernels
 
 struct Tuning {
     int kernel = kKernelBrick;
     int persistent = 0;
-    int block = 256;
+    int block = kBrickBlockMax;
     int resident_max = 0;    // 0 = autotune
     int graph = 1;
     int autotune = 1;

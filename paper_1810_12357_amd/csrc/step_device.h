@@ -67,6 +67,10 @@ __device__ inline float pulse32(const DevParams &p, int64_t step) {
 // holds bitwise.
 constexpr float kUTiny = 2.5e-4f;
 
+// third descriptor word of a raw (unswizzled, stride 0) buffer resource on
+// gfx9-family chips: 32-bit data format, range checked against num_records
+constexpr int kBufferRsrcWord3 = 0x00020000;
+
 struct PairK {
     float hinv;     // 0.5 / span
     float moff;     // -T_min / span
@@ -76,7 +80,12 @@ struct PairK {
 };
 
 __device__ __forceinline__ PairK pair_consts(const DevParams &p) {
-    return PairK{p.f_half_inv_span, p.f_m_off, p.f_inv2, p.f_c_tiny, p.f_w_tiny};
+    PairK k{p.f_half_inv_span, p.f_m_off, p.f_inv2, p.f_c_tiny, p.f_w_tiny};
+    // m = (Ti + Tj) * hinv + moff reads two uniform operands; a VALU instruction
+    // reads at most one scalar register, so moff is held in a vector register
+    // (otherwise it is copied into one for every pair term)
+    asm volatile("" : "+v"(k.moff));
+    return k;
 }
 
 __device__ __forceinline__ float pair32(float Ti, float Tj, const PairK &k) {
@@ -182,17 +191,12 @@ struct LedgerTerms {
     float e2l, src, lt;
 };
 
-__device__ __forceinline__ void kahan_add(float &S, float &comp, float f) {
-    const float y = f - comp;
-    const float t = S + y;
-    comp = (t - S) - y;
-    S = t;
-}
-
-// coupling, source, compensated update and range check of one lane, given
-// the neighbour sum S = span * sum_j f(theta_i, theta_j)
+// coupling, source and state update of one lane, given the neighbour sum
+// S = span * sum_j f(theta_i, theta_j) accumulated in FP64.  The state is the
+// FP32 pair (hi, lo) with T = hi + lo exact in FP64: the increment is added in
+// FP64 and the sum split back into a rounded hi and its remainder lo.
 __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t slot, bool valid,
-                                                    float Ti, float S, float lo, float tl,
+                                                    float Ti, double S, float lo, float tl,
                                                     float sw, float *__restrict__ Thi_n,
                                                     float *__restrict__ Tlo, int64_t step,
                                                     unsigned *err) {
@@ -205,15 +209,9 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
         float q = 0.0f;
         if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * sw;
         const float loc = (q - coup) * invc;
-        const float dT = p.f_dt * fmaf(p.f_K, S, loc);
-        // (hi, lo) + dT without rounding error: TwoSum then renormalise
-        const float s = Ti + dT;
-        const float bp = s - Ti;
-        const float er = (Ti - (s - bp)) + (dT - bp);
-        const float lo2 = lo + er;
-        hi_new = s + lo2;
-        const float lo_new = lo2 - (hi_new - s);
-        Tlo[slot] = lo_new;
+        const double T = ((double)Ti + (double)lo) + p.dt * (p.K * S + (double)loc);
+        hi_new = (float)T;
+        Tlo[slot] = (float)(T - (double)hi_new);
         r = LedgerTerms{coup, q, -loc};
         if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
     }
@@ -233,7 +231,7 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
     const PairK pk = pair_consts(p);
-    float S = 0.0f, comp = 0.0f;   // span * sum_j f(theta_i, theta_j), Kahan-compensated
+    double S = 0.0;   // span * sum_j f(theta_i, theta_j), in row order
     const int32_t w = si.width;
     Ref cur[C], nxt[C];
 #pragma unroll
@@ -246,77 +244,107 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
         for (int u = 0; u < C; ++u) Tj[u] = (k0 + u < w) ? val_of(cur[u]) : Ti;
 #pragma unroll
         for (int u = 0; u < C; ++u)
-            if (k0 + u < w) kahan_add(S, comp, pair32(Ti, Tj[u], pk));
+            if (k0 + u < w) S += (double)pair32(Ti, Tj[u], pk);
 #pragma unroll
         for (int u = 0; u < C; ++u) cur[u] = nxt[u];
     }
     return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, step, err);
 }
 
-// LDS-tile form: the row is read as packed pairs of LDS byte offsets, two
-// chunks of 8 neighbours ahead of their use.  Same terms in the same order
-// as slice_core_fp32c.
-__device__ __forceinline__ LedgerTerms slice_core_brick(const SliceInfo &si, int32_t sl, int lane,
+// LDS-tile form for one slice.  w is the slice's row width and row the first
+// word of its packed table (both wave-uniform).  Each word holds the LDS byte
+// offsets of two neighbours; a chunk is 4 words = 8 neighbours.  The words of
+// chunk c + 2 are requested once those of chunk c have been turned into LDS
+// reads, alternating between two buffers.  Same terms in the same order as
+// slice_core_fp32c.
+__device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot, bool valid,
                                                         const DevParams &p, float Ti, float lo,
                                                         float tl, float sw,
-                                                        const uint32_t *__restrict__ cw,
-                                                        const float *tile,
+                                                        const uint32_t *__restrict__ row,
+                                                        int lane, const float *tile,
                                                         float *__restrict__ Thi_n,
                                                         float *__restrict__ Tlo, int64_t step,
                                                         unsigned *err) {
-    const int32_t slot = sl * kWave + lane;
-    const bool valid = lane < si.n_valid;
     const PairK pk = pair_consts(p);
     const char *tb = reinterpret_cast<const char *>(tile);
-    float S = 0.0f, comp = 0.0f;
-    const int32_t w = si.width;
     const int32_t nwd = (w + 1) >> 1;
-    uint32_t c0[4], c1[4], c2[4];
+    const int32_t nch = (w + 7) >> 3;
+    double S = 0.0;
+    // The row is read through a buffer resource spanning exactly its nwd word
+    // rows: the lane offset is a constant vector register and the word row a
+    // scalar offset, so no vector instruction goes into addressing.  Word
+    // indices past the row's end are clamped to its last word (a re-read of a
+    // line just fetched), so every load is unconditional and inside the row.
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(row), 0, nwd * kWave * (int)sizeof(uint32_t), kBufferRsrcWord3);
+    const int32_t lane_off = lane * (int)sizeof(uint32_t);
+    auto load = [&](int32_t c, uint32_t (&d)[4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        c0[u] = (u < nwd) ? cw[u * kWave] : 0u;
-        c1[u] = (4 + u < nwd) ? cw[(4 + u) * kWave] : 0u;
-    }
-    for (int32_t k0 = 0; k0 < w; k0 += 8) {
-        const int32_t w0 = k0 >> 1;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) c2[u] = (w0 + 8 + u < nwd) ? cw[(w0 + 8 + u) * kWave] : 0u;
+        for (int u = 0; u < 4; ++u) {
+            const int32_t wi = min(4 * c + u, nwd - 1);
+            d[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_off,
+                                                        wi * kWave * (int)sizeof(uint32_t), 0);
+        }
+    };
+    auto at = [&](uint32_t off) { return *reinterpret_cast<const float *>(tb + off); };
+    // LDS reads of chunk c (the offsets are consumed here), then the next request
+    // into the same buffer, then the 8 pair terms
+    auto chunk = [&](int32_t c, uint32_t (&d)[4]) {
         float Tj[8];
+        const bool full = 8 * c + 8 <= w;
+        if (full) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            Tj[2 * u] = (k0 + 2 * u < w)
-                            ? *reinterpret_cast<const float *>(tb + (c0[u] & 0xffffu)) : Ti;
-            Tj[2 * u + 1] = (k0 + 2 * u + 1 < w)
-                                ? *reinterpret_cast<const float *>(tb + (c0[u] >> 16)) : Ti;
+            for (int u = 0; u < 4; ++u) {
+                Tj[2 * u] = at(d[u] & 0xffffu);
+                Tj[2 * u + 1] = at(d[u] >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                Tj[2 * u] = (8 * c + 2 * u < w) ? at(d[u] & 0xffffu) : Ti;
+                Tj[2 * u + 1] = (8 * c + 2 * u + 1 < w) ? at(d[u] >> 16) : Ti;
+            }
         }
+        load(c + 2, d);
+        if (full) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (k0 + u < w) kahan_add(S, comp, pair32(Ti, Tj[u], pk));
+            for (int u = 0; u < 8; ++u) S += (double)pair32(Ti, Tj[u], pk);
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c0[u] = c1[u];
-            c1[u] = c2[u];
+            for (int u = 0; u < 8; ++u)
+                if (8 * c + u < w) S += (double)pair32(Ti, Tj[u], pk);
         }
+    };
+    if (nch > 0) {
+        uint32_t A[4], B[4];
+        load(0, A);
+        load(1, B);
+        const int32_t n2 = nch >> 1;
+        for (int32_t c = 0; c < 2 * n2; c += 2) {
+            chunk(c, A);
+            chunk(c + 1, B);
+        }
+        if (nch & 1) chunk(nch - 1, A);
     }
     return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, step, err);
 }
 
-// wave sums of the ledger terms, added in FP64 to a per-slice accumulator
-struct LedgerAcc {
-    double e2l = 0.0, src = 0.0, lt = 0.0;
-    __device__ __forceinline__ void add(const LedgerTerms &t, double dt) {
-        e2l += (double)wave_sum_f32(t.e2l) * dt;
-        src += (double)wave_sum_f32(t.src) * dt;
-        lt += (double)wave_sum_f32(t.lt) * dt;
+// wave sums of ledger terms, added in FP64 to one ledger row.  A row is
+// updated by one wave per sub-step and the sub-steps are ordered launches, so
+// the additions happen in a fixed order; the FP64 atomic only spares the wave
+// the wait for the old value.
+__device__ __forceinline__ void ledger_add(double *__restrict__ ledger, int32_t row_id, int lane,
+                                           const LedgerTerms &t, double dt) {
+    const double e2l = (double)wave_sum_f32(t.e2l) * dt;
+    const double src = (double)wave_sum_f32(t.src) * dt;
+    const double lt = (double)wave_sum_f32(t.lt) * dt;
+    if (lane == 0) {
+        double *row = ledger + 3 * (int64_t)row_id;
+        unsafeAtomicAdd(row + 0, e2l);
+        unsafeAtomicAdd(row + 1, src);
+        unsafeAtomicAdd(row + 2, lt);
     }
-    __device__ __forceinline__ void flush(double *ledger, int32_t sl, int lane) const {
-        if (lane == 0) {
-            ledger[3 * (int64_t)sl + 0] += e2l;
-            ledger[3 * (int64_t)sl + 1] += src;
-            ledger[3 * (int64_t)sl + 2] += lt;
-        }
-    }
-};
+}
 
 // global-gather form over the int32 table (one slice)
 __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl, int lane,
@@ -336,9 +364,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
     const LedgerTerms t = slice_core_fp32c(
         si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
         [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, step, err);
-    LedgerAcc acc;
-    acc.add(t, p.dt);
-    acc.flush(ledger, sl, lane);
+    ledger_add(ledger, sl, lane, t, p.dt);
 }
 
 }  // namespace dev
