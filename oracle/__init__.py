@@ -12,7 +12,10 @@ Function map (paper passages):
                      (remark after Eq. 8)
   pair               the pair term of Eq. 2, literal two-exponential form
   run                forward-Euler sub-steps of Eq. 2 with coupling and Eq. 10
-                     source (Section 2.1), ledgers of Eq. 6
+                     source (Section 2.1), ledgers of Eq. 6 (per system and,
+                     optionally, per atom)
+  coupling           Eq. 8 coupling coefficient of the damping force
+  damping_step       one explicit velocity step of Eq. 5
   energies           sum of the per-atom electronic energy and of T
   adjoint            discrete adjoint of ``run`` (derived from Eq. 2)
   run_cs             complex-step forward run (directional derivatives)
@@ -75,7 +78,9 @@ def _load():
         lib.or_neighbors.argtypes = [i32, pd, pd, pd, pd, pd, pi32, d, i32, pi64, pi32, i64]
         lib.or_lattice_temp.argtypes = [i32, pi64, pi32, pd, pd, pd, pd, d, i32, pd, pi32]
         lib.or_run.restype = i64
-        lib.or_run.argtypes = [i32, pi64, pi32, pd, pd, pi32, pd, P(Params), i64, i32, pd]
+        lib.or_run.argtypes = [i32, pi64, pi32, pd, pd, pi32, pd, P(Params), i64, i32, pd, pd]
+        lib.or_coupling.argtypes = [i32, i32, pd, pd, pi32, pd, d, d, d, pd, pd, pd, pd, pd]
+        lib.or_damping_step.argtypes = [i32, d, pd, pd, pd, pd, pd, pd, pd, pd]
         lib.or_energies.argtypes = [i32, pd, P(Params), pd]
         lib.or_adjoint.restype = C.c_int
         lib.or_adjoint.argtypes = [i32, pi64, pi32, pd, pd, pi32, pd, P(Params), i64, i32,
@@ -166,24 +171,70 @@ def _opt(a, dtype, n):
 
 
 def run(row, col, T, T_lat, params: dict, n_steps: int, step0: int = 0, gated=None,
-        x=None, ledger=None):
+        x=None, ledger=None, e_atom=None):
     """Forward-Euler sub-steps.  Returns (T_new, ledger[3], n_out_of_range).
 
     ledger = [energy to lattice (eV), source energy (eV), temperature ledger (K)],
-    accumulated onto the ``ledger`` argument when given."""
+    accumulated onto the ``ledger`` argument when given.  ``e_atom`` (float64
+    array [n], optional) accumulates in place each atom's energy to the
+    lattice, sum over sub-steps of g (T_i - T_lat,i) dt (Eq. 6)."""
     T = _f64(T).copy()
     n = T.size
     Tl = _f64(T_lat)
     g, gp = _opt(gated, np.int32, n)
     xx, xp = _opt(x, np.float64, n)
     led = np.zeros(3) if ledger is None else _f64(ledger).copy()
+    if e_atom is not None:
+        assert e_atom.dtype == np.float64 and e_atom.shape == (n,) and e_atom.flags.c_contiguous
     pp = make_params(params)
     bad = _load().or_run(n, _p(row, C.c_int64), _p(col, C.c_int32), _p(T, C.c_double),
                          _p(Tl, C.c_double), gp, xp, C.byref(pp), int(step0), int(n_steps),
-                         _p(led, C.c_double))
+                         _p(led, C.c_double), None if e_atom is None else _p(e_atom, C.c_double))
     if bad < 0:
         raise MemoryError("oracle run allocation failed")
     return T, led, int(bad)
+
+
+XI_INSTANT, XI_LEDGER = 0, 1
+
+
+def coupling(mode, T, T_lat, gated, e_atom, g, dt_md, ke_eps, vel, mass):
+    """Eq. 8 coupling coefficient xi_i = P_i / (2 K_i), K_i = 1/2 m_i |v_i|^2:
+    P_i = g (T_i - T_lat,i) (mode XI_INSTANT) or e_atom_i / dt_md (XI_LEDGER);
+    0 where gated or K_i < ke_eps.  vel is (3, n) A/fs, mass amu."""
+    T = _f64(T)
+    n = T.size
+    Tl = _f64(T_lat)
+    g_, gp = _opt(gated, np.int32, n)
+    e = _f64(e_atom if e_atom is not None else np.zeros(n))
+    vel = _f64(vel)
+    vx, vy, vz = (np.ascontiguousarray(vel[d]) for d in range(3))
+    m = _f64(mass)
+    xi = np.empty(n)
+    _load().or_coupling(n, int(mode), _p(T, C.c_double), _p(Tl, C.c_double), gp,
+                        _p(e, C.c_double), float(g), float(dt_md), float(ke_eps),
+                        _p(vx, C.c_double), _p(vy, C.c_double), _p(vz, C.c_double),
+                        _p(m, C.c_double), _p(xi, C.c_double))
+    return xi
+
+
+def damping_step(dt_md, xi, force, mass, vel):
+    """One explicit step of Eq. 5: v + dt_md (F/m + xi v).  force (3, n) eV/A or
+    None; returns the new (3, n) velocities."""
+    xi = _f64(xi)
+    n = xi.size
+    m = _f64(mass)
+    v = np.array(_f64(vel), copy=True)
+    vx, vy, vz = (np.ascontiguousarray(v[d]) for d in range(3))
+    if force is None:
+        fx = fy = fz = None
+    else:
+        force = _f64(force)
+        fx, fy, fz = (np.ascontiguousarray(force[d]) for d in range(3))
+    fp = [None if a is None else _p(a, C.c_double) for a in (fx, fy, fz)]
+    _load().or_damping_step(n, float(dt_md), _p(xi, C.c_double), *fp, _p(m, C.c_double),
+                            _p(vx, C.c_double), _p(vy, C.c_double), _p(vz, C.c_double))
+    return np.stack([vx, vy, vz])
 
 
 def energies(T, params: dict):

@@ -20,7 +20,10 @@
  *     sub-steps (Section 2.1), every read taken from the step-n state;
  *   - the laser source of Eq. 10 as an energy rate per atom divided by the
  *     atom's heat capacity;
- *   - the energy and temperature ledgers (Eq. 6 rate integrated per step);
+ *   - the energy and temperature ledgers (Eq. 6 rate integrated per step),
+ *     per system and optionally per atom;
+ *   - the lattice side: the coupling coefficient of Eq. 8 and one explicit
+ *     velocity step of the damped equation of motion Eq. 5;
  *   - the discrete adjoint of the forward-Euler map (derived from Eq. 2) and
  *     a complex-step forward run for directional derivatives.
  *
@@ -381,12 +384,16 @@ static int64_t or_count_out_of_range(int32_t n, const double *T, const or_params
  * Advance n_steps sub-steps from step index step0 (t_n = n dt).  T is
  * updated in place.  ledger[0..2] accumulate sum g(T-T_lat) dt (energy to
  * the lattice, eV), sum q dt (source energy, eV) and
- * sum dt (g(T-T_lat) - q)/c (temperature ledger, K).  Returns the number of
- * (atom, step) states with theta outside [0,1] or non-finite.
+ * sum dt (g(T-T_lat) - q)/c (temperature ledger, K).  When e_atom is not
+ * NULL, e_atom[i] accumulates atom i's own share of ledger[0], the energy it
+ * handed to the lattice (Eq. 6 rate times dt, summed over the sub-steps).
+ * Returns the number of (atom, step) states with theta outside [0,1] or
+ * non-finite.
  */
 int64_t or_run(int32_t n, const int64_t *row_ptr, const int32_t *col, double *T,
                const double *T_lat, const int32_t *gated, const double *x,
-               const or_params *p, int64_t step0, int32_t n_steps, double *ledger)
+               const or_params *p, int64_t step0, int32_t n_steps, double *ledger,
+               double *e_atom)
 {
     size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *Tn = malloc(sz), *e2l = malloc(sz), *src = malloc(sz), *ic = malloc(sz);
@@ -404,11 +411,57 @@ int64_t or_run(int32_t n, const int64_t *row_ptr, const int32_t *col, double *T,
         ledger[0] += a;
         ledger[1] += b;
         ledger[2] += c;
+        if (e_atom)
+            for (int32_t i = 0; i < n; ++i) e_atom[i] += e2l[i] * p->dt;
         memcpy(T, Tn, sz);
         bad += or_count_out_of_range(n, T, p);
     }
     free(Tn); free(e2l); free(src); free(ic);
     return bad;
+}
+
+/* ---- lattice side: Eq. 8 coupling coefficient, Eq. 5 velocity step --------
+ * The damping force xi_i m_i v_i of Eq. 5 does work 2 xi_i K_i per unit time
+ * (Eq. 7) with K_i = 1/2 m_i |v_i|^2; Eq. 8 sets it equal to the rate P_i at
+ * which atom i's electrons hand energy to the lattice (Eq. 6):
+ *   xi_i = P_i / (2 K_i).
+ * mode 0: P_i = g (T_i - T_lat,i) at the current electronic temperature
+ *         (Section 2.1: T_e is updated first, then xi);
+ * mode 1: P_i = E_i / dt_md, the energy the atom handed over during the
+ *         sub-steps of the last MD step (e_atom of or_run) spread over that
+ *         step, so the work of the damping force over the step matches the
+ *         electronic ledger.
+ * xi_i = 0 where the kinetic-energy gate holds (remark after Eq. 8) or where
+ * K_i < ke_eps.  Units: P eV/fs, K eV, xi 1/fs. */
+void or_coupling(int32_t n, int32_t mode, const double *T, const double *T_lat,
+                 const int32_t *gated, const double *e_atom, double g, double dt_md,
+                 double ke_eps, const double *vx, const double *vy, const double *vz,
+                 const double *mass, double *xi)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double Ki = 0.5 * mass[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) * OR_MVV2E;
+        double P = (mode == 0) ? g * (T[i] - T_lat[i]) : e_atom[i] / dt_md;
+        xi[i] = ((gated && gated[i]) || !(Ki >= ke_eps)) ? 0.0 : P / (2.0 * Ki);
+    }
+}
+
+/* One explicit step of Eq. 5 for the velocities over the MD step dt_md:
+ *   v_i <- v_i + dt_md (F_i / m_i + xi_i v_i)
+ * F in eV/A (NULL components: no interatomic force), m in amu, v in A/fs;
+ * F/m is converted to A/fs^2 by 1 amu A^2/fs^2 = OR_MVV2E eV. */
+void or_damping_step(int32_t n, double dt_md, const double *xi, const double *fx,
+                     const double *fy, const double *fz, const double *mass, double *vx,
+                     double *vy, double *vz)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double inv_m = 1.0 / (mass[i] * OR_MVV2E);
+        double ax = (fx ? fx[i] * inv_m : 0.0) + xi[i] * vx[i];
+        double ay = (fy ? fy[i] * inv_m : 0.0) + xi[i] * vy[i];
+        double az = (fz ? fz[i] * inv_m : 0.0) + xi[i] * vz[i];
+        vx[i] = vx[i] + dt_md * ax;
+        vy[i] = vy[i] + dt_md * ay;
+        vz[i] = vz[i] + dt_md * az;
+    }
 }
 
 /* out[0] = sum_i E(T_i) (integral of c from 0), out[1] = sum_i T_i */

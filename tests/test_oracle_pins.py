@@ -410,3 +410,131 @@ def test_paper_constants_give_per_atom_values():
     assert lat == pytest.approx(12 * a * a, rel=1e-12)
     K = 2 * c["kappa_e_W_per_mK"]["value"] * c["d_md"]["value"] / (c["Ce_J_per_m3K"]["value"] * lat)
     assert K * 1e-15 == pytest.approx(W.K_NI, rel=1e-4)
+
+
+# ------------------------------------------------- lattice side: Eq. 5, Eq. 8 ----
+MVV2E = W.AMU_A2_PER_FS2_IN_EV
+
+
+def _kinetic(vel, mass):
+    """1/2 m |v|^2 per atom in eV (vel (3, n) A/fs, mass amu)."""
+    return 0.5 * mass * (vel * vel).sum(axis=0) * MVV2E
+
+
+def _isolated_atoms(n=300, seed=11):
+    """Atoms farther apart than the cut-off: no exchange, pure relaxation."""
+    rng = np.random.default_rng(seed)
+    T0 = rng.uniform(500.0, 8000.0, n)
+    Tl = rng.uniform(100.0, 3000.0, n)
+    gated = (rng.uniform(0, 1, n) < 0.15).astype(np.int32)
+    row = np.zeros(n + 1, np.int64)
+    col = np.zeros(0, np.int32)
+    return row, col, T0, Tl, gated
+
+
+def test_atom_ledger_isolated_atoms_closed_form():
+    row, col, T0, Tl, gated = _isolated_atoms()
+    g, c, n = 3e-4, 0.05, 700
+    p = W.default_params(g=g, ce_model=W.CE_CONST, ce_const=c)
+    e = np.zeros(T0.size)
+    T, led, bad = oracle.run(row, col, T0, Tl, p, n, gated=gated, e_atom=e)
+    assert bad == 0
+    # T_i^n = T_l + (T_0 - T_l)(1 - a)^n with a = dt g / c; the energy handed
+    # over is the heat-capacity drop c (T_0 - T^n); gated atoms keep T_0
+    decay = (1.0 - p["dt"] * g / c) ** n
+    free = gated == 0
+    np.testing.assert_allclose(e[free], c * (T0 - Tl)[free] * (1.0 - decay), rtol=1e-11)
+    assert np.all(e[~free] == 0.0) and np.array_equal(T[~free], T0[~free])
+    assert led[0] == pytest.approx(e.sum(), rel=1e-12)
+
+
+def test_xi_ledger_mode_one_substep_is_eq8_before_the_step():
+    # after one sub-step the recorded energy is g (T_0 - T_l) dt, so the
+    # ledger form over dt_md = dt equals Eq. 8 evaluated on the state T_0
+    row, col, T0, Tl, gated = _isolated_atoms(seed=12)
+    p = W.default_params(g=2e-4, ce_model=W.CE_LINEAR, gamma=1e-4)
+    mass = np.full(T0.size, W.MASS_NI)
+    vel = W.maxwell_velocities(T0.size, 600.0, mass, seed=13)
+    vel[:, :5] *= 1e-4                         # kinetic energy below epsilon
+    e = np.zeros(T0.size)
+    oracle.run(row, col, T0, Tl, p, 1, gated=gated, e_atom=e)
+    xl = oracle.coupling(oracle.XI_LEDGER, T0, Tl, gated, e, p["g"], p["dt"], p["ke_eps"], vel, mass)
+    xi = oracle.coupling(oracle.XI_INSTANT, T0, Tl, gated, None, p["g"], p["dt"], p["ke_eps"], vel,
+                         mass)
+    np.testing.assert_allclose(xl, xi, rtol=1e-13, atol=0)
+    K = _kinetic(vel, mass)
+    off = (gated == 1) | (K < p["ke_eps"])
+    assert off[:5].all() and np.all(xi[off] == 0.0) and np.all(xi[~off] != 0.0)
+    # heating where T_e > T_l, cooling where T_e < T_l
+    assert np.array_equal(np.sign(xi[~off]), np.sign((T0 - Tl)[~off]))
+
+
+def _coupled_md_step():
+    w = W.c3(n_cells=5, n_substeps=1)
+    s = w.systems[0]
+    row, col = _nbrs(s, w.r_cut)
+    p = dict(s.params, g=4e-5, ce_model=W.CE_CONST, ce_const=W.C_NI * 40)
+    Tl, gated = oracle.lattice_temperature(row, col, s.vel, s.mass, p["ke_eps"])
+    return s, row, col, p, Tl, gated
+
+
+def test_damping_work_matches_atom_ledger_exactly():
+    # one explicit step v' = v (1 + xi dt_md) without forces changes the
+    # kinetic energy by K ((1 + xi dt_md)^2 - 1) = 2 xi K dt_md + (xi dt_md)^2 K,
+    # which with xi = E / (2 K dt_md) is E + E^2 / (4 K): the energy the atom's
+    # electrons handed over, plus a second-order remainder
+    s, row, col, p, Tl, gated = _coupled_md_step()
+    n_sub = 10
+    dt_md = n_sub * p["dt"]
+    e = np.zeros(s.n)
+    T, led, bad = oracle.run(row, col, s.T_e0, Tl, p, n_sub, gated=gated, e_atom=e)
+    assert bad == 0
+    xi = oracle.coupling(oracle.XI_LEDGER, T, Tl, gated, e, p["g"], dt_md, p["ke_eps"], s.vel,
+                         s.mass)
+    v1 = oracle.damping_step(dt_md, xi, None, s.mass, s.vel)
+    K0, K1 = _kinetic(s.vel, s.mass), _kinetic(v1, s.mass)
+    on = xi != 0.0
+    assert on.sum() > 0.9 * s.n
+    np.testing.assert_allclose((K1 - K0)[on], (e + e * e / (4.0 * K0))[on], rtol=1e-9)
+    assert np.array_equal(v1[:, ~on], s.vel[:, ~on])
+    assert np.all(e[~on] == 0.0)
+
+
+def test_md_step_energy_balance_second_order_remainder():
+    # constant uniform c, no source: the exchange conserves sum T, so the
+    # electrons lose exactly sum_i E_i; the damped lattice gains
+    # sum_i E_i + E_i^2 / (4 K_i).  The total changes by the remainder only.
+    s, row, col, p, Tl, gated = _coupled_md_step()
+    p = dict(p, g=4e-6)                    # xi dt_md well below 1: a small remainder
+    n_sub = 20
+    dt_md = n_sub * p["dt"]
+    E0, _ = oracle.energies(s.T_e0, p)
+    e = np.zeros(s.n)
+    T, led, _ = oracle.run(row, col, s.T_e0, Tl, p, n_sub, gated=gated, e_atom=e)
+    E1, _ = oracle.energies(T, p)
+    xi = oracle.coupling(oracle.XI_LEDGER, T, Tl, gated, e, p["g"], dt_md, p["ke_eps"], s.vel,
+                         s.mass)
+    v1 = oracle.damping_step(dt_md, xi, None, s.mass, s.vel)
+    K0 = _kinetic(s.vel, s.mass)
+    dKE = _kinetic(v1, s.mass).sum() - K0.sum()
+    rem = np.where(xi != 0.0, e * e / (4.0 * K0), 0.0).sum()
+    assert (E1 - E0) == pytest.approx(-e.sum(), rel=1e-10)
+    assert (E1 - E0) + dKE == pytest.approx(rem, rel=1e-6, abs=1e-12 * abs(E1 - E0))
+    assert 0.0 < rem < 5e-2 * abs(E1 - E0)
+
+
+def test_damping_step_force_obeys_newton_in_md_units():
+    # without damping, the momentum change over dt_md is dt_md * sum F in
+    # amu A/fs, with F in eV/A converted by 1 amu A^2/fs^2 = 103.6427 eV
+    rng = np.random.default_rng(21)
+    n = 500
+    mass = rng.uniform(20.0, 200.0, n)
+    vel = rng.normal(0.0, 0.01, (3, n))
+    force = rng.normal(0.0, 0.5, (3, n))
+    dt = 0.7
+    v1 = oracle.damping_step(dt, np.zeros(n), force, mass, vel)
+    dp = ((v1 - vel) * mass[None, :]).sum(axis=1)
+    np.testing.assert_allclose(dp, dt * force.sum(axis=1) / MVV2E, rtol=1e-12)
+    # a uniform xi scales every velocity by (1 + xi dt) and leaves directions
+    v2 = oracle.damping_step(dt, np.full(n, 0.05), None, mass, vel)
+    np.testing.assert_allclose(v2, vel * (1.0 + 0.05 * dt), rtol=1e-15)
