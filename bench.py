@@ -3,16 +3,21 @@
 One step = one pass of the whole path over the 4,000,000-atom jittered FCC
 system (100^3 cells, cut-off 1.2a): cell binning and neighbour sets, the
 Eq. 4 lattice temperature from velocities with the kinetic-energy gate,
-parameters, T_e, 10,000 FP32C sub-steps of Eq. 2 in the tuned (persistent,
-hipGraph-captured) launch, and the FP64 energy ledger.  Inputs are resident in
-HBM before the timed region starts.
+parameters, T_e, 10,000 FP32C sub-steps of Eq. 2 in the tuned launch (one
+LDS-brick launch per sub-step, the sub-steps of an advance captured in one
+hipGraph), and the FP64 energy ledger.  Inputs are resident in HBM before the
+timed region starts.
 
 Also reported:
   * roofline of the dominant kernel (the FP32C sub-step launch), from HIP events
     on the library's stream, against 8 TB/s HBM, with the algorithmic bytes
-    24 + 4 n_mean per atom-substep;
+    24 + 2 n_mean (brick form) or 24 + 4 n_mean (global gathers) per
+    atom-substep, and the HBM traffic rocprofv3 measured for it;
   * the batched FP32C form vs the plain FP64 form on the 256-system laser batch
     (same sub-step count for both);
+  * the lattice side on the same system: sub-step cost with the per-atom energy
+    record off and on, the Eq. 8 coupling coefficient and one Eq. 5 velocity
+    step, against HBM bandwidth;
   * the FP64 CPU oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -120,6 +125,51 @@ def bench_c4_speedup(L, torch, n_sub):
                 speedup=out["fp32c_batched"] / out["fp64_plain"])
 
 
+def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):
+    """Lattice side on the same system: one MD step of n_sub sub-steps with the
+    per-atom energy record off and on, then the Eq. 8 coupling coefficient
+    (ledger mode) and one Eq. 5 velocity step on device arrays, each timed
+    with HIP events on the library's stream."""
+    dev = d["vel"].device
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        fn()                                    # warm-up (graph capture, autotune)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k * 1e3      # us per call
+
+    out = {}
+    for on in (0, 1):
+        L.l2t_set_option(h, L.L2T_OPT_ATOM_LEDGER, on)
+        out["substep_us_record_" + ("on" if on else "off")] = \
+            timed(lambda: L.l2t_advance(h, n_sub), 5) / n_sub
+    dt_md = n_sub * sy.params["dt"]
+    xi = torch.empty(sy.n, dtype=torch.float64, device=dev)
+    v = d["vel"].clone()
+    cu = timed(lambda: L.l2t_coupling(h, 0, L.L2T_XI_LEDGER, dt_md, d["vel"], d["mass"], xi), reps)
+    du = timed(lambda: L.l2t_damping_step(h, 0, dt_md, xi, None, d["mass"], v), reps)
+    L.l2t_set_option(h, L.L2T_OPT_ATOM_LEDGER, 0)
+    # algorithmic bytes per atom: coupling reads the slot map (4), v (24), m (8),
+    # T_lat (4) and the record (8) and writes xi (8); the velocity step reads
+    # xi (8), m (8) and v (24) and writes v (24)
+    bc, bd = 56.0, 64.0
+    out.update(coupling_us=cu, damping_step_us=du,
+               coupling_GBps=bc * sy.n / (cu * 1e-6) / 1e9,
+               damping_step_GBps=bd * sy.n / (du * 1e-6) / 1e9)
+    out["coupling_frac"] = out["coupling_GBps"] / HBM_PEAK_GBS
+    out["damping_step_frac"] = out["damping_step_GBps"] / HBM_PEAK_GBS
+    out["record_overhead"] = out["substep_us_record_on"] / out["substep_us_record_off"] - 1.0
+    log(f"  MD coupling: sub-step {out['substep_us_record_off']:.1f} us (record off), "
+        f"{out['substep_us_record_on']:.1f} us (on); xi {cu:.1f} us, velocity step {du:.1f} us")
+    return out
+
+
 def cpu_baseline(sy, r_cut, n_steps):
     import oracle
     row, col = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, r_cut)
@@ -144,6 +194,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-md", action="store_true", help="skip the lattice-side (Eq. 5, 8) timing")
     ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto")
     ap.add_argument("--brick-edge", type=int, default=0)
     ap.add_argument("--block", type=int, default=0,
@@ -197,6 +248,10 @@ def main():
         log(f"step {k + 1}/{args.steps}: advance {adv_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    md = None
+    if not args.no_md:
+        log("MD coupling (Eq. 5, Eq. 8) ...")
+        md = bench_md_coupling(L, torch, h, sy, d)
     n_atom_steps = sy.n * args.substeps * args.steps
     value = n_atom_steps / wall
     mx, mean = L.l2t_build_neighbors(h, w.r_cut)
@@ -234,6 +289,8 @@ def main():
                roofline=roof,
                energy=dict(E_e=e["E_e"], sum_T=e["sum_T"], T_ledger=e["sum_T"] + e["T_ledger_acc"],
                            T_max=e["T_max_atom"]))
+    if md is not None:
+        out["md_coupling"] = md
     ctx.close()
     if not args.no_c4:
         log("C4 batched vs plain ...")

@@ -21,7 +21,10 @@
  *     and q_i the laser source of Eq. 10 taken as energy per unit time per
  *     atom;
  *   - the per-system energy ledger: the exchange rate of Eq. 6 integrated
- *     over each sub-step, the source energy, and the electronic energy;
+ *     over each sub-step, the source energy, and the electronic energy; on
+ *     request the same exchange per atom;
+ *   - the lattice side: the coupling coefficient of Eq. 8 and one explicit
+ *     velocity step of the damped equation of motion Eq. 5;
  *   - the discrete adjoint of the sub-step map, for gradients of a loss on
  *     the final T_e with respect to K, G and the initial field.
  *
@@ -76,6 +79,9 @@ extern "C" {
 #define L2T_FIELD_TL    1   /* lattice temperature T^lat, K (read/write; >= 0) */
 #define L2T_FIELD_GATE  2   /* 1.0 where the kinetic-energy gate holds, else 0.0 (read/write) */
 #define L2T_FIELD_NBRS  3   /* neighbour count |N(i)| as a double (read only) */
+#define L2T_FIELD_ELAT  4   /* energy the atom handed to the lattice during the last advance of its
+                               system, sum over sub-steps of g (T_i - T_i^lat) dt, eV (read only;
+                               recorded while L2T_OPT_ATOM_LEDGER is on) */
 
 /* ---- electronic heat capacity models (per atom) ---------------------------- */
 #define L2T_CE_CONST   0   /* c = ce_const */
@@ -91,6 +97,13 @@ extern "C" {
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
 #define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
 #define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells for the next l2t_build_neighbors (0 = automatic) */
+#define L2T_OPT_ATOM_LEDGER    7   /* 1 = record each atom's energy to the lattice during every advance
+                                      (L2T_FIELD_ELAT, L2T_XI_LEDGER); costs 16 bytes per atom-substep
+                                      of extra traffic while on (default 0) */
+
+/* ---- source of the energy rate in the coupling coefficient (l2t_coupling) ------ */
+#define L2T_XI_INSTANT  0   /* P_i = g (T_i - T_i^lat) at the current T_e (Section 2.1 order) */
+#define L2T_XI_LEDGER   1   /* P_i = E_i / dt_md, E_i the recorded energy of the last advance */
 
 typedef struct l2t_ctx l2t_ctx;
 
@@ -253,6 +266,44 @@ int l2t_set_option(l2t_ctx *ctx, int32_t option, int64_t value);
 
 /* Read a tuning choice the autotuner or the caller made. */
 int l2t_get_option(l2t_ctx *ctx, int32_t option, int64_t *value);
+
+/* ---- lattice side (Eq. 5 - Eq. 8) ---------------------------------------------- */
+
+/* Coupling coefficient of the damping force of Eq. 5 for every atom of
+ * system sys: the damping force xi_i m_i v_i does work 2 xi_i K_i per unit time
+ * (Eq. 7), with K_i = 1/2 m_i |v_i|^2 the atom's kinetic energy; Eq. 8 sets it
+ * equal to the rate P_i at which the atom's electrons hand energy to the
+ * lattice (Eq. 6):
+ *     xi_i = P_i / (2 K_i)                                  [1/fs]
+ * mode L2T_XI_INSTANT: P_i = g (T_i - T_i^lat) from the current T_e, as the
+ *   paper's implementation does once the sub-steps of an MD step are done;
+ * mode L2T_XI_LEDGER: P_i = E_i / dt_md with E_i = L2T_FIELD_ELAT, the energy
+ *   the atom handed over during the last advance (which spans the MD step
+ *   dt_md), so that one velocity step of Eq. 5 gives the lattice that energy
+ *   to first order in dt_md.
+ * xi_i = 0 where the kinetic-energy gate of l2t_set_velocities holds (the
+ * remark after Eq. 8) and where K_i < ke_eps.  v[3*n] (SoA, A/fs) and
+ * mass[n] (amu) are the velocities the damping force will act on; xi[n] is
+ * written (FP64, caller order).  All three live in memory space mem.
+ * Synchronises when mem == L2T_HOST.
+ * Errors: EINVAL (bad mode, dt_md <= 0 in ledger mode, NULL, mass <= 0),
+ * ESTATE (T_e or T^lat not set; ledger mode without a recorded advance of
+ * this system). */
+int l2t_coupling(l2t_ctx *ctx, int32_t sys, int32_t mode, double dt_md, const double *v,
+                 const double *mass, double *xi, int32_t mem);
+
+/* One explicit step of the damped equation of motion Eq. 5 for the atoms of
+ * system sys over the MD step dt_md:
+ *     v_i <- v_i + dt_md (F_i / m_i + xi_i v_i)
+ * in place on v[3*n] (SoA, A/fs), with forces force[3*n] (SoA, eV/A; NULL =
+ * no interatomic force), masses mass[n] (amu) and xi[n] (1/fs, e.g. from
+ * l2t_coupling); F/m is converted with 1 amu A^2/fs^2 = 103.6427 eV.  The
+ * library's MD integrator is the caller's: this step is the reference form of
+ * Eq. 5 (and what the energy check against L2T_FIELD_ELAT uses).  All arrays
+ * live in memory space mem.  Synchronises when mem == L2T_HOST.
+ * Errors: EINVAL (NULL, dt_md <= 0). */
+int l2t_damping_step(l2t_ctx *ctx, int32_t sys, double dt_md, const double *xi,
+                     const double *force, const double *mass, double *v, int32_t mem);
 
 /* ---- helpers ------------------------------------------------------------------ */
 

@@ -88,6 +88,7 @@ int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, 
     dfree(c->Tl32);
     dfree(c->srcw32);
     dfree(c->ledger);
+    dfree(c->eatom);
     dfree(c->slice_red);
     dfree(c->bricks);
     dfree(c->brick_list);
@@ -120,6 +121,7 @@ int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, 
         ALLOC(c->srcw32, NI);
     }
     ALLOC(c->ledger, 3 * NS);
+    ALLOC(c->eatom, NI);
     ALLOC(c->slice_red, 4 * NS);
     ALLOC(c->bricks, (size_t)n_bricks);
     ALLOC(c->brick_list, (size_t)n_list);
@@ -163,6 +165,19 @@ int check_err(l2t_ctx *c) {
     if (h & l2t::kErrRange)
         return l2t::fail(c, L2T_ERANGE,
                          "a sub-step produced theta outside [0,1] or a non-finite temperature");
+    return L2T_OK;
+}
+
+// start of an advance over systems [s0, s1): clear their per-atom ledger
+// while recording; otherwise the old record no longer describes the last advance
+int begin_atom_ledger(l2t_ctx *c, int32_t s0, int32_t s1) {
+    for (int32_t s = s0; s < s1; ++s) c->sys[s].eatom_valid = c->atom_ledger;
+    if (!c->atom_ledger) return L2T_OK;
+    if (s1 - s0 == (int32_t)c->sys.size()) return l2t::zero_atom_ledger(c, -1);
+    for (int32_t s = s0; s < s1; ++s) {
+        int rc = l2t::zero_atom_ledger(c, s);
+        if (rc != L2T_OK) return rc;
+    }
     return L2T_OK;
 }
 
@@ -248,6 +263,7 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c->Tl32);
     dfree(c->srcw32);
     dfree(c->ledger);
+    dfree(c->eatom);
     dfree(c->slice_red);
     dfree(c->energy_out);
     dfree(c->dparams);
@@ -364,6 +380,7 @@ int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mea
     for (auto &st : c->sys) {
         st.has_te = false;   // internal order changed: fields must be written again
         st.has_tl = false;
+        st.eatom_valid = false;
     }
     // per-atom fields start at zero (T^lat = 0, no gate)
     if (c->precision == L2T_FP64) {
@@ -472,11 +489,13 @@ int l2t_set_field(l2t_ctx *c, int32_t sys, int32_t field, const double *src, int
 
 int l2t_get_field(l2t_ctx *c, int32_t sys, int32_t field, double *dst, int32_t mem) {
     if (bad_sys(c, sys) || !dst) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
-    if (field < L2T_FIELD_TE || field > L2T_FIELD_NBRS)
+    if (field < L2T_FIELD_TE || field > L2T_FIELD_ELAT)
         return l2t::fail(c, L2T_EINVAL, "unknown field");
     if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
     if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
     const SystemState &st = c->sys[sys];
+    if (field == L2T_FIELD_ELAT && !st.eatom_valid)
+        return l2t::fail(c, L2T_ESTATE, "no advance of this system recorded with L2T_OPT_ATOM_LEDGER");
     double *d = mem == L2T_DEVICE ? dst : c->stage;
     int rc = l2t::permute_out(c, sys, field, d);
     if (rc != L2T_OK) return rc;
@@ -540,6 +559,11 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             if (value < 0 || value > 16) return l2t::fail(c, L2T_EINVAL, "brick edge must be 0..16");
             t.brick_edge = (int)value;
             return L2T_OK;
+        case L2T_OPT_ATOM_LEDGER:
+            // not a tuning choice: leaves the tuned launch shape alone
+            if ((value != 0) != c->atom_ledger) l2t::drop_graphs(c);
+            c->atom_ledger = value != 0;
+            return L2T_OK;
         case L2T_OPT_KERNEL:
             if (value != l2t::kKernelSliced && value != l2t::kKernelBrick)
                 return l2t::fail(c, L2T_EINVAL, "kernel must be 0 (global) or 1 (brick)");
@@ -571,6 +595,7 @@ int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
         case L2T_OPT_GRAPH: *value = t.graph; break;
         case L2T_OPT_AUTOTUNE: *value = t.autotune; break;
         case L2T_OPT_KERNEL: *value = t.kernel; break;
+        case L2T_OPT_ATOM_LEDGER: *value = c->atom_ledger ? 1 : 0; break;
         case L2T_OPT_BRICK_EDGE: *value = c->brick_edge_used; break;
         default: return l2t::fail(c, L2T_EINVAL, "unknown option");
     }
@@ -583,6 +608,8 @@ int l2t_advance(l2t_ctx *c, int32_t n) {
     if (!ready_to_advance(c, 0, (int32_t)c->sys.size(), &why)) return l2t::fail(c, L2T_ESTATE, why);
     c->rec.valid = false;
     if (n == 0) return L2T_OK;
+    int rc0 = begin_atom_ledger(c, 0, (int32_t)c->sys.size());
+    if (rc0 != L2T_OK) return rc0;
     if (c->precision == L2T_FP64) {
         for (int32_t s = 0; s < (int32_t)c->sys.size(); ++s) {
             int rc = l2t::advance_plain(c, s, n);
@@ -603,6 +630,8 @@ int l2t_advance_system(l2t_ctx *c, int32_t sys, int32_t n) {
     if (!ready_to_advance(c, sys, sys + 1, &why)) return l2t::fail(c, L2T_ESTATE, why);
     c->rec.valid = false;
     if (n == 0) return L2T_OK;
+    int rc = begin_atom_ledger(c, sys, sys + 1);
+    if (rc != L2T_OK) return rc;
     return l2t::advance_plain(c, sys, n);
 }
 
@@ -628,6 +657,8 @@ int l2t_advance_recorded(l2t_ctx *c, int32_t n, int32_t ckpt_every) {
     }
     r.step0.resize(c->sys.size());
     for (size_t s = 0; s < c->sys.size(); ++s) r.step0[s] = c->sys[s].step;
+    int rc0 = begin_atom_ledger(c, 0, (int32_t)c->sys.size());
+    if (rc0 != L2T_OK) return rc0;
     for (int64_t k = 0; k < r.n_ckpt; ++k) {
         int rc = l2t::record_checkpoint(c, k);
         if (rc != L2T_OK) return rc;
@@ -658,6 +689,83 @@ int l2t_adjoint(l2t_ctx *c, const double *dL_dTN, int32_t mem, double *dL_dK, do
         L2T_HIP(c, hipStreamSynchronize(c->stream));
     }
     return check_err(c);
+}
+
+int l2t_coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *v,
+                 const double *mass, double *xi, int32_t mem) {
+    if (bad_sys(c, sys) || !v || !mass || !xi)
+        return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
+    if (mode != L2T_XI_INSTANT && mode != L2T_XI_LEDGER)
+        return l2t::fail(c, L2T_EINVAL, "mode must be L2T_XI_INSTANT or L2T_XI_LEDGER");
+    if (mode == L2T_XI_LEDGER && !(dt_md > 0.0 && std::isfinite(dt_md)))
+        return l2t::fail(c, L2T_EINVAL, "dt_md must be > 0");
+    if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
+    const SystemState &st = c->sys[sys];
+    if (!st.has_te || !st.has_tl || !st.has_params)
+        return l2t::fail(c, L2T_ESTATE, "T_e, T_lat and parameters must be set");
+    if (mode == L2T_XI_LEDGER && !st.eatom_valid)
+        return l2t::fail(c, L2T_ESTATE, "no advance of this system recorded with L2T_OPT_ATOM_LEDGER");
+    const int64_t n = st.desc.n_atoms;
+    const double *dv = v, *dm = mass;
+    double *dxi = xi;
+    if (mem == L2T_HOST) {
+        if (l2t::ensure_scratch(c, sizeof(double) * 5 * (size_t)n) != L2T_OK)
+            return l2t::fail(c, L2T_ENOMEM, "staging allocation failed");
+        double *sc = (double *)c->scratch;
+        L2T_HIP(c, hipMemcpyAsync(sc, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+        L2T_HIP(c, hipMemcpyAsync(sc + 3 * n, mass, sizeof(double) * n, hipMemcpyHostToDevice,
+                                  c->stream));
+        dv = sc;
+        dm = sc + 3 * n;
+        dxi = sc + 4 * n;
+    }
+    bool ok = true;
+    int rc = l2t::check_field_range(c, dm, n, 1e-300, HUGE_VAL, &ok);
+    if (rc != L2T_OK) return rc;
+    if (!ok) return l2t::fail(c, L2T_EINVAL, "masses must be finite and > 0");
+    rc = l2t::coupling(c, sys, mode, dt_md, dv, dm, dxi);
+    if (rc != L2T_OK) return rc;
+    if (mem == L2T_HOST) {
+        L2T_HIP(c, hipMemcpyAsync(xi, dxi, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return L2T_OK;
+}
+
+int l2t_damping_step(l2t_ctx *c, int32_t sys, double dt_md, const double *xi,
+                     const double *force, const double *mass, double *v, int32_t mem) {
+    if (bad_sys(c, sys) || !xi || !mass || !v)
+        return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
+    if (!(dt_md > 0.0 && std::isfinite(dt_md))) return l2t::fail(c, L2T_EINVAL, "dt_md must be > 0");
+    const int64_t n = c->sys[sys].desc.n_atoms;
+    const double *dxi = xi, *dF = force, *dm = mass;
+    double *dv = v;
+    if (mem == L2T_HOST) {
+        if (l2t::ensure_scratch(c, sizeof(double) * 8 * (size_t)n) != L2T_OK)
+            return l2t::fail(c, L2T_ENOMEM, "staging allocation failed");
+        double *sc = (double *)c->scratch;
+        L2T_HIP(c, hipMemcpyAsync(sc, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+        L2T_HIP(c, hipMemcpyAsync(sc + 3 * n, mass, sizeof(double) * n, hipMemcpyHostToDevice,
+                                  c->stream));
+        L2T_HIP(c, hipMemcpyAsync(sc + 4 * n, xi, sizeof(double) * n, hipMemcpyHostToDevice,
+                                  c->stream));
+        if (force)
+            L2T_HIP(c, hipMemcpyAsync(sc + 5 * n, force, sizeof(double) * 3 * n,
+                                      hipMemcpyHostToDevice, c->stream));
+        dv = sc;
+        dm = sc + 3 * n;
+        dxi = sc + 4 * n;
+        dF = force ? sc + 5 * n : nullptr;
+    }
+    int rc = l2t::damping_step(c->stream, n, dt_md, dxi, dF, dm, dv);
+    if (rc != L2T_OK) return l2t::fail(c, rc, "damping step launch failed");
+    if (mem == L2T_HOST) {
+        L2T_HIP(c, hipMemcpyAsync(v, dv, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return L2T_OK;
 }
 
 int l2t_energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out) {

@@ -135,7 +135,7 @@ int autotune(l2t_ctx *c) {
         float ms_min = 1e30f;
         for (int rep = 0; rep < 2 && rc == L2T_OK; ++rep) {
             L2T_HIP(c, hipEventRecord(e0, c->stream));
-            rc = fp32c_launch(c, probe, ch.kernel, ch.persistent, ch.block);
+            rc = fp32c_launch(c, probe, ch.kernel, ch.persistent, ch.block, nullptr);
             L2T_HIP(c, hipEventRecord(e1, c->stream));
             L2T_HIP(c, hipEventSynchronize(e1));
             float ms = 0.0f;

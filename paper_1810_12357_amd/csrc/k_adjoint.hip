@@ -172,7 +172,7 @@ __global__ void k_forward_step(const SliceInfo *slices, int32_t n_slices, const 
     if (sl >= n_slices) return;
     const SliceInfo si = slices[sl];
     slice_step_fp32c(si, sl, lane, P[si.sys], col, Thi, Thi_n, Tlo, Tl, srcw,
-                     dstep[si.sys] + rel, ledger, err);
+                     dstep[si.sys] + rel, ledger, nullptr, err);
 }
 
 __global__ void k_zero_d(double *p, int64_t n) {

@@ -387,7 +387,7 @@ __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm,
 __global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                             int32_t field, int32_t precision, const double *T64, const float *Thi,
                             const float *Tlo, const double *Tl64, const float *Tl32,
-                            const int32_t *cnt, double *dst) {
+                            const int32_t *cnt, const double *eatom, double *dst) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_pad) return;
     int32_t slot = atom_off + k;
@@ -403,6 +403,8 @@ __global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm
         v = s ? 1.0 : 0.0;
     } else if (field == L2T_FIELD_NBRS) {
         v = (double)cnt[slot];
+    } else if (field == L2T_FIELD_ELAT) {
+        v = eatom[slot];
     }
     dst[g - caller_off] = v;
 }
@@ -994,7 +996,8 @@ int permute_out(l2t_ctx *c, int32_t sys, int32_t field, double *dst_dev) {
     const SystemState &st = c->sys[sys];
     hipLaunchKernelGGL(k_field_out, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream,
                        st.atom_off, st.n_pad, c->perm, st.caller_off, field, c->precision,
-                       c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32, c->cnt, dst_dev);
+                       c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32, c->cnt, c->eatom,
+                       dst_dev);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;
 }

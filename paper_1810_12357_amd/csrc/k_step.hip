@@ -36,14 +36,15 @@ __global__ __launch_bounds__(256) void k_step_fp64(const SliceInfo *slices, int3
                                                    const double *T, double *Tn, const double *Tl,
                                                    const double *srcw, const DevParams *P,
                                                    const int64_t *dstep, int32_t rel,
-                                                   double *ledger, unsigned *err) {
+                                                   double *ledger, double *eatom, unsigned *err) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
     if (q >= n_slices) return;
     const int32_t sl = slice0 + q;
     const SliceInfo si = slices[sl];
     const DevParams &p = P[si.sys];
-    slice_step_fp64(si, sl, lane, p, col, T, Tn, Tl, srcw, dstep[si.sys] + rel, ledger, err);
+    slice_step_fp64(si, sl, lane, p, col, T, Tn, Tl, srcw, dstep[si.sys] + rel, ledger, eatom,
+                    err);
 }
 
 __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int32_t slice0,
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
                                                     const float *Thi, float *Thi_n, float *Tlo,
                                                     const float *Tl, const float *srcw,
                                                     const DevParams *P, const int64_t *dstep,
-                                                    int32_t rel, double *ledger, unsigned *err) {
+                                                    int32_t rel, double *ledger, double *eatom,
+                                                    unsigned *err) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
     if (q >= n_slices) return;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
     const SliceInfo si = slices[sl];
     const DevParams &p = P[si.sys];
     slice_step_fp32c(si, sl, lane, p, col, Thi, Thi_n, Tlo, Tl, srcw, dstep[si.sys] + rel, ledger,
-                     err);
+                     eatom, err);
 }
 
 // LDS-tile FP32C sub-step: one workgroup per brick stages the FP32 hi
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
     const int32_t *__restrict__ halo, const float *__restrict__ Thi, float *__restrict__ Thi_n,
     float *__restrict__ Tlo, const float *__restrict__ Tl, const float *__restrict__ srcw,
     const DevParams *__restrict__ P, const int64_t *__restrict__ dstep, int32_t rel,
-    double *__restrict__ ledger, unsigned *__restrict__ err) {
+    double *__restrict__ ledger, double *__restrict__ eatom, unsigned *__restrict__ err) {
     extern __shared__ float tile[];
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         const float Ti = tile[q * kWave + lane];
         const LedgerTerms t = slice_core_brick(w, slot, lane < nv, p, Ti, lo, tl, sw,
                                                colw + (int64_t)base * kWave, lane, tile, Thi_n,
-                                               Tlo, step, err);
+                                               Tlo, eatom, step, err);
         acc.e2l += t.e2l;
         acc.src += t.src;
         acc.lt += t.lt;
@@ -184,7 +186,7 @@ __device__ inline bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned k,
 __global__ __launch_bounds__(256) void k_persistent_fp32c(
     const SliceInfo *slices, int32_t n_slices, const int32_t *col, float *Thi0, float *Thi1,
     float *Tlo, const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep,
-    int32_t n_steps, double *ledger, unsigned *err, unsigned *bar) {
+    int32_t n_steps, double *ledger, double *eatom, unsigned *err, unsigned *bar) {
     const unsigned G = gridDim.x;
     const unsigned b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(256) void k_persistent_fp32c(
         for (int32_t sl = s_lo + wave; sl < s_hi; sl += nw) {
             const SliceInfo si = slices[sl];
             slice_step_fp32c(si, sl, lane, P[si.sys], col, Tin, Tout, Tlo, Tl, srcw,
-                             dstep[si.sys] + st, ledger, err);
+                             dstep[si.sys] + st, ledger, eatom, err);
         }
         if (!grid_barrier(bar, G, (unsigned)st + 1u, err)) return;
     }
@@ -367,21 +369,32 @@ int reset_ledger(l2t_ctx *c, int32_t sys) {
 }
 
 // One system (sys >= 0) or all systems (sys < 0), one launch per sub-step.
+int zero_atom_ledger(l2t_ctx *c, int32_t sys) {
+    const int64_t off = sys < 0 ? 0 : c->sys[sys].atom_off;
+    const int64_t len = sys < 0 ? c->n_int : c->sys[sys].n_pad;
+    if (len > 0)
+        hipLaunchKernelGGL(k_zero_f64, dim3(nblk(len, 256)), dim3(256), 0, c->stream,
+                           c->eatom + off, len);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
 int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     const int32_t s0 = sys < 0 ? 0 : c->sys[sys].slice0;
     const int32_t ns = sys < 0 ? c->n_slices : c->sys[sys].n_slices;
     const int wpb = 4;
     const dim3 grid(nblk(ns, wpb)), block(wpb * kWave);
+    double *eatom = atom_ledger_ptr(c);
     int cur = c->cur;
     for (int32_t k = 0; k < n; ++k) {
         if (c->precision == L2T_FP64) {
             hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
                                c->T64[cur], c->T64[cur ^ 1], c->Tl64, c->srcw64, c->dparams,
-                               c->dstep, k, c->ledger, c->derr);
+                               c->dstep, k, c->ledger, eatom, c->derr);
         } else {
             hipLaunchKernelGGL(k_step_fp32c, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
                                c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32,
-                               c->dparams, c->dstep, k, c->ledger, c->derr);
+                               c->dparams, c->dstep, k, c->ledger, eatom, c->derr);
         }
         cur ^= 1;
     }
@@ -421,7 +434,7 @@ static int persistent_grid(l2t_ctx *c, int block) {
 }
 
 // FP32C, all systems, n sub-steps starting at the current state.
-int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
+int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom) {
     int cur = c->cur;
     if (kernel == kKernelBrick) {
         const int32_t nl = c->n_brick_list;
@@ -431,7 +444,7 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
             hipLaunchKernelGGL(k_brick_fp32c, dim3(grid), dim3(block), lds, c->stream, c->bricks,
                                c->brick_list, nl, c->slices, c->colw, c->halo, c->Thi[cur],
                                c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32, c->dparams, c->dstep,
-                               k, c->ledger, c->derr);
+                               k, c->ledger, eatom, c->derr);
             cur ^= 1;
         }
     } else if (persistent) {
@@ -440,7 +453,7 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->dbar, 2);
         hipLaunchKernelGGL(k_persistent_fp32c, dim3(grid), dim3(block), 0, c->stream, c->slices,
                            c->n_slices, c->col, c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32,
-                           c->srcw32, c->dparams, c->dstep, n, c->ledger, c->derr, c->dbar);
+                           c->srcw32, c->dparams, c->dstep, n, c->ledger, eatom, c->derr, c->dbar);
     } else {
         block = std::min(block, kSlicedBlockMax);
         const int wpb = block / kWave;
@@ -448,7 +461,7 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block) {
         for (int32_t k = 0; k < n; ++k) {
             hipLaunchKernelGGL(k_step_fp32c, g, b, 0, c->stream, c->slices, 0, c->n_slices, c->col,
                                c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32,
-                               c->dparams, c->dstep, k, c->ledger, c->derr);
+                               c->dparams, c->dstep, k, c->ledger, eatom, c->derr);
             cur ^= 1;
         }
     }
@@ -469,7 +482,7 @@ void drop_graphs(l2t_ctx *c) {
 int advance_fp32c(l2t_ctx *c, int32_t n) {
     const Tuning &t = c->tune;
     if (!t.graph) {
-        int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block);
+        int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
         if (rc != L2T_OK) return rc;
     } else {
         GraphKey key{n, (c->cur << 8) | (t.persistent << 4) | t.kernel, t.block};
@@ -483,7 +496,7 @@ int advance_fp32c(l2t_ctx *c, int32_t n) {
             hipStream_t user = c->stream;
             L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
             c->stream = c->cap_stream;
-            int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block);
+            int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
             c->stream = user;
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc != L2T_OK) return rc;

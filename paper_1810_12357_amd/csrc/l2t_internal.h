@@ -77,6 +77,7 @@ struct SystemState {
     int32_t nc[3] = {1, 1, 1};
     int64_t cell_off = 0, ncell = 0;
     int64_t step = 0;            // sub-steps since the last T_e write
+    bool eatom_valid = false;    // the per-atom ledger holds this system's last advance
     int32_t max_nbrs = 0;
 };
 
@@ -170,6 +171,9 @@ struct l2t_ctx {
     int cur = 0;
 
     double *ledger = nullptr;    // [n_slices][3]
+    double *eatom = nullptr;     // internal [n_int]: energy to the lattice over the last advance
+    bool atom_ledger = false;    // record eatom during advances
+    bool eatom_valid = false;    // eatom holds the record of the last advance
     double *slice_red = nullptr; // [n_slices][4]
     double *energy_out = nullptr;// [n_sys][8]
     l2t::DevParams *dparams = nullptr;
@@ -217,9 +221,18 @@ int advance_fp32c(l2t_ctx *c, int32_t n);                 // all systems, tuned 
 int reset_ledger(l2t_ctx *c, int32_t sys);
 int energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out);
 int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream_t s);
-int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block);
+int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom);
+// per-atom record of the energy handed to the lattice (nullptr while off)
+inline double *atom_ledger_ptr(l2t_ctx *c) { return c->atom_ledger ? c->eatom : nullptr; }
+int zero_atom_ledger(l2t_ctx *c, int32_t sys);   // sys < 0: every system
 int bump_steps(l2t_ctx *c, int32_t sys, int32_t n);
 void drop_graphs(l2t_ctx *c);
+
+// ---- lattice side (k_lattice.hip) ------------------------------------------
+int coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *v_dev,
+             const double *m_dev, double *xi_dev);
+int damping_step(hipStream_t s, int64_t n, double dt_md, const double *xi, const double *force,
+                 const double *mass, double *v);
 
 // ---- adjoint (k_adjoint.hip) ------------------------------------------------
 int record_checkpoint(l2t_ctx *c, int64_t slot);

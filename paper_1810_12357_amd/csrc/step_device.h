@@ -125,7 +125,8 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
                                        const double *__restrict__ T, double *__restrict__ Tn,
                                        const double *__restrict__ Tl,
                                        const double *__restrict__ srcw, int64_t step,
-                                       double *__restrict__ ledger, unsigned *err) {
+                                       double *__restrict__ ledger, double *__restrict__ eatom,
+                                       unsigned *err) {
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
     const double Ti = T[slot];
@@ -145,6 +146,7 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
         if (p.laser_on) q = p.i0 * srcw[slot] * pulse64(p, step);
         Tnew = Ti + p.dt * (p.A * S - coup / c + q / c);
         e2l = coup * p.dt;
+        if (eatom) eatom[slot] += e2l;
         lt = p.dt * (coup - q) / c;
         q *= p.dt;
         const double th = (Tnew - p.T_min) * p.inv_span;
@@ -198,7 +200,8 @@ struct LedgerTerms {
 __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t slot, bool valid,
                                                     float Ti, double S, float lo, float tl,
                                                     float sw, float *__restrict__ Thi_n,
-                                                    float *__restrict__ Tlo, int64_t step,
+                                                    float *__restrict__ Tlo,
+                                                    double *__restrict__ eatom, int64_t step,
                                                     unsigned *err) {
     float hi_new = Ti;
     LedgerTerms r{0.0f, 0.0f, 0.0f};
@@ -213,6 +216,7 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
         hi_new = (float)T;
         Tlo[slot] = (float)(T - (double)hi_new);
         r = LedgerTerms{coup, q, -loc};
+        if (eatom) eatom[slot] += (double)coup * p.dt;
         if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
     }
     Thi_n[slot] = hi_new;
@@ -224,7 +228,8 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
                                                         const DevParams &p, float Ti, float lo,
                                                         float tl, float sw, IdxAt idx_at,
                                                         ValOf val_of, float *__restrict__ Thi_n,
-                                                        float *__restrict__ Tlo, int64_t step,
+                                                        float *__restrict__ Tlo,
+                                                        double *__restrict__ eatom, int64_t step,
                                                         unsigned *err) {
     constexpr int C = 8;
     using Ref = decltype(idx_at(0));
@@ -248,7 +253,7 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
 #pragma unroll
         for (int u = 0; u < C; ++u) cur[u] = nxt[u];
     }
-    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, step, err);
+    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, step, err);
 }
 
 // LDS-tile form for one slice.  w is the slice's row width and row the first
@@ -263,7 +268,8 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
                                                         const uint32_t *__restrict__ row,
                                                         int lane, const float *tile,
                                                         float *__restrict__ Thi_n,
-                                                        float *__restrict__ Tlo, int64_t step,
+                                                        float *__restrict__ Tlo,
+                                                        double *__restrict__ eatom, int64_t step,
                                                         unsigned *err) {
     const PairK pk = pair_consts(p);
     const char *tb = reinterpret_cast<const char *>(tile);
@@ -326,7 +332,7 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
         }
         if (nch & 1) chunk(nch - 1, A);
     }
-    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, step, err);
+    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, step, err);
 }
 
 // wave sums of ledger terms, added in FP64 to one ledger row.  A row is
@@ -355,7 +361,8 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
                                                  float *__restrict__ Tlo,
                                                  const float *__restrict__ Tl,
                                                  const float *__restrict__ srcw, int64_t step,
-                                                 double *__restrict__ ledger, unsigned *err) {
+                                                 double *__restrict__ ledger,
+                                                 double *__restrict__ eatom, unsigned *err) {
     const int32_t slot = sl * kWave + lane;
     const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
     const float Ti = Thi[slot];
@@ -363,7 +370,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
     const float sw = p.laser_on ? srcw[slot] : 0.0f;
     const LedgerTerms t = slice_core_fp32c(
         si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
-        [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, step, err);
+        [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, eatom, step, err);
     ledger_add(ledger, sl, lane, t, p.dt);
 }
 

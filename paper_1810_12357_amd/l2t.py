@@ -23,16 +23,18 @@ L2T_OK, L2T_WUNSTABLE = 0, 1
 L2T_EINVAL, L2T_ENOMEM, L2T_EHIP, L2T_ESTATE, L2T_ERANGE, L2T_ENOTIMPL = -1, -2, -3, -4, -5, -6
 L2T_FP64, L2T_FP32C = 0, 1
 L2T_HOST, L2T_DEVICE = 0, 1
-L2T_FIELD_TE, L2T_FIELD_TL, L2T_FIELD_GATE, L2T_FIELD_NBRS = 0, 1, 2, 3
+L2T_FIELD_TE, L2T_FIELD_TL, L2T_FIELD_GATE, L2T_FIELD_NBRS, L2T_FIELD_ELAT = 0, 1, 2, 3, 4
 L2T_CE_CONST, L2T_CE_LINEAR, L2T_CE_CAPPED = 0, 1, 2
 L2T_OPT_PERSISTENT, L2T_OPT_BLOCK, L2T_OPT_RESIDENT_MAX, L2T_OPT_GRAPH, L2T_OPT_AUTOTUNE = 0, 1, 2, 3, 4
-L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE = 5, 6
+L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE, L2T_OPT_ATOM_LEDGER = 5, 6, 7
+L2T_XI_INSTANT, L2T_XI_LEDGER = 0, 1
 
 # every symbol the header declares (checked by the CPU test suite)
 EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbors",
            "l2t_get_neighbors", "l2t_set_params", "l2t_set_field", "l2t_get_field",
            "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
            "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
+           "l2t_coupling", "l2t_damping_step",
            "l2t_exchange_rate", "l2t_pair_fp32", "l2t_strerror", "l2t_last_error",
            "l2t_version")
 
@@ -101,6 +103,8 @@ def load() -> C.CDLL:
         "l2t_sync": (C.c_int, [vp]),
         "l2t_set_option": (C.c_int, [vp, i32, i64]),
         "l2t_get_option": (C.c_int, [vp, i32, P(i64)]),
+        "l2t_coupling": (C.c_int, [vp, i32, i32, d, vp, vp, vp, i32]),
+        "l2t_damping_step": (C.c_int, [vp, i32, d, vp, vp, vp, vp, i32]),
         "l2t_exchange_rate": (d, [d, d, i32, d]),
         "l2t_pair_fp32": (C.c_int, [vp, vp, vp, i64, vp]),
         "l2t_strerror": (C.c_char_p, [C.c_int]),
@@ -251,6 +255,41 @@ def l2t_adjoint(ctx, dL_dTN, n_systems: int, dL_dT0=None):
             raise TypeError("dL_dTN and dL_dT0 must live in the same memory space")
     _check(ctx, load().l2t_adjoint(ctx, pw, mem, dK.ctypes.data, dg.ctypes.data, p0))
     return dK, dg
+
+
+def _out_ptr(a):
+    """Pointer of an output array, which must be written in place."""
+    if not _is_torch(a) and not (isinstance(a, np.ndarray) and a.dtype == np.float64
+                                 and a.flags.c_contiguous):
+        raise TypeError("output must be a contiguous float64 numpy array or torch tensor")
+    return _ptr(a)
+
+
+def l2t_coupling(ctx, sys: int, mode: int, dt_md: float, v, mass, xi):
+    """Eq. 8 coupling coefficient into xi (see l2t.h)."""
+    pv, mem, kv = _ptr(v)
+    pm, mem2, km = _ptr(mass)
+    px, mem3, kx = _out_ptr(xi)
+    if not (mem == mem2 == mem3):
+        raise TypeError("v, mass and xi must live in the same memory space")
+    _check(ctx, load().l2t_coupling(ctx, sys, mode, float(dt_md), pv, pm, px, mem))
+    return xi
+
+
+def l2t_damping_step(ctx, sys: int, dt_md: float, xi, force, mass, v):
+    """One explicit step of Eq. 5 on v in place (see l2t.h)."""
+    px, mem, kx = _ptr(xi)
+    pm, mem2, km = _ptr(mass)
+    pv, mem3, kv = _out_ptr(v)
+    pf, kf = None, None
+    if force is not None:
+        pf, mem4, kf = _ptr(force)
+        if mem4 != mem:
+            raise TypeError("force must live in the same memory space as v")
+    if not (mem == mem2 == mem3):
+        raise TypeError("xi, mass and v must live in the same memory space")
+    _check(ctx, load().l2t_damping_step(ctx, sys, float(dt_md), px, pf, pm, pv, mem))
+    return v
 
 
 def l2t_energies(ctx, sys: int, check: bool = True) -> dict:

@@ -1,0 +1,203 @@
+"""Lattice side (Eq. 5 - Eq. 8) through the C ABI against the FP64 oracle: the
+per-atom record of the energy handed to the lattice, the coupling coefficient
+of Eq. 8 in both modes, the explicit velocity step of Eq. 5, and the work
+identity of one damped step on the full-size system."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import gpu_context, light_cone, oracle_neighbors, sub_problem
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1810_12357_amd.l2t")
+
+MVV2E = W.AMU_A2_PER_FS2_IN_EV
+N_SUB = 10                        # electronic sub-steps per MD step (Section 3.2)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _kinetic(vel, mass):
+    return 0.5 * mass * (vel * vel).sum(axis=0) * MVV2E
+
+
+def _norm_rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _md_workload(n_cells=8):
+    """C3-shaped system (hot electron spot, hot lattice core, 300 K Maxwell
+    velocities) with a coupling strong enough that E_i is far above rounding."""
+    w = W.c3(n_cells=n_cells, n_substeps=N_SUB)
+    sy = w.systems[0]
+    sy.params = dict(sy.params, g=4e-5)
+    return w, sy
+
+
+def _oracle_md_step(sy, r_cut, n_sub=N_SUB):
+    row, col = oracle_neighbors(sy, r_cut)
+    Tl, gated = oracle.lattice_temperature(row, col, sy.vel, sy.mass, sy.params["ke_eps"])
+    e = np.zeros(sy.n)
+    T, led, bad = oracle.run(row, col, sy.T_e0, Tl, sy.params, n_sub, gated=gated, e_atom=e)
+    assert bad == 0
+    return T, Tl, gated, e, led
+
+
+TOL = {0: 1e-11, 1: 1e-5}          # FP64, FP32C
+
+
+@pytest.mark.parametrize("precision", [L.L2T_FP64, L.L2T_FP32C])
+def test_atom_ledger_and_coupling_match_oracle(precision):
+    w, sy = _md_workload()
+    ctx = gpu_context(w, precision)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 1)
+    ctx.advance(N_SUB)
+    E = ctx.get(0, L.L2T_FIELD_ELAT)
+    To, Tl, gated, e, led = _oracle_md_step(sy, w.r_cut)
+    assert _norm_rel(E, e) < TOL[precision]
+    assert np.all(E[gated == 1] == 0.0)
+    rep = ctx.energies(0)
+    assert E.sum() == pytest.approx(rep["E_e_to_l"], rel=1e-6 if precision else 1e-11)
+    assert E.sum() == pytest.approx(led[0], rel=1e-5 if precision else 1e-11)
+    dt_md = N_SUB * sy.params["dt"]
+    for mode in (L.L2T_XI_INSTANT, L.L2T_XI_LEDGER):
+        xi = np.empty(sy.n)
+        L.l2t_coupling(ctx.h, 0, mode, dt_md, sy.vel.reshape(-1), sy.mass, xi)
+        xo = oracle.coupling(mode, To, Tl, gated, e, sy.params["g"], dt_md,
+                             sy.params["ke_eps"], sy.vel, sy.mass)
+        assert np.array_equal(xi == 0.0, xo == 0.0)
+        assert _norm_rel(xi, xo) < TOL[precision], mode
+    ctx.close()
+
+
+def test_coupling_on_device_pointers_and_damping_step_bitwise():
+    import torch
+    w, sy = _md_workload(n_cells=6)
+    ctx = gpu_context(w, L.L2T_FP32C)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 1)
+    ctx.advance(N_SUB)
+    dt_md = N_SUB * sy.params["dt"]
+    dev = torch.device("cuda:0")
+    v_d = torch.from_numpy(np.ascontiguousarray(sy.vel.reshape(-1))).to(dev)
+    m_d = torch.from_numpy(np.ascontiguousarray(sy.mass)).to(dev)
+    xi_d = torch.empty(sy.n, dtype=torch.float64, device=dev)
+    L.l2t_coupling(ctx.h, 0, L.L2T_XI_LEDGER, dt_md, v_d, m_d, xi_d)
+    xi_h = np.empty(sy.n)
+    L.l2t_coupling(ctx.h, 0, L.L2T_XI_LEDGER, dt_md, sy.vel.reshape(-1), sy.mass, xi_h)
+    torch.cuda.synchronize()
+    assert np.array_equal(xi_d.cpu().numpy(), xi_h)
+    # the velocity step is elementwise FP64 in the oracle's operation order
+    rng = np.random.default_rng(31)
+    force = rng.normal(0.0, 0.3, (3, sy.n))
+    mass = rng.uniform(20.0, 200.0, sy.n)
+    xi = np.where(rng.uniform(0, 1, sy.n) < 0.2, 0.0, rng.normal(0.0, 1e-3, sy.n))
+    for f in (force, None):
+        vo = oracle.damping_step(0.5, xi, f, mass, sy.vel)
+        v_h = np.ascontiguousarray(sy.vel.reshape(-1)).copy()
+        L.l2t_damping_step(ctx.h, 0, 0.5, xi, None if f is None else f.reshape(-1), mass, v_h)
+        assert np.array_equal(v_h.reshape(3, sy.n), vo)
+        v_dd = torch.from_numpy(np.ascontiguousarray(sy.vel.reshape(-1))).to(dev)
+        f_d = None if f is None else torch.from_numpy(np.ascontiguousarray(f.reshape(-1))).to(dev)
+        L.l2t_damping_step(ctx.h, 0, 0.5, torch.from_numpy(xi).to(dev), f_d,
+                           torch.from_numpy(mass).to(dev), v_dd)
+        torch.cuda.synchronize()
+        assert np.array_equal(v_dd.cpu().numpy().reshape(3, sy.n), vo)
+    ctx.close()
+
+
+def test_atom_ledger_lifetime_and_per_system_advance():
+    w = W.c4(n_systems=3, n_substeps=N_SUB, size_lo=800, size_hi=3000)
+    for sy in w.systems:
+        sy.params = dict(sy.params, g=4e-5)
+        sy.T_e0 = sy.T_e0 + np.linspace(0.0, 2000.0, sy.n)     # electrons above the lattice
+    ctx = gpu_context(w, L.L2T_FP32C)
+    ctx.advance(N_SUB)                                  # not recorded
+    with pytest.raises(L.L2TError) as ex:
+        ctx.get(0, L.L2T_FIELD_ELAT)
+    assert ex.value.status == L.L2T_ESTATE
+    xi = np.empty(w.systems[0].n)
+    with pytest.raises(L.L2TError):
+        L.l2t_coupling(ctx.h, 0, L.L2T_XI_LEDGER, 0.5, np.zeros(3 * w.systems[0].n),
+                       w.systems[0].mass if w.systems[0].mass is not None
+                       else np.ones(w.systems[0].n), xi)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 1)
+    assert L.l2t_get_option(ctx.h, L.L2T_OPT_ATOM_LEDGER) == 1
+    before = [ctx.energies(s)["E_e_to_l"] for s in range(3)]
+    ctx.advance(N_SUB)
+    E0 = [ctx.get(s, L.L2T_FIELD_ELAT) for s in range(3)]
+    for s in range(3):
+        # the system ledger runs since the last T_e write; the record covers this advance
+        assert E0[s].sum() == pytest.approx(ctx.energies(s)["E_e_to_l"] - before[s], rel=1e-6)
+        assert E0[s].sum() > 0
+    # one system alone: only its record is replaced
+    L.l2t_advance_system(ctx.h, 1, 3)
+    E1 = [ctx.get(s, L.L2T_FIELD_ELAT) for s in range(3)]
+    assert np.array_equal(E1[0], E0[0]) and np.array_equal(E1[2], E0[2])
+    assert not np.array_equal(E1[1], E0[1])
+    # the 3-sub-step record continues from the state after the 2 x N_SUB sub-steps
+    sy = w.systems[1]
+    row, col = oracle_neighbors(sy, w.r_cut)
+    Tl = np.asarray(sy.T_l, dtype=np.float64)
+    x = sy.pos[0] if sy.params["laser_on"] else None
+    T, _, _ = oracle.run(row, col, sy.T_e0, Tl, sy.params, 2 * N_SUB, x=x)
+    e = np.zeros(sy.n)
+    oracle.run(row, col, T, Tl, sy.params, 3, step0=2 * N_SUB, x=x, e_atom=e)
+    assert _norm_rel(E1[1], e) < 1e-5
+    # recording switched off: the record no longer describes the last advance
+    L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 0)
+    ctx.advance(1)
+    with pytest.raises(L.L2TError):
+        ctx.get(2, L.L2T_FIELD_ELAT)
+    ctx.close()
+
+
+def test_damped_step_work_identity_full_size(c3_full):
+    """4M atoms in the benchmark's launch configuration: one MD step of 10
+    sub-steps recorded per atom, xi from the record, one damped velocity step.
+    Every atom's kinetic energy rises by exactly E_i + E_i^2 / (4 K_i); sampled
+    atoms' E_i match the oracle on their light cone."""
+    import torch
+    w, sy, row, col = c3_full
+    ctx = gpu_context(w, L.L2T_FP32C)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 1)
+    ctx.advance(N_SUB)
+    dt_md = N_SUB * sy.params["dt"]
+    dev = torch.device("cuda:0")
+    v_d = torch.from_numpy(np.ascontiguousarray(sy.vel.reshape(-1))).to(dev)
+    m_d = torch.from_numpy(np.ascontiguousarray(sy.mass)).to(dev)
+    xi_d = torch.empty(sy.n, dtype=torch.float64, device=dev)
+    L.l2t_coupling(ctx.h, 0, L.L2T_XI_LEDGER, dt_md, v_d, m_d, xi_d)
+    L.l2t_damping_step(ctx.h, 0, dt_md, xi_d, None, m_d, v_d)
+    torch.cuda.synchronize()
+    E = ctx.get(0, L.L2T_FIELD_ELAT)
+    xi = xi_d.cpu().numpy()
+    v1 = v_d.cpu().numpy().reshape(3, sy.n)
+    K0, K1 = _kinetic(sy.vel, sy.mass), _kinetic(v1, sy.mass)
+    on = xi != 0.0
+    assert on.sum() > 0.9 * sy.n
+    np.testing.assert_allclose((K1 - K0)[on], (E + E * E / (4.0 * K0))[on], rtol=1e-8,
+                               atol=1e-15)
+    assert np.array_equal(v1[:, ~on], sy.vel[:, ~on])
+    # sampled atoms against the oracle: E_i depends on T_i over the first
+    # N_SUB - 1 sub-steps, hence on atoms within N_SUB - 1 hops
+    Tl, gated = oracle.lattice_temperature(row, col, sy.vel, sy.mass, sy.params["ke_eps"])
+    r2 = ((sy.pos - (sy.box_len / 2)[:, None]) ** 2).sum(0)
+    rng = np.random.default_rng(1)
+    seeds = np.r_[np.argsort(r2)[:2], np.argmin(np.abs(np.sqrt(r2) - 18.0)),
+                  rng.integers(0, sy.n, 3)]
+    scale = np.max(np.abs(E))
+    for sd in seeds:
+        keep = light_cone(row, col, [sd], N_SUB)
+        r, c = sub_problem(row, col, keep)
+        e = np.zeros(keep.size)
+        oracle.run(r, c, sy.T_e0[keep], Tl[keep], sy.params, N_SUB, gated=gated[keep], e_atom=e)
+        i = int(np.searchsorted(keep, sd))
+        assert abs(E[sd] - e[i]) < 1e-5 * scale
+    ctx.close()

@@ -248,14 +248,6 @@ def test_c4_plain_fp64_systems_one_after_another_matches_oracle():
 
 
 # ---------------------------------------------- C3 at full size, sampled ----
-@pytest.fixture(scope="module")
-def c3_full():
-    w = W.c3()                       # 4,000,000 atoms
-    sy = w.systems[0]
-    row, col = oracle_neighbors(sy, w.r_cut)
-    return w, sy, row, col
-
-
 def test_c3_full_size_sampled_light_cone(c3_full):
     """4M-atom jittered FCC in the benchmark's launch configuration: after n
     sub-steps an atom depends only on atoms within n neighbour hops, so the
