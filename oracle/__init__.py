@@ -14,6 +14,7 @@ Function map (paper passages):
   run                forward-Euler sub-steps of Eq. 2 with coupling and Eq. 10
                      source (Section 2.1), ledgers of Eq. 6 (per system and,
                      optionally, per atom)
+  mean_field         mean-field heat capacity and exchange rate (Section 2)
   coupling           Eq. 8 coupling coefficient of the damping force
   damping_step       one explicit velocity step of Eq. 5
   energies           sum of the per-atom electronic energy and of T
@@ -78,7 +79,9 @@ def _load():
         lib.or_neighbors.argtypes = [i32, pd, pd, pd, pd, pd, pi32, d, i32, pi64, pi32, i64]
         lib.or_lattice_temp.argtypes = [i32, pi64, pi32, pd, pd, pd, pd, d, i32, pd, pi32]
         lib.or_run.restype = i64
-        lib.or_run.argtypes = [i32, pi64, pi32, pd, pd, pi32, pd, P(Params), i64, i32, pd, pd]
+        lib.or_run.argtypes = [i32, pi64, pi32, pd, pd, pi32, pd, P(Params), i64, i32, pd, pd,
+                               pi32]
+        lib.or_mean_field.argtypes = [i32, pd, pd, d, d, pd]
         lib.or_coupling.argtypes = [i32, i32, pd, pd, pi32, pd, d, d, d, pd, pd, pd, pd, pd]
         lib.or_damping_step.argtypes = [i32, d, pd, pd, pd, pd, pd, pd, pd, pd]
         lib.or_energies.argtypes = [i32, pd, P(Params), pd]
@@ -171,17 +174,21 @@ def _opt(a, dtype, n):
 
 
 def run(row, col, T, T_lat, params: dict, n_steps: int, step0: int = 0, gated=None,
-        x=None, ledger=None, e_atom=None):
+        x=None, ledger=None, e_atom=None, fixed=None):
     """Forward-Euler sub-steps.  Returns (T_new, ledger[3], n_out_of_range).
 
     ledger = [energy to lattice (eV), source energy (eV), temperature ledger (K)],
     accumulated onto the ``ledger`` argument when given.  ``e_atom`` (float64
     array [n], optional) accumulates in place each atom's energy to the
-    lattice, sum over sub-steps of g (T_i - T_lat,i) dt (Eq. 6)."""
+    lattice, sum over sub-steps of g (T_i - T_lat,i) dt (Eq. 6).  ``fixed``
+    (int array [n], optional): atoms that hold their electronic temperature
+    (Dirichlet boundary); the exchange they would receive goes to the
+    temperature ledger."""
     T = _f64(T).copy()
     n = T.size
     Tl = _f64(T_lat)
     g, gp = _opt(gated, np.int32, n)
+    fx, fp = _opt(fixed, np.int32, n)
     xx, xp = _opt(x, np.float64, n)
     led = np.zeros(3) if ledger is None else _f64(ledger).copy()
     if e_atom is not None:
@@ -189,10 +196,22 @@ def run(row, col, T, T_lat, params: dict, n_steps: int, step0: int = 0, gated=No
     pp = make_params(params)
     bad = _load().or_run(n, _p(row, C.c_int64), _p(col, C.c_int32), _p(T, C.c_double),
                          _p(Tl, C.c_double), gp, xp, C.byref(pp), int(step0), int(n_steps),
-                         _p(led, C.c_double), None if e_atom is None else _p(e_atom, C.c_double))
+                         _p(led, C.c_double), None if e_atom is None else _p(e_atom, C.c_double),
+                         fp)
     if bad < 0:
         raise MemoryError("oracle run allocation failed")
     return T, led, int(bad)
+
+
+def mean_field(T, T_lat, lambda_atom, k_coef):
+    """Mean-field parameters of Section 2: (c, K) = (lambda_atom mean(T_e),
+    k_coef / mean(T_lat))."""
+    T = _f64(T)
+    Tl = _f64(T_lat)
+    out = np.zeros(2)
+    _load().or_mean_field(T.size, _p(T, C.c_double), _p(Tl, C.c_double), float(lambda_atom),
+                          float(k_coef), _p(out, C.c_double))
+    return float(out[0]), float(out[1])
 
 
 XI_INSTANT, XI_LEDGER = 0, 1

@@ -344,11 +344,18 @@ void or_lattice_temp(int32_t n, const int64_t *row_ptr, const int32_t *col,
 
 /* ---- one forward-Euler sub-step of Eq. 2 (+ coupling + source) -----------
  * Reads T (step n), writes Tn (step n+1).  Per-atom ledger terms go to
- * e2l (g_i (T_i - T_lat,i)), src (q_i) and inv_c (1/c_i). */
+ * e2l (g_i (T_i - T_lat,i)), src (q_i) and lt (the rate of the temperature
+ * ledger: (g_i (T_i - T_lat,i) - q_i) / c_i).
+ * Atoms with fixed[i] != 0 hold their electronic temperature (the Dirichlet
+ * electronic boundary of Section 4): their neighbours still exchange with
+ * them, they keep T_i, and the exchange they would have received,
+ * span K S_i, goes to the temperature ledger instead, so that
+ * sum_i T_i + ledger stays invariant (the exchange sums to zero over all
+ * atoms). */
 static void or_step(int32_t n, const int64_t *row_ptr, const int32_t *col,
                     const double *T, const double *T_lat, const int32_t *gated,
-                    const double *x, const or_params *p, double t,
-                    double *Tn, double *e2l, double *src, double *inv_c)
+                    const int32_t *fixed, const double *x, const or_params *p, double t,
+                    double *Tn, double *e2l, double *src, double *lt)
 {
     const double span = p->T_max - p->T_min;
     #pragma omp parallel for schedule(static)
@@ -363,11 +370,35 @@ static void or_step(int32_t n, const int64_t *row_ptr, const int32_t *col,
         double coup = (gated && gated[i]) ? 0.0 : p->g * (T[i] - T_lat[i]);
         double qi = or_laser_q(p, x ? x[i] : 0.0, t);
         double R = span * p->K * S - coup / c + qi / c;
-        Tn[i] = T[i] + p->dt * R;
         e2l[i] = coup;
         src[i] = qi;
-        inv_c[i] = 1.0 / c;
+        if (fixed && fixed[i]) {
+            Tn[i] = T[i];
+            lt[i] = span * p->K * S;
+        } else {
+            Tn[i] = T[i] + p->dt * R;
+            lt[i] = (coup - qi) / c;
+        }
     }
+}
+
+/* Mean-field parameters of Section 2: at each MD step the heat capacity and
+ * the exchange rate follow the system's mean electronic and lattice
+ * temperatures, C_e = lambda mean(T_e) and kappa_e = kappa_0 mean(T_e) /
+ * mean(T_lat); in Eq. 3 mean(T_e) cancels, K = 2 d kappa_0 / (lambda S
+ * mean(T_lat)).  out[0] = c = lambda_atom mean(T_e) (eV/K per atom), out[1] =
+ * K = k_coef / mean(T_lat) (1/fs), k_coef = 2 d kappa_0 / (lambda S) (K/fs).
+ * Means over all atoms of the system in ascending order. */
+void or_mean_field(int32_t n, const double *T, const double *T_lat, double lambda_atom,
+                   double k_coef, double *out)
+{
+    double st = 0.0, sl = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        st += T[i];
+        sl += T_lat[i];
+    }
+    out[0] = lambda_atom * (st / (double)n);
+    out[1] = k_coef / (sl / (double)n);
 }
 
 static int64_t or_count_out_of_range(int32_t n, const double *T, const or_params *p)
@@ -393,20 +424,20 @@ static int64_t or_count_out_of_range(int32_t n, const double *T, const or_params
 int64_t or_run(int32_t n, const int64_t *row_ptr, const int32_t *col, double *T,
                const double *T_lat, const int32_t *gated, const double *x,
                const or_params *p, int64_t step0, int32_t n_steps, double *ledger,
-               double *e_atom)
+               double *e_atom, const int32_t *fixed)
 {
     size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
-    double *Tn = malloc(sz), *e2l = malloc(sz), *src = malloc(sz), *ic = malloc(sz);
-    if (!Tn || !e2l || !src || !ic) { free(Tn); free(e2l); free(src); free(ic); return -1; }
+    double *Tn = malloc(sz), *e2l = malloc(sz), *src = malloc(sz), *lt = malloc(sz);
+    if (!Tn || !e2l || !src || !lt) { free(Tn); free(e2l); free(src); free(lt); return -1; }
     int64_t bad = or_count_out_of_range(n, T, p);
     for (int32_t s = 0; s < n_steps; ++s) {
         double t = (double)(step0 + s) * p->dt;
-        or_step(n, row_ptr, col, T, T_lat, gated, x, p, t, Tn, e2l, src, ic);
+        or_step(n, row_ptr, col, T, T_lat, gated, fixed, x, p, t, Tn, e2l, src, lt);
         double a = 0, b = 0, c = 0;
         for (int32_t i = 0; i < n; ++i) {
             a += e2l[i] * p->dt;
             b += src[i] * p->dt;
-            c += p->dt * (e2l[i] - src[i]) * ic[i];
+            c += p->dt * lt[i];
         }
         ledger[0] += a;
         ledger[1] += b;
@@ -416,7 +447,7 @@ int64_t or_run(int32_t n, const int64_t *row_ptr, const int32_t *col, double *T,
         memcpy(T, Tn, sz);
         bad += or_count_out_of_range(n, T, p);
     }
-    free(Tn); free(e2l); free(src); free(ic);
+    free(Tn); free(e2l); free(src); free(lt);
     return bad;
 }
 
@@ -501,7 +532,7 @@ int or_adjoint(int32_t n, const int64_t *row_ptr, const int32_t *col, const doub
     if (n_steps > 0) memcpy(states, T0, sz);
     for (int32_t s = 0; s + 1 < n_steps; ++s) {
         double t = (double)(step0 + s) * p->dt;
-        or_step(n, row_ptr, col, states + (size_t)s * n, T_lat, gated, x, p, t,
+        or_step(n, row_ptr, col, states + (size_t)s * n, T_lat, gated, NULL, x, p, t,
                 states + (size_t)(s + 1) * n, e2l, src, ic);
     }
     memcpy(lam, w, sz);

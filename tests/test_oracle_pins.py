@@ -538,3 +538,91 @@ def test_damping_step_force_obeys_newton_in_md_units():
     # a uniform xi scales every velocity by (1 + xi dt) and leaves directions
     v2 = oracle.damping_step(dt, np.full(n, 0.05), None, mass, vel)
     np.testing.assert_allclose(v2, vel * (1.0 + 0.05 * dt), rtol=1e-15)
+
+
+# ---------------------- Section 2 mean-field mode, Section 4 fixed electrons ----
+def _bar(nx=16, nyz=3):
+    """FCC bar, periodic in y and z, free in x."""
+    pos, L = W.fcc(nx, nyz, nyz)
+    lo = np.array([-0.25 * W.A_LAT, 0.0, 0.0])
+    box = np.array([L[0] + 0.5 * W.A_LAT, L[1], L[2]])
+    return pos, lo, box, np.array([0, 1, 1], np.int32)
+
+
+def test_fixed_atoms_hold_and_temperature_ledger_books_their_exchange():
+    s = W.c4_slab(3000, 0.4)
+    row, col = _nbrs(s, 1.1 * W.A_LAT)
+    p = dict(s.params, g=2e-6)
+    x = s.pos[0]
+    T0 = s.T_e0 + np.linspace(0, 500, s.n)
+    fixed = ((x < x.min() + W.A_LAT) | (x > x.max() - W.A_LAT)).astype(np.int32)
+    assert 0 < fixed.sum() < s.n // 2
+    T, led, bad = oracle.run(row, col, T0, s.T_l, p, 3000, x=x, fixed=fixed)
+    assert bad == 0
+    held = fixed == 1
+    assert np.array_equal(T[held], T0[held])
+    assert not np.allclose(T[~held], T0[~held])
+    # the exchange sums to zero over all atoms, so the held atoms' share booked
+    # in the temperature ledger keeps sum T + ledger invariant
+    assert T.sum() + led[2] == pytest.approx(T0.sum(), rel=1e-13)
+
+
+def test_fixed_ends_relax_bar_to_the_linear_steady_profile():
+    # small amplitude around 3,000 K, no coupling: the linearised exchange on a
+    # centrosymmetric lattice annihilates any linear profile, so with the two
+    # end cells held on a line the free atoms converge onto that line
+    pos, lo, box, per = _bar()
+    row, col = oracle.neighbors(pos, lo, box, per, 1.1 * W.A_LAT)
+    x = pos[0]
+    delta = 5.0
+    line = 3000.0 + delta * (2.0 * (x - x.min()) / (x.max() - x.min()) - 1.0)
+    fixed = ((x < x.min() + 0.9 * W.A_LAT) | (x > x.max() - 0.9 * W.A_LAT)).astype(np.int32)
+    rng = np.random.default_rng(41)
+    T0 = np.where(fixed == 1, line, 3000.0 + rng.uniform(-delta, delta, x.size))
+    p = W.default_params(g=0.0, ce_model=W.CE_CONST, ce_const=W.C_NI)
+    T1, _, _ = oracle.run(row, col, T0, np.full(x.size, 300.0), p, 6000, fixed=fixed)
+    T2, _, _ = oracle.run(row, col, T1, np.full(x.size, 300.0), p, 2000, step0=6000, fixed=fixed)
+    free = fixed == 0
+    assert np.max(np.abs(T2 - T1)[free]) < 1e-6 * delta          # converged
+    # the O((dT/T_max)^2) nonlinearity of the pair term bends it by < 1e-3 delta
+    assert np.max(np.abs(T2 - line)[free]) < 1e-3 * delta
+
+
+def test_mean_field_rate_drops_mean_Te_and_matches_eq3_in_si():
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    a = W.A_LAT * 1e-10
+    v_atom = a ** 3 / 4
+    eV = 1.602176634e-19
+    lam = c["lambda_J_per_m3K2"]["value"]
+    kap0 = c["kappa_e_W_per_mK"]["value"]
+    d = c["d_md"]["value"]
+    S = 12 * a * a                        # lattice sum of the 1.1a shell (pinned above)
+    lam_atom = lam * v_atom / eV          # eV/K^2 per atom
+    k_coef = 2 * d * kap0 / (lam * S) * 1e-15   # K/fs
+    rng = np.random.default_rng(43)
+    Tl = rng.uniform(250.0, 350.0, 400)
+    Ks = []
+    for Te_mean in (400.0, 3000.0, 9000.0):
+        T = rng.normal(Te_mean, 40.0, 400)
+        cc, K = oracle.mean_field(T, Tl, lam_atom, k_coef)
+        # Eq. 3 in SI with the Section 2 relations kappa_e = kappa_0 Te / Tl, C_e = lambda Te
+        Te_b, Tl_b = T.mean(), Tl.mean()
+        K_si = 2 * (kap0 * Te_b / Tl_b) * d / ((lam * Te_b) * S)
+        assert K == pytest.approx(K_si * 1e-15, rel=1e-12)
+        assert cc == pytest.approx(lam * Te_b * v_atom / eV, rel=1e-12)
+        Ks.append(K)
+    assert Ks[0] == pytest.approx(Ks[1], rel=1e-14) == pytest.approx(Ks[2], rel=1e-14)
+    # at T_e = T_lat = C_e / lambda the mean-field rate is the Section 3.1 constant K
+    Teq = c["Ce_J_per_m3K"]["value"] / lam
+    _, K_eq = oracle.mean_field(np.full(10, Teq), np.full(10, Teq), lam_atom, k_coef)
+    assert K_eq == pytest.approx(W.K_NI, rel=1e-4)
+
+
+def test_mean_field_heat_capacity_sets_relaxation_of_uniform_system():
+    row, col, _, _, _ = _isolated_atoms(n=50)
+    T0, Tl = np.full(50, 5000.0), np.full(50, 300.0)
+    cc, K = oracle.mean_field(T0, Tl, 1e-5, 300.0)
+    p = W.default_params(g=2e-4, K=K, ce_model=W.CE_CONST, ce_const=cc)
+    T, led, _ = oracle.run(row, col, T0, Tl, p, 500)
+    # c = lambda mean(T_e) = 0.05 eV/K held over the advance
+    np.testing.assert_allclose(T, 300.0 + 4700.0 * (1.0 - p["dt"] * 2e-4 / 0.05) ** 500, rtol=1e-12)
