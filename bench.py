@@ -18,6 +18,8 @@ Also reported:
   * the lattice side on the same system: sub-step cost with the per-atom energy
     record off and on, the Eq. 8 coupling coefficient and one Eq. 5 velocity
     step, against HBM bandwidth;
+  * the sub-step cost with a shell of held electronic temperatures and the
+    mean-field parameter refresh at every advance;
   * the FP64 CPU oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -170,6 +172,43 @@ def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):
     return out
 
 
+def bench_boundary_mean_field(L, torch, h, sy, n_sub=10, reps=40):
+    """Held electronic temperatures on a spherical shell (Section 4 boundary)
+    and the Section 2 mean-field refresh at the start of every advance, on the
+    same system: cost per sub-step against the plain advance."""
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def per_substep():
+        L.l2t_advance(h, n_sub)                 # warm-up (graph capture)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            L.l2t_advance(h, n_sub)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e3 / (reps * n_sub)
+
+    plain = per_substep()
+    r2 = ((sy.pos - (sy.box_len / 2)[:, None]) ** 2).sum(0)
+    held = ((r2 > 60.0 ** 2) & (r2 < 64.0 ** 2)).astype(np.float64)
+    lam_atom = 1065.0 * (sy.params["v_atom"] * 1e-30) / 1.602176634e-19
+    k_coef = 2 * 3 * 91.0 / (1065.0 * 12 * (3.61e-10) ** 2) * 1e-15
+    L.l2t_set_field(h, 0, L.L2T_FIELD_FIXED, held)
+    held_only = per_substep()
+    L.l2t_set_mean_field(h, 0, True, lam_atom, k_coef)
+    both = per_substep()
+    L.l2t_set_field(h, 0, L.L2T_FIELD_FIXED, np.zeros(sy.n))
+    mf_only = per_substep()
+    L.l2t_set_mean_field(h, 0, False)
+    log(f"  per sub-step: plain {plain:.1f} us, held shell {held_only:.1f} us, mean field "
+        f"{mf_only:.1f} us, both {both:.1f} us")
+    return dict(substeps_per_advance=n_sub, held_atoms=int(held.sum()), substep_us_plain=plain,
+                substep_us_held=held_only, substep_us_mean_field=mf_only,
+                substep_us_held_and_mean_field=both,
+                mean_field_refresh_us_per_advance=(mf_only - plain) * n_sub)
+
+
 def cpu_baseline(sy, r_cut, n_steps):
     import oracle
     row, col = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, r_cut)
@@ -248,10 +287,12 @@ def main():
         log(f"step {k + 1}/{args.steps}: advance {adv_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    md = None
+    md = bnd = None
     if not args.no_md:
         log("MD coupling (Eq. 5, Eq. 8) ...")
         md = bench_md_coupling(L, torch, h, sy, d)
+        log("held atoms and mean-field refresh ...")
+        bnd = bench_boundary_mean_field(L, torch, h, sy)
     n_atom_steps = sy.n * args.substeps * args.steps
     value = n_atom_steps / wall
     mx, mean = L.l2t_build_neighbors(h, w.r_cut)
@@ -291,6 +332,7 @@ def main():
                            T_max=e["T_max_atom"]))
     if md is not None:
         out["md_coupling"] = md
+        out["boundary_mean_field"] = bnd
     ctx.close()
     if not args.no_c4:
         log("C4 batched vs plain ...")

@@ -82,6 +82,8 @@ extern "C" {
 #define L2T_FIELD_ELAT  4   /* energy the atom handed to the lattice during the last advance of its
                                system, sum over sub-steps of g (T_i - T_i^lat) dt, eV (read only;
                                recorded while L2T_OPT_ATOM_LEDGER is on) */
+#define L2T_FIELD_FIXED 5   /* 1.0 where the atom holds its T_e (the fixed electronic boundary of
+                               Section 4), else 0.0 (read/write; cleared by l2t_build_neighbors) */
 
 /* ---- electronic heat capacity models (per atom) ---------------------------- */
 #define L2T_CE_CONST   0   /* c = ce_const */
@@ -137,10 +139,25 @@ typedef struct {
     double v_atom;          /* atomic volume V_atom = V/N, A^3 */
 } l2t_params;
 
+/* Mean-field parameter mode of Section 2: the heat capacity and the exchange
+ * rate follow the system's mean electronic and lattice temperatures, C_e =
+ * lambda mean(T_e) and kappa_e = kappa_0 mean(T_e) / mean(T_lat).  With Eq. 3
+ * the mean electronic temperature cancels from K.  The means are taken on the
+ * device at the start of every advance (once per MD step of the caller) and
+ * held for its sub-steps. */
+typedef struct {
+    int32_t on;             /* 1 = refresh c and K at the start of every advance */
+    int32_t reserved;       /* 0 */
+    double lambda;          /* c = lambda mean(T_e): lambda_vol V_atom, eV/K^2 per atom (> 0) */
+    double k_coef;          /* K = k_coef / mean(T^lat): 2 d kappa_0 / (lambda_vol S), K/fs (> 0),
+                               S the lattice sum of |r_ij|^2 as in l2t_exchange_rate */
+} l2t_mean_field;
+
 /* Per-system ledger, FP64.  With any heat capacity model,
  * sum_T + T_ledger_acc is conserved by the sub-step (the exchange term sums
- * to zero over the system); with a constant uniform c,
- * E_e + E_e_to_l - E_src is conserved too. */
+ * to zero over the system; the exchange an atom with a fixed T_e would have
+ * received is booked in T_ledger_acc); with a constant uniform c and no fixed
+ * atoms, E_e + E_e_to_l - E_src is conserved too. */
 typedef struct {
     double t;               /* time of the current state, fs */
     int64_t step;           /* sub-steps taken since the last l2t_set_field(TE) */
@@ -198,6 +215,19 @@ int l2t_get_neighbors(l2t_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *col,
  * non-positive heat capacity constants, laser_lp or laser_sigma <= 0). */
 int l2t_set_params(l2t_ctx *ctx, int32_t sys, const l2t_params *p);
 
+/* Mean-field parameter mode of system sys (Section 2, see l2t_mean_field).
+ * While on, the system's ce_model and ce_const and its K are replaced at the
+ * start of every advance: c = lambda mean(T_e) (constant over the system and
+ * over the advance), K = k_coef / mean(T^lat).  Needs T^lat for the advance.
+ * Errors: EINVAL (lambda or k_coef not > 0 while on), ESTATE (parameters not
+ * set).  An advance whose mean T^lat is not > 0 reports ERANGE. */
+int l2t_set_mean_field(l2t_ctx *ctx, int32_t sys, const l2t_mean_field *mf);
+
+/* The parameters of system sys in effect for the last (or next) sub-step:
+ * those of l2t_set_params, with K, ce_model and ce_const as the last
+ * mean-field refresh set them.  Synchronises. */
+int l2t_get_params(l2t_ctx *ctx, int32_t sys, l2t_params *out);
+
 /* Write a per-atom field of system sys from src[n] (FP64, caller order).
  * Writing L2T_FIELD_TE restarts the system's ledger and step counter.
  * Synchronises.  Errors: ESTATE (neighbours not built), EINVAL (unknown or
@@ -224,7 +254,8 @@ int l2t_set_velocities(l2t_ctx *ctx, int32_t sys, const double *v, const double 
 
 /* Advance every system by n_substeps explicit forward-Euler sub-steps of
  * Eq. 2 (Section 2.1), Jacobi-synchronous: every read in sub-step n sees the
- * step-n state.  L2T_FP64: one launch per sub-step per system, the systems
+ * step-n state.  Atoms flagged L2T_FIELD_FIXED keep their T_e; their
+ * neighbours exchange with them as usual.  L2T_FP64: one launch per sub-step per system, the systems
  * one after another.  L2T_FP32C: all systems together; with
  * L2T_OPT_PERSISTENT, all sub-steps in one persistent launch.  Asynchronous;
  * a range violation is reported by the next synchronising call as ERANGE.
@@ -238,7 +269,8 @@ int l2t_advance_system(l2t_ctx *ctx, int32_t sys, int32_t n_substeps);
  * state is stored every ckpt_every sub-steps (device memory, about
  * ceil(n/ckpt) * 8 bytes per atom) and the sub-steps in between are recomputed
  * by the adjoint with the same kernels, so the recomputation is bitwise equal
- * to the forward.  Errors: as l2t_advance; EINVAL (ckpt_every < 1); ENOMEM. */
+ * to the forward.  Errors: as l2t_advance; EINVAL (ckpt_every < 1); ENOMEM;
+ * ENOTIMPL (a system with fixed atoms or in the mean-field mode). */
 int l2t_advance_recorded(l2t_ctx *ctx, int32_t n_substeps, int32_t ckpt_every);
 
 /* Discrete adjoint of the last recorded advance (derived from Eq. 2 by

@@ -165,6 +165,8 @@ int check_err(l2t_ctx *c) {
     if (h & l2t::kErrRange)
         return l2t::fail(c, L2T_ERANGE,
                          "a sub-step produced theta outside [0,1] or a non-finite temperature");
+    if (h & l2t::kErrMeanField)
+        return l2t::fail(c, L2T_ERANGE, "mean-field refresh: a system's mean T_lat is not > 0");
     return L2T_OK;
 }
 
@@ -208,7 +210,7 @@ bool ready_to_advance(l2t_ctx *c, int32_t s0, int32_t s1, std::string *why) {
 
 extern "C" {
 
-int l2t_version(void) { return 10000; }
+int l2t_version(void) { return 10100; }
 
 const char *l2t_strerror(int status) {
     switch (status) {
@@ -266,6 +268,7 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c->eatom);
     dfree(c->slice_red);
     dfree(c->energy_out);
+    if (c->mf_chunks) (void)hipFree(c->mf_chunks);
     dfree(c->dparams);
     dfree(c->dstep);
     dfree(c->derr);
@@ -381,13 +384,18 @@ int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mea
         st.has_te = false;   // internal order changed: fields must be written again
         st.has_tl = false;
         st.eatom_valid = false;
+        st.has_fixed = false;
     }
-    // per-atom fields start at zero (T^lat = 0, no gate)
+    // per-atom fields start at zero (T^lat = 0, no gate, no fixed atoms)
     if (c->precision == L2T_FP64) {
         L2T_HIP(c, hipMemsetAsync(c->Tl64, 0, sizeof(double) * c->n_int, c->stream));
+        L2T_HIP(c, hipMemsetAsync(c->srcw64, 0, sizeof(double) * c->n_int, c->stream));
     } else {
         L2T_HIP(c, hipMemsetAsync(c->Tl32, 0, sizeof(float) * c->n_int, c->stream));
+        L2T_HIP(c, hipMemsetAsync(c->srcw32, 0, sizeof(float) * c->n_int, c->stream));
     }
+    rc = l2t::upload_params(c);   // new layout offsets, no fixed atoms
+    if (rc != L2T_OK) return rc;
     for (int32_t s = 0; s < (int32_t)c->sys.size(); ++s)
         if (c->sys[s].has_params) {
             rc = l2t::source_weights(c, s);
@@ -452,7 +460,8 @@ int l2t_set_params(l2t_ctx *c, int32_t sys, const l2t_params *p) {
 
 int l2t_set_field(l2t_ctx *c, int32_t sys, int32_t field, const double *src, int32_t mem) {
     if (bad_sys(c, sys) || !src) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
-    if (field != L2T_FIELD_TE && field != L2T_FIELD_TL && field != L2T_FIELD_GATE)
+    if (field != L2T_FIELD_TE && field != L2T_FIELD_TL && field != L2T_FIELD_GATE &&
+        field != L2T_FIELD_FIXED)
         return l2t::fail(c, L2T_EINVAL, "unknown or read-only field");
     if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
     SystemState &st = c->sys[sys];
@@ -482,6 +491,17 @@ int l2t_set_field(l2t_ctx *c, int32_t sys, int32_t field, const double *src, int
         c->rec.valid = false;
     } else if (field == L2T_FIELD_TL) {
         st.has_tl = true;
+    } else if (field == L2T_FIELD_FIXED) {
+        // any nonzero entry marks the system as holding some atoms
+        bool none = true;
+        rc = l2t::check_field_range(c, dsrc, st.desc.n_atoms, 0.0, 0.0, &none);
+        if (rc != L2T_OK) return rc;
+        st.has_fixed = !none;
+        c->rec.valid = false;
+        rc = l2t::mark_held_slices(c, sys);
+        if (rc != L2T_OK) return rc;
+        rc = l2t::upload_params(c);
+        if (rc != L2T_OK) return rc;
     }
     L2T_HIP(c, hipStreamSynchronize(c->stream));
     return L2T_OK;
@@ -489,7 +509,7 @@ int l2t_set_field(l2t_ctx *c, int32_t sys, int32_t field, const double *src, int
 
 int l2t_get_field(l2t_ctx *c, int32_t sys, int32_t field, double *dst, int32_t mem) {
     if (bad_sys(c, sys) || !dst) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
-    if (field < L2T_FIELD_TE || field > L2T_FIELD_ELAT)
+    if (field < L2T_FIELD_TE || field > L2T_FIELD_FIXED)
         return l2t::fail(c, L2T_EINVAL, "unknown field");
     if (mem != L2T_HOST && mem != L2T_DEVICE) return l2t::fail(c, L2T_EINVAL, "bad mem");
     if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
@@ -639,6 +659,10 @@ int l2t_advance_recorded(l2t_ctx *c, int32_t n, int32_t ckpt_every) {
     if (!c || n < 1 || ckpt_every < 1) return l2t::fail(c, L2T_EINVAL, "need n >= 1, ckpt >= 1");
     if (c->precision != L2T_FP32C)
         return l2t::fail(c, L2T_ENOTIMPL, "the adjoint is provided for the FP32C path");
+    for (const auto &st : c->sys)
+        if (st.has_fixed || st.mf.on)
+            return l2t::fail(c, L2T_ENOTIMPL,
+                             "the adjoint is not provided for fixed atoms or the mean-field mode");
     std::string why;
     if (!ready_to_advance(c, 0, (int32_t)c->sys.size(), &why)) return l2t::fail(c, L2T_ESTATE, why);
     l2t::Recording &r = c->rec;
@@ -689,6 +713,37 @@ int l2t_adjoint(l2t_ctx *c, const double *dL_dTN, int32_t mem, double *dL_dK, do
         L2T_HIP(c, hipStreamSynchronize(c->stream));
     }
     return check_err(c);
+}
+
+int l2t_set_mean_field(l2t_ctx *c, int32_t sys, const l2t_mean_field *mf) {
+    if (bad_sys(c, sys) || !mf) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    SystemState &st = c->sys[sys];
+    if (!st.has_params) return l2t::fail(c, L2T_ESTATE, "set parameters before the mean-field mode");
+    if (mf->on && (!(mf->lambda > 0.0) || !std::isfinite(mf->lambda) || !(mf->k_coef > 0.0) ||
+                   !std::isfinite(mf->k_coef)))
+        return l2t::fail(c, L2T_EINVAL, "lambda and k_coef must be finite and > 0");
+    st.mf = *mf;
+    st.mf.on = mf->on ? 1 : 0;
+    c->rec.valid = false;
+    l2t::drop_graphs(c);
+    int rc = l2t::upload_params(c);
+    if (rc != L2T_OK) return rc;
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    return L2T_OK;
+}
+
+int l2t_get_params(l2t_ctx *c, int32_t sys, l2t_params *out) {
+    if (bad_sys(c, sys) || !out) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    const SystemState &st = c->sys[sys];
+    if (!st.has_params) return l2t::fail(c, L2T_ESTATE, "parameters not set");
+    l2t::DevParams p{};
+    L2T_HIP(c, hipMemcpyAsync(&p, c->dparams + sys, sizeof(p), hipMemcpyDeviceToHost, c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    *out = st.params;
+    out->K = p.K;
+    out->ce_model = p.ce_model;
+    out->ce_const = p.ce_const;
+    return L2T_OK;
 }
 
 int l2t_coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *v,

@@ -354,7 +354,8 @@ __global__ void k_halo_expand(const HaloCell *hc, int64_t n_hc, const BrickInfo 
 
 __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                            const double *src, int32_t field, int32_t precision, double *T64,
-                           float *Thi, float *Tlo, double *Tl64, float *Tl32) {
+                           float *Thi, float *Tlo, double *Tl64, float *Tl32, double *srcw64,
+                           float *srcw32) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_pad) return;
     int32_t slot = atom_off + k;
@@ -381,13 +382,22 @@ __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm,
         } else {
             Tl32[slot] = gated ? -fabsf(Tl32[slot]) : fabsf(Tl32[slot]);
         }
+    } else if (field == L2T_FIELD_FIXED) {
+        // the sign bit of the source weight marks an atom that holds its T_e
+        bool fixed = (g >= 0) && v != 0.0;
+        if (precision == L2T_FP64) {
+            srcw64[slot] = fixed ? -fabs(srcw64[slot]) : fabs(srcw64[slot]);
+        } else {
+            srcw32[slot] = fixed ? -fabsf(srcw32[slot]) : fabsf(srcw32[slot]);
+        }
     }
 }
 
 __global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                             int32_t field, int32_t precision, const double *T64, const float *Thi,
                             const float *Tlo, const double *Tl64, const float *Tl32,
-                            const int32_t *cnt, const double *eatom, double *dst) {
+                            const int32_t *cnt, const double *eatom, const double *srcw64,
+                            const float *srcw32, double *dst) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_pad) return;
     int32_t slot = atom_off + k;
@@ -405,8 +415,26 @@ __global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm
         v = (double)cnt[slot];
     } else if (field == L2T_FIELD_ELAT) {
         v = eatom[slot];
+    } else if (field == L2T_FIELD_FIXED) {
+        bool s = (precision == L2T_FP64) ? signbit(srcw64[slot]) : signbit(srcw32[slot]);
+        v = s ? 1.0 : 0.0;
     }
     dst[g - caller_off] = v;
+}
+
+// kSliceHeld of every slice of a system from the sign bits of its source weights
+__global__ void k_slice_held(SliceInfo *slices, int32_t slice0, int32_t n_slices,
+                             int32_t precision, const double *srcw64, const float *srcw32) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (q >= n_slices) return;
+    const int32_t sl = slice0 + q;
+    const int32_t slot = sl * kWave + lane;
+    const bool held = lane < slices[sl].n_valid &&
+                      ((precision == L2T_FP64) ? signbit(srcw64[slot]) : signbit(srcw32[slot]));
+    const bool any = __any(held);
+    if (lane == 0) slices[sl].flags = any ? (slices[sl].flags | kSliceHeld)
+                                          : (slices[sl].flags & ~kSliceHeld);
 }
 
 __global__ void k_range_count(const double *v, int64_t n, double lo, double hi, unsigned *bad) {
@@ -522,8 +550,9 @@ __global__ void k_source_weights(int32_t atom_off, int32_t n_pad, const int32_t 
     if (k >= n_pad) return;
     int32_t slot = atom_off + k;
     double w = (perm[slot] >= 0) ? exp(-(qx[slot] - x0) / lp) : 0.0;
-    if (w64) w64[slot] = w;
-    if (w32) w32[slot] = (float)w;
+    // keep the sign bit: it marks atoms that hold their T_e
+    if (w64) w64[slot] = copysign(w, w64[slot]);
+    if (w32) w32[slot] = copysignf((float)w, w32[slot]);
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -987,7 +1016,16 @@ int permute_in(l2t_ctx *c, int32_t sys, const double *src_dev, int32_t field) {
     const SystemState &st = c->sys[sys];
     hipLaunchKernelGGL(k_field_in, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream, st.atom_off,
                        st.n_pad, c->perm, st.caller_off, src_dev, field, c->precision,
-                       c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32);
+                       c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32, c->srcw64,
+                       c->srcw32);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+int mark_held_slices(l2t_ctx *c, int32_t sys) {
+    const SystemState &st = c->sys[sys];
+    hipLaunchKernelGGL(k_slice_held, dim3(nblk(st.n_slices, 4)), dim3(256), 0, c->stream, c->slices,
+                       st.slice0, st.n_slices, c->precision, c->srcw64, c->srcw32);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;
 }
@@ -997,7 +1035,7 @@ int permute_out(l2t_ctx *c, int32_t sys, int32_t field, double *dst_dev) {
     hipLaunchKernelGGL(k_field_out, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream,
                        st.atom_off, st.n_pad, c->perm, st.caller_off, field, c->precision,
                        c->T64[c->cur], c->Thi[c->cur], c->Tlo, c->Tl64, c->Tl32, c->cnt, c->eatom,
-                       dst_dev);
+                       c->srcw64, c->srcw32, dst_dev);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;
 }

@@ -130,9 +130,10 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         const int32_t w = __builtin_amdgcn_readfirstlane(slices[sl].width);
         const int32_t nv = __builtin_amdgcn_readfirstlane(slices[sl].n_valid);
         const int32_t base = __builtin_amdgcn_readfirstlane(slices[sl].colw_base64);
+        const int32_t held = __builtin_amdgcn_readfirstlane(slices[sl].flags) & kSliceHeld;
         const int32_t slot = sl * kWave + lane;
         const float lo = Tlo[slot], tl = Tl[slot];
-        const float sw = p.laser_on ? srcw[slot] : 0.0f;
+        const float sw = (p.laser_on | held) ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
         const LedgerTerms t = slice_core_brick(w, slot, lane < nv, p, Ti, lo, tl, sw,
                                                colw + (int64_t)base * kWave, lane, tile, Thi_n,
@@ -204,6 +205,78 @@ __global__ __launch_bounds__(256) void k_persistent_fp32c(
                              dstep[si.sys] + st, ledger, eatom, err);
         }
         if (!grid_barrier(bar, G, (unsigned)st + 1u, err)) return;
+    }
+}
+
+// Mean-field parameters (Section 2), first level: one workgroup of 4 waves per
+// chunk of a system's slices; lanes accumulate T_e and |T^lat| of the valid
+// atoms of slices wave, wave + 4, ..., then a fixed-order reduction.
+__global__ __launch_bounds__(256) void k_mf_chunks(const MfChunk *chunks, int32_t chunk0,
+                                                   const SliceInfo *slices, int32_t precision,
+                                                   const double *T64, const float *Thi,
+                                                   const float *Tlo, const double *Tl64,
+                                                   const float *Tl32, double *part) {
+    const MfChunk ch = chunks[chunk0 + blockIdx.x];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    double t = 0.0, l = 0.0;
+    for (int32_t sl = ch.slice_begin + wave; sl < ch.slice_end; sl += 4) {
+        if (lane < slices[sl].n_valid) {
+            const int32_t slot = sl * kWave + lane;
+            t += (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+            l += (precision == L2T_FP64) ? fabs(Tl64[slot]) : (double)fabsf(Tl32[slot]);
+        }
+    }
+    t = wave_sum(t);
+    l = wave_sum(l);
+    __shared__ double sh[2][4];
+    if (lane == 0) {
+        sh[0][wave] = t;
+        sh[1][wave] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * (int64_t)(chunk0 + blockIdx.x)] = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+        part[2 * (int64_t)(chunk0 + blockIdx.x) + 1] = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+    }
+}
+
+// Second level, one workgroup of 256 per system: fixed-order sum of the chunk
+// partials, then c = lambda mean(T_e) and K = k_coef / mean(T^lat) into the
+// parameter table.
+__global__ __launch_bounds__(256) void k_mf_apply(DevParams *P, int32_t sys0, const double *part,
+                                                  unsigned *err) {
+    DevParams &p = P[sys0 + blockIdx.x];
+    if (!p.mean_field) return;
+    __shared__ double sh[2][256];
+    double t = 0.0, l = 0.0;
+    for (int32_t k = threadIdx.x; k < p.mf_nchunk; k += blockDim.x) {
+        t += part[2 * (int64_t)(p.mf_chunk0 + k)];
+        l += part[2 * (int64_t)(p.mf_chunk0 + k) + 1];
+    }
+    sh[0][threadIdx.x] = t;
+    sh[1][threadIdx.x] = l;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double Te = sh[0][0] / (double)p.n_atoms, Tl = sh[1][0] / (double)p.n_atoms;
+        if (!(Tl > 0.0)) {
+            atomicOr(err, kErrMeanField);
+            return;
+        }
+        const double cv = p.mf_lambda * Te, K = p.mf_kcoef / Tl;
+        p.ce_model = L2T_CE_CONST;
+        p.ce_const = cv;
+        p.f_ce_const = (float)cv;
+        p.K = K;
+        p.A = p.span * K;
+        p.f_A = (float)p.A;
+        p.f_K = (float)K;
     }
 }
 
@@ -345,7 +418,39 @@ int upload_params(l2t_ctx *c) {
         p.f_inv2 = (float)(p.inv_span * p.inv_span);
         p.f_c_tiny = (float)(-p.inv_span * p.inv_span / 3.0);
         p.f_w_tiny = (float)((double)dev::kUTiny * p.span * p.span);
+        p.has_fixed = st.has_fixed ? 1 : 0;
+        p.mean_field = st.mf.on ? 1 : 0;
+        p.n_atoms = st.desc.n_atoms;
+        p.mf_lambda = st.mf.lambda;
+        p.mf_kcoef = st.mf.k_coef;
     }
+    // mean-field chunk table: every system in the mode, in order, its slices in
+    // chunks of kMfChunk
+    std::vector<MfChunk> &chunks = c->h_mf_chunks;
+    chunks.clear();
+    for (int s = 0; s < S; ++s) {
+        DevParams &p = c->hparams[s];
+        const SystemState &st = c->sys[s];
+        p.mf_chunk0 = (int32_t)chunks.size();
+        if (st.mf.on)
+            for (int32_t b = 0; b < st.n_slices; b += kMfChunk)
+                chunks.push_back(MfChunk{s, st.slice0 + b, st.slice0 + std::min(st.n_slices, b + kMfChunk), 0});
+        p.mf_nchunk = (int32_t)chunks.size() - p.mf_chunk0;
+    }
+    c->n_mf_chunks = (int32_t)chunks.size();
+    if (c->n_mf_chunks > c->mf_chunks_cap) {
+        drop_graphs(c);   // captured refreshes hold the old table
+        (void)hipStreamSynchronize(c->stream);
+        if (c->mf_chunks) (void)hipFree(c->mf_chunks);
+        c->mf_chunks = nullptr;
+        c->mf_chunks_cap = 0;
+        if (hipMalloc(&c->mf_chunks, sizeof(MfChunk) * chunks.size()) != hipSuccess)
+            return fail(c, L2T_ENOMEM, "mean-field chunk table allocation failed");
+        c->mf_chunks_cap = c->n_mf_chunks;
+    }
+    if (!chunks.empty())
+        L2T_HIP(c, hipMemcpyAsync(c->mf_chunks, chunks.data(), sizeof(MfChunk) * chunks.size(),
+                                  hipMemcpyHostToDevice, c->stream));
     L2T_HIP(c, hipMemcpyAsync(c->dparams, c->hparams.data(), sizeof(DevParams) * S,
                               hipMemcpyHostToDevice, c->stream));
     return L2T_OK;
@@ -369,6 +474,24 @@ int reset_ledger(l2t_ctx *c, int32_t sys) {
 }
 
 // One system (sys >= 0) or all systems (sys < 0), one launch per sub-step.
+int mean_field_refresh(l2t_ctx *c, int32_t sys) {
+    const int32_t s0 = sys < 0 ? 0 : sys, s1 = sys < 0 ? (int32_t)c->sys.size() : sys + 1;
+    bool any = false;
+    for (int32_t s = s0; s < s1; ++s) any |= c->sys[s].mf.on != 0;
+    if (!any) return L2T_OK;
+    // the chunks of systems s0..s1-1 are contiguous in the table
+    const int32_t ch0 = c->hparams[s0].mf_chunk0;
+    const int32_t ch1 = c->hparams[s1 - 1].mf_chunk0 + c->hparams[s1 - 1].mf_nchunk;
+    if (ch1 > ch0)
+        hipLaunchKernelGGL(k_mf_chunks, dim3(ch1 - ch0), dim3(256), 0, c->stream, c->mf_chunks, ch0,
+                           c->slices, c->precision, c->T64[c->cur], c->Thi[c->cur], c->Tlo,
+                           c->Tl64, c->Tl32, c->slice_red);
+    hipLaunchKernelGGL(k_mf_apply, dim3(s1 - s0), dim3(256), 0, c->stream, c->dparams, s0,
+                       c->slice_red, c->derr);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
 int zero_atom_ledger(l2t_ctx *c, int32_t sys) {
     const int64_t off = sys < 0 ? 0 : c->sys[sys].atom_off;
     const int64_t len = sys < 0 ? c->n_int : c->sys[sys].n_pad;
@@ -385,6 +508,8 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     const int wpb = 4;
     const dim3 grid(nblk(ns, wpb)), block(wpb * kWave);
     double *eatom = atom_ledger_ptr(c);
+    int rc0 = mean_field_refresh(c, sys);
+    if (rc0 != L2T_OK) return rc0;
     int cur = c->cur;
     for (int32_t k = 0; k < n; ++k) {
         if (c->precision == L2T_FP64) {
@@ -482,7 +607,8 @@ void drop_graphs(l2t_ctx *c) {
 int advance_fp32c(l2t_ctx *c, int32_t n) {
     const Tuning &t = c->tune;
     if (!t.graph) {
-        int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
+        int rc = mean_field_refresh(c, -1);
+        if (rc == L2T_OK) rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
         if (rc != L2T_OK) return rc;
     } else {
         GraphKey key{n, (c->cur << 8) | (t.persistent << 4) | t.kernel, t.block};
@@ -496,7 +622,9 @@ int advance_fp32c(l2t_ctx *c, int32_t n) {
             hipStream_t user = c->stream;
             L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
             c->stream = c->cap_stream;
-            int rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
+            int rc = mean_field_refresh(c, -1);
+            if (rc == L2T_OK)
+                rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
             c->stream = user;
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
             if (rc != L2T_OK) return rc;

@@ -22,6 +22,7 @@ constexpr unsigned kErrRange = 1u;      // theta outside [0,1] or non-finite T
 constexpr unsigned kErrBox = 2u;        // atom outside the box on a free axis
 constexpr unsigned kErrBarrier = 4u;    // persistent-kernel barrier spin limit hit
 constexpr unsigned kErrCellOverflow = 8u;
+constexpr unsigned kErrMeanField = 16u;  // mean T^lat not > 0 at a mean-field refresh
 
 // One wavefront-sized slice of 64 consecutive internal atoms.  The neighbour
 // indices of the slice are stored column-major: entry k of lane l lives at
@@ -34,8 +35,10 @@ struct SliceInfo {
     int32_t n_valid;
     int32_t brick;      // brick that owns the slice
     int32_t colw_base64;  // packed brick-local table: word k/2 of lane l at 64*(colw_base64 + k/2) + l
-    int32_t pad_[2];
+    int32_t flags;      // kSliceHeld: some atom of the slice holds its T_e
+    int32_t pad_;
 };
+constexpr int32_t kSliceHeld = 1;
 
 // A brick of up to b x b x b cells: its own slots (padded to 64) and the halo
 // atoms of the surrounding one-cell shell, staged together in LDS.  shell maps
@@ -64,6 +67,18 @@ struct DevParams {
     float f_inv_span, f_half_inv_span, f_m_off, f_A, f_K, f_dt, f_g;
     float f_ce_const, f_gamma, f_ce_cap, f_T_min, f_T_max, f_i0;
     float f_inv2, f_c_tiny, f_w_tiny;
+    // fixed electronic temperatures (sign bit of the source weight) and the
+    // mean-field refresh of c and K at the start of every advance
+    int32_t has_fixed, mean_field;
+    int32_t n_atoms, pad_;
+    double mf_lambda, mf_kcoef;
+    int32_t mf_chunk0, mf_nchunk;   // this system's chunks in the mean-field chunk table
+};
+
+// mean-field reduction: a system's slices in chunks of kMfChunk slices
+constexpr int32_t kMfChunk = 32;
+struct MfChunk {
+    int32_t sys, slice_begin, slice_end, pad_;
 };
 
 struct SystemState {
@@ -78,6 +93,8 @@ struct SystemState {
     int64_t cell_off = 0, ncell = 0;
     int64_t step = 0;            // sub-steps since the last T_e write
     bool eatom_valid = false;    // the per-atom ledger holds this system's last advance
+    bool has_fixed = false;      // some atoms hold their T_e
+    l2t_mean_field mf{};         // mean-field parameter mode
     int32_t max_nbrs = 0;
 };
 
@@ -171,6 +188,9 @@ struct l2t_ctx {
     int cur = 0;
 
     double *ledger = nullptr;    // [n_slices][3]
+    l2t::MfChunk *mf_chunks = nullptr;   // mean-field chunk table
+    std::vector<l2t::MfChunk> h_mf_chunks;   // its host copy (source of the upload)
+    int32_t n_mf_chunks = 0, mf_chunks_cap = 0;
     double *eatom = nullptr;     // internal [n_int]: energy to the lattice over the last advance
     bool atom_ledger = false;    // record eatom during advances
     bool eatom_valid = false;    // eatom holds the record of the last advance
@@ -207,6 +227,7 @@ int hip_fail(l2t_ctx *c, hipError_t e, const char *what);
 int build_neighbors(l2t_ctx *c, double r_cut);
 int permute_in(l2t_ctx *c, int32_t sys, const double *src_dev, int32_t field);
 int permute_out(l2t_ctx *c, int32_t sys, int32_t field, double *dst_dev);
+int mark_held_slices(l2t_ctx *c, int32_t sys);   // kSliceHeld from the held atoms
 int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_caller, const double *m_caller,
                         int32_t global_com);
 int neighbors_to_host(l2t_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *col, int64_t cap);
@@ -225,6 +246,8 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
 // per-atom record of the energy handed to the lattice (nullptr while off)
 inline double *atom_ledger_ptr(l2t_ctx *c) { return c->atom_ledger ? c->eatom : nullptr; }
 int zero_atom_ledger(l2t_ctx *c, int32_t sys);   // sys < 0: every system
+// c and K of mean-field systems from their current means (sys < 0: all)
+int mean_field_refresh(l2t_ctx *c, int32_t sys);
 int bump_steps(l2t_ctx *c, int32_t sys, int32_t n);
 void drop_graphs(l2t_ctx *c);
 

@@ -139,18 +139,25 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
         S += tj * (1.0 - ti) * exp(ti - tj) - ti * (1.0 - tj) * exp(tj - ti);
     }
     double e2l = 0.0, q = 0.0, lt = 0.0, Tnew = Ti;
+    // the source weight's sign bit marks atoms that hold their T_e
+    const double sw = (p.laser_on | (si.flags & kSliceHeld)) ? srcw[slot] : 0.0;
     if (valid) {
         const double c = ce64(p, Ti);
         const double tl = Tl[slot];
         const double coup = signbit(tl) ? 0.0 : p.g * (Ti - tl);
-        if (p.laser_on) q = p.i0 * srcw[slot] * pulse64(p, step);
-        Tnew = Ti + p.dt * (p.A * S - coup / c + q / c);
+        if (p.laser_on) q = p.i0 * fabs(sw) * pulse64(p, step);
         e2l = coup * p.dt;
         if (eatom) eatom[slot] += e2l;
-        lt = p.dt * (coup - q) / c;
+        if (p.has_fixed && signbit(sw)) {
+            // held: the exchange it would receive goes to the temperature ledger
+            lt = p.dt * (p.A * S);
+        } else {
+            Tnew = Ti + p.dt * (p.A * S - coup / c + q / c);
+            lt = p.dt * (coup - q) / c;
+            const double th = (Tnew - p.T_min) * p.inv_span;
+            if (!(th >= 0.0 && th <= 1.0)) atomicOr(err, kErrRange);
+        }
         q *= p.dt;
-        const double th = (Tnew - p.T_min) * p.inv_span;
-        if (!(th >= 0.0 && th <= 1.0)) atomicOr(err, kErrRange);
     }
     Tn[slot] = Tnew;
     e2l = wave_sum(e2l);
@@ -210,14 +217,19 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
         const float invc = 1.0f / c;
         const float coup = signbit(tl) ? 0.0f : p.f_g * (Ti - tl);
         float q = 0.0f;
-        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * sw;
+        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * fabsf(sw);
         const float loc = (q - coup) * invc;
-        const double T = ((double)Ti + (double)lo) + p.dt * (p.K * S + (double)loc);
-        hi_new = (float)T;
-        Tlo[slot] = (float)(T - (double)hi_new);
-        r = LedgerTerms{coup, q, -loc};
         if (eatom) eatom[slot] += (double)coup * p.dt;
-        if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
+        if (p.has_fixed && signbit(sw)) {
+            // held: the exchange it would receive goes to the temperature ledger
+            r = LedgerTerms{coup, q, (float)(p.K * S)};
+        } else {
+            const double T = ((double)Ti + (double)lo) + p.dt * (p.K * S + (double)loc);
+            hi_new = (float)T;
+            Tlo[slot] = (float)(T - (double)hi_new);
+            r = LedgerTerms{coup, q, -loc};
+            if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
+        }
     }
     Thi_n[slot] = hi_new;
     return r;
@@ -367,7 +379,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
     const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
     const float Ti = Thi[slot];
     const float lo = Tlo[slot], tl = Tl[slot];
-    const float sw = p.laser_on ? srcw[slot] : 0.0f;
+    const float sw = (p.laser_on | (si.flags & kSliceHeld)) ? srcw[slot] : 0.0f;
     const LedgerTerms t = slice_core_fp32c(
         si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
         [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, eatom, step, err);

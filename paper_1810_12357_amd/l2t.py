@@ -24,6 +24,7 @@ L2T_EINVAL, L2T_ENOMEM, L2T_EHIP, L2T_ESTATE, L2T_ERANGE, L2T_ENOTIMPL = -1, -2,
 L2T_FP64, L2T_FP32C = 0, 1
 L2T_HOST, L2T_DEVICE = 0, 1
 L2T_FIELD_TE, L2T_FIELD_TL, L2T_FIELD_GATE, L2T_FIELD_NBRS, L2T_FIELD_ELAT = 0, 1, 2, 3, 4
+L2T_FIELD_FIXED = 5
 L2T_CE_CONST, L2T_CE_LINEAR, L2T_CE_CAPPED = 0, 1, 2
 L2T_OPT_PERSISTENT, L2T_OPT_BLOCK, L2T_OPT_RESIDENT_MAX, L2T_OPT_GRAPH, L2T_OPT_AUTOTUNE = 0, 1, 2, 3, 4
 L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE, L2T_OPT_ATOM_LEDGER = 5, 6, 7
@@ -34,7 +35,7 @@ EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbor
            "l2t_get_neighbors", "l2t_set_params", "l2t_set_field", "l2t_get_field",
            "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
            "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
-           "l2t_coupling", "l2t_damping_step",
+           "l2t_coupling", "l2t_damping_step", "l2t_set_mean_field", "l2t_get_params",
            "l2t_exchange_rate", "l2t_pair_fp32", "l2t_strerror", "l2t_last_error",
            "l2t_version")
 
@@ -53,6 +54,11 @@ class l2t_params(C.Structure):
                 ("laser_fluence", C.c_double), ("laser_lp", C.c_double),
                 ("laser_t0", C.c_double), ("laser_sigma", C.c_double),
                 ("laser_x0", C.c_double), ("v_atom", C.c_double)]
+
+
+class l2t_mean_field(C.Structure):
+    _fields_ = [("on", C.c_int32), ("reserved", C.c_int32), ("lambda_", C.c_double),
+                ("k_coef", C.c_double)]
 
 
 class l2t_energy_report(C.Structure):
@@ -104,6 +110,8 @@ def load() -> C.CDLL:
         "l2t_set_option": (C.c_int, [vp, i32, i64]),
         "l2t_get_option": (C.c_int, [vp, i32, P(i64)]),
         "l2t_coupling": (C.c_int, [vp, i32, i32, d, vp, vp, vp, i32]),
+        "l2t_set_mean_field": (C.c_int, [vp, i32, P(l2t_mean_field)]),
+        "l2t_get_params": (C.c_int, [vp, i32, P(l2t_params)]),
         "l2t_damping_step": (C.c_int, [vp, i32, d, vp, vp, vp, vp, i32]),
         "l2t_exchange_rate": (d, [d, d, i32, d]),
         "l2t_pair_fp32": (C.c_int, [vp, vp, vp, i64, vp]),
@@ -255,6 +263,21 @@ def l2t_adjoint(ctx, dL_dTN, n_systems: int, dL_dT0=None):
             raise TypeError("dL_dTN and dL_dT0 must live in the same memory space")
     _check(ctx, load().l2t_adjoint(ctx, pw, mem, dK.ctypes.data, dg.ctypes.data, p0))
     return dK, dg
+
+
+def l2t_set_mean_field(ctx, sys: int, on: bool, lambda_atom: float = 0.0,
+                       k_coef: float = 0.0) -> int:
+    """Mean-field parameter mode of Section 2 (see l2t.h)."""
+    mf = l2t_mean_field(on=int(bool(on)), reserved=0, lambda_=float(lambda_atom),
+                        k_coef=float(k_coef))
+    return _check(ctx, load().l2t_set_mean_field(ctx, sys, C.byref(mf)))
+
+
+def l2t_get_params(ctx, sys: int) -> dict:
+    """Parameters in effect (K, ce_model, ce_const after a mean-field refresh)."""
+    p = l2t_params()
+    _check(ctx, load().l2t_get_params(ctx, sys, C.byref(p)))
+    return {k: getattr(p, k) for k, _ in p._fields_}
 
 
 def _out_ptr(a):
