@@ -15,6 +15,8 @@ Function map (paper passages):
                      source (Section 2.1), ledgers of Eq. 6 (per system and,
                      optionally, per atom)
   mean_field         mean-field heat capacity and exchange rate (Section 2)
+  run_2t             two-temperature bar: Eq. 2 electrons with a finite-
+                     difference Fourier lattice in the same step (Section 3.1)
   coupling           Eq. 8 coupling coefficient of the damping force
   damping_step       one explicit velocity step of Eq. 5
   energies           sum of the per-atom electronic energy and of T
@@ -82,6 +84,8 @@ def _load():
         lib.or_run.argtypes = [i32, pi64, pi32, pd, pd, pi32, pd, P(Params), i64, i32, pd, pd,
                                pi32]
         lib.or_mean_field.argtypes = [i32, pd, pd, d, d, pd]
+        lib.or_run_2t.restype = i64
+        lib.or_run_2t.argtypes = [i32, pi64, pi32, pd, pd, P(Params), d, d, i64, i32, pd]
         lib.or_coupling.argtypes = [i32, i32, pd, pd, pi32, pd, d, d, d, pd, pd, pd, pd, pd]
         lib.or_damping_step.argtypes = [i32, d, pd, pd, pd, pd, pd, pd, pd, pd]
         lib.or_energies.argtypes = [i32, pd, P(Params), pd]
@@ -201,6 +205,23 @@ def run(row, col, T, T_lat, params: dict, n_steps: int, step0: int = 0, gated=No
     if bad < 0:
         raise MemoryError("oracle run allocation failed")
     return T, led, int(bad)
+
+
+def run_2t(row, col, T, T_lat, params: dict, K_lat: float, c_lat: float, n_steps: int,
+           step0: int = 0, ledger=None):
+    """Two-temperature bar (Section 3.1): electrons by Eq. 2 and the lattice by
+    the Fourier law K_lat sum_j (T_l,j - T_l,i) + (g/c_lat)(T - T_l), one
+    forward-Euler step for both.  Returns (T, T_lat, ledger[3], n_out_of_range)."""
+    T = _f64(T).copy()
+    Tl = _f64(T_lat).copy()
+    led = np.zeros(3) if ledger is None else _f64(ledger).copy()
+    pp = make_params(params)
+    bad = _load().or_run_2t(T.size, _p(row, C.c_int64), _p(col, C.c_int32), _p(T, C.c_double),
+                            _p(Tl, C.c_double), C.byref(pp), float(K_lat), float(c_lat),
+                            int(step0), int(n_steps), _p(led, C.c_double))
+    if bad < 0:
+        raise MemoryError("oracle run allocation failed")
+    return T, Tl, led, int(bad)
 
 
 def mean_field(T, T_lat, lambda_atom, k_coef):

@@ -24,6 +24,8 @@
  *     per system and optionally per atom;
  *   - the lattice side: the coupling coefficient of Eq. 8 and one explicit
  *     velocity step of the damped equation of motion Eq. 5;
+ *   - the two-temperature bar of Section 3.1: the lattice temperature
+ *     advanced by a finite-difference Fourier law in step with Eq. 2;
  *   - the discrete adjoint of the forward-Euler map (derived from Eq. 2) and
  *     a complex-step forward run for directional derivatives.
  *
@@ -493,6 +495,53 @@ void or_damping_step(int32_t n, double dt_md, const double *xi, const double *fx
         vy[i] = vy[i] + dt_md * ay;
         vz[i] = vz[i] + dt_md * az;
     }
+}
+
+/* ---- two-temperature bar of Section 3.1 ------------------------------------
+ * Electrons by Eq. 2 as in or_run; the lattice temperature is a state too,
+ * advanced in the same forward-Euler step (every read at step n) by the
+ * Fourier law with the coupling as its source (the lattice line of Eq. 9):
+ *   dT_l,i/dt = K_lat sum_{j in N(i)} (T_l,j - T_l,i) + (g / c_lat) (T_i - T_l,i)
+ * On a chain of spacing b with the two nearest neighbours, K_lat =
+ * kappa_lat / (rho C_lat b^2) makes the sum the three-point stencil of
+ * Section 3.1.  No kinetic-energy gate.  T and T_lat are updated in place;
+ * ledger as in or_run. */
+int64_t or_run_2t(int32_t n, const int64_t *row_ptr, const int32_t *col, double *T,
+                  double *T_lat, const or_params *p, double K_lat, double c_lat, int64_t step0,
+                  int32_t n_steps, double *ledger)
+{
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *Tn = malloc(sz), *Tln = malloc(sz), *e2l = malloc(sz), *src = malloc(sz);
+    double *lt = malloc(sz);
+    if (!Tn || !Tln || !e2l || !src || !lt) {
+        free(Tn); free(Tln); free(e2l); free(src); free(lt);
+        return -1;
+    }
+    int64_t bad = or_count_out_of_range(n, T, p);
+    for (int32_t s = 0; s < n_steps; ++s) {
+        double t = (double)(step0 + s) * p->dt;
+        or_step(n, row_ptr, col, T, T_lat, NULL, NULL, NULL, p, t, Tn, e2l, src, lt);
+        #pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            double L = 0.0;
+            for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) L += T_lat[col[q]] - T_lat[i];
+            Tln[i] = T_lat[i] + p->dt * (K_lat * L + (p->g / c_lat) * (T[i] - T_lat[i]));
+        }
+        double a = 0, b = 0, c = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            a += e2l[i] * p->dt;
+            b += src[i] * p->dt;
+            c += p->dt * lt[i];
+        }
+        ledger[0] += a;
+        ledger[1] += b;
+        ledger[2] += c;
+        memcpy(T, Tn, sz);
+        memcpy(T_lat, Tln, sz);
+        bad += or_count_out_of_range(n, T, p);
+    }
+    free(Tn); free(Tln); free(e2l); free(src); free(lt);
+    return bad;
 }
 
 /* out[0] = sum_i E(T_i) (integral of c from 0), out[1] = sum_i T_i */

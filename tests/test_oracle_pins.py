@@ -626,3 +626,50 @@ def test_mean_field_heat_capacity_sets_relaxation_of_uniform_system():
     T, led, _ = oracle.run(row, col, T0, Tl, p, 500)
     # c = lambda mean(T_e) = 0.05 eV/K held over the advance
     np.testing.assert_allclose(T, 300.0 + 4700.0 * (1.0 - p["dt"] * 2e-4 / 0.05) ** 500, rtol=1e-12)
+
+
+# ------------------------------------------- two-temperature bar, Section 3.1 ----
+def _bar_system():
+    w = W.c6(n_bars=1)
+    s = w.systems[0]
+    row, col = oracle.neighbors(s.pos, s.box_lo, s.box_len, s.periodic, w.r_cut)
+    assert np.all(np.diff(row) == 2)                  # the chain's two neighbours
+    return w, s, row, col
+
+
+def test_bar_means_relax_to_the_papers_equilibrium_in_closed_form():
+    # the electron exchange and the lattice stencil both conserve their sums,
+    # so D = mean(T_e) - mean(T_l) obeys D_n = D_0 (1 - dt (g/c_e + g/c_l))^n
+    # and c_e mean(T_e) + c_l mean(T_l) is conserved: both means approach
+    # T_eq = (C_e <T_e0> + rho C_l <T_l0>) / (C_e + rho C_l) (Section 3.1)
+    w, s, row, col = _bar_system()
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    Ce = c["Ce_J_per_m3K"]["value"]
+    rhoCl = 8890.0 * 400.0                       # Section 3.1: rho = 8890 kg/m^3, C_l = 400 J/kg/K
+    Teq = (Ce * s.T_e0.mean() + rhoCl * s.T_l.mean()) / (Ce + rhoCl)
+    n = 12000
+    T, Tl, led, bad = oracle.run_2t(row, col, s.T_e0, s.T_l, s.params, w.extra["K_lat"],
+                                    w.extra["c_lat"], n)
+    assert bad == 0
+    g, ce, cl, dt = s.params["g"], s.params["ce_const"], w.extra["c_lat"], s.params["dt"]
+    Dn = (s.T_e0.mean() - s.T_l.mean()) * (1.0 - dt * (g / ce + g / cl)) ** n
+    assert T.mean() == pytest.approx(Teq + rhoCl / (Ce + rhoCl) * Dn, rel=1e-12)
+    assert Tl.mean() == pytest.approx(Teq - Ce / (Ce + rhoCl) * Dn, rel=1e-12)
+    # the energy the lattice received is the electrons' loss
+    assert cl * (Tl.mean() - s.T_l.mean()) * s.n == pytest.approx(led[0], rel=1e-11)
+
+
+def test_bar_lattice_fourier_modes_decay_at_the_stencil_rate():
+    # no coupling: the lattice alone is the forward-Euler three-point Fourier
+    # law on a ring, whose cosines decay by 1 - dt K_l (2 - 2 cos(2 pi k / N))
+    w, s, row, col = _bar_system()
+    N = s.n
+    x = np.arange(N)
+    p = dict(s.params, g=0.0)
+    for k in (1, 5, 40):
+        Tl0 = 300.0 + 20.0 * np.cos(2 * np.pi * k * x / N)
+        _, Tl, _, _ = oracle.run_2t(row, col, np.full(N, 300.0), Tl0, p, w.extra["K_lat"],
+                                    w.extra["c_lat"], 3000)
+        r = (1.0 - p["dt"] * w.extra["K_lat"] * (2.0 - 2.0 * np.cos(2 * np.pi * k / N))) ** 3000
+        np.testing.assert_allclose(Tl, 300.0 + 20.0 * r * np.cos(2 * np.pi * k * x / N),
+                                   rtol=0, atol=1e-10)

@@ -248,6 +248,59 @@ C5_K0 = 0.05             # fs^-1
 C5_G0 = 1.1727e-7        # eV fs^-1 K^-1 per atom (g0/c = 5e-3 fs^-1)
 
 
+# --- two-temperature 1D Ni bar (Section 3.1), per-node units ---------------------
+A0_BAR = 3.562                       # A, fcc Ni lattice constant quoted for the bar
+B_BAR = A0_BAR / math.sqrt(2.0)      # A, node spacing b = a0/sqrt(2)
+EV_J = 1.602176634e-19               # J per eV
+V_BAR = (A0_BAR * 1e-10) ** 3 / 4.0  # m^3 per node (cancels from every rate)
+G_BAR = 3.6e17 * V_BAR / EV_J * 1e-15            # g = G V, eV/(fs K)
+C_E_BAR = 3.6886e5 * V_BAR / EV_J                # c_e = C_e V, eV/K
+C_L_BAR = 8890.0 * 400.0 * V_BAR / EV_J          # c_lat = rho C_l V, eV/K
+# Eq. 3 with d = 1, Z = 2 over the chain: K = 2 kappa_e / (C_e 2 b^2)
+K_E_BAR = 91.0 / (3.6886e5 * (B_BAR * 1e-10) ** 2) * 1e-15          # 1/fs
+# three-point Fourier stencil of the lattice, kappa_lat = 0.05 kappa_e
+K_L_BAR = 0.05 * 91.0 / (8890.0 * 400.0 * (B_BAR * 1e-10) ** 2) * 1e-15   # 1/fs
+
+
+def c6_bar(n_nodes: int = 141, hot_T: float = 6000.0, hot_span_a0: float = 2.0,
+           centre: int | None = None) -> System:
+    """One periodic chain of n_nodes nodes spaced b (x), electrons and lattice
+    at 300 K, electrons at hot_T over a span of hot_span_a0 * a0 around the
+    centre node.  T_l holds the initial lattice temperature."""
+    x = np.arange(n_nodes) * B_BAR
+    pos = np.zeros((3, n_nodes))
+    pos[0] = x
+    c = n_nodes // 2 if centre is None else centre
+    d = np.abs(x - x[c])
+    d = np.minimum(d, n_nodes * B_BAR - d)
+    Te = np.where(d <= 0.5 * hot_span_a0 * A0_BAR + 1e-9, hot_T, 300.0)
+    p = default_params(T_max=T_MAX, K=K_E_BAR, dt=0.1, g=G_BAR, ce_model=CE_CONST,
+                       ce_const=C_E_BAR, v_atom=V_BAR * 1e30)
+    return System(pos=pos, box_lo=np.array([0.0, -1.0, -1.0]),
+                  box_len=np.array([n_nodes * B_BAR, 2.0, 2.0]),
+                  periodic=np.array([1, 0, 0], np.int32), T_e0=Te, params=p,
+                  T_l=np.full(n_nodes, 300.0))
+
+
+def c6(n_bars: int = 2048, n_nodes: int = 141, n_substeps: int = 30000,
+       seed: int = 6001) -> Workload:
+    """Batch of two-temperature 1D Ni bars (Section 3.1): bar 0 is the paper's
+    (6,000 K over 2 a0 at the centre, 3 ps at dt = 0.1 fs); the others draw the
+    hot temperature from U[3,000, 9,000] K, the span from U[1, 6] a0 and the
+    centre node uniformly (seeded).  Electrons by Eq. 2 with K from Eq. 3
+    (d = 1, Z = 2), lattice by the three-point Fourier stencil; the lattice
+    rate and heat capacity are in extra."""
+    rng = np.random.default_rng(seed)
+    systems = [c6_bar(n_nodes)]
+    for _ in range(n_bars - 1):
+        systems.append(c6_bar(n_nodes, hot_T=float(rng.uniform(3000.0, 9000.0)),
+                              hot_span_a0=float(rng.uniform(1.0, 6.0)),
+                              centre=int(rng.integers(0, n_nodes))))
+    return Workload("c6_ni_bar_2t_fp64", systems, r_cut=1.05 * B_BAR, n_substeps=n_substeps,
+                    precision="fp64", checkpoint_every=1000,
+                    extra={"K_lat": K_L_BAR, "c_lat": C_L_BAR})
+
+
 def c5(n_systems: int = 64, n_cells: int = 20, n_substeps: int = 2000,
        seed: int = 5001) -> Workload:
     """Differentiation case: identical periodic FCC systems with the C1
