@@ -20,6 +20,7 @@ Also reported:
     step, against HBM bandwidth;
   * the sub-step cost with a shell of held electronic temperatures and the
     mean-field parameter refresh at every advance;
+  * the batch of two-temperature 1D bars (FP64, electrons and lattice);
   * the FP64 CPU oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -150,7 +151,7 @@ def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):
     for on in (0, 1):
         L.l2t_set_option(h, L.L2T_OPT_ATOM_LEDGER, on)
         out["substep_us_record_" + ("on" if on else "off")] = \
-            timed(lambda: L.l2t_advance(h, n_sub), 5) / n_sub
+            timed(lambda: L.l2t_advance(h, n_sub), 40) / n_sub
     dt_md = n_sub * sy.params["dt"]
     xi = torch.empty(sy.n, dtype=torch.float64, device=dev)
     v = d["vel"].clone()
@@ -207,6 +208,37 @@ def bench_boundary_mean_field(L, torch, h, sy, n_sub=10, reps=40):
                 substep_us_held=held_only, substep_us_mean_field=mf_only,
                 substep_us_held_and_mean_field=both,
                 mean_field_refresh_us_per_advance=(mf_only - plain) * n_sub)
+
+
+def bench_bar_batch(L, torch, n_sub=30000):
+    """Two-temperature bars of Section 3.1: 2048 periodic 141-node Ni bars,
+    electrons by Eq. 2 and lattice by the three-point Fourier law, FP64, one
+    launch per sub-step for the whole batch, 3 ps at dt = 0.1 fs."""
+    import workloads as W
+    w = W.c6(n_substeps=n_sub)
+    ctx = L.Context(w.systems, L.L2T_FP64)
+    ctx.setup(w.r_cut)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, 1)
+    for s in range(len(w.systems)):
+        L.l2t_set_lattice_fd(ctx.h, s, True, W.K_L_BAR, W.C_L_BAR)
+    ctx.advance(100)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    ctx.advance(n_sub)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    nodes = sum(sy.n for sy in w.systems)
+    ctx.close()
+    log(f"  bars: {len(w.systems)} x {w.systems[0].n} nodes, {n_sub} sub-steps in {ms:.1f} ms")
+    # algorithmic bytes per node-substep: T_e and T_lat read and written (32)
+    # and two int32 neighbour indices (8)
+    per = 40.0
+    return dict(workload=f"c6: {len(w.systems)} two-temperature Ni bars of {w.systems[0].n} nodes, "
+                         f"{n_sub} FP64 sub-steps (3 ps)",
+                node_substeps_per_s=nodes * n_sub / (ms * 1e-3), substep_us=ms * 1e3 / n_sub,
+                algorithmic_GBps=per * nodes * n_sub / (ms * 1e-3) / 1e9)
 
 
 def cpu_baseline(sy, r_cut, n_steps):
@@ -337,6 +369,9 @@ def main():
     if not args.no_c4:
         log("C4 batched vs plain ...")
         out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps)
+    if not args.no_md:
+        log("two-temperature bars (Section 3.1) ...")
+        out["bar_batch"] = bench_bar_batch(L, torch)
     if not args.no_cpu:
         log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(sy, w.r_cut, args.cpu_steps)

@@ -98,10 +98,13 @@ extern "C" {
 #define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
 #define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
-#define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells for the next l2t_build_neighbors (0 = automatic) */
+#define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells (1..1024) for the next l2t_build_neighbors (0 = automatic) */
 #define L2T_OPT_ATOM_LEDGER    7   /* 1 = record each atom's energy to the lattice during every advance
                                       (L2T_FIELD_ELAT, L2T_XI_LEDGER); costs 16 bytes per atom-substep
                                       of extra traffic while on (default 0) */
+
+#define L2T_OPT_BATCH_FP64     8   /* FP64: 1 = one launch per sub-step over all systems; 0 = the
+                                      systems one after another (default 0) */
 
 /* ---- source of the energy rate in the coupling coefficient (l2t_coupling) ------ */
 #define L2T_XI_INSTANT  0   /* P_i = g (T_i - T_i^lat) at the current T_e (Section 2.1 order) */
@@ -152,6 +155,21 @@ typedef struct {
     double k_coef;          /* K = k_coef / mean(T^lat): 2 d kappa_0 / (lambda_vol S), K/fs (> 0),
                                S the lattice sum of |r_ij|^2 as in l2t_exchange_rate */
 } l2t_mean_field;
+
+/* Two-temperature lattice of Section 3.1 (the lattice line of Eq. 9): the
+ * lattice temperature becomes a state advanced with the electrons in the same
+ * forward-Euler step (every read at step n),
+ *     dT_l,i/dt = K_lat sum_{j in N(i)} (T_l,j - T_l,i) + (g / c_lat)(T_i - T_l,i),
+ * the Fourier law over the neighbour set with the coupling as its source.  On
+ * a chain of spacing b holding the two nearest neighbours, K_lat =
+ * kappa_lat / (rho C_lat b^2) is the three-point stencil of Section 3.1; in
+ * general K_lat = 2 d kappa_lat / (rho C_lat S), the lattice form of Eq. 3. */
+typedef struct {
+    int32_t on;             /* 1 = evolve T^lat */
+    int32_t reserved;       /* 0 */
+    double K_lat;           /* 1/fs (>= 0) */
+    double c_lat;           /* lattice heat capacity per atom, rho C_lat V_atom, eV/K (> 0) */
+} l2t_lattice_fd;
 
 /* Per-system ledger, FP64.  With any heat capacity model,
  * sum_T + T_ledger_acc is conserved by the sub-step (the exchange term sums
@@ -223,6 +241,15 @@ int l2t_set_params(l2t_ctx *ctx, int32_t sys, const l2t_params *p);
  * set).  An advance whose mean T^lat is not > 0 reports ERANGE. */
 int l2t_set_mean_field(l2t_ctx *ctx, int32_t sys, const l2t_mean_field *mf);
 
+/* Two-temperature lattice mode of system sys (Section 3.1, see
+ * l2t_lattice_fd).  FP64 contexts only.  The initial T^lat comes from
+ * l2t_set_field(L2T_FIELD_TL) or l2t_set_velocities and is read back with
+ * l2t_get_field; while on, the kinetic-energy gate is ignored.  With a
+ * constant c, sum_i (c T_i + c_lat T_l,i) is conserved.
+ * Errors: EINVAL (K_lat < 0, c_lat <= 0 while on), ENOTIMPL (FP32C context),
+ * ESTATE (parameters not set). */
+int l2t_set_lattice_fd(l2t_ctx *ctx, int32_t sys, const l2t_lattice_fd *lf);
+
 /* The parameters of system sys in effect for the last (or next) sub-step:
  * those of l2t_set_params, with K, ce_model and ce_const as the last
  * mean-field refresh set them.  Synchronises. */
@@ -255,8 +282,9 @@ int l2t_set_velocities(l2t_ctx *ctx, int32_t sys, const double *v, const double 
 /* Advance every system by n_substeps explicit forward-Euler sub-steps of
  * Eq. 2 (Section 2.1), Jacobi-synchronous: every read in sub-step n sees the
  * step-n state.  Atoms flagged L2T_FIELD_FIXED keep their T_e; their
- * neighbours exchange with them as usual.  L2T_FP64: one launch per sub-step per system, the systems
- * one after another.  L2T_FP32C: all systems together; with
+ * neighbours exchange with them as usual.  L2T_FP64: one launch per sub-step
+ * per system, the systems one after another (L2T_OPT_BATCH_FP64: one launch
+ * per sub-step for all).  L2T_FP32C: all systems together; with
  * L2T_OPT_PERSISTENT, all sub-steps in one persistent launch.  Asynchronous;
  * a range violation is reported by the next synchronising call as ERANGE.
  * Errors: ESTATE (neighbours, parameters or T_e missing), EINVAL. */

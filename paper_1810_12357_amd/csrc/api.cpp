@@ -83,6 +83,7 @@ int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, 
         dfree(c->Thi[b]);
     }
     dfree(c->Tl64);
+    dfree(c->Tl64b);
     dfree(c->srcw64);
     dfree(c->Tlo);
     dfree(c->Tl32);
@@ -112,6 +113,7 @@ int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, 
         ALLOC(c->T64[0], NI);
         ALLOC(c->T64[1], NI);
         ALLOC(c->Tl64, NI);
+        ALLOC(c->Tl64b, NI);
         ALLOC(c->srcw64, NI);
     } else {
         ALLOC(c->Thi[0], NI);
@@ -260,6 +262,7 @@ void l2t_destroy(l2t_ctx *c) {
         dfree(c->Thi[b]);
     }
     dfree(c->Tl64);
+    dfree(c->Tl64b);
     dfree(c->srcw64);
     dfree(c->Tlo);
     dfree(c->Tl32);
@@ -576,13 +579,17 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
         case L2T_OPT_RESIDENT_MAX: t.resident_max = (int)value; break;
         case L2T_OPT_GRAPH: t.graph = value ? 1 : 0; break;
         case L2T_OPT_BRICK_EDGE:
-            if (value < 0 || value > 16) return l2t::fail(c, L2T_EINVAL, "brick edge must be 0..16");
+            if (value < 0 || value > l2t::kMaxBrickEdge)
+                return l2t::fail(c, L2T_EINVAL, "brick edge must be 0..1024");
             t.brick_edge = (int)value;
             return L2T_OK;
         case L2T_OPT_ATOM_LEDGER:
             // not a tuning choice: leaves the tuned launch shape alone
             if ((value != 0) != c->atom_ledger) l2t::drop_graphs(c);
             c->atom_ledger = value != 0;
+            return L2T_OK;
+        case L2T_OPT_BATCH_FP64:
+            c->batch_fp64 = value != 0;
             return L2T_OK;
         case L2T_OPT_KERNEL:
             if (value != l2t::kKernelSliced && value != l2t::kKernelBrick)
@@ -616,6 +623,7 @@ int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
         case L2T_OPT_AUTOTUNE: *value = t.autotune; break;
         case L2T_OPT_KERNEL: *value = t.kernel; break;
         case L2T_OPT_ATOM_LEDGER: *value = c->atom_ledger ? 1 : 0; break;
+        case L2T_OPT_BATCH_FP64: *value = c->batch_fp64 ? 1 : 0; break;
         case L2T_OPT_BRICK_EDGE: *value = c->brick_edge_used; break;
         default: return l2t::fail(c, L2T_EINVAL, "unknown option");
     }
@@ -631,6 +639,7 @@ int l2t_advance(l2t_ctx *c, int32_t n) {
     int rc0 = begin_atom_ledger(c, 0, (int32_t)c->sys.size());
     if (rc0 != L2T_OK) return rc0;
     if (c->precision == L2T_FP64) {
+        if (c->batch_fp64) return l2t::advance_plain(c, -1, n);
         for (int32_t s = 0; s < (int32_t)c->sys.size(); ++s) {
             int rc = l2t::advance_plain(c, s, n);
             if (rc != L2T_OK) return rc;
@@ -726,6 +735,23 @@ int l2t_set_mean_field(l2t_ctx *c, int32_t sys, const l2t_mean_field *mf) {
     st.mf.on = mf->on ? 1 : 0;
     c->rec.valid = false;
     l2t::drop_graphs(c);
+    int rc = l2t::upload_params(c);
+    if (rc != L2T_OK) return rc;
+    L2T_HIP(c, hipStreamSynchronize(c->stream));
+    return L2T_OK;
+}
+
+int l2t_set_lattice_fd(l2t_ctx *c, int32_t sys, const l2t_lattice_fd *lf) {
+    if (bad_sys(c, sys) || !lf) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    if (c->precision != L2T_FP64)
+        return l2t::fail(c, L2T_ENOTIMPL, "the two-temperature lattice runs in FP64 contexts");
+    SystemState &st = c->sys[sys];
+    if (!st.has_params) return l2t::fail(c, L2T_ESTATE, "set parameters before the lattice mode");
+    if (lf->on && (!(lf->K_lat >= 0.0) || !std::isfinite(lf->K_lat) || !(lf->c_lat > 0.0) ||
+                   !std::isfinite(lf->c_lat)))
+        return l2t::fail(c, L2T_EINVAL, "need K_lat >= 0 and c_lat > 0");
+    st.lf = *lf;
+    st.lf.on = lf->on ? 1 : 0;
     int rc = l2t::upload_params(c);
     if (rc != L2T_OK) return rc;
     L2T_HIP(c, hipStreamSynchronize(c->stream));

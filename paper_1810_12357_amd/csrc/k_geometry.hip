@@ -571,36 +571,49 @@ struct SysLayout {
     std::vector<int32_t> rank_of_cell, cell_of_rank, brick_cell0;
 };
 
-// Brick edge (cells), one for all systems of the context.  The (b+2)^3-cell
-// tile at the densest system's density must fit the LDS cap with room for
-// fluctuations; among the edges that fit, take the one with the least
-// estimated time: rounds of resident workgroups over all bricks of all
-// systems (one brick per workgroup; a CU holds as many tiles as its 160 KB of
-// LDS and its 8 workgroups of 4 waves allow) times the work of a full brick
-// (own atoms, plus the halo staging counted at 0.3 of an own atom).
+// Brick edge (cells), one for all systems of the context; along an axis with
+// fewer cells than the edge a brick spans the whole axis.  A brick's own
+// slots are padded to whole 64-lane slices and its tile adds the one-cell
+// halo (clipped to the system's extent, where the halo wraps onto the brick
+// itself).  The tile at each system's mean density, with room for
+// fluctuations, must fit the LDS cap; among the edges that fit, take the one
+// with the least estimated time: rounds of resident workgroups over all bricks
+// of all systems (one brick per workgroup; a CU holds as many tiles as its
+// 160 KB of LDS and its 8 workgroups of 4 waves allow) times the work of the
+// largest brick (its padded slots, plus the halo staging counted at 0.3 of a
+// slot).  Edges grow until every axis of every system fits in one brick.
 int32_t brick_edge(const l2t_ctx *c, int32_t limit) {
-    double dens = 1e-9;
-    for (const SystemState &st : c->sys)
-        dens = std::max(dens, (double)st.desc.n_atoms / (double)std::max<int64_t>(1, st.ncell));
     int32_t best = 1;
     double best_cost = 1e300;
     for (int32_t b = 1; b <= limit; ++b) {
-        const double tile = 1.1 * std::pow(b + 2.0, 3) * dens + kWave;
-        if (tile > kTileCapFloats) break;
-        double nbrick = 0.0;
+        double tile_max = 0.0, work_max = 0.0, nbrick = 0.0;
+        bool grows = false;
         for (const SystemState &st : c->sys) {
-            double nb = 1.0;
-            for (int d = 0; d < 3; ++d) nb *= std::ceil((double)st.nc[d] / std::min(b, st.nc[d]));
+            const double dens =
+                (double)st.desc.n_atoms / (double)std::max<int64_t>(1, st.ncell);
+            double own = 1.0, with_halo = 1.0, nb = 1.0;
+            for (int d = 0; d < 3; ++d) {
+                const int32_t e = std::min(b, st.nc[d]);
+                own *= e;
+                with_halo *= std::min(e + 2, st.nc[d]);
+                nb *= std::ceil((double)st.nc[d] / e);
+                grows |= st.nc[d] > b;
+            }
+            const double slots = std::ceil(dens * own / kWave) * kWave;
+            const double halo = dens * (with_halo - own);
+            tile_max = std::max(tile_max, 1.1 * dens * with_halo + kWave);
+            work_max = std::max(work_max, slots + 0.3 * halo);
             nbrick += nb;
         }
-        const double per_cu = std::max(1.0, std::min(8.0, std::floor(163840.0 / (4.0 * tile))));
+        if (tile_max > kTileCapFloats) break;
+        const double per_cu = std::max(1.0, std::min(8.0, std::floor(163840.0 / (4.0 * tile_max))));
         const double rounds = std::ceil(nbrick / (per_cu * std::max(1, c->n_cu)));
-        const double work = std::pow((double)b, 3) + 0.3 * (std::pow(b + 2.0, 3) - std::pow(b, 3));
-        const double cost = rounds * work;
+        const double cost = rounds * work_max;
         if (cost < best_cost * 0.999) {
             best_cost = cost;
             best = b;
         }
+        if (!grows) break;
     }
     return best;
 }
@@ -999,15 +1012,18 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
 }
 
 int build_neighbors(l2t_ctx *c, double r_cut) {
-    int32_t limit = 8;
+    int32_t limit = kMaxBrickEdge;
     c->brick_edge_used = 0;
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int attempt = 0; attempt < 12; ++attempt) {
         bool overflow = false;
         int rc = build_neighbors_once(c, r_cut, limit, &overflow);
         if (rc != L2T_OK) return rc;
         if (!overflow) return L2T_OK;
-        limit = std::max(1, limit / 2);
+        // a tile overflowed its LDS cap: retry below the edge that was used
+        const int32_t used = c->brick_edge_used;
         c->brick_edge_used = 0;
+        if (used <= 1) break;
+        limit = used / 2;
     }
     return fail(c, L2T_EINVAL, "atom density too high for the LDS tile of one cell and its halo");
 }

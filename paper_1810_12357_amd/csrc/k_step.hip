@@ -34,7 +34,8 @@ using namespace dev;
 __global__ __launch_bounds__(256) void k_step_fp64(const SliceInfo *slices, int32_t slice0,
                                                    int32_t n_slices, const int32_t *col,
                                                    const double *T, double *Tn, const double *Tl,
-                                                   const double *srcw, const DevParams *P,
+                                                   double *Tl_out, const double *srcw,
+                                                   const DevParams *P,
                                                    const int64_t *dstep, int32_t rel,
                                                    double *ledger, double *eatom, unsigned *err) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -43,8 +44,8 @@ __global__ __launch_bounds__(256) void k_step_fp64(const SliceInfo *slices, int3
     const int32_t sl = slice0 + q;
     const SliceInfo si = slices[sl];
     const DevParams &p = P[si.sys];
-    slice_step_fp64(si, sl, lane, p, col, T, Tn, Tl, srcw, dstep[si.sys] + rel, ledger, eatom,
-                    err);
+    slice_step_fp64(si, sl, lane, p, col, T, Tn, Tl, Tl_out, srcw, dstep[si.sys] + rel, ledger,
+                    eatom, err);
 }
 
 __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int32_t slice0,
@@ -423,6 +424,9 @@ int upload_params(l2t_ctx *c) {
         p.n_atoms = st.desc.n_atoms;
         p.mf_lambda = st.mf.lambda;
         p.mf_kcoef = st.mf.k_coef;
+        p.lat_fd = st.lf.on ? 1 : 0;
+        p.K_lat = st.lf.K_lat;
+        p.g_over_clat = st.lf.on ? q.g / st.lf.c_lat : 0.0;
     }
     // mean-field chunk table: every system in the mode, in order, its slices in
     // chunks of kMfChunk
@@ -510,11 +514,19 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     double *eatom = atom_ledger_ptr(c);
     int rc0 = mean_field_refresh(c, sys);
     if (rc0 != L2T_OK) return rc0;
+    // two-temperature lattice: T^lat alternates between the two buffers
+    bool lat = false;
+    if (c->precision == L2T_FP64)
+        for (int32_t s = (sys < 0 ? 0 : sys); s < (sys < 0 ? (int32_t)c->sys.size() : sys + 1); ++s)
+            lat |= c->sys[s].lf.on != 0;
+    double *tl_buf[2] = {c->Tl64, c->Tl64b};
     int cur = c->cur;
     for (int32_t k = 0; k < n; ++k) {
         if (c->precision == L2T_FP64) {
+            const double *tl_in = lat ? tl_buf[k & 1] : c->Tl64;
+            double *tl_out = lat ? tl_buf[(k & 1) ^ 1] : nullptr;
             hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
-                               c->T64[cur], c->T64[cur ^ 1], c->Tl64, c->srcw64, c->dparams,
+                               c->T64[cur], c->T64[cur ^ 1], tl_in, tl_out, c->srcw64, c->dparams,
                                c->dstep, k, c->ledger, eatom, c->derr);
         } else {
             hipLaunchKernelGGL(k_step_fp32c, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
@@ -524,6 +536,17 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
         cur ^= 1;
     }
     L2T_HIP(c, hipGetLastError());
+    if (lat && (n & 1)) {
+        if (sys < 0) {
+            std::swap(c->Tl64, c->Tl64b);   // every slot was carried over
+        } else {
+            const SystemState &st = c->sys[sys];
+            hipLaunchKernelGGL(k_copy_range_f64, dim3(nblk(st.n_pad, 256)), dim3(256), 0,
+                               c->stream, c->Tl64b + st.atom_off, c->Tl64 + st.atom_off,
+                               (int64_t)st.n_pad);
+            L2T_HIP(c, hipGetLastError());
+        }
+    }
     if (n & 1) {
         if (sys < 0) {
             c->cur ^= 1;

@@ -73,6 +73,9 @@ struct DevParams {
     int32_t n_atoms, pad_;
     double mf_lambda, mf_kcoef;
     int32_t mf_chunk0, mf_nchunk;   // this system's chunks in the mean-field chunk table
+    // two-temperature lattice (Section 3.1): T^lat evolves with the electrons
+    int32_t lat_fd, pad2_;
+    double K_lat, g_over_clat;
 };
 
 // mean-field reduction: a system's slices in chunks of kMfChunk slices
@@ -95,6 +98,7 @@ struct SystemState {
     bool eatom_valid = false;    // the per-atom ledger holds this system's last advance
     bool has_fixed = false;      // some atoms hold their T_e
     l2t_mean_field mf{};         // mean-field parameter mode
+    l2t_lattice_fd lf{};         // two-temperature lattice mode
     int32_t max_nbrs = 0;
 };
 
@@ -110,6 +114,7 @@ struct GraphKey {
 constexpr int kKernelSliced = 0;   // global gathers through the int32 table
 constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
 constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
+constexpr int32_t kMaxBrickEdge = 1024;  // largest brick edge (cells) the layout considers
 constexpr int kSlicedBlockMax = 256;  // threads per workgroup, global-gather kernels
 
 struct Tuning {
@@ -180,6 +185,7 @@ struct l2t_ctx {
 
     double *T64[2] = {nullptr, nullptr};
     double *Tl64 = nullptr;
+    double *Tl64b = nullptr;     // second T^lat buffer of the two-temperature lattice mode
     double *srcw64 = nullptr;
     float *Thi[2] = {nullptr, nullptr};
     float *Tlo = nullptr;
@@ -193,6 +199,7 @@ struct l2t_ctx {
     int32_t n_mf_chunks = 0, mf_chunks_cap = 0;
     double *eatom = nullptr;     // internal [n_int]: energy to the lattice over the last advance
     bool atom_ledger = false;    // record eatom during advances
+    bool batch_fp64 = false;     // FP64: one launch per sub-step over all systems
     bool eatom_valid = false;    // eatom holds the record of the last advance
     double *slice_red = nullptr; // [n_slices][4]
     double *energy_out = nullptr;// [n_sys][8]

@@ -124,12 +124,27 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
                                        const DevParams &p, const int32_t *__restrict__ col,
                                        const double *__restrict__ T, double *__restrict__ Tn,
                                        const double *__restrict__ Tl,
+                                       double *__restrict__ Tl_out,
                                        const double *__restrict__ srcw, int64_t step,
                                        double *__restrict__ ledger, double *__restrict__ eatom,
                                        unsigned *err) {
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
     const double Ti = T[slot];
+    // two-temperature lattice (Section 3.1): the Fourier law over the same
+    // neighbours plus the coupling, from the step-n states; other systems
+    // carry T^lat over to the output buffer
+    if (Tl_out) {
+        double tl_new = Tl[slot];
+        if (p.lat_fd && valid) {
+            const double tli = fabs(Tl[slot]);
+            const int64_t b0 = (int64_t)si.col_base64 * kWave + lane;
+            double Lsum = 0.0;
+            for (int32_t k = 0; k < si.width; ++k) Lsum += fabs(Tl[col[b0 + (int64_t)k * kWave]]) - tli;
+            tl_new = tli + p.dt * (p.K_lat * Lsum + p.g_over_clat * (Ti - tli));
+        }
+        Tl_out[slot] = tl_new;
+    }
     const double ti = (Ti - p.T_min) * p.inv_span;
     const int64_t base = (int64_t)si.col_base64 * kWave + lane;
     double S = 0.0;
@@ -144,7 +159,7 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
     if (valid) {
         const double c = ce64(p, Ti);
         const double tl = Tl[slot];
-        const double coup = signbit(tl) ? 0.0 : p.g * (Ti - tl);
+        const double coup = (signbit(tl) && !p.lat_fd) ? 0.0 : p.g * (Ti - fabs(tl));
         if (p.laser_on) q = p.i0 * fabs(sw) * pulse64(p, step);
         e2l = coup * p.dt;
         if (eatom) eatom[slot] += e2l;

@@ -27,7 +27,7 @@ L2T_FIELD_TE, L2T_FIELD_TL, L2T_FIELD_GATE, L2T_FIELD_NBRS, L2T_FIELD_ELAT = 0, 
 L2T_FIELD_FIXED = 5
 L2T_CE_CONST, L2T_CE_LINEAR, L2T_CE_CAPPED = 0, 1, 2
 L2T_OPT_PERSISTENT, L2T_OPT_BLOCK, L2T_OPT_RESIDENT_MAX, L2T_OPT_GRAPH, L2T_OPT_AUTOTUNE = 0, 1, 2, 3, 4
-L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE, L2T_OPT_ATOM_LEDGER = 5, 6, 7
+L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE, L2T_OPT_ATOM_LEDGER, L2T_OPT_BATCH_FP64 = 5, 6, 7, 8
 L2T_XI_INSTANT, L2T_XI_LEDGER = 0, 1
 
 # every symbol the header declares (checked by the CPU test suite)
@@ -36,6 +36,7 @@ EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbor
            "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
            "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
            "l2t_coupling", "l2t_damping_step", "l2t_set_mean_field", "l2t_get_params",
+           "l2t_set_lattice_fd",
            "l2t_exchange_rate", "l2t_pair_fp32", "l2t_strerror", "l2t_last_error",
            "l2t_version")
 
@@ -59,6 +60,11 @@ class l2t_params(C.Structure):
 class l2t_mean_field(C.Structure):
     _fields_ = [("on", C.c_int32), ("reserved", C.c_int32), ("lambda_", C.c_double),
                 ("k_coef", C.c_double)]
+
+
+class l2t_lattice_fd(C.Structure):
+    _fields_ = [("on", C.c_int32), ("reserved", C.c_int32), ("K_lat", C.c_double),
+                ("c_lat", C.c_double)]
 
 
 class l2t_energy_report(C.Structure):
@@ -112,6 +118,7 @@ def load() -> C.CDLL:
         "l2t_coupling": (C.c_int, [vp, i32, i32, d, vp, vp, vp, i32]),
         "l2t_set_mean_field": (C.c_int, [vp, i32, P(l2t_mean_field)]),
         "l2t_get_params": (C.c_int, [vp, i32, P(l2t_params)]),
+        "l2t_set_lattice_fd": (C.c_int, [vp, i32, P(l2t_lattice_fd)]),
         "l2t_damping_step": (C.c_int, [vp, i32, d, vp, vp, vp, vp, i32]),
         "l2t_exchange_rate": (d, [d, d, i32, d]),
         "l2t_pair_fp32": (C.c_int, [vp, vp, vp, i64, vp]),
@@ -271,6 +278,12 @@ def l2t_set_mean_field(ctx, sys: int, on: bool, lambda_atom: float = 0.0,
     mf = l2t_mean_field(on=int(bool(on)), reserved=0, lambda_=float(lambda_atom),
                         k_coef=float(k_coef))
     return _check(ctx, load().l2t_set_mean_field(ctx, sys, C.byref(mf)))
+
+
+def l2t_set_lattice_fd(ctx, sys: int, on: bool, K_lat: float = 0.0, c_lat: float = 1.0) -> int:
+    """Two-temperature lattice mode of Section 3.1 (see l2t.h)."""
+    lf = l2t_lattice_fd(on=int(bool(on)), reserved=0, K_lat=float(K_lat), c_lat=float(c_lat))
+    return _check(ctx, load().l2t_set_lattice_fd(ctx, sys, C.byref(lf)))
 
 
 def l2t_get_params(ctx, sys: int) -> dict:

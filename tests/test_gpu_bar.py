@@ -1,0 +1,124 @@
+"""Two-temperature 1D bar of Section 3.1 (electrons by Eq. 2, lattice by the
+three-point Fourier law) through the C ABI against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import max_rel, oracle_neighbors
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1810_12357_amd.l2t")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _context(systems, r_cut, batch, lat=None):
+    ctx = L.Context(systems, L.L2T_FP64)
+    ctx.setup(r_cut)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, int(batch))
+    for s, on in enumerate(lat if lat is not None else [True] * len(systems)):
+        if on:
+            L.l2t_set_lattice_fd(ctx.h, s, True, W.K_L_BAR, W.C_L_BAR)
+    return ctx
+
+
+@pytest.mark.parametrize("batch", [0, 1])
+def test_bars_match_oracle_with_odd_step_counts(batch):
+    w = W.c6(n_bars=5, n_substeps=3000)
+    ctx = _context(w.systems, w.r_cut, batch)
+    chunks = (999, 1001, 1000)
+    want = []
+    for sy in w.systems:
+        row, col = oracle_neighbors(sy, w.r_cut)
+        T, Tl, out, step = sy.T_e0, sy.T_l, [], 0
+        for k in chunks:
+            T, Tl, _, bad = oracle.run_2t(row, col, T, Tl, sy.params, W.K_L_BAR, W.C_L_BAR, k,
+                                          step0=step)
+            assert bad == 0
+            step += k
+            out.append((T.copy(), Tl.copy()))
+        want.append(out)
+    for i, k in enumerate(chunks):
+        ctx.advance(k)
+        for s in range(len(w.systems)):
+            assert max_rel(ctx.get(s), want[s][i][0]) < 1e-12
+            assert max_rel(ctx.get(s, L.L2T_FIELD_TL), want[s][i][1]) < 1e-12
+    ctx.close()
+
+
+def test_one_bar_alone_and_a_bar_beside_an_ordinary_system():
+    bar = W.c6(n_bars=1).systems[0]
+    # an FCC system in the same context keeps its own (frozen) lattice temperature
+    c1 = W.c1(n_cells=4).systems[0]
+    r_cut = 1.05 * W.B_BAR                     # nearest FCC shell at a/sqrt(2) = 2.553 A
+    for batch in (0, 1):
+        ctx = _context([bar, c1], r_cut, batch, lat=[True, False])
+        if batch:
+            ctx.advance(501)
+        else:
+            L.l2t_advance_system(ctx.h, 0, 501)
+            L.l2t_advance_system(ctx.h, 1, 501)
+        rowb, colb = oracle_neighbors(bar, r_cut)
+        T, Tl, _, _ = oracle.run_2t(rowb, colb, bar.T_e0, bar.T_l, bar.params, W.K_L_BAR,
+                                    W.C_L_BAR, 501)
+        assert max_rel(ctx.get(0), T) < 1e-12
+        assert max_rel(ctx.get(0, L.L2T_FIELD_TL), Tl) < 1e-12
+        row1, col1 = oracle_neighbors(c1, r_cut)
+        T1, _, _ = oracle.run(row1, col1, c1.T_e0, c1.T_l, c1.params, 501)
+        assert max_rel(ctx.get(1), T1) < 1e-12
+        assert np.array_equal(ctx.get(1, L.L2T_FIELD_TL), c1.T_l)
+        ctx.close()
+    # FP32C contexts do not carry the lattice mode
+    ctx = L.Context([bar], L.L2T_FP32C)
+    ctx.setup(1.05 * W.B_BAR)
+    with pytest.raises(L.L2TError) as ex:
+        L.l2t_set_lattice_fd(ctx.h, 0, True, W.K_L_BAR, W.C_L_BAR)
+    assert ex.value.status == L.L2T_ENOTIMPL
+    ctx.close()
+
+
+def _closed_form_means(sy, n):
+    g, ce, dt = sy.params["g"], sy.params["ce_const"], sy.params["dt"]
+    cl = W.C_L_BAR
+    Teq = (ce * sy.T_e0.mean() + cl * sy.T_l.mean()) / (ce + cl)
+    D = (sy.T_e0.mean() - sy.T_l.mean()) * (1.0 - dt * (g / ce + g / cl)) ** n
+    return Teq + cl / (ce + cl) * D, Teq - ce / (ce + cl) * D
+
+
+def test_full_bar_batch_three_picoseconds():
+    """2048 bars, 30,000 sub-steps (3 ps at 0.1 fs) in the batched launch the
+    benchmark times: every bar keeps c_e sum T_e + c_lat sum T_l and follows
+    the closed-form means toward the Section 3.1 equilibrium; sampled bars
+    match the oracle node by node."""
+    w = W.c6()
+    ctx = _context(w.systems, w.r_cut, 1)
+    n = w.n_substeps
+    ctx.advance(n)
+    L.l2t_sync(ctx.h)
+    ce = w.systems[0].params["ce_const"]
+    for s, sy in enumerate(w.systems):
+        T, Tl = ctx.get(s), ctx.get(s, L.L2T_FIELD_TL)
+        e0 = ce * sy.T_e0.sum() + W.C_L_BAR * sy.T_l.sum()
+        assert ce * T.sum() + W.C_L_BAR * Tl.sum() == pytest.approx(e0, rel=1e-12)
+        mT, mTl = _closed_form_means(sy, n)
+        assert T.mean() == pytest.approx(mT, rel=1e-11)
+        assert Tl.mean() == pytest.approx(mTl, rel=1e-11)
+    rng = np.random.default_rng(2)
+    for s in np.r_[0, rng.integers(1, len(w.systems), 3)]:
+        sy = w.systems[int(s)]
+        row, col = oracle_neighbors(sy, w.r_cut)
+        T, Tl, _, _ = oracle.run_2t(row, col, sy.T_e0, sy.T_l, sy.params, W.K_L_BAR, W.C_L_BAR, n)
+        assert max_rel(ctx.get(int(s)), T) < 1e-11
+        assert max_rel(ctx.get(int(s), L.L2T_FIELD_TL), Tl) < 1e-11
+    # the paper's bar after 3 ps: electrons and lattice within a few K of each
+    # other everywhere, heading to T_eq = 311.4 K
+    T0, Tl0 = ctx.get(0), ctx.get(0, L.L2T_FIELD_TL)
+    assert np.max(np.abs(T0 - Tl0)) < 10.0 and abs(T0.mean() - 311.4) < 6.0
+    ctx.close()
