@@ -69,66 +69,89 @@ void dfree(T *&p) {
 
 namespace l2t {
 
+void *tmp_buf(l2t_ctx *c, int slot, size_t bytes) {
+    if (bytes > c->tmp_cap[slot]) {
+        (void)hipStreamSynchronize(c->stream);
+        if (c->tmp[slot]) (void)hipFree(c->tmp[slot]);
+        c->tmp[slot] = nullptr;
+        c->tmp_cap[slot] = 0;
+        if (hipMalloc(&c->tmp[slot], bytes) != hipSuccess) return nullptr;
+        c->tmp_cap[slot] = bytes;
+    }
+    return c->tmp[slot];
+}
+
+// Size the internal-order buffers for n_int slots and the brick tables.
+// Buffers only grow: a rebuild of the same shape (every pass of an MD loop)
+// keeps every allocation.  Their contents are rewritten by the build and by
+// the field setters, which a rebuild requires anyway.
 int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, int64_t shell_len,
                    int64_t halo_len) {
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    dfree(c->pos_int);
-    dfree(c->perm);
-    dfree(c->cell_int);
-    dfree(c->cnt);
-    dfree(c->slices);
-    for (int b = 0; b < 2; ++b) {
-        dfree(c->T64[b]);
-        dfree(c->Thi[b]);
-    }
-    dfree(c->Tl64);
-    dfree(c->Tl64b);
-    dfree(c->srcw64);
-    dfree(c->Tlo);
-    dfree(c->Tl32);
-    dfree(c->srcw32);
-    dfree(c->ledger);
-    dfree(c->eatom);
-    dfree(c->slice_red);
-    dfree(c->bricks);
-    dfree(c->brick_list);
-    dfree(c->shell);
-    dfree(c->halo);
     c->n_int = n_int;
     c->n_slices = n_int / kWave;
     c->n_bricks = n_bricks;
     c->n_brick_list = n_list;
     c->cur = 0;
-    const size_t NI = (size_t)n_int, NS = (size_t)c->n_slices;
     int rc = L2T_OK;
 #define ALLOC(p, n)                                    \
     if (rc == L2T_OK) rc = dalloc(c, &(p), (size_t)(n));
-    ALLOC(c->pos_int, 3 * NI);
-    ALLOC(c->perm, NI);
-    ALLOC(c->cell_int, NI);
-    ALLOC(c->cnt, NI);
-    ALLOC(c->slices, NS);
-    if (c->precision == L2T_FP64) {
-        ALLOC(c->T64[0], NI);
-        ALLOC(c->T64[1], NI);
-        ALLOC(c->Tl64, NI);
-        ALLOC(c->Tl64b, NI);
-        ALLOC(c->srcw64, NI);
-    } else {
-        ALLOC(c->Thi[0], NI);
-        ALLOC(c->Thi[1], NI);
-        ALLOC(c->Tlo, NI);
-        ALLOC(c->Tl32, NI);
-        ALLOC(c->srcw32, NI);
+    if ((size_t)n_int > c->cap_ni) {
+        dfree(c->pos_int);
+        dfree(c->perm);
+        dfree(c->cell_int);
+        dfree(c->cnt);
+        dfree(c->slices);
+        for (int b = 0; b < 2; ++b) {
+            dfree(c->T64[b]);
+            dfree(c->Thi[b]);
+        }
+        dfree(c->Tl64);
+        dfree(c->Tl64b);
+        dfree(c->srcw64);
+        dfree(c->Tlo);
+        dfree(c->Tl32);
+        dfree(c->srcw32);
+        dfree(c->ledger);
+        dfree(c->eatom);
+        dfree(c->slice_red);
+        c->cap_ni = 0;
+        const size_t NI = (size_t)n_int, NS = NI / kWave;
+        ALLOC(c->pos_int, 3 * NI);
+        ALLOC(c->perm, NI);
+        ALLOC(c->cell_int, NI);
+        ALLOC(c->cnt, NI);
+        ALLOC(c->slices, NS);
+        if (c->precision == L2T_FP64) {
+            ALLOC(c->T64[0], NI);
+            ALLOC(c->T64[1], NI);
+            ALLOC(c->Tl64, NI);
+            ALLOC(c->Tl64b, NI);
+            ALLOC(c->srcw64, NI);
+        } else {
+            ALLOC(c->Thi[0], NI);
+            ALLOC(c->Thi[1], NI);
+            ALLOC(c->Tlo, NI);
+            ALLOC(c->Tl32, NI);
+            ALLOC(c->srcw32, NI);
+        }
+        ALLOC(c->ledger, 3 * NS);
+        ALLOC(c->eatom, NI);
+        ALLOC(c->slice_red, 4 * NS);
+        if (rc == L2T_OK) c->cap_ni = NI;
     }
-    ALLOC(c->ledger, 3 * NS);
-    ALLOC(c->eatom, NI);
-    ALLOC(c->slice_red, 4 * NS);
-    ALLOC(c->bricks, (size_t)n_bricks);
-    ALLOC(c->brick_list, (size_t)n_list);
-    ALLOC(c->shell, (size_t)shell_len);
-    ALLOC(c->halo, (size_t)halo_len);
+    auto grow = [&](auto *&p, size_t &cap, size_t n) {
+        if (rc != L2T_OK || n <= cap) return;
+        dfree(p);
+        cap = 0;
+        rc = dalloc(c, &p, n);
+        if (rc == L2T_OK) cap = n;
+    };
+    grow(c->bricks, c->cap_nb, (size_t)n_bricks);
+    grow(c->brick_list, c->cap_nl, (size_t)n_list);
+    grow(c->shell, c->cap_sh, (size_t)shell_len);
+    grow(c->halo, c->cap_ha, (size_t)halo_len);
 #undef ALLOC
     if (rc != L2T_OK) return fail(c, L2T_ENOMEM, "internal buffer allocation failed");
     return L2T_OK;
@@ -278,6 +301,8 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c->dbar);
     dfree(c->stage);
     if (c->scratch) (void)hipFree(c->scratch);
+    for (void *p : c->tmp)
+        if (p) (void)hipFree(p);
     if (c->rec.buf) (void)hipFree(c->rec.buf);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
+#include <thread>
 #include <vector>
 
 #include "l2t_internal.h"
@@ -115,6 +116,54 @@ __global__ void k_scan_excl(const int32_t *in, int32_t *out, int64_t n) {
         out[i] = (int32_t)acc;
         acc += v;
     }
+}
+
+// Multi-block exclusive scan of the cell counts: tile sums, a scan of the tile
+// sums (k_scan_excl on the short array), then each tile's local scan.
+constexpr int kScanPer = 8, kScanThreads = 256, kScanTile = kScanPer * kScanThreads;
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t *in, int64_t n,
+                                                            int32_t *bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t s = 0;
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (base + k < n) s += in[base + k];
+    __shared__ int32_t sh[kScanThreads];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t *in, int64_t n,
+                                                            const int32_t *boff, int32_t *out) {
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanPer;
+    int32_t v[kScanPer], s = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        v[u] = base + u < n ? in[base + u] : 0;
+        s += v[u];
+    }
+    __shared__ int32_t sh[kScanThreads];
+    sh[t] = s;
+    __syncthreads();
+    for (int w = 1; w < kScanThreads; w <<= 1) {   // inclusive scan of the thread sums
+        const int32_t add = t >= w ? sh[t - w] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int32_t acc = boff[blockIdx.x] + sh[t] - s;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        if (base + u < n) out[base + u] = acc;
+        acc += v[u];
+    }
+    if (blockIdx.x == 0 && t == 0) out[n] = boff[gridDim.x];
 }
 
 __global__ void k_scatter(const int32_t *cell_of, int32_t n, const int32_t *start, int32_t *fill,
@@ -695,15 +744,19 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
             for (int32_t r = L.brick_cell0[b]; r < L.brick_cell0[b + 1]; ++r)
                 h_brick[L.rank_off + r] = L.brick0 + b;
     }
-    DevBuf<int32_t> d_rank(c, ranks_total), d_cell(c, ranks_total), d_brick(c, ranks_total),
-        d_count(c, cells_total), d_start(c, cells_total);
-    if (!d_rank.ok() || !d_cell.ok() || !d_brick.ok() || !d_count.ok() || !d_start.ok())
+    // grow-only temporaries owned by the context (kept for the next build)
+    int32_t *d_rank = tmp_of<int32_t>(c, 0, ranks_total);
+    int32_t *d_cell = tmp_of<int32_t>(c, 1, ranks_total);
+    int32_t *d_brick = tmp_of<int32_t>(c, 2, ranks_total);
+    int32_t *d_count = tmp_of<int32_t>(c, 3, cells_total);
+    int32_t *d_start = tmp_of<int32_t>(c, 4, cells_total);
+    if (!d_rank || !d_cell || !d_brick || !d_count || !d_start)
         return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
-    L2T_HIP(c, hipMemcpyAsync(d_rank.p, h_rank.data(), sizeof(int32_t) * ranks_total,
+    L2T_HIP(c, hipMemcpyAsync(d_rank, h_rank.data(), sizeof(int32_t) * ranks_total,
                               hipMemcpyHostToDevice, st_));
-    L2T_HIP(c, hipMemcpyAsync(d_cell.p, h_cell.data(), sizeof(int32_t) * ranks_total,
+    L2T_HIP(c, hipMemcpyAsync(d_cell, h_cell.data(), sizeof(int32_t) * ranks_total,
                               hipMemcpyHostToDevice, st_));
-    L2T_HIP(c, hipMemcpyAsync(d_brick.p, h_brick.data(), sizeof(int32_t) * ranks_total,
+    L2T_HIP(c, hipMemcpyAsync(d_brick, h_brick.data(), sizeof(int32_t) * ranks_total,
                               hipMemcpyHostToDevice, st_));
     L2T_HIP(c, hipMemsetAsync(c->derr, 0, sizeof(unsigned), st_));
     // ---- binning in brick order (device) -------------------------------------------
@@ -719,16 +772,26 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         }
         const int32_t n = st.desc.n_atoms;
         const double *px = c->pos + st.caller_off, *py = px + c->n_tot, *pz = py + c->n_tot;
-        int32_t *count = d_count.p + cstart_off[s];
-        int32_t *start = d_start.p + cstart_off[s];
+        int32_t *count = d_count + cstart_off[s];
+        int32_t *start = d_start + cstart_off[s];
         int32_t *cell_of = c->cell_of + st.caller_off;
         int32_t *sorted = c->sorted_local + st.caller_off;
-        const int32_t *rank_of_cell = d_rank.p + lay[s].rank_off;
+        const int32_t *rank_of_cell = d_rank + lay[s].rank_off;
         hipLaunchKernelGGL(k_fill_i32, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, count,
                            st.ncell, 0);
         hipLaunchKernelGGL(k_bin, dim3(nblk(n, 256)), dim3(256), 0, st_, px, py, pz, n, g,
                            rank_of_cell, cell_of, count, c->derr);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st_, count, start, st.ncell);
+        {
+            const unsigned nt = nblk(st.ncell, kScanTile);
+            int32_t *bsum = tmp_of<int32_t>(c, 11, 2 * (int64_t)nt + 1);
+            if (!bsum) return fail(c, L2T_ENOMEM, "scan scratch allocation failed");
+            hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(kScanThreads), 0, st_, count,
+                               (int64_t)st.ncell, bsum);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st_, bsum, bsum + nt,
+                               (int64_t)nt);
+            hipLaunchKernelGGL(k_tile_scan, dim3(nt), dim3(kScanThreads), 0, st_, count,
+                               (int64_t)st.ncell, bsum + nt, start);
+        }
         hipLaunchKernelGGL(k_fill_i32, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_, count,
                            st.ncell, 0);
         hipLaunchKernelGGL(k_scatter, dim3(nblk(n, 256)), dim3(256), 0, st_, cell_of, n, start,
@@ -738,38 +801,38 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     }
     L2T_HIP(c, hipGetLastError());
     std::vector<int32_t> h_start(cells_total);
-    L2T_HIP(c, hipMemcpyAsync(h_start.data(), d_start.p, sizeof(int32_t) * cells_total,
+    L2T_HIP(c, hipMemcpyAsync(h_start.data(), d_start, sizeof(int32_t) * cells_total,
                               hipMemcpyDeviceToHost, st_));
     unsigned herr = 0;
     L2T_HIP(c, hipMemcpyAsync(&herr, c->derr, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
     if (herr & kErrBox) return fail(c, L2T_EINVAL, "an atom lies outside the box on a free axis");
     // ---- slot layout, halo tables (host) -------------------------------------------
+    // slots and shell offsets in brick order (sequential, cheap); then every
+    // brick's shell table and halo cell list (independent, split over host
+    // threads); then halo offsets in brick order
     std::vector<BrickInfo> hb(nbricks);
     std::vector<int32_t> h_atom0(nbricks), h_list;
     std::vector<int32_t> h_shell;
     std::vector<HaloCell> h_halo;
     int32_t slot = 0;
-    int64_t halo_total = 0;
+    int64_t halo_total = 0, shell_total = 0;
     int32_t tile_max = 0;
+    std::vector<int32_t> sys_of_brick(nbricks);
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         const SysLayout &L = lay[s];
         const int32_t *start = h_start.data() + cstart_off[s];
         st.atom_off = slot;
-        std::vector<int32_t> stamp(st.ncell, -1), stamp_off(st.ncell, 0);
         for (int32_t b = 0; b < L.nbrick; ++b) {
             const int32_t gb = L.brick0 + b;
             BrickInfo &bi = hb[gb];
+            sys_of_brick[gb] = s;
             const int32_t X = b / (L.nb[1] * L.nb[2]), Y = (b / L.nb[2]) % L.nb[1], Z = b % L.nb[2];
             bi.o[0] = X * L.b[0];
             bi.o[1] = Y * L.b[1];
             bi.o[2] = Z * L.b[2];
-            int32_t e[3];
-            for (int d = 0; d < 3; ++d) {
-                e[d] = std::min(L.b[d], st.nc[d] - bi.o[d]);
-                bi.sh[d] = e[d] + 2;
-            }
+            for (int d = 0; d < 3; ++d) bi.sh[d] = std::min(L.b[d], st.nc[d] - bi.o[d]) + 2;
             const int32_t a0 = start[L.brick_cell0[b]], a1 = start[L.brick_cell0[b + 1]];
             h_atom0[gb] = a0;
             bi.sys = s;
@@ -777,62 +840,113 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
             bi.n_own = a1 - a0;
             bi.n_own_pad = (bi.n_own + kWave - 1) / kWave * kWave;
             bi.slice0 = slot / kWave;
-            bi.halo_off = (int32_t)halo_total;
             bi.n_halo = 0;
-            bi.shell_off = (int32_t)h_shell.size();
+            bi.halo_off = 0;
+            bi.shell_off = (int32_t)shell_total;
             slot += bi.n_own_pad;
             if (bi.n_own == 0) continue;
             h_list.push_back(gb);
-            const int32_t nsh = bi.sh[0] * bi.sh[1] * bi.sh[2];
-            h_shell.resize(h_shell.size() + nsh);
-            int32_t *shl = h_shell.data() + bi.shell_off;
-            for (int32_t p0 = 0; p0 < bi.sh[0]; ++p0)
-                for (int32_t p1 = 0; p1 < bi.sh[1]; ++p1)
-                    for (int32_t p2 = 0; p2 < bi.sh[2]; ++p2) {
-                        const int32_t p[3] = {p0, p1, p2};
-                        int32_t cc[3];
-                        bool valid = true, own = true;
-                        for (int d = 0; d < 3; ++d) {
-                            int32_t v = bi.o[d] + p[d] - 1;
-                            if (st.desc.periodic[d]) {
-                                v = (v % st.nc[d] + st.nc[d]) % st.nc[d];
-                            } else if (v < 0 || v >= st.nc[d]) {
-                                valid = false;
-                            }
-                            cc[d] = v;
-                            own = own && v >= bi.o[d] && v < bi.o[d] + e[d];
-                        }
-                        int32_t &out = shl[(p0 * bi.sh[1] + p1) * bi.sh[2] + p2];
-                        if (!valid) {
-                            out = -2;
-                            continue;
-                        }
-                        if (own) {
-                            out = -1;
-                            continue;
-                        }
-                        const int32_t cell = (cc[0] * st.nc[1] + cc[1]) * st.nc[2] + cc[2];
-                        if (stamp[cell] != gb) {
-                            stamp[cell] = gb;
-                            stamp_off[cell] = bi.n_halo;
-                            const int32_t rk = L.rank_of_cell[cell];
-                            const int32_t cnt = start[rk + 1] - start[rk];
-                            HaloCell h;
-                            h.brick = gb;
-                            h.start_index = (int32_t)(cstart_off[s] + rk);
-                            h.offset = bi.n_halo;
-                            h.pos_base = (int32_t)st.caller_off;
-                            h_halo.push_back(h);
-                            bi.n_halo += cnt;
-                        }
-                        out = stamp_off[cell];
-                    }
-            halo_total += bi.n_halo;
-            tile_max = std::max(tile_max, bi.n_own_pad + bi.n_halo);
+            shell_total += (int64_t)bi.sh[0] * bi.sh[1] * bi.sh[2];
         }
         st.n_pad = slot - st.atom_off;
         st.slice0 = st.atom_off / kWave;
         st.n_slices = st.n_pad / kWave;
+    }
+    if (shell_total > INT32_MAX) return fail(c, L2T_ENOMEM, "shell tables too large");
+    h_shell.assign((size_t)shell_total, 0);
+    const int32_t n_list = (int32_t)h_list.size();
+    const int n_thr = (int)std::max<int64_t>(
+        1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), n_list / 32}));
+    std::vector<std::vector<HaloCell>> part(n_thr);
+    auto tables = [&](int t) {
+        const int32_t q0 = (int32_t)((int64_t)n_list * t / n_thr);
+        const int32_t q1 = (int32_t)((int64_t)n_list * (t + 1) / n_thr);
+        std::vector<int32_t> cv[3], seen;
+        std::vector<char> ok[3], own[3];
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t gb = h_list[q];
+            BrickInfo &bi = hb[gb];
+            const int s = sys_of_brick[gb];
+            const SystemState &st = c->sys[s];
+            const SysLayout &L = lay[s];
+            const int32_t *start = h_start.data() + cstart_off[s];
+            // per axis: wrapped cell coordinate, inside the grid, inside the brick
+            bool wraps = false;
+            for (int d = 0; d < 3; ++d) {
+                const int32_t e = bi.sh[d] - 2;
+                cv[d].resize(bi.sh[d]);
+                ok[d].resize(bi.sh[d]);
+                own[d].resize(bi.sh[d]);
+                for (int32_t p = 0; p < bi.sh[d]; ++p) {
+                    int32_t v = bi.o[d] + p - 1;
+                    bool in = true;
+                    if (st.desc.periodic[d])
+                        v = (v % st.nc[d] + st.nc[d]) % st.nc[d];
+                    else if (v < 0 || v >= st.nc[d])
+                        in = false;
+                    cv[d][p] = v;
+                    ok[d][p] = in;
+                    own[d][p] = v >= bi.o[d] && v < bi.o[d] + e;
+                }
+                // a periodic axis shorter than the shell maps two shell cells onto one
+                wraps |= st.desc.periodic[d] && st.nc[d] < bi.sh[d];
+            }
+            seen.clear();
+            int32_t *shl = h_shell.data() + bi.shell_off;
+            for (int32_t p0 = 0; p0 < bi.sh[0]; ++p0)
+                for (int32_t p1 = 0; p1 < bi.sh[1]; ++p1)
+                    for (int32_t p2 = 0; p2 < bi.sh[2]; ++p2) {
+                        int32_t &out = shl[(p0 * bi.sh[1] + p1) * bi.sh[2] + p2];
+                        if (!(ok[0][p0] && ok[1][p1] && ok[2][p2])) {
+                            out = -2;
+                            continue;
+                        }
+                        if (own[0][p0] && own[1][p1] && own[2][p2]) {
+                            out = -1;
+                            continue;
+                        }
+                        const int32_t cell = (cv[0][p0] * st.nc[1] + cv[1][p1]) * st.nc[2] + cv[2][p2];
+                        if (wraps) {   // the cell may already be in this brick's halo
+                            int32_t hit = -1;
+                            for (size_t k = 0; k < seen.size(); k += 2)
+                                if (seen[k] == cell) {
+                                    hit = seen[k + 1];
+                                    break;
+                                }
+                            if (hit >= 0) {
+                                out = hit;
+                                continue;
+                            }
+                            seen.push_back(cell);
+                            seen.push_back(bi.n_halo);
+                        }
+                        const int32_t rk = L.rank_of_cell[cell];
+                        HaloCell h;
+                        h.brick = gb;
+                        h.start_index = (int32_t)(cstart_off[s] + rk);
+                        h.offset = bi.n_halo;
+                        h.pos_base = (int32_t)st.caller_off;
+                        part[t].push_back(h);
+                        out = bi.n_halo;
+                        bi.n_halo += start[rk + 1] - start[rk];
+                    }
+        }
+    };
+    if (n_thr == 1) {
+        tables(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < n_thr; ++t) pool.emplace_back(tables, t);
+        for (auto &th : pool) th.join();
+    }
+    size_t n_cells_halo = 0;
+    for (const auto &v : part) n_cells_halo += v.size();
+    h_halo.reserve(n_cells_halo);
+    for (const auto &v : part) h_halo.insert(h_halo.end(), v.begin(), v.end());
+    for (BrickInfo &bi : hb) {   // empty bricks keep n_halo = 0 and the running offset
+        bi.halo_off = (int32_t)std::min<int64_t>(halo_total, INT32_MAX);
+        halo_total += bi.n_halo;
+        if (bi.n_own > 0) tile_max = std::max(tile_max, bi.n_own_pad + bi.n_halo);
     }
     if (tile_max > kTileCapFloats) {
         *tile_overflow = true;
@@ -851,13 +965,13 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     if (!h_shell.empty())
         L2T_HIP(c, hipMemcpyAsync(c->shell, h_shell.data(), sizeof(int32_t) * h_shell.size(),
                                   hipMemcpyHostToDevice, st_));
-    DevBuf<int32_t> d_atom0(c, nbricks);
-    DevBuf<HaloCell> d_halo(c, (int64_t)h_halo.size());
-    if (!d_atom0.ok() || !d_halo.ok()) return fail(c, L2T_ENOMEM, "brick table allocation failed");
-    L2T_HIP(c, hipMemcpyAsync(d_atom0.p, h_atom0.data(), sizeof(int32_t) * nbricks,
+    int32_t *d_atom0 = tmp_of<int32_t>(c, 5, nbricks);
+    HaloCell *d_halo = tmp_of<HaloCell>(c, 6, (int64_t)h_halo.size());
+    if (!d_atom0 || !d_halo) return fail(c, L2T_ENOMEM, "brick table allocation failed");
+    L2T_HIP(c, hipMemcpyAsync(d_atom0, h_atom0.data(), sizeof(int32_t) * nbricks,
                               hipMemcpyHostToDevice, st_));
     if (!h_halo.empty())
-        L2T_HIP(c, hipMemcpyAsync(d_halo.p, h_halo.data(), sizeof(HaloCell) * h_halo.size(),
+        L2T_HIP(c, hipMemcpyAsync(d_halo, h_halo.data(), sizeof(HaloCell) * h_halo.size(),
                                   hipMemcpyHostToDevice, st_));
     // ---- slots, counts (device) ----------------------------------------------------
     const double rc2 = r_cut * r_cut;
@@ -872,13 +986,13 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                            st.atom_off, st.n_pad, c->perm, c->cell_int, qx, qy, qz, c->cnt);
         hipLaunchKernelGGL(k_assign, dim3(nblk(n, 256)), dim3(256), 0, st_,
                            c->sorted_local + st.caller_off, n, st.atom_off, st.caller_off, px, py,
-                           pz, c->cell_of + st.caller_off, d_brick.p + ro, c->bricks, d_atom0.p,
+                           pz, c->cell_of + st.caller_off, d_brick + ro, c->bricks, d_atom0,
                            grids[s], c->perm, c->inv, c->cell_int, c->pos_slot + st.caller_off,
                            qx, qy, qz);
         hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
                            c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
-                           d_start.p + cstart_off[s], d_rank.p + ro, d_cell.p + ro,
-                           d_brick.p + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, nullptr,
+                           d_start + cstart_off[s], d_rank + ro, d_cell + ro,
+                           d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, nullptr,
                            nullptr, nullptr);
     }
     L2T_HIP(c, hipGetLastError());
@@ -887,46 +1001,47 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     for (int32_t gb : h_list) own_max_all = std::max(own_max_all, hb[gb].n_own);
     if (c->n_brick_list > 0 && own_max_all <= 12288) {   // counts staged in 48 KB of LDS
         const int64_t NIi = c->n_int;
-        DevBuf<int32_t> to(c, NIi), ti(c, 3 * NIi);
-        DevBuf<double> td(c, 3 * NIi);
-        if (!to.ok() || !ti.ok() || !td.ok())
+        int32_t *to = tmp_of<int32_t>(c, 7, NIi);
+        int32_t *ti = tmp_of<int32_t>(c, 8, 3 * NIi);
+        double *td = tmp_of<double>(c, 9, 3 * NIi);
+        if (!to || !ti || !td)
             return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
         int32_t own_max = 0;
         for (int32_t gb : h_list) own_max = std::max(own_max, hb[gb].n_own);
         const dim3 gi(nblk(NIi, 256)), bi(256);
-        hipLaunchKernelGGL(k_iota, gi, bi, 0, st_, to.p, c->n_int);
+        hipLaunchKernelGGL(k_iota, gi, bi, 0, st_, to, c->n_int);
         hipLaunchKernelGGL(k_brick_rank, dim3(c->n_brick_list), dim3(256),
                            sizeof(int32_t) * (size_t)own_max, st_, c->bricks, c->brick_list,
-                           c->cnt, to.p);
-        L2T_HIP(c, hipMemcpyAsync(ti.p, c->perm, sizeof(int32_t) * NIi, hipMemcpyDeviceToDevice,
+                           c->cnt, to);
+        L2T_HIP(c, hipMemcpyAsync(ti, c->perm, sizeof(int32_t) * NIi, hipMemcpyDeviceToDevice,
                                   st_));
-        L2T_HIP(c, hipMemcpyAsync(ti.p + NIi, c->cell_int, sizeof(int32_t) * NIi,
+        L2T_HIP(c, hipMemcpyAsync(ti + NIi, c->cell_int, sizeof(int32_t) * NIi,
                                   hipMemcpyDeviceToDevice, st_));
-        L2T_HIP(c, hipMemcpyAsync(ti.p + 2 * NIi, c->cnt, sizeof(int32_t) * NIi,
+        L2T_HIP(c, hipMemcpyAsync(ti + 2 * NIi, c->cnt, sizeof(int32_t) * NIi,
                                   hipMemcpyDeviceToDevice, st_));
-        L2T_HIP(c, hipMemcpyAsync(td.p, c->pos_int, sizeof(double) * 3 * NIi,
+        L2T_HIP(c, hipMemcpyAsync(td, c->pos_int, sizeof(double) * 3 * NIi,
                                   hipMemcpyDeviceToDevice, st_));
-        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti.p, to.p, c->n_int, c->perm);
-        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti.p + NIi, to.p, c->n_int, c->cell_int);
-        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti.p + 2 * NIi, to.p, c->n_int, c->cnt);
+        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti, to, c->n_int, c->perm);
+        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti + NIi, to, c->n_int, c->cell_int);
+        hipLaunchKernelGGL(k_scatter_i32, gi, bi, 0, st_, ti + 2 * NIi, to, c->n_int, c->cnt);
         for (int d = 0; d < 3; ++d)
-            hipLaunchKernelGGL(k_scatter_f64, gi, bi, 0, st_, td.p + d * NIi, to.p, c->n_int,
+            hipLaunchKernelGGL(k_scatter_f64, gi, bi, 0, st_, td + d * NIi, to, c->n_int,
                                c->pos_int + d * NIi);
         hipLaunchKernelGGL(k_inverse, gi, bi, 0, st_, c->perm, c->n_int, c->inv);
         hipLaunchKernelGGL(k_remap, dim3(nblk(c->n_tot, 256)), dim3(256), 0, st_, c->pos_slot,
-                           c->n_tot, to.p);
+                           c->n_tot, to);
         L2T_HIP(c, hipGetLastError());
         L2T_HIP(c, hipStreamSynchronize(st_));
     }
     // ---- slice widths -> column offsets (host scan) -------------------------------
-    DevBuf<int32_t> dw(c, 2 * (int64_t)c->n_slices + 2);
-    if (!dw.ok()) return fail(c, L2T_ENOMEM, "slice width allocation failed");
+    int32_t *dw = tmp_of<int32_t>(c, 10, 2 * (int64_t)c->n_slices + 2);
+    if (!dw) return fail(c, L2T_ENOMEM, "slice width allocation failed");
     hipLaunchKernelGGL(k_slice_width, dim3(nblk(c->n_slices, 256)), dim3(256), 0, st_, c->cnt,
-                       c->perm, c->n_slices, dw.p, dw.p + c->n_slices);
+                       c->perm, c->n_slices, dw, dw + c->n_slices);
     L2T_HIP(c, hipGetLastError());
     std::vector<int32_t> hw(2 * (size_t)c->n_slices);
     if (!hw.empty())
-        L2T_HIP(c, hipMemcpyAsync(hw.data(), dw.p, sizeof(int32_t) * hw.size(),
+        L2T_HIP(c, hipMemcpyAsync(hw.data(), dw, sizeof(int32_t) * hw.size(),
                                   hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
     std::vector<SliceInfo> hs(c->n_slices);
@@ -981,15 +1096,15 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         const int64_t ro = lay[s].rank_off;
         hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
                            c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
-                           d_start.p + cstart_off[s], d_rank.p + ro, d_cell.p + ro,
-                           d_brick.p + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, c->slices,
+                           d_start + cstart_off[s], d_rank + ro, d_cell + ro,
+                           d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, c->slices,
                            c->col, (uint16_t *)c->colw);
     }
     hipLaunchKernelGGL(k_pad_rows, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
                        c->slices, c->bricks, c->n_int, c->col, (uint16_t *)c->colw);
     if (!h_halo.empty())
         hipLaunchKernelGGL(k_halo_expand, dim3(nblk((int64_t)h_halo.size(), 256)), dim3(256), 0,
-                           st_, d_halo.p, (int64_t)h_halo.size(), c->bricks, d_start.p,
+                           st_, d_halo, (int64_t)h_halo.size(), c->bricks, d_start,
                            c->pos_slot, c->halo);
     L2T_HIP(c, hipGetLastError());
     // ---- statistics ----------------------------------------------------------------------

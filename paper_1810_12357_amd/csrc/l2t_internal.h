@@ -210,6 +210,11 @@ struct l2t_ctx {
     double *stage = nullptr;     // staging [max(n_tot, 3 * max_n)]
     void *scratch = nullptr;     // temporary (autotune snapshot, velocities)
     size_t scratch_bytes = 0;
+    // grow-only capacities of the internal-order buffers and the brick tables
+    size_t cap_ni = 0, cap_nb = 0, cap_nl = 0, cap_sh = 0, cap_ha = 0;
+    // grow-only temporaries of the neighbour build, one per use
+    void *tmp[12] = {};
+    size_t tmp_cap[12] = {};
 
     std::vector<l2t::DevParams> hparams;
     l2t::Tuning tune;
@@ -274,6 +279,12 @@ int autotune(l2t_ctx *c);
 
 // ---- buffers ---------------------------------------------------------------
 int ensure_scratch(l2t_ctx *c, size_t bytes);
+// temporary device buffer `slot` of at least n elements (kept for the next call)
+void *tmp_buf(l2t_ctx *c, int slot, size_t bytes);
+template <class T>
+inline T *tmp_of(l2t_ctx *c, int slot, int64_t n) {
+    return static_cast<T *>(tmp_buf(c, slot, sizeof(T) * (size_t)(n > 0 ? n : 1)));
+}
 // (re)allocate every internal-order buffer for n_int slots and the brick tables
 int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, int64_t shell_len,
                    int64_t halo_len);
