@@ -625,42 +625,57 @@ void drop_graphs(l2t_ctx *c) {
     c->graphs.clear();
 }
 
-// FP32C advance of all systems with the tuned configuration, captured once
-// per (n, buffer parity, configuration) in a hipGraph and replayed.
+// FP32C advance of all systems with the tuned configuration.  The mean-field
+// parameters are refreshed from the state at the start of the advance; the
+// sub-steps then run as replays of captured hipGraphs of kGraphChunk
+// sub-steps plus one graph for the remainder, each captured once per
+// (length, buffer parity, configuration).  Every captured chunk ends by
+// advancing the device step counters, so a replay does not depend on where
+// in the advance it runs, and a new neighbour table costs one short capture
+// rather than one node per sub-step of the whole advance.
 int advance_fp32c(l2t_ctx *c, int32_t n) {
     const Tuning &t = c->tune;
+    int rc = mean_field_refresh(c, -1);
+    if (rc != L2T_OK) return rc;
+    double *eatom = atom_ledger_ptr(c);
     if (!t.graph) {
-        int rc = mean_field_refresh(c, -1);
-        if (rc == L2T_OK) rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
+        rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, eatom);
         if (rc != L2T_OK) return rc;
+        if (n & 1) c->cur ^= 1;
     } else {
-        GraphKey key{n, (c->cur << 8) | (t.persistent << 4) | t.kernel, t.block};
-        auto it = c->graphs.find(key);
-        if (it == c->graphs.end()) {
-            // capture on a private stream (the caller's may be the legacy null
-            // stream, which cannot be captured), replay on the caller's
-            if (!c->cap_stream)
-                L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-            hipGraph_t g = nullptr;
-            hipStream_t user = c->stream;
-            L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-            c->stream = c->cap_stream;
-            int rc = mean_field_refresh(c, -1);
-            if (rc == L2T_OK)
-                rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, atom_ledger_ptr(c));
-            c->stream = user;
-            hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-            if (rc != L2T_OK) return rc;
-            if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-            hipGraphExec_t ge = nullptr;
-            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-            it = c->graphs.emplace(key, ge).first;
+        for (int32_t left = n; left > 0;) {
+            const int32_t k = std::min(left, kGraphChunk);
+            GraphKey key{k, (c->cur << 8) | (t.persistent << 4) | t.kernel | (eatom ? 1 << 12 : 0),
+                         t.block};
+            auto it = c->graphs.find(key);
+            if (it == c->graphs.end()) {
+                // capture on a private stream (the caller's may be the legacy
+                // null stream, which cannot be captured), replay on the caller's
+                if (!c->cap_stream)
+                    L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                hipStream_t user = c->stream;
+                L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+                c->stream = c->cap_stream;
+                rc = fp32c_launch(c, k, t.kernel, t.persistent, t.block, eatom);
+                c->stream = user;
+                hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+                if (rc != L2T_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+                hipGraphExec_t ge = nullptr;
+                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+                it = c->graphs.emplace(key, ge).first;
+            }
+            L2T_HIP(c, hipGraphLaunch(it->second, c->stream));
+            if (k & 1) c->cur ^= 1;
+            left -= k;
         }
-        L2T_HIP(c, hipGraphLaunch(it->second, c->stream));
     }
-    if (n & 1) c->cur ^= 1;
     for (auto &st : c->sys) st.step += n;
     return L2T_OK;
 }

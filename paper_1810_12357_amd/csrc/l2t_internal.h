@@ -111,6 +111,10 @@ struct GraphKey {
     }
 };
 
+// sub-steps per captured hipGraph of the FP32C advance (even, so a replay
+// leaves the state in the buffer it started from)
+constexpr int32_t kGraphChunk = 256;
+
 constexpr int kKernelSliced = 0;   // global gathers through the int32 table
 constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
 constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
