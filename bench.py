@@ -21,6 +21,8 @@ Also reported:
   * the sub-step cost with a shell of held electronic temperatures and the
     mean-field parameter refresh at every advance;
   * the batch of two-temperature 1D bars (FP64, electrons and lattice);
+  * the recorded forward and the adjoint on the differentiation workload
+    (64 systems of 32,000 atoms, 2,000 sub-steps, checkpoints every 100);
   * the FP64 CPU oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -210,6 +212,75 @@ def bench_boundary_mean_field(L, torch, h, sy, n_sub=10, reps=40):
                 mean_field_refresh_us_per_advance=(mf_only - plain) * n_sub)
 
 
+def bench_adjoint(L, torch):
+    """Differentiation workload (64 FCC systems of 32,000 atoms, 2,000 FP32C
+    sub-steps, a checkpoint every 100): the recorded forward, then the adjoint
+    (recomputation between checkpoints and the reverse sub-steps) of the MSE
+    loss against targets run with each system's perturbed K and g.  Inputs
+    and dL/dT^N are device-resident; both calls end synchronised and are timed
+    on the wall clock after one untimed round."""
+    import workloads as W
+    w = W.c5()
+    n, ck = w.n_substeps, w.checkpoint_every
+    dev = torch.device("cuda:0")
+    tw = W.c5()
+    for s, sy in enumerate(tw.systems):
+        K, g = tw.extra["target_params"][s]
+        sy.params = dict(sy.params, K=K, g=g)
+    ctx_t = L.Context(tw.systems, L.L2T_FP32C)
+    ctx_t.setup(tw.r_cut)
+    ctx_t.advance(n)
+    tgt = np.concatenate([ctx_t.get(s) for s in range(len(tw.systems))])
+    ctx_t.close()
+    ctx = L.Context(w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
+    _, mean, _ = ctx.setup(w.r_cut)
+    h, S = ctx.h, len(w.systems)
+    N = w.n_atoms
+    T0 = [torch.from_numpy(np.ascontiguousarray(sy.T_e0)).to(dev) for sy in w.systems]
+    times = []
+    for rep in range(2):
+        for s in range(S):
+            L.l2t_set_field(h, s, L.L2T_FIELD_TE, T0[s])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.l2t_advance_recorded(h, n, ck)
+        L.l2t_sync(h)
+        t1 = time.perf_counter()
+        TN = np.concatenate([ctx.get(s) for s in range(S)])
+        dL = torch.from_numpy(2.0 * (TN - tgt) / N).to(dev)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        dK, dg = L.l2t_adjoint(h, dL, S)
+        t3 = time.perf_counter()
+        times.append((t1 - t0, t3 - t2))
+    kernel = L.l2t_get_option(h, L.L2T_OPT_KERNEL)
+    ctx.close()
+    fwd, adj = times[-1]
+    # algorithmic bytes per atom-substep, 2 B per neighbour index in the brick
+    # form and 4 B in the global-gather form.  Forward: hi+lo read and write
+    # (16), T_lat (4), row offset (4).  Reverse: T hi (4), lambda hi+lo read
+    # and write (16), T_lat (4), row offset (4).  The recomputation runs the
+    # forward and copies lo into the segment (8) on all but one sub-step per
+    # checkpoint.
+    per_nbr = 2.0 if kernel == 1 else 4.0
+    fb = 24.0 + per_nbr * mean
+    ab = (28.0 + per_nbr * mean) + (fb + 8.0) * (ck - 1) / ck
+    out = dict(workload=f"c5: {S} FCC systems of {w.systems[0].n} atoms, {n} FP32C sub-steps, "
+                        f"checkpoint every {ck}",
+               kernel=["global-gather", "lds-brick"][kernel], mean_neighbors=mean,
+               forward_recorded_atom_substeps_per_s=N * n / fwd,
+               adjoint_atom_substeps_per_s=N * n / adj,
+               adjoint_over_forward=adj / fwd,
+               forward_GBps=fb * N * n / fwd / 1e9,
+               adjoint_GBps=ab * N * n / adj / 1e9,
+               loss=float(np.mean((TN - tgt) ** 2)),
+               dL_dK_sys0=float(dK[0]), dL_dg_sys0=float(dg[0]))
+    out["adjoint_frac"] = out["adjoint_GBps"] / HBM_PEAK_GBS
+    log(f"  adjoint: forward {fwd * 1e3:.1f} ms, adjoint {adj * 1e3:.1f} ms "
+        f"({N} atoms x {n} sub-steps)")
+    return out
+
+
 def bench_bar_batch(L, torch, n_sub=30000):
     """Two-temperature bars of Section 3.1: 2048 periodic 141-node Ni bars,
     electrons by Eq. 2 and lattice by the three-point Fourier law, FP64, one
@@ -265,6 +336,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the recorded forward and adjoint timing")
     ap.add_argument("--no-md", action="store_true", help="skip the lattice-side (Eq. 5, 8) timing")
     ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto")
     ap.add_argument("--brick-edge", type=int, default=0)
@@ -372,6 +445,9 @@ def main():
     if not args.no_md:
         log("two-temperature bars (Section 3.1) ...")
         out["bar_batch"] = bench_bar_batch(L, torch)
+    if not args.no_adjoint:
+        log("adjoint (differentiation workload) ...")
+        out["adjoint"] = bench_adjoint(L, torch)
     if not args.no_cpu:
         log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(sy, w.r_cut, args.cpu_steps)

@@ -715,13 +715,19 @@ int l2t_advance_recorded(l2t_ctx *c, int32_t n, int32_t ckpt_every) {
     }
     r.step0.resize(c->sys.size());
     for (size_t s = 0; s < c->sys.size(); ++s) r.step0[s] = c->sys[s].step;
+    // the segments between checkpoints run in the tuned launch form (all forms
+    // give the same states bit for bit), which the adjoint's recomputation follows
+    if (c->tune.autotune && !c->tune.tuned) {
+        int rc = l2t::autotune(c);
+        if (rc != L2T_OK) return rc;
+    }
     int rc0 = begin_atom_ledger(c, 0, (int32_t)c->sys.size());
     if (rc0 != L2T_OK) return rc0;
     for (int64_t k = 0; k < r.n_ckpt; ++k) {
         int rc = l2t::record_checkpoint(c, k);
         if (rc != L2T_OK) return rc;
         int32_t len = (int32_t)std::min<int64_t>(ckpt_every, n - k * ckpt_every);
-        rc = l2t::advance_plain(c, -1, len);
+        rc = l2t::advance_fp32c(c, len);
         if (rc != L2T_OK) return rc;
     }
     r.valid = true;

@@ -29,60 +29,59 @@ namespace {
 
 using namespace dev;
 
-// f and d1f of one pair from FP32 temperatures (same d, m, u as pair32)
-// f is returned in temperature units (span * f), as the forward sums it
-__device__ __forceinline__ void pair32_with_d1(float Tk, float Tj, const PairK &pk,
-                                               float inv_span, float *f, float *d1) {
-    *f = pair32(Tk, Tj, pk);
-    const float d = (Tj - Tk) * inv_span;
+// f and d1f of one pair from FP32 temperatures.  With d = theta_j - theta_k,
+// m = (theta_k + theta_j)/2, u = d^2, C(u) = cosh d and Q(u) = sinh(d)/d,
+//   f   = d [C - (u/2 + 2m(1-m)) Q]                 (the pair term of Eq. 2)
+//   d1f = -[(1 - 2m(1-m) - u/2) C + (1 - 2m) d Q]    (its derivative in theta_k)
+// so both come from one evaluation of C and Q.  f is returned in temperature
+// units (span * f), as the forward sums it.  For u <= kUTiny the series stop
+// after their linear terms (the dropped terms are below 3e-9 relative); above,
+// they run to u^5 (below 3e-9 for |d| <= 1).
+__device__ __forceinline__ void pair_adj(float Tk, float Tj, const PairK &pk, float inv_span,
+                                         float &f, float &d1) {
+    const float dT = Tj - Tk;
     const float m = fmaf(Tk + Tj, pk.hinv, pk.moff);
+    const float a = fmaf(-m, m, m);
+    const float d = dT * inv_span;
     const float u = d * d;
-    // cosh d = sum u^k/(2k)!,  sinh(d)/d = sum u^k/(2k+1)!
-    float ch = fmaf(u, 1.0f / 3628800.0f, 1.0f / 40320.0f);
-    ch = fmaf(u, ch, 1.0f / 720.0f);
-    ch = fmaf(u, ch, 1.0f / 24.0f);
-    ch = fmaf(u, ch, 0.5f);
-    ch = fmaf(u, ch, 1.0f);
-    float sq = fmaf(u, 1.0f / 39916800.0f, 1.0f / 362880.0f);
-    sq = fmaf(u, sq, 1.0f / 5040.0f);
-    sq = fmaf(u, sq, 1.0f / 120.0f);
-    sq = fmaf(u, sq, 1.0f / 6.0f);
-    sq = fmaf(u, sq, 1.0f);
-    const float cm = fmaf(2.0f * m, m - 1.0f, 1.0f);   // 1 - 2 m (1 - m)
-    *d1 = -fmaf(cm - 0.5f * u, ch, (1.0f - 2.0f * m) * (d * sq));
+    float C, Q;
+    if (u <= kUTiny) {
+        C = fmaf(u, 0.5f, 1.0f);
+        Q = fmaf(u, 1.0f / 6.0f, 1.0f);
+    } else {
+        C = fmaf(u, 1.0f / 3628800.0f, 1.0f / 40320.0f);
+        C = fmaf(u, C, 1.0f / 720.0f);
+        C = fmaf(u, C, 1.0f / 24.0f);
+        C = fmaf(u, C, 0.5f);
+        C = fmaf(u, C, 1.0f);
+        Q = fmaf(u, 1.0f / 39916800.0f, 1.0f / 362880.0f);
+        Q = fmaf(u, Q, 1.0f / 5040.0f);
+        Q = fmaf(u, Q, 1.0f / 120.0f);
+        Q = fmaf(u, Q, 1.0f / 6.0f);
+        Q = fmaf(u, Q, 1.0f);
+    }
+    const float hu = 0.5f * u;
+    f = dT * fmaf(-fmaf(2.0f, a, hu), Q, C);
+    d1 = -fmaf(fmaf(-2.0f, a, 1.0f) - hu, C, fmaf(-2.0f, m, 1.0f) * (d * Q));
 }
 
-__global__ __launch_bounds__(256) void k_adjoint_step(
-    const SliceInfo *slices, int32_t n_slices, const int32_t *col, const float *Thi,
-    const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep, int32_t rel,
-    const float *lam, float *lam_n, float *lam_lo, double *grad /*[n_slices][2]*/) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int32_t sl = blockIdx.x * (blockDim.x / kWave) + wave;
-    if (sl >= n_slices) return;
-    const SliceInfo si = slices[sl];
-    const DevParams &p = P[si.sys];
-    const int32_t slot = sl * kWave + lane;
-    const bool valid = lane < si.n_valid;
-    const float Tk = Thi[slot];
-    const float lk = lam[slot];
-    const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
-    const PairK pk = pair_consts(p);
-    float S = 0.0f, cS = 0.0f, D = 0.0f, cD = 0.0f;
-    for (int32_t q = 0; q < si.width; ++q) {
-        const int32_t j = cp[q * kWave];
-        float f, d1;
-        pair32_with_d1(Tk, Thi[j], pk, p.f_inv_span, &f, &d1);
-        const float term = d1 * (lk - lam[j]);
-        float y = f - cS, t = S + y;
-        cS = (t - S) - y;
-        S = t;
-        y = term - cD;
-        t = D + y;
-        cD = (t - D) - y;
-        D = t;
-    }
+struct AdjGrad {
+    double k, g;
+};
+
+// reverse update of one lane given S = span * sum_j f and D = sum_j d1f (lambda_k -
+// lambda_j), both accumulated in FP64 in row order.  lambda is the FP32 pair
+// (hi, lo) with hi + lo exact in FP64; the increment is added in FP64 and the
+// sum split back, as the forward does with T.  Returns this lane's terms of
+// dL/dK and dL/dg.
+__device__ __forceinline__ AdjGrad adjoint_finish(const DevParams &p, bool valid, int32_t slot,
+                                                  float Tk, float lk, double S, double D,
+                                                  const float *__restrict__ Tl,
+                                                  const float *__restrict__ srcw,
+                                                  float *__restrict__ lam_n,
+                                                  float *__restrict__ lam_lo, int64_t step) {
     float l_new = lk;
-    double gK = 0.0, gG = 0.0;
+    AdjGrad r{0.0, 0.0};
     if (valid) {
         const float tl = Tl[slot];
         const bool gated = signbit(tl);
@@ -92,28 +91,157 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
             cpr = p.f_gamma;
         const float ge = gated ? 0.0f : p.f_g;
         float q = 0.0f;
-        if (p.laser_on) q = (p.f_i0 * pulse32(p, dstep[si.sys] + rel)) * srcw[slot];
+        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * srcw[slot];
         const float invc = 1.0f / c;
         const float dloc = -ge * invc + (ge * (Tk - tl) - q) * cpr * invc * invc;
-        const float dl = p.f_dt * fmaf(p.f_K, D, lk * dloc);
-        // compensated lambda update, as for the forward state
-        const float lo = lam_lo[slot];
-        const float s = lk + dl;
-        const float bp = s - lk;
-        const float er = (lk - (s - bp)) + (dl - bp);
-        const float lo2 = lo + er;
-        l_new = s + lo2;
-        lam_lo[slot] = lo2 - (l_new - s);
-        const double lfull = (double)lk + (double)lo;
-        gK = lfull * p.dt * (double)S;          // S = span * sum_j f
-        gG = gated ? 0.0 : -lfull * p.dt * (double)(Tk - tl) * (double)invc;
+        const double lfull = (double)lk + (double)lam_lo[slot];
+        const double ln = lfull + p.dt * (p.K * D + (double)(lk * dloc));
+        l_new = (float)ln;
+        lam_lo[slot] = (float)(ln - (double)l_new);
+        r.k = lfull * p.dt * S;
+        r.g = gated ? 0.0 : -lfull * p.dt * (double)(Tk - tl) * (double)invc;
     }
     lam_n[slot] = l_new;
-    gK = wave_sum(gK);
-    gG = wave_sum(gG);
+    return r;
+}
+
+// global-gather form: one wave per slice, neighbours through the int32 table
+__global__ __launch_bounds__(256) void k_adjoint_step(
+    const SliceInfo *__restrict__ slices, int32_t n_slices, const int32_t *__restrict__ col,
+    const float *__restrict__ Thi, const float *__restrict__ Tl, const float *__restrict__ srcw,
+    const DevParams *__restrict__ P, const int64_t *__restrict__ dstep, int32_t rel,
+    const float *__restrict__ lam, float *__restrict__ lam_n, float *__restrict__ lam_lo,
+    double *__restrict__ grad /*[n_slices][2]*/) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t sl = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (sl >= n_slices) return;
+    const SliceInfo si = slices[sl];
+    const DevParams &p = P[si.sys];
+    const int32_t slot = sl * kWave + lane;
+    const float Tk = Thi[slot];
+    const float lk = lam[slot];
+    const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
+    const PairK pk = pair_consts(p);
+    double S = 0.0, D = 0.0;
+    for (int32_t q = 0; q < si.width; ++q) {
+        const int32_t j = cp[q * kWave];
+        float f, d1;
+        pair_adj(Tk, Thi[j], pk, p.f_inv_span, f, d1);
+        S += (double)f;
+        D += (double)(d1 * (lk - lam[j]));
+    }
+    const AdjGrad g = adjoint_finish(p, lane < si.n_valid, slot, Tk, lk, S, D, Tl, srcw, lam_n,
+                                     lam_lo, dstep[si.sys] + rel);
+    const double gK = wave_sum(g.k), gG = wave_sum(g.g);
     if (lane == 0) {
         grad[2 * (int64_t)sl + 0] += gK;
         grad[2 * (int64_t)sl + 1] += gG;
+    }
+}
+
+// LDS-brick form: one workgroup per brick stages T^n and lambda^{n+1} of the
+// brick's slots and of its halo list in two tiles of tile_max floats; the
+// slices then read both through the uint16 table (the byte offset of atom j
+// in the T tile; lambda_j sits tile_max floats further).  Same terms in the
+// same order as k_adjoint_step, so lambda is bitwise equal; the gradient
+// terms are summed per lane over the wave's slices and added once per wave
+// to the row of its first slice.
+__global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
+    const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
+    const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
+    const int32_t *__restrict__ halo, int32_t tile_max, const float *__restrict__ Thi,
+    const float *__restrict__ Tl, const float *__restrict__ srcw, const DevParams *__restrict__ P,
+    const int64_t *__restrict__ dstep, int32_t rel, const float *__restrict__ lam,
+    float *__restrict__ lam_n, float *__restrict__ lam_lo, double *__restrict__ grad) {
+    extern __shared__ float tile[];
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+    if ((int32_t)logical >= n_list) return;
+    const BrickInfo bi = bricks[list[logical]];
+    float *lt = tile + tile_max;
+    const int32_t B = blockDim.x;
+    constexpr int U = 8;
+    for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
+        float v[U], w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = min(t0 + u * B, bi.n_own_pad - 1);
+            v[u] = Thi[bi.slot0 + t];
+            w[u] = lam[bi.slot0 + t];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u * B < bi.n_own_pad) {
+                tile[t0 + u * B] = v[u];
+                lt[t0 + u * B] = w[u];
+            }
+    }
+    const int32_t *hl = halo + bi.halo_off;
+    for (int32_t t0 = threadIdx.x; t0 < bi.n_halo; t0 += U * B) {
+        int32_t id[U];
+        float v[U], w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) id[u] = hl[min(t0 + u * B, bi.n_halo - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = Thi[id[u]];
+            w[u] = lam[id[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u * B < bi.n_halo) {
+                tile[bi.n_own_pad + t0 + u * B] = v[u];
+                lt[bi.n_own_pad + t0 + u * B] = w[u];
+            }
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    const int32_t ns = bi.n_own_pad / kWave;
+    if (wave >= ns) return;
+    const DevParams &p = P[bi.sys];
+    const int64_t step = dstep[bi.sys] + rel;
+    const PairK pk = pair_consts(p);
+    const char *tb = reinterpret_cast<const char *>(tile);
+    const char *lb = reinterpret_cast<const char *>(lt);
+    double gK = 0.0, gG = 0.0;
+    for (int32_t q = wave; q < ns; q += nw) {
+        const int32_t sl = bi.slice0 + q;
+        const int32_t w = __builtin_amdgcn_readfirstlane(slices[sl].width);
+        const int32_t nv = __builtin_amdgcn_readfirstlane(slices[sl].n_valid);
+        const int32_t base = __builtin_amdgcn_readfirstlane(slices[sl].colw_base64);
+        const int32_t slot = sl * kWave + lane;
+        const float Tk = tile[q * kWave + lane];
+        const float lk = lt[q * kWave + lane];
+        const uint32_t *row = colw + (int64_t)base * kWave + lane;
+        double S = 0.0, D = 0.0;
+        auto term = [&](uint32_t off) {
+            const float Tj = *reinterpret_cast<const float *>(tb + off);
+            const float lj = *reinterpret_cast<const float *>(lb + off);
+            float f, d1;
+            pair_adj(Tk, Tj, pk, p.f_inv_span, f, d1);
+            S += (double)f;
+            D += (double)(d1 * (lk - lj));
+        };
+        const int32_t full = w >> 1;
+#pragma unroll 4
+        for (int32_t k = 0; k < full; ++k) {
+            const uint32_t wd = row[(int64_t)k * kWave];
+            term(wd & 0xffffu);
+            term(wd >> 16);
+        }
+        if (w & 1) term(row[(int64_t)full * kWave] & 0xffffu);
+        const AdjGrad g = adjoint_finish(p, lane < nv, slot, Tk, lk, S, D, Tl, srcw, lam_n,
+                                         lam_lo, step);
+        gK += g.k;
+        gG += g.g;
+    }
+    gK = wave_sum(gK);
+    gG = wave_sum(gG);
+    if (lane == 0) {
+        grad[2 * (int64_t)(bi.slice0 + wave) + 0] += gK;
+        grad[2 * (int64_t)(bi.slice0 + wave) + 1] += gG;
     }
 }
 
@@ -227,6 +355,13 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
     hipLaunchKernelGGL(k_zero_d, dim3(nblk(2 * NS, 256)), dim3(256), 0, s_, grad, (int64_t)(2 * NS));
     hipLaunchKernelGGL(k_zero_d, dim3(nblk(3 * NS, 256)), dim3(256), 0, s_, led, (int64_t)(3 * NS));
     const dim3 g(nblk(NS, 4)), b(256);
+    // the brick forms when the tuned forward is the brick kernel and both
+    // tiles of the reverse step fit in 64 KB of LDS
+    const bool brick = c->tune.kernel == kKernelBrick && c->n_brick_list > 0 &&
+                       c->tile_max <= 8192;
+    const int bblock = std::min(std::max(c->tune.block, kWave), kBrickBlockMax);
+    const unsigned bgrid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
+    const size_t blds = 2 * sizeof(float) * (size_t)c->tile_max;
     std::vector<int64_t> hstep(S);
     for (int64_t k = r.n_ckpt - 1; k >= 0; --k) {
         const int64_t start = k * C;
@@ -239,14 +374,26 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
             float *in = seg + (size_t)m * 2 * NI, *out = seg + (size_t)(m + 1) * 2 * NI;
             L2T_HIP(c, hipMemcpyAsync(out + NI, in + NI, sizeof(float) * NI,
                                       hipMemcpyDeviceToDevice, s_));
-            hipLaunchKernelGGL(k_forward_step, g, b, 0, s_, c->slices, c->n_slices, c->col, in, out,
-                               out + NI, c->Tl32, c->srcw32, c->dparams, dst, m, led, c->derr);
+            if (brick) {
+                int rc = brick_step_fp32c(c, bblock, in, out, out + NI, dst, m, led);
+                if (rc != L2T_OK) return rc;
+            } else {
+                hipLaunchKernelGGL(k_forward_step, g, b, 0, s_, c->slices, c->n_slices, c->col,
+                                   in, out, out + NI, c->Tl32, c->srcw32, c->dparams, dst, m, led,
+                                   c->derr);
+            }
         }
         for (int32_t m = L - 1; m >= 0; --m) {
             const float *Tst = seg + (size_t)m * 2 * NI;
-            hipLaunchKernelGGL(k_adjoint_step, g, b, 0, s_, c->slices, c->n_slices, c->col, Tst,
-                               c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc], lam[lc ^ 1], lamlo,
-                               grad);
+            if (brick)
+                hipLaunchKernelGGL(k_adjoint_brick, dim3(bgrid), dim3(bblock), blds, s_, c->bricks,
+                                   c->brick_list, c->n_brick_list, c->slices, c->colw, c->halo,
+                                   c->tile_max, Tst, c->Tl32, c->srcw32, c->dparams, dst, m,
+                                   lam[lc], lam[lc ^ 1], lamlo, grad);
+            else
+                hipLaunchKernelGGL(k_adjoint_step, g, b, 0, s_, c->slices, c->n_slices, c->col,
+                                   Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc],
+                                   lam[lc ^ 1], lamlo, grad);
             lc ^= 1;
         }
         L2T_HIP(c, hipGetLastError());

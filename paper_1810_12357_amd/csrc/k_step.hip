@@ -620,6 +620,21 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
     return L2T_OK;
 }
 
+// one FP32C sub-step of all systems in the LDS-brick form on explicit state
+// buffers (the adjoint's recomputation between checkpoints)
+int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, float *Tlo,
+                     const int64_t *dstep, int32_t rel, double *ledger) {
+    const int32_t nl = c->n_brick_list;
+    if (nl <= 0) return L2T_OK;
+    const unsigned grid = (unsigned)((nl + 7) / 8 * 8);
+    const size_t lds = sizeof(float) * (size_t)c->tile_max;
+    hipLaunchKernelGGL(k_brick_fp32c, dim3(grid), dim3(block), lds, c->stream, c->bricks,
+                       c->brick_list, nl, c->slices, c->colw, c->halo, Thi, Thi_n, Tlo, c->Tl32,
+                       c->srcw32, c->dparams, dstep, rel, ledger, nullptr, c->derr);
+    L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
 void drop_graphs(l2t_ctx *c) {
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();

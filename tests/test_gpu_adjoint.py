@@ -121,3 +121,86 @@ def test_autograd_function_gradients():
     assert K.grad[0].item() == pytest.approx(oK, rel=1e-4)
     assert g.grad[0].item() == pytest.approx(og, rel=1e-4)
     assert np.max(np.abs(T0.grad.cpu().numpy()[:n0] - lam)) < 1e-4 * np.abs(lam).max()
+
+
+def _adjoint_run(w, kernel, dL_fn, gate=None):
+    ctx = L.Context(w.systems, L.L2T_FP32C)
+    ctx.setup(w.r_cut)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+    if gate is not None:
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_GATE, gate)
+    L.l2t_advance_recorded(ctx.h, w.n_substeps, w.checkpoint_every)
+    TN = np.concatenate([ctx.get(s) for s in range(len(w.systems))])
+    dL = dL_fn(TN)
+    dT0 = np.zeros(TN.size)
+    dK, dg = L.l2t_adjoint(ctx.h, dL, len(w.systems), dL_dT0=dT0)
+    return ctx, TN, dT0, dK, dg
+
+
+@pytest.mark.parametrize("case", ["c5", "laser_slab"])
+def test_adjoint_brick_and_global_forms_agree(case):
+    """The LDS-brick reverse step (with the brick recomputation) and the
+    global-gather one evaluate the same per-atom terms in the same order:
+    lambda is bitwise equal; the gradient sums differ only in grouping."""
+    gate = None
+    if case == "c5":
+        w = W.c5(n_systems=3, n_cells=7, n_substeps=300)
+        w.checkpoint_every = 50
+    else:
+        s4 = W.c4_slab(1500, 0.4)
+        s4.params = dict(s4.params, laser_t0=20.0, laser_sigma=8.0, g=5e-6)
+        rng = np.random.default_rng(2)
+        s4.T_l = 300.0 + 200 * rng.uniform(0, 1, s4.n)
+        gate = (rng.uniform(0, 1, s4.n) < 0.1).astype(np.float64)
+        w = W.Workload("slab", [s4], 1.1 * W.A_LAT, 400, "fp32c", checkpoint_every=64)
+    rng = np.random.default_rng(7)
+    wv = rng.normal(size=w.n_atoms) * 1e-3
+    runs = [_adjoint_run(w, k, lambda TN: wv, gate) for k in (0, 1)]
+    for r in runs:
+        r[0].close()
+    (_, TN0, l0, K0, g0), (_, TN1, l1, K1, g1) = runs
+    assert np.array_equal(TN0, TN1)
+    assert np.array_equal(l0, l1)
+    np.testing.assert_allclose(K1, K0, rtol=1e-12)
+    np.testing.assert_allclose(g1, g0, rtol=1e-12)
+
+
+def test_full_size_c5_adjoint_forms_and_finite_difference():
+    """64 systems of 32,000 atoms, 2,000 sub-steps, a checkpoint every 100 (the
+    benchmark's differentiation workload): both launch forms give the same
+    lambda, and dL/dK of system 0 matches a central difference of the GPU
+    forward."""
+    w = W.c5()
+    n = w.n_substeps
+    tw = W.c5()
+    for s, sy in enumerate(tw.systems):
+        K, g = tw.extra["target_params"][s]
+        sy.params = dict(sy.params, K=K, g=g)
+    ct = L.Context(tw.systems, L.L2T_FP32C)
+    ct.setup(tw.r_cut)
+    ct.advance(n)
+    tgt = np.concatenate([ct.get(s) for s in range(len(tw.systems))])
+    ct.close()
+    N = w.n_atoms
+    loss = lambda TN: float(np.mean((TN - tgt) ** 2))
+    dL_fn = lambda TN: 2.0 * (TN - tgt) / N
+    ctx1, TN1, l1, K1, g1 = _adjoint_run(w, 1, dL_fn)
+    ctx0, TN0, l0, K0, g0 = _adjoint_run(w, 0, dL_fn)
+    ctx0.close()
+    assert np.array_equal(TN0, TN1)
+    assert np.array_equal(l0, l1)
+    np.testing.assert_allclose(K1, K0, rtol=1e-12)
+    np.testing.assert_allclose(g1, g0, rtol=1e-12)
+    sy0 = w.systems[0]
+    eps = 1e-3 * sy0.params["K"]
+
+    def run_K(Kv):
+        L.l2t_set_params(ctx1.h, 0, dict(sy0.params, K=Kv))
+        for s, sy in enumerate(w.systems):
+            L.l2t_set_field(ctx1.h, s, L.L2T_FIELD_TE, sy.T_e0)
+        ctx1.advance(n)
+        return loss(np.concatenate([ctx1.get(s) for s in range(len(w.systems))]))
+
+    fd = (run_K(sy0.params["K"] + eps) - run_K(sy0.params["K"] - eps)) / (2 * eps)
+    assert K1[0] == pytest.approx(fd, rel=2e-3)
+    ctx1.close()
