@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <vector>
 
 #include "l2t_internal.h"
@@ -34,9 +35,9 @@ using namespace dev;
 //   f   = d [C - (u/2 + 2m(1-m)) Q]                 (the pair term of Eq. 2)
 //   d1f = -[(1 - 2m(1-m) - u/2) C + (1 - 2m) d Q]    (its derivative in theta_k)
 // so both come from one evaluation of C and Q.  f is returned in temperature
-// units (span * f), as the forward sums it.  For u <= kUTiny the series stop
-// after their linear terms (the dropped terms are below 3e-9 relative); above,
-// they run to u^5 (below 3e-9 for |d| <= 1).
+// units (span * f), as the forward sums it.  The series run to u^5 (the
+// dropped terms are below 3e-9 for |d| <= 1); one straight-line form for
+// every pair measured faster than branching to shorter series for small u.
 __device__ __forceinline__ void pair_adj(float Tk, float Tj, const PairK &pk, float inv_span,
                                          float &f, float &d1) {
     const float dT = Tj - Tk;
@@ -44,22 +45,16 @@ __device__ __forceinline__ void pair_adj(float Tk, float Tj, const PairK &pk, fl
     const float a = fmaf(-m, m, m);
     const float d = dT * inv_span;
     const float u = d * d;
-    float C, Q;
-    if (u <= kUTiny) {
-        C = fmaf(u, 0.5f, 1.0f);
-        Q = fmaf(u, 1.0f / 6.0f, 1.0f);
-    } else {
-        C = fmaf(u, 1.0f / 3628800.0f, 1.0f / 40320.0f);
-        C = fmaf(u, C, 1.0f / 720.0f);
-        C = fmaf(u, C, 1.0f / 24.0f);
-        C = fmaf(u, C, 0.5f);
-        C = fmaf(u, C, 1.0f);
-        Q = fmaf(u, 1.0f / 39916800.0f, 1.0f / 362880.0f);
-        Q = fmaf(u, Q, 1.0f / 5040.0f);
-        Q = fmaf(u, Q, 1.0f / 120.0f);
-        Q = fmaf(u, Q, 1.0f / 6.0f);
-        Q = fmaf(u, Q, 1.0f);
-    }
+    float C = fmaf(u, 1.0f / 3628800.0f, 1.0f / 40320.0f);
+    C = fmaf(u, C, 1.0f / 720.0f);
+    C = fmaf(u, C, 1.0f / 24.0f);
+    C = fmaf(u, C, 0.5f);
+    C = fmaf(u, C, 1.0f);
+    float Q = fmaf(u, 1.0f / 39916800.0f, 1.0f / 362880.0f);
+    Q = fmaf(u, Q, 1.0f / 5040.0f);
+    Q = fmaf(u, Q, 1.0f / 120.0f);
+    Q = fmaf(u, Q, 1.0f / 6.0f);
+    Q = fmaf(u, Q, 1.0f);
     const float hu = 0.5f * u;
     f = dT * fmaf(-fmaf(2.0f, a, hu), Q, C);
     d1 = -fmaf(fmaf(-2.0f, a, 1.0f) - hu, C, fmaf(-2.0f, m, 1.0f) * (d * Q));
@@ -225,7 +220,7 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
             D += (double)(d1 * (lk - lj));
         };
         const int32_t full = w >> 1;
-#pragma unroll 4
+#pragma unroll 2
         for (int32_t k = 0; k < full; ++k) {
             const uint32_t wd = row[(int64_t)k * kWave];
             term(wd & 0xffffu);
@@ -328,8 +323,10 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
     const int32_t C = r.ckpt;
     // scratch: segment states [C][hi, lo], lambda hi x2 + lo, ledger, grads, dstep, outputs
     const size_t seg_f = (size_t)C * 2 * NI;
+    const size_t nck = (size_t)r.n_ckpt;
     const size_t bytes = sizeof(float) * (seg_f + 3 * NI) +
-                         sizeof(double) * (3 * NS + 2 * NS + 2 * S) + sizeof(int64_t) * S + 256;
+                         sizeof(double) * (3 * NS + 2 * NS + 2 * S) +
+                         sizeof(int64_t) * S * (1 + nck) + 256;
     if (ensure_scratch(c, bytes) != L2T_OK) return L2T_ENOMEM;
     char *p = (char *)c->scratch;
     float *seg = (float *)p;
@@ -347,6 +344,7 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
     double *gout = (double *)p;
     p += sizeof(double) * 2 * S;
     int64_t *dst = (int64_t *)p;
+    int64_t *dtab = dst + S;   // step counters at the start of every segment [n_ckpt][S]
     float *lam[2] = {lam0, lam1};
     int lc = 0;
     const hipStream_t s_ = c->stream;
@@ -362,41 +360,92 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
     const int bblock = std::min(std::max(c->tune.block, kWave), kBrickBlockMax);
     const unsigned bgrid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
     const size_t blds = 2 * sizeof(float) * (size_t)c->tile_max;
-    std::vector<int64_t> hstep(S);
-    for (int64_t k = r.n_ckpt - 1; k >= 0; --k) {
-        const int64_t start = k * C;
-        const int32_t L = (int32_t)std::min<int64_t>(C, r.n_steps - start);
-        const float *ck = (const float *)r.buf + (size_t)k * 2 * NI;
-        L2T_HIP(c, hipMemcpyAsync(seg, ck, sizeof(float) * 2 * NI, hipMemcpyDeviceToDevice, s_));
-        for (size_t q = 0; q < S; ++q) hstep[q] = r.step0[q] + start;
-        L2T_HIP(c, hipMemcpyAsync(dst, hstep.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s_));
+    std::vector<int64_t> htab(nck * S);
+    for (size_t k = 0; k < nck; ++k)
+        for (size_t q = 0; q < S; ++q) htab[k * S + q] = r.step0[q] + (int64_t)k * C;
+    L2T_HIP(c, hipMemcpyAsync(dtab, htab.data(), sizeof(int64_t) * htab.size(),
+                              hipMemcpyHostToDevice, s_));
+    // the sub-steps of one checkpoint segment: the recomputation of states
+    // 1..L-1 from the segment's checkpoint, then L reverse sub-steps from
+    // lambda buffer `l0`.  Captured once per (L, l0) for this call and replayed
+    // for every segment of that length; the checkpoint copy and the step
+    // counters go in before each replay.
+    auto segment = [&](int32_t L, int l0) -> int {
+        int lc2 = l0;
         for (int32_t m = 0; m + 1 < L; ++m) {
             float *in = seg + (size_t)m * 2 * NI, *out = seg + (size_t)(m + 1) * 2 * NI;
             L2T_HIP(c, hipMemcpyAsync(out + NI, in + NI, sizeof(float) * NI,
-                                      hipMemcpyDeviceToDevice, s_));
+                                      hipMemcpyDeviceToDevice, c->stream));
             if (brick) {
                 int rc = brick_step_fp32c(c, bblock, in, out, out + NI, dst, m, led);
                 if (rc != L2T_OK) return rc;
             } else {
-                hipLaunchKernelGGL(k_forward_step, g, b, 0, s_, c->slices, c->n_slices, c->col,
-                                   in, out, out + NI, c->Tl32, c->srcw32, c->dparams, dst, m, led,
-                                   c->derr);
+                hipLaunchKernelGGL(k_forward_step, g, b, 0, c->stream, c->slices, c->n_slices,
+                                   c->col, in, out, out + NI, c->Tl32, c->srcw32, c->dparams, dst,
+                                   m, led, c->derr);
             }
         }
         for (int32_t m = L - 1; m >= 0; --m) {
             const float *Tst = seg + (size_t)m * 2 * NI;
             if (brick)
-                hipLaunchKernelGGL(k_adjoint_brick, dim3(bgrid), dim3(bblock), blds, s_, c->bricks,
-                                   c->brick_list, c->n_brick_list, c->slices, c->colw, c->halo,
-                                   c->tile_max, Tst, c->Tl32, c->srcw32, c->dparams, dst, m,
-                                   lam[lc], lam[lc ^ 1], lamlo, grad);
+                hipLaunchKernelGGL(k_adjoint_brick, dim3(bgrid), dim3(bblock), blds, c->stream,
+                                   c->bricks, c->brick_list, c->n_brick_list, c->slices, c->colw,
+                                   c->halo, c->tile_max, Tst, c->Tl32, c->srcw32, c->dparams, dst,
+                                   m, lam[lc2], lam[lc2 ^ 1], lamlo, grad);
             else
-                hipLaunchKernelGGL(k_adjoint_step, g, b, 0, s_, c->slices, c->n_slices, c->col,
-                                   Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc],
-                                   lam[lc ^ 1], lamlo, grad);
-            lc ^= 1;
+                hipLaunchKernelGGL(k_adjoint_step, g, b, 0, c->stream, c->slices, c->n_slices,
+                                   c->col, Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc2],
+                                   lam[lc2 ^ 1], lamlo, grad);
+            lc2 ^= 1;
         }
         L2T_HIP(c, hipGetLastError());
+        return L2T_OK;
+    };
+    // executable graphs of this call; on every way out the stream is drained
+    // before they are destroyed
+    struct Graphs {
+        hipStream_t s;
+        std::map<std::pair<int32_t, int>, hipGraphExec_t> m;
+        ~Graphs() {
+            if (m.empty()) return;
+            (void)hipStreamSynchronize(s);
+            for (auto &kv : m) (void)hipGraphExecDestroy(kv.second);
+        }
+    } graphs{s_, {}};
+    for (int64_t k = r.n_ckpt - 1; k >= 0; --k) {
+        const int64_t start = k * C;
+        const int32_t L = (int32_t)std::min<int64_t>(C, r.n_steps - start);
+        const float *ck = (const float *)r.buf + (size_t)k * 2 * NI;
+        L2T_HIP(c, hipMemcpyAsync(seg, ck, sizeof(float) * 2 * NI, hipMemcpyDeviceToDevice, s_));
+        L2T_HIP(c, hipMemcpyAsync(dst, dtab + (size_t)k * S, sizeof(int64_t) * S,
+                                  hipMemcpyDeviceToDevice, s_));
+        if (!c->tune.graph) {
+            int rc = segment(L, lc);
+            if (rc != L2T_OK) return rc;
+        } else {
+            auto it = graphs.m.find({L, lc});
+            if (it == graphs.m.end()) {
+                if (!c->cap_stream)
+                    L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                hipGraph_t gr = nullptr;
+                L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+                c->stream = c->cap_stream;
+                int rc = segment(L, lc);
+                c->stream = s_;
+                hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+                if (rc != L2T_OK || e != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return rc != L2T_OK ? rc : hip_fail(c, e, "hipStreamEndCapture");
+                }
+                hipGraphExec_t ge = nullptr;
+                e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+                it = graphs.m.emplace(std::make_pair(L, lc), ge).first;
+            }
+            L2T_HIP(c, hipGraphLaunch(it->second, s_));
+        }
+        if (L & 1) lc ^= 1;
     }
     for (size_t q = 0; q < S; ++q) {
         const SystemState &st = c->sys[q];

@@ -123,10 +123,11 @@ def test_autograd_function_gradients():
     assert np.max(np.abs(T0.grad.cpu().numpy()[:n0] - lam)) < 1e-4 * np.abs(lam).max()
 
 
-def _adjoint_run(w, kernel, dL_fn, gate=None):
+def _adjoint_run(w, kernel, dL_fn, gate=None, graph=1):
     ctx = L.Context(w.systems, L.L2T_FP32C)
     ctx.setup(w.r_cut)
     L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, graph)
     if gate is not None:
         L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_GATE, gate)
     L.l2t_advance_recorded(ctx.h, w.n_substeps, w.checkpoint_every)
@@ -141,7 +142,8 @@ def _adjoint_run(w, kernel, dL_fn, gate=None):
 def test_adjoint_brick_and_global_forms_agree(case):
     """The LDS-brick reverse step (with the brick recomputation) and the
     global-gather one evaluate the same per-atom terms in the same order:
-    lambda is bitwise equal; the gradient sums differ only in grouping."""
+    lambda is bitwise equal; the gradient sums differ only in grouping.  The
+    segments replayed from captured graphs equal the directly launched ones."""
     gate = None
     if case == "c5":
         w = W.c5(n_systems=3, n_cells=7, n_substeps=300)
@@ -155,10 +157,12 @@ def test_adjoint_brick_and_global_forms_agree(case):
         w = W.Workload("slab", [s4], 1.1 * W.A_LAT, 400, "fp32c", checkpoint_every=64)
     rng = np.random.default_rng(7)
     wv = rng.normal(size=w.n_atoms) * 1e-3
-    runs = [_adjoint_run(w, k, lambda TN: wv, gate) for k in (0, 1)]
+    runs = [_adjoint_run(w, k, lambda TN: wv, gate, graph) for k, graph in ((0, 1), (1, 1), (1, 0))]
     for r in runs:
         r[0].close()
-    (_, TN0, l0, K0, g0), (_, TN1, l1, K1, g1) = runs
+    (_, TN0, l0, K0, g0), (_, TN1, l1, K1, g1), (_, TN2, l2, K2, g2) = runs
+    assert np.array_equal(TN1, TN2) and np.array_equal(l1, l2)
+    assert np.array_equal(K1, K2) and np.array_equal(g1, g2)
     assert np.array_equal(TN0, TN1)
     assert np.array_equal(l0, l1)
     np.testing.assert_allclose(K1, K0, rtol=1e-12)
