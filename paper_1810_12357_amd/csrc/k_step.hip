@@ -519,6 +519,57 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     if (c->precision == L2T_FP64)
         for (int32_t s = (sys < 0 ? 0 : sys); s < (sys < 0 ? (int32_t)c->sys.size() : sys + 1); ++s)
             lat |= c->sys[s].lf.on != 0;
+    if (sys < 0 && c->precision == L2T_FP64 && c->tune.graph) {
+        // all systems: replays of captured chunks, as in the FP32C advance.
+        // A chunk is keyed by its length, the state buffer it starts from,
+        // the lattice mode and which lattice buffer holds T^lat.
+        for (int32_t left = n; left > 0;) {
+            const int32_t k = std::min(left, kGraphChunk);
+            const int mode = (1 << 16) | (c->cur << 8) | ((int)lat << 9) |
+                             ((int)(c->Tl64 > c->Tl64b) << 10) | (eatom ? 1 << 12 : 0);
+            GraphKey key{k, mode, 0};
+            auto it = c->graphs.find(key);
+            if (it == c->graphs.end()) {
+                if (!c->cap_stream)
+                    L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                hipStream_t user = c->stream;
+                L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+                c->stream = c->cap_stream;
+                double *tlb[2] = {c->Tl64, c->Tl64b};
+                for (int32_t q = 0; q < k; ++q) {
+                    const int cu = c->cur ^ (q & 1);
+                    hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns,
+                                       c->col, c->T64[cu], c->T64[cu ^ 1],
+                                       lat ? tlb[q & 1] : c->Tl64, lat ? tlb[(q & 1) ^ 1] : nullptr,
+                                       c->srcw64, c->dparams, c->dstep, q, c->ledger, eatom,
+                                       c->derr);
+                }
+                hipLaunchKernelGGL(k_bump, dim3(nblk((int64_t)c->sys.size(), 256)), dim3(256), 0,
+                                   c->stream, c->dstep, 0, (int32_t)c->sys.size(), k);
+                const hipError_t el = hipGetLastError();
+                c->stream = user;
+                hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+                if (el != hipSuccess || e != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return hip_fail(c, el != hipSuccess ? el : e, "plain advance capture");
+                }
+                hipGraphExec_t ge = nullptr;
+                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+                it = c->graphs.emplace(key, ge).first;
+            }
+            L2T_HIP(c, hipGraphLaunch(it->second, c->stream));
+            if (k & 1) {
+                c->cur ^= 1;
+                if (lat) std::swap(c->Tl64, c->Tl64b);
+            }
+            left -= k;
+        }
+        for (auto &st : c->sys) st.step += n;
+        return L2T_OK;
+    }
     double *tl_buf[2] = {c->Tl64, c->Tl64b};
     int cur = c->cur;
     for (int32_t k = 0; k < n; ++k) {

@@ -19,20 +19,23 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _context(systems, r_cut, batch, lat=None):
+def _context(systems, r_cut, batch, lat=None, graph=1):
     ctx = L.Context(systems, L.L2T_FP64)
     ctx.setup(r_cut)
     L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, int(batch))
+    L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, int(graph))
     for s, on in enumerate(lat if lat is not None else [True] * len(systems)):
         if on:
             L.l2t_set_lattice_fd(ctx.h, s, True, W.K_L_BAR, W.C_L_BAR)
     return ctx
 
 
-@pytest.mark.parametrize("batch", [0, 1])
-def test_bars_match_oracle_with_odd_step_counts(batch):
+@pytest.mark.parametrize("batch,graph", [(0, 1), (1, 0), (1, 1)])
+def test_bars_match_oracle_with_odd_step_counts(batch, graph):
+    """Advances of 999, 1001 and 1000 sub-steps: the batched launch replays
+    256-sub-step graphs and odd remainders, which swap the lattice buffers."""
     w = W.c6(n_bars=5, n_substeps=3000)
-    ctx = _context(w.systems, w.r_cut, batch)
+    ctx = _context(w.systems, w.r_cut, batch, graph=graph)
     chunks = (999, 1001, 1000)
     want = []
     for sy in w.systems:
