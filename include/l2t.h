@@ -94,7 +94,11 @@ extern "C" {
 #define L2T_OPT_PERSISTENT     0   /* FP32C global-gather kernel: 1 = all sub-steps in one persistent launch */
 #define L2T_OPT_BLOCK          1   /* FP32C: threads per workgroup, multiple of 64 up to 512; the
                                       global-gather kernels use at most 256 (0 = autotune) */
-#define L2T_OPT_RESIDENT_MAX   2   /* FP32C: largest system kept whole in LDS (atoms; 0 = autotune, -1 = never) */
+#define L2T_OPT_RESIDENT_MAX   2   /* batched FP64 advance: largest system (slots, padded to whole
+                                      64-lane slices) that one workgroup keeps whole in LDS for all
+                                      sub-steps of an advance; used when every system of the context
+                                      fits.  0 = the default 1024, -1 = never (one launch per
+                                      sub-step).  Results are bitwise equal either way. */
 #define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
 #define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */

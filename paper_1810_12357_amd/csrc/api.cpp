@@ -262,6 +262,7 @@ void l2t_destroy(l2t_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     l2t::drop_graphs(c);
+    dfree(c->res);
     dfree(c->pos);
     dfree(c->pos_int);
     dfree(c->perm);
@@ -407,6 +408,7 @@ int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mea
     int rc = l2t::build_neighbors(c, r_cut);
     if (rc != L2T_OK) return rc;
     c->nbrs_built = true;
+    c->res_valid = false;
     if (!c->tune.pinned) c->tune.tuned = false;   // new layout: tune again unless pinned
     for (auto &st : c->sys) {
         st.has_te = false;   // internal order changed: fields must be written again

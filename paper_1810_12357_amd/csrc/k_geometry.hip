@@ -630,12 +630,15 @@ struct SysLayout {
 // of all systems (one brick per workgroup; a CU holds as many tiles as its
 // 160 KB of LDS and its 8 workgroups of 4 waves allow) times the work of the
 // largest brick (its padded slots, plus the halo staging counted at 0.3 of a
-// slot).  Edges grow until every axis of every system fits in one brick.
+// slot).  Edges within 0.1 % of the least time are told apart by the padded
+// slots of all bricks together (a few small systems fit in one round at any
+// edge, and one-cell bricks would pad every cell to a whole slice).  Edges
+// grow until every axis of every system fits in one brick.
 int32_t brick_edge(const l2t_ctx *c, int32_t limit) {
     int32_t best = 1;
-    double best_cost = 1e300;
+    double best_cost = 1e300, best_total = 1e300;
     for (int32_t b = 1; b <= limit; ++b) {
-        double tile_max = 0.0, work_max = 0.0, nbrick = 0.0;
+        double tile_max = 0.0, work_max = 0.0, nbrick = 0.0, total = 0.0;
         bool grows = false;
         for (const SystemState &st : c->sys) {
             const double dens =
@@ -653,13 +656,15 @@ int32_t brick_edge(const l2t_ctx *c, int32_t limit) {
             tile_max = std::max(tile_max, 1.1 * dens * with_halo + kWave);
             work_max = std::max(work_max, slots + 0.3 * halo);
             nbrick += nb;
+            total += nb * slots;
         }
         if (tile_max > kTileCapFloats) break;
         const double per_cu = std::max(1.0, std::min(8.0, std::floor(163840.0 / (4.0 * tile_max))));
         const double rounds = std::ceil(nbrick / (per_cu * std::max(1, c->n_cu)));
         const double cost = rounds * work_max;
-        if (cost < best_cost * 0.999) {
-            best_cost = cost;
+        if (cost < best_cost * 0.999 || (cost <= best_cost * 1.001 && total < best_total)) {
+            best_cost = std::min(best_cost, cost);
+            best_total = total;
             best = b;
         }
         if (!grows) break;

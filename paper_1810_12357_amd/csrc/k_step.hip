@@ -506,6 +506,126 @@ int zero_atom_ledger(l2t_ctx *c, int32_t sys) {
     return L2T_OK;
 }
 
+// All n sub-steps of one small system in one workgroup (FP64): the system's
+// T and T^lat live in LDS, double-buffered, and a sub-step ends with a
+// workgroup barrier, so no state goes through HBM between sub-steps.  One
+// thread per slot (blockDim covers the largest system); neighbours are the
+// global slots of the table minus the system's first slot.  The per-lane
+// arithmetic is that of the per-sub-step kernel and the ledger rows and
+// per-atom records receive the same additions in the same order, so the
+// results are bitwise equal to n launches of k_step_fp64.
+namespace {
+
+__global__ __launch_bounds__(kResidentMaxSlots) void k_resident_fp64(
+    const ResidentSys *__restrict__ rsys, const SliceInfo *__restrict__ slices,
+    const int32_t *__restrict__ col, const double *T_in, double *T_even, double *T_odd,
+    const double *Tl_in, double *Tl_even, double *Tl_odd, const double *__restrict__ srcw,
+    const DevParams *__restrict__ P, const int64_t *__restrict__ dstep, int32_t n,
+    double *__restrict__ ledger, double *__restrict__ eatom, unsigned *__restrict__ err) {
+    extern __shared__ double sh[];
+    const ResidentSys r = rsys[blockIdx.x];
+    const int32_t np = blockDim.x;        // LDS stride: T[2][np], T^lat[2][np]
+    const int32_t t = threadIdx.x;
+    const bool mine = t < r.n_pad;        // whole waves: n_pad is a multiple of 64
+    const int lane = t % kWave;
+    const int32_t slot = r.slot0 + t;
+    const int32_t sl = r.slice0 + t / kWave;
+    SliceInfo si{};
+    double sw = 0.0, ea = 0.0, l0 = 0.0, l1 = 0.0, l2 = 0.0;
+    const DevParams &p = P[r.sys];
+    if (mine) {
+        si = slices[sl];
+        sh[t] = T_in[slot];
+        sh[2 * np + t] = Tl_in[slot];
+        if (p.laser_on | (si.flags & kSliceHeld)) sw = srcw[slot];
+        if (eatom) ea = eatom[slot];
+        if (lane == 0) {
+            l0 = ledger[3 * (int64_t)sl + 0];
+            l1 = ledger[3 * (int64_t)sl + 1];
+            l2 = ledger[3 * (int64_t)sl + 2];
+        }
+    }
+    __syncthreads();
+    const int64_t step0 = dstep[r.sys];
+    const bool valid = mine && lane < si.n_valid;
+    for (int32_t k = 0; k < n; ++k) {
+        const double *Tc = sh + (k & 1) * np, *Lc = sh + (2 + (k & 1)) * np;
+        double *Tn = sh + ((k & 1) ^ 1) * np, *Ln = sh + (2 + ((k & 1) ^ 1)) * np;
+        if (mine) {
+            const Fp64Lane o = lane_step_fp64(
+                si, lane, valid, p, col, Tc[t], Lc[t], sw,
+                [&](int32_t j) { return Tc[j - r.slot0]; },
+                [&](int32_t j) { return Lc[j - r.slot0]; }, step0 + k, err);
+            Tn[t] = o.Tnew;
+            Ln[t] = o.tl_new;
+            if (eatom && valid) ea += o.e2l;
+            const double e2l = wave_sum(o.e2l), q = wave_sum(o.q), lt = wave_sum(o.lt);
+            l0 += e2l;
+            l1 += q;
+            l2 += lt;
+        }
+        __syncthreads();
+    }
+    if (!mine) return;
+    // the final state goes where n launches would leave it: the output buffer
+    // of the last sub-step
+    (n & 1 ? T_odd : T_even)[slot] = sh[(n & 1) * np + t];
+    (n & 1 ? Tl_odd : Tl_even)[slot] = sh[(2 + (n & 1)) * np + t];
+    if (eatom) eatom[slot] = ea;
+    if (lane == 0) {
+        ledger[3 * (int64_t)sl + 0] = l0;
+        ledger[3 * (int64_t)sl + 1] = l1;
+        ledger[3 * (int64_t)sl + 2] = l2;
+    }
+}
+
+}  // namespace
+
+// Batched FP64 advance with every system resident in one workgroup, when
+// all systems fit (L2T_OPT_RESIDENT_MAX); L2T_ENOTIMPL otherwise, and the
+// caller takes the per-sub-step launches.
+static int resident_fp64(l2t_ctx *c, int32_t n, bool lat, double *eatom) {
+    const int lim = c->tune.resident_max == 0 ? kResidentMaxSlots
+                                              : std::min(c->tune.resident_max, kResidentMaxSlots);
+    if (lim <= 0 || c->sys.empty()) return L2T_ENOTIMPL;
+    int32_t np = 0;
+    for (const auto &st : c->sys) {
+        if (st.n_pad > lim) return L2T_ENOTIMPL;
+        np = std::max(np, st.n_pad);
+    }
+    if (np <= 0) return L2T_ENOTIMPL;
+    if (!c->res_valid) {
+        c->h_res.resize(c->sys.size());
+        for (size_t s = 0; s < c->sys.size(); ++s)
+            c->h_res[s] = ResidentSys{(int32_t)s, c->sys[s].atom_off, c->sys[s].n_pad,
+                                      c->sys[s].slice0};
+        if (c->h_res.size() > c->res_cap) {
+            if (c->res) (void)hipFree(c->res);
+            c->res = nullptr;
+            c->res_cap = 0;
+            if (hipMalloc(&c->res, sizeof(ResidentSys) * c->h_res.size()) != hipSuccess)
+                return fail(c, L2T_ENOMEM, "resident system table allocation failed");
+            c->res_cap = c->h_res.size();
+        }
+        L2T_HIP(c, hipMemcpyAsync(c->res, c->h_res.data(), sizeof(ResidentSys) * c->h_res.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+        c->res_valid = true;
+    }
+    const int cur = c->cur;
+    // without the lattice mode T^lat stays in its buffer
+    double *tl_odd = lat ? c->Tl64b : c->Tl64;
+    hipLaunchKernelGGL(k_resident_fp64, dim3((unsigned)c->sys.size()), dim3(np),
+                       4 * sizeof(double) * (size_t)np, c->stream, c->res, c->slices, c->col,
+                       c->T64[cur], c->T64[cur], c->T64[cur ^ 1], c->Tl64, c->Tl64, tl_odd,
+                       c->srcw64, c->dparams, c->dstep, n, c->ledger, eatom, c->derr);
+    L2T_HIP(c, hipGetLastError());
+    if (n & 1) {
+        c->cur ^= 1;
+        if (lat) std::swap(c->Tl64, c->Tl64b);
+    }
+    return bump_steps(c, -1, n);
+}
+
 int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     const int32_t s0 = sys < 0 ? 0 : c->sys[sys].slice0;
     const int32_t ns = sys < 0 ? c->n_slices : c->sys[sys].n_slices;
@@ -519,6 +639,10 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     if (c->precision == L2T_FP64)
         for (int32_t s = (sys < 0 ? 0 : sys); s < (sys < 0 ? (int32_t)c->sys.size() : sys + 1); ++s)
             lat |= c->sys[s].lf.on != 0;
+    if (sys < 0 && c->precision == L2T_FP64) {
+        int rc = resident_fp64(c, n, lat, eatom);
+        if (rc != L2T_ENOTIMPL) return rc;
+    }
     if (sys < 0 && c->precision == L2T_FP64 && c->tune.graph) {
         // all systems: replays of captured chunks, as in the FP32C advance.
         // A chunk is keyed by its length, the state buffer it starts from,

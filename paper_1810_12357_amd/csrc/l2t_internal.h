@@ -120,6 +120,12 @@ constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
 constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
 constexpr int32_t kMaxBrickEdge = 1024;  // largest brick edge (cells) the layout considers
 constexpr int kSlicedBlockMax = 256;  // threads per workgroup, global-gather kernels
+constexpr int kResidentMaxSlots = 1024;  // largest system one workgroup keeps in LDS
+
+// one system of a resident (whole system per workgroup) launch
+struct ResidentSys {
+    int32_t sys, slot0, n_pad, slice0;
+};
 
 struct Tuning {
     int kernel = kKernelBrick;
@@ -204,6 +210,10 @@ struct l2t_ctx {
     double *eatom = nullptr;     // internal [n_int]: energy to the lattice over the last advance
     bool atom_ledger = false;    // record eatom during advances
     bool batch_fp64 = false;     // FP64: one launch per sub-step over all systems
+    l2t::ResidentSys *res = nullptr;       // resident launch table (device)
+    std::vector<l2t::ResidentSys> h_res;   // its host copy (source of the upload)
+    size_t res_cap = 0;
+    bool res_valid = false;                // false after a rebuild
     bool eatom_valid = false;    // eatom holds the record of the last advance
     double *slice_red = nullptr; // [n_slices][4]
     double *energy_out = nullptr;// [n_sys][8]

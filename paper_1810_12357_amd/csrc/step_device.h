@@ -119,7 +119,61 @@ __device__ __forceinline__ float pair32(float Ti, float Tj, const PairK &k) {
     return dT * h;
 }
 
-// ---- one FP64 plain sub-step of one slice ---------------------------------------
+// ---- one FP64 plain sub-step --------------------------------------------------------
+struct Fp64Lane {
+    double Tnew, tl_new, e2l, q, lt;
+};
+
+// One lane of the literal Eq. 2 sub-step in FP64.  Ti, tl_i and sw are the
+// lane's own T, T^lat and source weight; T_of(j) and Tl_of(j) return the
+// step-n values of the neighbour in global slot j (from HBM or from an LDS
+// copy of the system).  tl_new is the lattice temperature after the step
+// (the Section 3.1 Fourier law when the system carries the lattice mode,
+// otherwise tl_i); e2l, q and lt are the lane's ledger terms.
+template <class TOf, class TlOf>
+__device__ __forceinline__ Fp64Lane lane_step_fp64(const SliceInfo &si, int lane, bool valid,
+                                                   const DevParams &p,
+                                                   const int32_t *__restrict__ col, double Ti,
+                                                   double tl_i, double sw, TOf T_of, TlOf Tl_of,
+                                                   int64_t step, unsigned *err) {
+    Fp64Lane r{Ti, tl_i, 0.0, 0.0, 0.0};
+    const int64_t base = (int64_t)si.col_base64 * kWave + lane;
+    // two-temperature lattice (Section 3.1): the Fourier law over the same
+    // neighbours plus the coupling, from the step-n states
+    if (p.lat_fd && valid) {
+        const double tli = fabs(tl_i);
+        double Lsum = 0.0;
+        for (int32_t k = 0; k < si.width; ++k) Lsum += fabs(Tl_of(col[base + (int64_t)k * kWave])) - tli;
+        r.tl_new = tli + p.dt * (p.K_lat * Lsum + p.g_over_clat * (Ti - tli));
+    }
+    const double ti = (Ti - p.T_min) * p.inv_span;
+    double S = 0.0;
+    for (int32_t k = 0; k < si.width; ++k) {
+        const double tj = (T_of(col[base + (int64_t)k * kWave]) - p.T_min) * p.inv_span;
+        S += tj * (1.0 - ti) * exp(ti - tj) - ti * (1.0 - tj) * exp(tj - ti);
+    }
+    if (valid) {
+        const double c = ce64(p, Ti);
+        const double coup = (signbit(tl_i) && !p.lat_fd) ? 0.0 : p.g * (Ti - fabs(tl_i));
+        double q = 0.0;
+        if (p.laser_on) q = p.i0 * fabs(sw) * pulse64(p, step);
+        r.e2l = coup * p.dt;
+        if (p.has_fixed && signbit(sw)) {
+            // held: the exchange it would receive goes to the temperature ledger
+            r.lt = p.dt * (p.A * S);
+        } else {
+            r.Tnew = Ti + p.dt * (p.A * S - coup / c + q / c);
+            r.lt = p.dt * (coup - q) / c;
+            const double th = (r.Tnew - p.T_min) * p.inv_span;
+            if (!(th >= 0.0 && th <= 1.0)) atomicOr(err, kErrRange);
+        }
+        r.q = q * p.dt;
+    }
+    return r;
+}
+
+// one slice through HBM; Tl_out, when given, receives T^lat after the step
+// (carried over for systems without the lattice mode)
 __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane,
                                        const DevParams &p, const int32_t *__restrict__ col,
                                        const double *__restrict__ T, double *__restrict__ Tn,
@@ -130,54 +184,15 @@ __device__ inline void slice_step_fp64(const SliceInfo &si, int32_t sl, int lane
                                        unsigned *err) {
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
-    const double Ti = T[slot];
-    // two-temperature lattice (Section 3.1): the Fourier law over the same
-    // neighbours plus the coupling, from the step-n states; other systems
-    // carry T^lat over to the output buffer
-    if (Tl_out) {
-        double tl_new = Tl[slot];
-        if (p.lat_fd && valid) {
-            const double tli = fabs(Tl[slot]);
-            const int64_t b0 = (int64_t)si.col_base64 * kWave + lane;
-            double Lsum = 0.0;
-            for (int32_t k = 0; k < si.width; ++k) Lsum += fabs(Tl[col[b0 + (int64_t)k * kWave]]) - tli;
-            tl_new = tli + p.dt * (p.K_lat * Lsum + p.g_over_clat * (Ti - tli));
-        }
-        Tl_out[slot] = tl_new;
-    }
-    const double ti = (Ti - p.T_min) * p.inv_span;
-    const int64_t base = (int64_t)si.col_base64 * kWave + lane;
-    double S = 0.0;
-    for (int32_t k = 0; k < si.width; ++k) {
-        const int32_t j = col[base + (int64_t)k * kWave];
-        const double tj = (T[j] - p.T_min) * p.inv_span;
-        S += tj * (1.0 - ti) * exp(ti - tj) - ti * (1.0 - tj) * exp(tj - ti);
-    }
-    double e2l = 0.0, q = 0.0, lt = 0.0, Tnew = Ti;
     // the source weight's sign bit marks atoms that hold their T_e
     const double sw = (p.laser_on | (si.flags & kSliceHeld)) ? srcw[slot] : 0.0;
-    if (valid) {
-        const double c = ce64(p, Ti);
-        const double tl = Tl[slot];
-        const double coup = (signbit(tl) && !p.lat_fd) ? 0.0 : p.g * (Ti - fabs(tl));
-        if (p.laser_on) q = p.i0 * fabs(sw) * pulse64(p, step);
-        e2l = coup * p.dt;
-        if (eatom) eatom[slot] += e2l;
-        if (p.has_fixed && signbit(sw)) {
-            // held: the exchange it would receive goes to the temperature ledger
-            lt = p.dt * (p.A * S);
-        } else {
-            Tnew = Ti + p.dt * (p.A * S - coup / c + q / c);
-            lt = p.dt * (coup - q) / c;
-            const double th = (Tnew - p.T_min) * p.inv_span;
-            if (!(th >= 0.0 && th <= 1.0)) atomicOr(err, kErrRange);
-        }
-        q *= p.dt;
-    }
-    Tn[slot] = Tnew;
-    e2l = wave_sum(e2l);
-    q = wave_sum(q);
-    lt = wave_sum(lt);
+    const Fp64Lane r = lane_step_fp64(
+        si, lane, valid, p, col, T[slot], Tl[slot], sw, [&](int32_t j) { return T[j]; },
+        [&](int32_t j) { return Tl[j]; }, step, err);
+    if (Tl_out) Tl_out[slot] = r.tl_new;
+    if (eatom && valid) eatom[slot] += r.e2l;
+    Tn[slot] = r.Tnew;
+    const double e2l = wave_sum(r.e2l), q = wave_sum(r.q), lt = wave_sum(r.lt);
     if (lane == 0) {
         ledger[3 * (int64_t)sl + 0] += e2l;
         ledger[3 * (int64_t)sl + 1] += q;

@@ -125,3 +125,75 @@ def test_full_bar_batch_three_picoseconds():
     T0, Tl0 = ctx.get(0), ctx.get(0, L.L2T_FIELD_TL)
     assert np.max(np.abs(T0 - Tl0)) < 10.0 and abs(T0.mean() - 311.4) < 6.0
     ctx.close()
+
+
+def _energy_rows(ctx, n_sys):
+    return [ctx.energies(s) for s in range(n_sys)]
+
+
+def test_resident_launch_bitwise_equal_to_per_substep_launches():
+    """Every bar fits one workgroup, so the batched advance keeps each bar in
+    LDS for all its sub-steps; with L2T_OPT_RESIDENT_MAX = -1 it launches
+    once per sub-step instead.  States, lattice temperatures and ledgers are
+    bitwise equal after advances of odd and even lengths."""
+    w = W.c6(n_bars=6, n_substeps=3000)
+    out = []
+    for res in (0, -1):
+        ctx = _context(w.systems, w.r_cut, 1)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_RESIDENT_MAX, res)
+        got = []
+        for k in (999, 1001, 1000):
+            ctx.advance(k)
+            got.append([(ctx.get(s), ctx.get(s, L.L2T_FIELD_TL)) for s in range(len(w.systems))])
+        e = _energy_rows(ctx, len(w.systems))
+        out.append((got, e))
+        ctx.close()
+    (g0, e0), (g1, e1) = out
+    for a, b in zip(g0, g1):
+        for (Ta, La), (Tb, Lb) in zip(a, b):
+            assert np.array_equal(Ta, Tb) and np.array_equal(La, Lb)
+    for a, b in zip(e0, e1):
+        for key in ("E_e", "sum_T", "E_e_to_l", "E_src", "T_ledger_acc"):
+            assert a[key] == b[key], key
+
+
+def test_resident_launch_with_laser_held_atoms_and_atom_record():
+    """Small FP64 laser slabs (every local term, held atoms, the per-atom
+    energy record): the resident launch equals the per-sub-step launches bit
+    for bit and the oracle to 1e-12."""
+    w = W.c4(n_systems=4, n_substeps=300, size_lo=100, size_hi=300)
+    fixed = []
+    for sy in w.systems:
+        x = sy.pos[0]
+        fixed.append((x > x.max() - W.A_LAT).astype(np.float64))
+    runs = []
+    for res in (0, -1):
+        ctx = L.Context(w.systems, L.L2T_FP64)
+        ctx.setup(w.r_cut)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, 1)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_RESIDENT_MAX, res)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 1)
+        for s in range(len(w.systems)):
+            L.l2t_set_field(ctx.h, s, L.L2T_FIELD_FIXED, fixed[s])
+        ctx.advance(137)
+        ctx.advance(163)
+        runs.append(([ctx.get(s) for s in range(len(w.systems))],
+                     [ctx.get(s, L.L2T_FIELD_ELAT) for s in range(len(w.systems))],
+                     _energy_rows(ctx, len(w.systems))))
+        ctx.close()
+    (T0, E0, e0), (T1, E1, e1) = runs
+    for a, b in zip(T0, T1):
+        assert np.array_equal(a, b)
+    for a, b in zip(E0, E1):
+        assert np.array_equal(a, b)
+    for a, b in zip(e0, e1):
+        for key in ("E_e", "sum_T", "E_e_to_l", "E_src", "T_ledger_acc"):
+            assert a[key] == b[key], key
+    for s, sy in enumerate(w.systems):
+        row, col = oracle_neighbors(sy, w.r_cut)
+        T, _, bad = oracle.run(row, col, sy.T_e0, sy.T_l, sy.params, 137, x=sy.pos[0],
+                               fixed=fixed[s].astype(np.int32))
+        T, _, bad = oracle.run(row, col, T, sy.T_l, sy.params, 163, step0=137, x=sy.pos[0],
+                               fixed=fixed[s].astype(np.int32))
+        assert bad == 0
+        assert max_rel(T0[s], T) < 1e-12
