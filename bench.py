@@ -260,11 +260,11 @@ def bench_adjoint(L, torch):
     # form and 4 B in the global-gather form.  Forward: hi+lo read and write
     # (16), T_lat (4), row offset (4).  Reverse: T hi (4), lambda hi+lo read
     # and write (16), T_lat (4), row offset (4).  The recomputation runs the
-    # forward and copies lo into the segment (8) on all but one sub-step per
-    # checkpoint.
+    # forward on all but one sub-step per checkpoint (the global-gather form
+    # also copies lo into the next state of the segment, 8 B).
     per_nbr = 2.0 if kernel == 1 else 4.0
     fb = 24.0 + per_nbr * mean
-    ab = (28.0 + per_nbr * mean) + (fb + 8.0) * (ck - 1) / ck
+    ab = (28.0 + per_nbr * mean) + (fb + (0.0 if kernel == 1 else 8.0)) * (ck - 1) / ck
     out = dict(workload=f"c5: {S} FCC systems of {w.systems[0].n} atoms, {n} FP32C sub-steps, "
                         f"checkpoint every {ck}",
                kernel=["global-gather", "lds-brick"][kernel], mean_neighbors=mean,

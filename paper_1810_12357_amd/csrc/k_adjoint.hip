@@ -374,12 +374,12 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
         int lc2 = l0;
         for (int32_t m = 0; m + 1 < L; ++m) {
             float *in = seg + (size_t)m * 2 * NI, *out = seg + (size_t)(m + 1) * 2 * NI;
-            L2T_HIP(c, hipMemcpyAsync(out + NI, in + NI, sizeof(float) * NI,
-                                      hipMemcpyDeviceToDevice, c->stream));
             if (brick) {
-                int rc = brick_step_fp32c(c, bblock, in, out, out + NI, dst, m, led);
+                int rc = brick_step_fp32c(c, bblock, in, out, in + NI, out + NI, dst, m, led);
                 if (rc != L2T_OK) return rc;
             } else {
+                L2T_HIP(c, hipMemcpyAsync(out + NI, in + NI, sizeof(float) * NI,
+                                          hipMemcpyDeviceToDevice, c->stream));
                 hipLaunchKernelGGL(k_forward_step, g, b, 0, c->stream, c->slices, c->n_slices,
                                    c->col, in, out, out + NI, c->Tl32, c->srcw32, c->dparams, dst,
                                    m, led, c->derr);

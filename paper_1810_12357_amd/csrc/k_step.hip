@@ -71,13 +71,18 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
 // uint16 table.  Workgroup b runs on XCD b mod 8 and takes brick
 // (b mod 8) * (G/8) + b/8, so each XCD sweeps one contiguous range of bricks
 // and its L2 serves the halo loads.
+// LO_IN: read T_lo from lo_in and write the new T_lo to Tlo (two buffers, as
+// the adjoint's recomputation keeps every state of a segment); otherwise T_lo
+// is updated in place and lo_in is unused.
+template <bool LO_IN>
 __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(8))) void k_brick_fp32c(
     const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
     const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
     const int32_t *__restrict__ halo, const float *__restrict__ Thi, float *__restrict__ Thi_n,
-    float *__restrict__ Tlo, const float *__restrict__ Tl, const float *__restrict__ srcw,
-    const DevParams *__restrict__ P, const int64_t *__restrict__ dstep, int32_t rel,
-    double *__restrict__ ledger, double *__restrict__ eatom, unsigned *__restrict__ err) {
+    const float *__restrict__ lo_in, float *__restrict__ Tlo, const float *__restrict__ Tl,
+    const float *__restrict__ srcw, const DevParams *__restrict__ P,
+    const int64_t *__restrict__ dstep, int32_t rel, double *__restrict__ ledger,
+    double *__restrict__ eatom, unsigned *__restrict__ err) {
     extern __shared__ float tile[];
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
@@ -133,7 +138,8 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         const int32_t base = __builtin_amdgcn_readfirstlane(slices[sl].colw_base64);
         const int32_t held = __builtin_amdgcn_readfirstlane(slices[sl].flags) & kSliceHeld;
         const int32_t slot = sl * kWave + lane;
-        const float lo = Tlo[slot], tl = Tl[slot];
+        const float lo = LO_IN ? lo_in[slot] : Tlo[slot];
+        const float tl = Tl[slot];
         const float sw = (p.laser_on | held) ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
         const LedgerTerms t = slice_core_brick(w, slot, lane < nv, p, Ti, lo, tl, sw,
@@ -764,10 +770,10 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
         const unsigned grid = (unsigned)((nl + 7) / 8 * 8);
         const size_t lds = sizeof(float) * (size_t)c->tile_max;
         for (int32_t k = 0; k < n && nl > 0; ++k) {
-            hipLaunchKernelGGL(k_brick_fp32c, dim3(grid), dim3(block), lds, c->stream, c->bricks,
-                               c->brick_list, nl, c->slices, c->colw, c->halo, c->Thi[cur],
-                               c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32, c->dparams, c->dstep,
-                               k, c->ledger, eatom, c->derr);
+            hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(block), lds, c->stream,
+                               c->bricks, c->brick_list, nl, c->slices, c->colw, c->halo,
+                               c->Thi[cur], c->Thi[cur ^ 1], nullptr, c->Tlo, c->Tl32, c->srcw32,
+                               c->dparams, c->dstep, k, c->ledger, eatom, c->derr);
             cur ^= 1;
         }
     } else if (persistent) {
@@ -796,16 +802,17 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
 }
 
 // one FP32C sub-step of all systems in the LDS-brick form on explicit state
-// buffers (the adjoint's recomputation between checkpoints)
-int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, float *Tlo,
-                     const int64_t *dstep, int32_t rel, double *ledger) {
+// buffers, T_lo read from lo_in and written to Tlo (the adjoint's
+// recomputation between checkpoints)
+int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const float *lo_in,
+                     float *Tlo, const int64_t *dstep, int32_t rel, double *ledger) {
     const int32_t nl = c->n_brick_list;
     if (nl <= 0) return L2T_OK;
     const unsigned grid = (unsigned)((nl + 7) / 8 * 8);
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
-    hipLaunchKernelGGL(k_brick_fp32c, dim3(grid), dim3(block), lds, c->stream, c->bricks,
-                       c->brick_list, nl, c->slices, c->colw, c->halo, Thi, Thi_n, Tlo, c->Tl32,
-                       c->srcw32, c->dparams, dstep, rel, ledger, nullptr, c->derr);
+    hipLaunchKernelGGL(k_brick_fp32c<true>, dim3(grid), dim3(block), lds, c->stream, c->bricks,
+                       c->brick_list, nl, c->slices, c->colw, c->halo, Thi, Thi_n, lo_in, Tlo,
+                       c->Tl32, c->srcw32, c->dparams, dstep, rel, ledger, nullptr, c->derr);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;
 }

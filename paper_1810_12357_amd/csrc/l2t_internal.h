@@ -276,8 +276,8 @@ int zero_atom_ledger(l2t_ctx *c, int32_t sys);   // sys < 0: every system
 int mean_field_refresh(l2t_ctx *c, int32_t sys);
 int bump_steps(l2t_ctx *c, int32_t sys, int32_t n);
 void drop_graphs(l2t_ctx *c);
-int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, float *Tlo,
-                     const int64_t *dstep, int32_t rel, double *ledger);
+int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const float *lo_in,
+                     float *Tlo, const int64_t *dstep, int32_t rel, double *ledger);
 
 // ---- lattice side (k_lattice.hip) ------------------------------------------
 int coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *v_dev,
