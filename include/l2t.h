@@ -349,10 +349,14 @@ int l2t_get_option(l2t_ctx *ctx, int32_t option, int64_t *value);
  * remark after Eq. 8) and where K_i < ke_eps.  v[3*n] (SoA, A/fs) and
  * mass[n] (amu) are the velocities the damping force will act on; xi[n] is
  * written (FP64, caller order).  All three live in memory space mem.
- * Synchronises when mem == L2T_HOST.
- * Errors: EINVAL (bad mode, dt_md <= 0 in ledger mode, NULL, mass <= 0),
- * ESTATE (T_e or T^lat not set; ledger mode without a recorded advance of
- * this system). */
+ * Asynchronous on the context's stream when mem == L2T_DEVICE (no host
+ * synchronisation, so it can be captured in a caller's graph); synchronises
+ * when mem == L2T_HOST.
+ * Errors: EINVAL (bad mode, dt_md <= 0 in ledger mode, NULL), ESTATE (T_e or
+ * T^lat not set; ledger mode without a recorded advance of this system).
+ * A mass that is not finite and > 0 gives xi = 0 for its atom and EINVAL,
+ * returned by this call when mem == L2T_HOST and otherwise by the next call
+ * that synchronises (as ERANGE from l2t_advance is). */
 int l2t_coupling(l2t_ctx *ctx, int32_t sys, int32_t mode, double dt_md, const double *v,
                  const double *mass, double *xi, int32_t mem);
 
@@ -364,8 +368,10 @@ int l2t_coupling(l2t_ctx *ctx, int32_t sys, int32_t mode, double dt_md, const do
  * l2t_coupling); F/m is converted with 1 amu A^2/fs^2 = 103.6427 eV.  The
  * library's MD integrator is the caller's: this step is the reference form of
  * Eq. 5 (and what the energy check against L2T_FIELD_ELAT uses).  All arrays
- * live in memory space mem.  Synchronises when mem == L2T_HOST.
- * Errors: EINVAL (NULL, dt_md <= 0). */
+ * live in memory space mem.  Asynchronous when mem == L2T_DEVICE; synchronises
+ * when mem == L2T_HOST.
+ * Errors: EINVAL (NULL, dt_md <= 0).  An atom whose mass is not finite and
+ * > 0 keeps its velocity and raises EINVAL, reported as for l2t_coupling. */
 int l2t_damping_step(l2t_ctx *ctx, int32_t sys, double dt_md, const double *xi,
                      const double *force, const double *mass, double *v, int32_t mem);
 

@@ -192,6 +192,8 @@ int check_err(l2t_ctx *c) {
                          "a sub-step produced theta outside [0,1] or a non-finite temperature");
     if (h & l2t::kErrMeanField)
         return l2t::fail(c, L2T_ERANGE, "mean-field refresh: a system's mean T_lat is not > 0");
+    if (h & l2t::kErrMass)
+        return l2t::fail(c, L2T_EINVAL, "coupling or damping step: a mass is not finite and > 0");
     return L2T_OK;
 }
 
@@ -834,15 +836,11 @@ int l2t_coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const doub
         dm = sc + 3 * n;
         dxi = sc + 4 * n;
     }
-    bool ok = true;
-    int rc = l2t::check_field_range(c, dm, n, 1e-300, HUGE_VAL, &ok);
-    if (rc != L2T_OK) return rc;
-    if (!ok) return l2t::fail(c, L2T_EINVAL, "masses must be finite and > 0");
-    rc = l2t::coupling(c, sys, mode, dt_md, dv, dm, dxi);
+    int rc = l2t::coupling(c, sys, mode, dt_md, dv, dm, dxi);
     if (rc != L2T_OK) return rc;
     if (mem == L2T_HOST) {
         L2T_HIP(c, hipMemcpyAsync(xi, dxi, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-        L2T_HIP(c, hipStreamSynchronize(c->stream));
+        return check_err(c);   // synchronises; reports a bad mass now
     }
     return L2T_OK;
 }
@@ -873,11 +871,11 @@ int l2t_damping_step(l2t_ctx *c, int32_t sys, double dt_md, const double *xi,
         dxi = sc + 4 * n;
         dF = force ? sc + 5 * n : nullptr;
     }
-    int rc = l2t::damping_step(c->stream, n, dt_md, dxi, dF, dm, dv);
+    int rc = l2t::damping_step(c->stream, n, dt_md, dxi, dF, dm, dv, c->derr);
     if (rc != L2T_OK) return l2t::fail(c, rc, "damping step launch failed");
     if (mem == L2T_HOST) {
         L2T_HIP(c, hipMemcpyAsync(v, dv, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
-        L2T_HIP(c, hipStreamSynchronize(c->stream));
+        return check_err(c);   // synchronises; reports a bad mass now
     }
     return L2T_OK;
 }

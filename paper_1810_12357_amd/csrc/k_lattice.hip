@@ -17,6 +17,7 @@
 // gathers within a brick.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 
 #include "l2t_internal.h"
@@ -32,7 +33,8 @@ __global__ void k_coupling(int32_t n, int64_t caller_off, const int32_t *__restr
                            const double *__restrict__ Tl64, const float *__restrict__ Tl32,
                            const double *__restrict__ eatom, double g, double dt_md,
                            double ke_eps, const double *__restrict__ v,
-                           const double *__restrict__ mass, double *__restrict__ xi) {
+                           const double *__restrict__ mass, double *__restrict__ xi,
+                           unsigned *__restrict__ err) {
     // workgroup b runs on XCD b mod 8: give each XCD one contiguous eighth of
     // the atoms, so the slot-order lines its gathers touch are reused in its
     // own L2 (neighbouring caller atoms share bricks)
@@ -42,7 +44,11 @@ __global__ void k_coupling(int32_t n, int64_t caller_off, const int32_t *__restr
     if (i >= n) return;
     const int32_t slot = inv[caller_off + i];
     const double vx = v[i], vy = v[n + i], vz = v[2 * (int64_t)n + i];
-    const double Ki = 0.5 * mass[i] * (vx * vx + vy * vy + vz * vz) * kMvv2e;
+    const double mi = mass[i];
+    // a mass that is not finite and positive is reported, and its atom left undamped
+    const bool bad_m = !(mi > 0.0 && mi <= DBL_MAX);
+    if (bad_m) atomicOr(err, kErrMass);
+    const double Ki = 0.5 * mi * (vx * vx + vy * vy + vz * vz) * kMvv2e;
     bool gated;
     double tl;
     if (precision == L2T_FP64) {
@@ -62,16 +68,22 @@ __global__ void k_coupling(int32_t n, int64_t caller_off, const int32_t *__restr
     } else {
         P = eatom[slot] / dt_md;
     }
-    xi[i] = (gated || !(Ki >= ke_eps)) ? 0.0 : P / (2.0 * Ki);
+    xi[i] = (bad_m || gated || !(Ki >= ke_eps)) ? 0.0 : P / (2.0 * Ki);
 }
 
 // v_i <- v_i + dt_md (F_i / m_i + xi_i v_i); F/m converted to A/fs^2
 __global__ void k_damping_step(int64_t n, double dt_md, const double *__restrict__ xi,
                                const double *__restrict__ force,
-                               const double *__restrict__ mass, double *__restrict__ v) {
+                               const double *__restrict__ mass, double *__restrict__ v,
+                               unsigned *__restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double inv_m = 1.0 / (mass[i] * kMvv2e);
+    const double mi = mass[i];
+    if (!(mi > 0.0 && mi <= DBL_MAX)) {   // reported; the atom's velocity is left as it is
+        atomicOr(err, kErrMass);
+        return;
+    }
+    const double inv_m = 1.0 / (mi * kMvv2e);
     const double x = xi[i];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -91,15 +103,15 @@ int coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *
     hipLaunchKernelGGL(k_coupling, dim3(grid), dim3(256), 0, c->stream, n, st.caller_off,
                        c->inv, mode, c->precision, c->T64[c->cur], c->Thi[c->cur], c->Tlo,
                        c->Tl64, c->Tl32, c->eatom, st.params.g, dt_md, st.params.ke_eps, v_dev,
-                       m_dev, xi_dev);
+                       m_dev, xi_dev, c->derr);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;
 }
 
 int damping_step(hipStream_t s, int64_t n, double dt_md, const double *xi, const double *force,
-                 const double *mass, double *v) {
+                 const double *mass, double *v, unsigned *err) {
     hipLaunchKernelGGL(k_damping_step, dim3(nblk(n, 256)), dim3(256), 0, s, n, dt_md, xi, force,
-                       mass, v);
+                       mass, v, err);
     return hipGetLastError() == hipSuccess ? L2T_OK : L2T_EHIP;
 }
 

@@ -23,6 +23,7 @@ constexpr unsigned kErrBox = 2u;        // atom outside the box on a free axis
 constexpr unsigned kErrBarrier = 4u;    // persistent-kernel barrier spin limit hit
 constexpr unsigned kErrCellOverflow = 8u;
 constexpr unsigned kErrMeanField = 16u;  // mean T^lat not > 0 at a mean-field refresh
+constexpr unsigned kErrMass = 32u;       // a mass not finite and > 0 (lattice-side kernels)
 
 // One wavefront-sized slice of 64 consecutive internal atoms.  The neighbour
 // indices of the slice are stored column-major: entry k of lane l lives at
@@ -283,7 +284,7 @@ int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, cons
 int coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *v_dev,
              const double *m_dev, double *xi_dev);
 int damping_step(hipStream_t s, int64_t n, double dt_md, const double *xi, const double *force,
-                 const double *mass, double *v);
+                 const double *mass, double *v, unsigned *err);
 
 // ---- adjoint (k_adjoint.hip) ------------------------------------------------
 int record_checkpoint(l2t_ctx *c, int64_t slot);

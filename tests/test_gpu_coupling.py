@@ -201,3 +201,39 @@ def test_damped_step_work_identity_full_size(c3_full):
         i = int(np.searchsorted(keep, sd))
         assert abs(E[sd] - e[i]) < 1e-5 * scale
     ctx.close()
+
+
+def test_bad_mass_is_reported_without_a_per_call_sync():
+    """A mass that is not finite and > 0: on device arrays the coupling and
+    the velocity step stay asynchronous and the error comes from the next
+    synchronising call; on host arrays from the call itself.  The atom gets
+    xi = 0 and keeps its velocity."""
+    import torch
+    w, sy = _md_workload(n_cells=5)
+    ctx = gpu_context(w, L.L2T_FP32C)
+    dt_md = N_SUB * sy.params["dt"]
+    dev = torch.device("cuda:0")
+    mass = sy.mass.copy()
+    mass[7] = 0.0
+    mass[11] = np.nan
+    v_d = torch.from_numpy(np.ascontiguousarray(sy.vel.reshape(-1))).to(dev)
+    m_d = torch.from_numpy(mass).to(dev)
+    xi_d = torch.empty(sy.n, dtype=torch.float64, device=dev)
+    L.l2t_coupling(ctx.h, 0, L.L2T_XI_INSTANT, dt_md, v_d, m_d, xi_d)   # no error yet
+    with pytest.raises(L.L2TError) as ex:
+        L.l2t_sync(ctx.h)
+    assert ex.value.status == L.L2T_EINVAL
+    xi = xi_d.cpu().numpy()
+    assert xi[7] == 0.0 and xi[11] == 0.0
+    L.l2t_sync(ctx.h)                                                   # reported once
+    xi_h = np.empty(sy.n)
+    with pytest.raises(L.L2TError) as ex:
+        L.l2t_coupling(ctx.h, 0, L.L2T_XI_INSTANT, dt_md, sy.vel.reshape(-1), mass, xi_h)
+    assert ex.value.status == L.L2T_EINVAL
+    v_h = np.ascontiguousarray(sy.vel.reshape(-1)).copy()
+    with pytest.raises(L.L2TError) as ex:
+        L.l2t_damping_step(ctx.h, 0, dt_md, np.full(sy.n, 1e-3), None, mass, v_h)
+    assert ex.value.status == L.L2T_EINVAL
+    v3 = v_h.reshape(3, sy.n)
+    assert np.array_equal(v3[:, 7], sy.vel[:, 7]) and np.array_equal(v3[:, 11], sy.vel[:, 11])
+    ctx.close()
