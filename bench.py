@@ -12,7 +12,9 @@ Also reported:
   * roofline of the dominant kernel (the FP32C sub-step launch), from HIP events
     on the library's stream, against 8 TB/s HBM, with the algorithmic bytes
     24 + 2 n_mean (brick form) or 24 + 4 n_mean (global gathers) per
-    atom-substep, and the HBM traffic rocprofv3 measured for it;
+    atom-substep, the HBM traffic rocprofv3 measured for it (and that traffic
+    over the live launch time), and a 1 GiB device copy on the same GPU;
+  * the same system in the plain FP64 form (a bounded sample of sub-steps);
   * the batched FP32C form vs the plain FP64 form on the 256-system laser batch
     (same sub-step count for both);
   * the lattice side on the same system: sub-step cost with the per-atom energy
@@ -312,6 +314,44 @@ def bench_bar_batch(L, torch, n_sub=30000):
                 algorithmic_GBps=per * nodes * n_sub / (ms * 1e-3) / 1e9)
 
 
+def copy_rate(torch, dev, reps=5):
+    """STREAM-style copy of 1 GiB on the device (read + write bytes per second),
+    the practical bandwidth denominator next to the 8 TB/s peak."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbps
+
+
+def bench_c3_fp64(L, torch, w, n_sub=100):
+    """The same 4M-atom system in the plain FP64 form (one launch per
+    sub-step): a bounded sample of sub-steps timed with HIP events, for the
+    FP32C / FP64 ratio on this system."""
+    sy = w.systems[0]
+    ctx = L.Context(w.systems, L.L2T_FP64, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.setup(w.r_cut)
+    ctx.advance(4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.advance(n_sub)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / n_sub
+    ctx.close()
+    log(f"  C3 FP64 plain: {us:.1f} us per sub-step")
+    return dict(substeps=n_sub, substep_us=us, atom_substeps_per_s=sy.n / (us * 1e-6))
+
+
 def cpu_baseline(sy, r_cut, n_steps):
     import oracle
     row, col = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, r_cut)
@@ -328,7 +368,7 @@ def cpu_baseline(sy, r_cut, n_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--substeps", type=int, default=10000)
     ap.add_argument("--cells", type=int, default=100)
@@ -336,6 +376,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 sample on the 4M-atom system")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the recorded forward and adjoint timing")
     ap.add_argument("--no-md", action="store_true", help="skip the lattice-side (Eq. 5, 8) timing")
@@ -416,11 +458,18 @@ def main():
         launch_ms, units, kname = adv / args.substeps, sy.n, "k_step_fp32c"
     achieved = bytes_per * units / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(kname, sy.n) if units == sy.n else None
+    copy_gbps = copy_rate(torch, dev)
     roof = dict(bound="hbm", kernel=kname, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                 traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 algorithmic_bytes_per_atom_substep=bytes_per,
-                launch_ms=launch_ms, units_per_launch=units)
+                launch_ms=launch_ms, units_per_launch=units,
+                # measured HBM bytes over the live launch time (the bandwidth gate's reading)
+                measured_GBps=None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+                measured_frac=None if traffic is None else
+                traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                # a 1 GiB device copy on the same GPU: the practical denominator
+                copy_GBps=copy_gbps, frac_of_copy=achieved / copy_gbps)
     out = dict(metric="electron atom-substeps/s (4M-atom FCC, FP32C)", value=value,
                unit="atom-substeps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=wall / args.steps * 1e3, higher_is_better=True, scaling="weak",
@@ -432,6 +481,7 @@ def main():
                            brick_edge=L.l2t_get_option(h, L.L2T_OPT_BRICK_EDGE),
                            persistent=persistent, block=block),
                advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
+               advance_ms_median=float(np.median(adv_ms)),
                roofline=roof,
                energy=dict(E_e=e["E_e"], sum_T=e["sum_T"], T_ledger=e["sum_T"] + e["T_ledger_acc"],
                            T_max=e["T_max_atom"]))
@@ -439,6 +489,11 @@ def main():
         out["md_coupling"] = md
         out["boundary_mean_field"] = bnd
     ctx.close()
+    if not args.no_fp64:
+        log("C3 in plain FP64 ...")
+        f64 = bench_c3_fp64(L, torch, w)
+        f64["fp32c_over_fp64"] = out["advance_only_atom_substeps_per_s"] / f64["atom_substeps_per_s"]
+        out["c3_fp64"] = f64
     if not args.no_c4:
         log("C4 batched vs plain ...")
         out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps)
