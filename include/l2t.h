@@ -99,7 +99,7 @@ extern "C" {
                                       sub-steps of an advance; used when every system of the context
                                       fits.  0 = the default 1024, -1 = never (one launch per
                                       sub-step).  Results are bitwise equal either way. */
-#define L2T_OPT_GRAPH          3   /* capture the per-sub-step launches of one advance in a hipGraph (default 1) */
+#define L2T_OPT_GRAPH          3   /* replay the per-sub-step launches of an advance from captured hipGraphs of 256 sub-steps (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
 #define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
 #define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells (1..1024) for the next l2t_build_neighbors (0 = automatic) */
@@ -287,10 +287,13 @@ int l2t_set_velocities(l2t_ctx *ctx, int32_t sys, const double *v, const double 
  * Eq. 2 (Section 2.1), Jacobi-synchronous: every read in sub-step n sees the
  * step-n state.  Atoms flagged L2T_FIELD_FIXED keep their T_e; their
  * neighbours exchange with them as usual.  L2T_FP64: one launch per sub-step
- * per system, the systems one after another (L2T_OPT_BATCH_FP64: one launch
- * per sub-step for all).  L2T_FP32C: all systems together; with
- * L2T_OPT_PERSISTENT, all sub-steps in one persistent launch.  Asynchronous;
- * a range violation is reported by the next synchronising call as ERANGE.
+ * per system, the systems one after another (L2T_OPT_BATCH_FP64: all systems
+ * together, one launch per sub-step, or one launch for all sub-steps when
+ * every system fits a workgroup, see L2T_OPT_RESIDENT_MAX).  L2T_FP32C: all
+ * systems together, one launch per sub-step; with L2T_OPT_PERSISTENT, all
+ * sub-steps in one persistent launch.  Every form gives bitwise-equal results.
+ * Asynchronous; a range violation is reported by the next synchronising call
+ * as ERANGE.
  * Errors: ESTATE (neighbours, parameters or T_e missing), EINVAL. */
 int l2t_advance(l2t_ctx *ctx, int32_t n_substeps);
 
