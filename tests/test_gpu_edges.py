@@ -1,0 +1,126 @@
+"""Degenerate and ragged inputs through the C ABI against the FP64 oracle:
+atoms without a neighbour inside the cut-off, and one batch of systems of
+1, 2, 63, 64, 65 and 200 atoms beside a lattice, in every launch form."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import gpu_context, max_rel, oracle_neighbors
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1810_12357_amd.l2t")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _params():
+    return W.default_params(g=5e-6, ce_model=W.CE_CONST, ce_const=W.C_NI)
+
+
+def _grid_system(m=8, spacing=5.0, seed=21):
+    """m^3 atoms on a periodic cubic grid 5 A apart: no pair within 4 A."""
+    rng = np.random.default_rng(seed)
+    g = (np.arange(m) + 0.5) * spacing
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).copy()
+    n = pos.shape[1]
+    return W.System(pos=pos, box_lo=np.zeros(3), box_len=np.full(3, m * spacing),
+                    periodic=np.ones(3, np.int32), T_e0=300.0 + 3000.0 * rng.uniform(0, 1, n),
+                    params=_params(), T_l=300.0 + 200.0 * rng.uniform(0, 1, n))
+
+
+def _gas(n, box, seed):
+    """n atoms uniform in a free (non-periodic) box."""
+    rng = np.random.default_rng(seed)
+    return W.System(pos=rng.uniform(0.05, box - 0.05, (3, n)), box_lo=np.zeros(3),
+                    box_len=np.full(3, box), periodic=np.zeros(3, np.int32),
+                    T_e0=300.0 + 2500.0 * rng.uniform(0, 1, n), params=_params(),
+                    T_l=300.0 + 100.0 * rng.uniform(0, 1, n))
+
+
+@pytest.mark.parametrize("precision", [L.L2T_FP64, L.L2T_FP32C])
+def test_atoms_without_neighbours_relax_by_the_closed_form(precision):
+    """With no neighbour inside the cut-off only the coupling acts:
+    T_n - T_l = (T_0 - T_l) (1 - dt g / c)^n, and the energy handed to the
+    lattice is c (sum T_0 - sum T_n)."""
+    sy = _grid_system()
+    w = W.Workload("grid", [sy], 4.0, 400, "fp64")
+    ctx = gpu_context(w, precision)
+    n = 400
+    ctx.advance(n)
+    p = sy.params
+    want = sy.T_l + (sy.T_e0 - sy.T_l) * (1.0 - p["dt"] * p["g"] / p["ce_const"]) ** n
+    got = ctx.get(0)
+    assert max_rel(got, want) < (1e-12 if precision == L.L2T_FP64 else 1e-5)
+    row, col = oracle_neighbors(sy, w.r_cut)
+    assert row[-1] == 0
+    T, led, _ = oracle.run(row, col, sy.T_e0, sy.T_l, p, n)
+    assert max_rel(got, T) < (1e-12 if precision == L.L2T_FP64 else 1e-5)
+    e = ctx.energies(0)
+    ref = p["ce_const"] * (sy.T_e0.sum() - T.sum())
+    assert e["E_e_to_l"] == pytest.approx(ref, rel=1e-9 if precision == L.L2T_FP64 else 1e-5)
+    ctx.close()
+
+
+def _ragged():
+    systems = [_gas(n, box, 30 + k) for k, (n, box) in
+               enumerate([(1, 9.0), (2, 5.0), (63, 12.0), (64, 12.0), (65, 12.0), (200, 20.0)])]
+    systems.append(W.c1(n_cells=4).systems[0])
+    return W.Workload("ragged", systems, 4.0, 300, "fp32c")
+
+
+def _oracle_states(w, n):
+    out = []
+    for sy in w.systems:
+        row, col = oracle_neighbors(sy, w.r_cut)
+        T, _, bad = oracle.run(row, col, sy.T_e0, sy.T_l, sy.params, n)
+        assert bad == 0
+        out.append(T)
+    return out
+
+
+def test_ragged_batch_fp32c_every_launch_form():
+    w = _ragged()
+    n = 300
+    want = _oracle_states(w, n)
+    runs = []
+    for kernel, persistent, graph in ((0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 0, 1)):
+        ctx = gpu_context(w, L.L2T_FP32C, graph=graph)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+        if persistent:
+            L.l2t_set_option(ctx.h, L.L2T_OPT_PERSISTENT, 1)
+        ctx.advance(137)
+        ctx.advance(n - 137)
+        runs.append([ctx.get(s) for s in range(len(w.systems))])
+        ctx.close()
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
+    for got, T in zip(runs[0], want):
+        assert max_rel(got, T) < 1e-5
+
+
+def test_ragged_batch_fp64_resident_and_per_substep():
+    w = _ragged()
+    n = 300
+    want = _oracle_states(w, n)
+    runs = []
+    for batch, res in ((0, 0), (1, -1), (1, 0)):
+        ctx = gpu_context(w, L.L2T_FP64)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, batch)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_RESIDENT_MAX, res)
+        ctx.advance(137)
+        ctx.advance(n - 137)
+        runs.append([ctx.get(s) for s in range(len(w.systems))])
+        ctx.close()
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
+    for got, T in zip(runs[0], want):
+        assert max_rel(got, T) < 1e-12
