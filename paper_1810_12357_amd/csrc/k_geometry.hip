@@ -205,13 +205,14 @@ __global__ void k_init_slots(int32_t atom_off, int32_t n_pad, int32_t *perm, int
 }
 
 // final slot of the atom at cell-order position k: its brick's first slot
-// plus its offset inside the brick
+// plus its offset inside the brick.  The wrapped position is written by slot
+// (qx, qy, qz) and by cell order (sx, sy, sz: what the neighbour search reads)
 __global__ void k_assign(const int32_t *sorted, int32_t n, int32_t atom_off, int64_t caller_off,
                          const double *px, const double *py, const double *pz,
                          const int32_t *cell_of, const int32_t *brick_of_rank,
                          const BrickInfo *bricks, const int32_t *brick_atom0, Grid g,
                          int32_t *perm, int32_t *inv, int32_t *cell_int, int32_t *pos_slot,
-                         double *qx, double *qy, double *qz) {
+                         double *qx, double *qy, double *qz, double *sx, double *sy, double *sz) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int32_t i = sorted[k];
@@ -222,9 +223,15 @@ __global__ void k_assign(const int32_t *sorted, int32_t n, int32_t atom_off, int
     inv[caller_off + i] = slot;
     cell_int[slot] = r;
     pos_slot[k] = slot;
-    qx[slot] = g.lo[0] + wrap_coord(px[i], g.lo[0], g.len[0], g.periodic[0]);
-    qy[slot] = g.lo[1] + wrap_coord(py[i], g.lo[1], g.len[1], g.periodic[1]);
-    qz[slot] = g.lo[2] + wrap_coord(pz[i], g.lo[2], g.len[2], g.periodic[2]);
+    const double x = g.lo[0] + wrap_coord(px[i], g.lo[0], g.len[0], g.periodic[0]);
+    const double y = g.lo[1] + wrap_coord(py[i], g.lo[1], g.len[1], g.periodic[1]);
+    const double z = g.lo[2] + wrap_coord(pz[i], g.lo[2], g.len[2], g.periodic[2]);
+    qx[slot] = x;
+    qy[slot] = y;
+    qz[slot] = z;
+    sx[k] = x;
+    sy[k] = y;
+    sz[k] = z;
     (void)atom_off;
 }
 
@@ -232,10 +239,13 @@ __global__ void k_assign(const int32_t *sorted, int32_t n, int32_t atom_off, int
 // of one system.  Rows visit the distinct cells of the 3x3x3 stencil in a
 // fixed order and each cell's atoms in cell order; both tables hold the same
 // entries in the same order: col the global slot, col16 the index into the
-// brick's LDS tile (own slots first, then the halo list).
+// brick's LDS tile (own slots first, then the halo list).  Thread k is the
+// atom at cell-order position k; positions are read in cell order (cx, cy,
+// cz), so a candidate's distance needs no slot lookup, and the slot is read
+// only for an accepted neighbour of the FILL pass.
 template <bool FILL>
-__global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx,
-                            const double *qy, const double *qz, const int32_t *cell_int,
+__global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *cx,
+                            const double *cy, const double *cz, const int32_t *cell_int,
                             const int32_t *start, const int32_t *rank_of_cell,
                             const int32_t *cell_of_rank, const int32_t *brick_of_rank,
                             const BrickInfo *bricks, const int32_t *shell, Grid g, double rc2,
@@ -244,7 +254,7 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int32_t self = pos_slot[k];
-    const double xi = qx[self], yi = qy[self], zi = qz[self];
+    const double xi = cx[k], yi = cy[k], zi = cz[k];
     const int32_t rank0 = cell_int[self];
     const int32_t cell0 = cell_of_rank[rank0];
     int32_t ic[3] = {cell0 / (g.nc[1] * g.nc[2]), (cell0 / g.nc[2]) % g.nc[1], cell0 % g.nc[2]};
@@ -279,13 +289,13 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *qx
                     hbase = bi.n_own_pad + h;
                 }
                 for (int32_t q = start[rk]; q < start[rk + 1]; ++q) {
-                    const int32_t j = pos_slot[q];
-                    if (j == self) continue;
-                    double dx = min_image(qx[j] - xi, g.len[0], g.periodic[0]);
-                    double dy = min_image(qy[j] - yi, g.len[1], g.periodic[1]);
-                    double dz = min_image(qz[j] - zi, g.len[2], g.periodic[2]);
+                    if (q == k) continue;
+                    double dx = min_image(cx[q] - xi, g.len[0], g.periodic[0]);
+                    double dy = min_image(cy[q] - yi, g.len[1], g.periodic[1]);
+                    double dz = min_image(cz[q] - zi, g.len[2], g.periodic[2]);
                     if (dx * dx + dy * dy + dz * dz <= rc2) {
                         if (FILL && m < width) {
+                            const int32_t j = pos_slot[q];
                             col[base + (int64_t)m * kWave] = j;
                             const int32_t loc = own ? j - bi.slot0 : hbase + (q - start[rk]);
                             colh[2 * (basew + (int64_t)(m >> 1) * kWave) + (m & 1)] =
@@ -982,6 +992,10 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     const double rc2 = r_cut * r_cut;
     const int64_t NI = c->n_int;
     double *qx = c->pos_int, *qy = c->pos_int + NI, *qz = c->pos_int + 2 * NI;
+    // wrapped positions in cell order (all systems, caller offsets)
+    double *cpos = tmp_of<double>(c, 12, 3 * c->n_tot);
+    if (!cpos) return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
+    double *csx = cpos, *csy = cpos + c->n_tot, *csz = cpos + 2 * c->n_tot;
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         const int32_t n = st.desc.n_atoms;
@@ -993,9 +1007,11 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                            c->sorted_local + st.caller_off, n, st.atom_off, st.caller_off, px, py,
                            pz, c->cell_of + st.caller_off, d_brick + ro, c->bricks, d_atom0,
                            grids[s], c->perm, c->inv, c->cell_int, c->pos_slot + st.caller_off,
-                           qx, qy, qz);
+                           qx, qy, qz, csx + st.caller_off, csy + st.caller_off,
+                           csz + st.caller_off);
         hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
-                           c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
+                           c->pos_slot + st.caller_off, csx + st.caller_off, csy + st.caller_off,
+                           csz + st.caller_off, c->cell_int,
                            d_start + cstart_off[s], d_rank + ro, d_cell + ro,
                            d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, nullptr,
                            nullptr, nullptr);
@@ -1100,7 +1116,8 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         const int32_t n = st.desc.n_atoms;
         const int64_t ro = lay[s].rank_off;
         hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
-                           c->pos_slot + st.caller_off, qx, qy, qz, c->cell_int,
+                           c->pos_slot + st.caller_off, csx + st.caller_off, csy + st.caller_off,
+                           csz + st.caller_off, c->cell_int,
                            d_start + cstart_off[s], d_rank + ro, d_cell + ro,
                            d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, c->slices,
                            c->col, (uint16_t *)c->colw);

@@ -116,6 +116,9 @@ struct GraphKey {
 // leaves the state in the buffer it started from)
 constexpr int32_t kGraphChunk = 256;
 
+// grow-only temporary buffers of the neighbour build (tmp_buf slots)
+constexpr int kTmpSlots = 13;
+
 constexpr int kKernelSliced = 0;   // global gathers through the int32 table
 constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
 constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
@@ -228,8 +231,8 @@ struct l2t_ctx {
     // grow-only capacities of the internal-order buffers and the brick tables
     size_t cap_ni = 0, cap_nb = 0, cap_nl = 0, cap_sh = 0, cap_ha = 0;
     // grow-only temporaries of the neighbour build, one per use
-    void *tmp[12] = {};
-    size_t tmp_cap[12] = {};
+    void *tmp[l2t::kTmpSlots] = {};
+    size_t tmp_cap[l2t::kTmpSlots] = {};
 
     std::vector<l2t::DevParams> hparams;
     l2t::Tuning tune;
