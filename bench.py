@@ -389,8 +389,8 @@ def main():
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
-                                   "design note, not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; splitting the systems over "
+                                   "several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
