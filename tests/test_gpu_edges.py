@@ -124,3 +124,29 @@ def test_ragged_batch_fp64_resident_and_per_substep():
             assert np.array_equal(a, b)
     for got, T in zip(runs[0], want):
         assert max_rel(got, T) < 1e-12
+
+
+@pytest.mark.parametrize("precision", [L.L2T_FP64, L.L2T_FP32C])
+def test_uniform_temperature_is_stationary_and_g0_conserves(precision):
+    """T_e = T_lat uniform: every pair term and the coupling are exactly zero,
+    so the state does not move at all.  With G = 0 and constant c the
+    antisymmetric exchange keeps sum T (the ledger records no energy to the
+    lattice)."""
+    w = W.c1(n_cells=6, n_substeps=500)
+    sy = w.systems[0]
+    sy.params = dict(sy.params, ce_model=W.CE_CONST, ce_const=W.C_NI)
+    flat = W.System(pos=sy.pos, box_lo=sy.box_lo, box_len=sy.box_len, periodic=sy.periodic,
+                    T_e0=np.full(sy.n, 1234.5), params=sy.params, T_l=np.full(sy.n, 1234.5))
+    ctx = gpu_context(W.Workload("flat", [flat], w.r_cut, 500, "fp64"), precision)
+    ctx.advance(500)
+    assert np.array_equal(ctx.get(0), flat.T_e0)
+    ctx.close()
+    hot = W.System(pos=sy.pos, box_lo=sy.box_lo, box_len=sy.box_len, periodic=sy.periodic,
+                   T_e0=sy.T_e0, params=dict(sy.params, g=0.0), T_l=sy.T_l)
+    ctx = gpu_context(W.Workload("g0", [hot], w.r_cut, 500, "fp64"), precision)
+    ctx.advance(500)
+    T = ctx.get(0)
+    assert np.max(np.abs(T - hot.T_e0)) > 100.0             # the hotspot did spread
+    assert T.sum() == pytest.approx(hot.T_e0.sum(), rel=1e-13 if precision == L.L2T_FP64 else 1e-9)
+    assert ctx.energies(0)["E_e_to_l"] == 0.0
+    ctx.close()
