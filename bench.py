@@ -48,11 +48,12 @@ def log(msg):
 
 
 def library_source_hash() -> str:
-    """sha256 over the library sources (csrc/* and the C header)."""
-    import glob
+    """sha256 over the sources the sub-step kernels are compiled from (their
+    translation unit, the device helpers, the internal and the C header)."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1810_12357_amd", "csrc", "*")))
+    csrc = os.path.join(ROOT, "paper_1810_12357_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in ("k_step.hip", "step_device.h", "l2t_internal.h")]
     files.append(os.path.join(ROOT, "include", "l2t.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -64,7 +65,7 @@ def library_source_hash() -> str:
 def measured_traffic(kernel: str, n_atoms: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the summary is missing, covers another kernel or size, or was
-    taken on other library sources."""
+    taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_c3_4M_traffic.md")
     if n_atoms != 4_000_000 or not os.path.exists(path):
         return None

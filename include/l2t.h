@@ -320,6 +320,18 @@ int l2t_advance_recorded(l2t_ctx *ctx, int32_t n_substeps, int32_t ckpt_every);
 int l2t_adjoint(l2t_ctx *ctx, const double *dL_dTN, int32_t mem, double *dL_dK,
                 double *dL_dg, double *dL_dT0);
 
+/* Checkpoint / resume of a system's counters.  Writing L2T_FIELD_TE resets
+ * the system's sub-step counter (the time of the Eq. 10 source is step * dt)
+ * and its ledger accumulators; a resumed run calls this after restoring T_e
+ * (from L2T_FIELD_TE of the saved run, which restores the state bitwise) to
+ * set them to the saved report's step, E_e_to_l, E_src and T_ledger_acc.
+ * The sub-steps that follow then equal those of the uninterrupted run bit
+ * for bit; later ledger totals equal its totals up to FP64 summation order.
+ * Synchronises.  Errors: EINVAL (bad system, step < 0, a non-finite value),
+ * ESTATE (neighbours or T_e not set). */
+int l2t_set_counters(l2t_ctx *ctx, int32_t sys, int64_t step, double E_e_to_l, double E_src,
+                     double T_ledger_acc);
+
 /* Per-system ledger (FP64 reductions on the device).  Synchronises; returns
  * ERANGE if any sub-step since the last check produced theta outside [0,1]
  * or a non-finite T (the ledger is still written). */

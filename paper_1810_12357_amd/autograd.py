@@ -34,6 +34,9 @@ class L2TAdvance(torch.autograd.Function):
             L.l2t_set_field(h, s, L.L2T_FIELD_TE, T0d[off:off + sizes[s]])
             off += sizes[s]
         L.l2t_advance_recorded(h, int(n_substeps), int(ckpt_every))
+        # the context keeps one recording: a later recorded forward replaces it
+        gen = getattr(context, "_recording", 0) + 1
+        context._recording = gen
         TN = torch.empty_like(T0d)
         off = 0
         for s in range(len(sizes)):
@@ -41,10 +44,14 @@ class L2TAdvance(torch.autograd.Function):
             off += sizes[s]
         ctx.context = context
         ctx.n_sys = len(sizes)
+        ctx.recording = gen
         return TN
 
     @staticmethod
     def backward(ctx, grad_TN):
+        if getattr(ctx.context, "_recording", None) != ctx.recording:
+            raise RuntimeError("this forward's recording was replaced by a later recorded "
+                               "advance of the same context; run backward before the next forward")
         w = grad_TN.detach().double().contiguous()
         dT0 = torch.empty_like(w)
         dK, dg = L.l2t_adjoint(ctx.context.h, w, ctx.n_sys, dL_dT0=dT0)

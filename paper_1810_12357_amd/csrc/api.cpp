@@ -890,6 +890,28 @@ int l2t_energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out) {
     return check_err(c);
 }
 
+int l2t_set_counters(l2t_ctx *c, int32_t sys, int64_t step, double E_e_to_l, double E_src,
+                     double T_ledger_acc) {
+    if (bad_sys(c, sys) || step < 0 || !std::isfinite(E_e_to_l) || !std::isfinite(E_src) ||
+        !std::isfinite(T_ledger_acc))
+        return l2t::fail(c, L2T_EINVAL, "bad system index, step < 0 or non-finite ledger value");
+    SystemState &st = c->sys[sys];
+    if (!c->nbrs_built || !st.has_te)
+        return l2t::fail(c, L2T_ESTATE, "restore T_e before the counters (writing T_e resets them)");
+    int rc = l2t::reset_ledger(c, sys);
+    if (rc != L2T_OK) return rc;
+    // the system's totals go into its first ledger row; the report sums its rows
+    const double row[3] = {E_e_to_l, E_src, T_ledger_acc};
+    L2T_HIP(c, hipMemcpyAsync(c->ledger + 3 * (int64_t)st.slice0, row, sizeof row,
+                              hipMemcpyHostToDevice, c->stream));
+    L2T_HIP(c, hipMemcpyAsync(c->dstep + sys, &step, sizeof step, hipMemcpyHostToDevice,
+                              c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));   // the sources are locals
+    st.step = step;
+    c->rec.valid = false;
+    return L2T_OK;
+}
+
 int l2t_sync(l2t_ctx *c) {
     if (!c) return L2T_EINVAL;
     return check_err(c);

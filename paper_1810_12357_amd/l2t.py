@@ -36,7 +36,7 @@ EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbor
            "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
            "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
            "l2t_coupling", "l2t_damping_step", "l2t_set_mean_field", "l2t_get_params",
-           "l2t_set_lattice_fd",
+           "l2t_set_lattice_fd", "l2t_set_counters",
            "l2t_exchange_rate", "l2t_pair_fp32", "l2t_strerror", "l2t_last_error",
            "l2t_version")
 
@@ -113,6 +113,7 @@ def load() -> C.CDLL:
         "l2t_adjoint": (C.c_int, [vp, vp, i32, vp, vp, vp]),
         "l2t_energies": (C.c_int, [vp, i32, P(l2t_energy_report)]),
         "l2t_sync": (C.c_int, [vp]),
+        "l2t_set_counters": (C.c_int, [vp, i32, i64, d, d, d]),
         "l2t_set_option": (C.c_int, [vp, i32, i64]),
         "l2t_get_option": (C.c_int, [vp, i32, P(i64)]),
         "l2t_coupling": (C.c_int, [vp, i32, i32, d, vp, vp, vp, i32]),
@@ -340,6 +341,13 @@ def l2t_energies(ctx, sys: int, check: bool = True) -> dict:
 
 def l2t_sync(ctx) -> int:
     return _check(ctx, load().l2t_sync(ctx))
+
+
+def l2t_set_counters(ctx, sys: int, step: int, E_e_to_l: float, E_src: float,
+                     T_ledger_acc: float) -> int:
+    """Restore a system's sub-step counter and ledger totals (see l2t.h)."""
+    return _check(ctx, load().l2t_set_counters(ctx, sys, int(step), float(E_e_to_l),
+                                               float(E_src), float(T_ledger_acc)))
 
 
 def l2t_set_option(ctx, option: int, value: int) -> int:

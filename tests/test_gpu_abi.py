@@ -142,3 +142,38 @@ def test_advance_system_and_field_round_trip():
     vals = np.linspace(300.0, 900.0, w.systems[2].n)
     L.l2t_set_field(ctx.h, 2, L.L2T_FIELD_TE, vals)
     assert max_rel(ctx.get(2), vals) < 1e-13        # hi + lo keeps ~48 bits
+
+
+@pytest.mark.parametrize("precision", [L.L2T_FP64, L.L2T_FP32C])
+def test_checkpoint_resume_is_bitwise(precision):
+    """Laser slabs run 300 sub-steps straight, and 137 sub-steps, saved
+    (T_e and the counters of the energy report), restored into a fresh
+    context and run 163 more: T_e is bitwise equal (the Eq. 10 source resumes
+    at the saved step), step and t agree, the ledger totals agree to FP64
+    summation order."""
+    w = W.c4(n_systems=3, n_substeps=300, size_lo=800, size_hi=3000)
+    S = len(w.systems)
+    a = gpu_context(w, precision)
+    a.advance(300)
+    TA = [a.get(s) for s in range(S)]
+    eA = [a.energies(s) for s in range(S)]
+    a.close()
+    b = gpu_context(w, precision)
+    b.advance(137)
+    saved = [(b.get(s), b.energies(s)) for s in range(S)]
+    b.close()
+    c = gpu_context(w, precision)
+    with pytest.raises(L.L2TError):
+        L.l2t_set_counters(c.h, 0, -1, 0.0, 0.0, 0.0)
+    for s, (T, e) in enumerate(saved):
+        L.l2t_set_field(c.h, s, L.L2T_FIELD_TE, T)
+        L.l2t_set_counters(c.h, s, e["step"], e["E_e_to_l"], e["E_src"], e["T_ledger_acc"])
+    c.advance(163)
+    for s in range(S):
+        assert np.array_equal(c.get(s), TA[s])
+        e = c.energies(s)
+        assert e["step"] == eA[s]["step"] == 300
+        assert e["t"] == eA[s]["t"]
+        for key in ("E_e_to_l", "E_src", "T_ledger_acc"):
+            assert e[key] == pytest.approx(eA[s][key], rel=1e-12, abs=1e-12), key
+    c.close()

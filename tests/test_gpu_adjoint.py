@@ -121,6 +121,12 @@ def test_autograd_function_gradients():
     assert K.grad[0].item() == pytest.approx(oK, rel=1e-4)
     assert g.grad[0].item() == pytest.approx(og, rel=1e-4)
     assert np.max(np.abs(T0.grad.cpu().numpy()[:n0] - lam)) < 1e-4 * np.abs(lam).max()
+    # a later recorded forward replaces the recording: the earlier graph refuses backward
+    T1 = A.advance(T0, K, g, ctx, 50, 25)
+    T2 = A.advance(T0, K, g, ctx, 50, 25)
+    with pytest.raises(RuntimeError):
+        T1.sum().backward()
+    T2.sum().backward()
 
 
 def _adjoint_run(w, kernel, dL_fn, gate=None, graph=1):
