@@ -546,7 +546,13 @@ __global__ void k_momentum(const double *vm, int32_t n_pad, double *out /*[4]*/)
 
 // T_i^lat = sum_{j in {i} U N(i)} 1/2 m_j |v_j - v_com|^2 / (3/2 k_B N_j); the
 // coupling of atom i is gated off where 1/2 m_i |v_i - v_com|^2 < ke_eps.  The
-// gate is stored in the sign bit of T^lat.
+// gate is stored in the sign bit of T^lat.  With the local centre of mass
+// (the Eq. 4 form) one pass over the neighbours accumulates, for the
+// velocities u_j = v_j - v_i shifted by the atom's own, M = sum m_j,
+// P = sum m_j u_j and Q = sum m_j |u_j|^2: then v_i - v_com = -P/M and
+// sum 1/2 m_j |v_j - v_com|^2 = 1/2 (Q - |P|^2/M).  The shift keeps the
+// subtraction at the scale of the thermal spread (a common drift cancels
+// in u exactly), as in the shifted-data form of a variance.
 __global__ void k_lattice_temp(int32_t atom_off, int32_t n_pad, const int32_t *perm,
                                const SliceInfo *slices, const int32_t *col, const double *vm,
                                const double *gmom, int32_t global_com, double ke_eps,
@@ -558,37 +564,41 @@ __global__ void k_lattice_temp(int32_t atom_off, int32_t n_pad, const int32_t *p
     const double *vx = vm, *vy = vm + n_pad, *vz = vm + 2 * n_pad, *ms = vm + 3 * n_pad;
     const SliceInfo si = slices[slot / kWave];
     const int64_t base = (int64_t)si.col_base64 * kWave + (slot & (kWave - 1));
-    double vc[3];
-    if (global_com) {
-        vc[0] = gmom[0] / gmom[3];
-        vc[1] = gmom[1] / gmom[3];
-        vc[2] = gmom[2] / gmom[3];
-    } else {
-        double P[3] = {ms[k] * vx[k], ms[k] * vy[k], ms[k] * vz[k]}, M = ms[k];
-        for (int32_t q = 0; q < si.width; ++q) {
-            int32_t j = col[base + (int64_t)q * kWave];
-            if (j == slot) continue;
-            int32_t l = j - atom_off;
-            P[0] += ms[l] * vx[l];
-            P[1] += ms[l] * vy[l];
-            P[2] += ms[l] * vz[l];
-            M += ms[l];
-        }
-        vc[0] = P[0] / M;
-        vc[1] = P[1] / M;
-        vc[2] = P[2] / M;
-    }
-    double ux = vx[k] - vc[0], uy = vy[k] - vc[1], uz = vz[k] - vc[2];
-    double Ki = 0.5 * ms[k] * (ux * ux + uy * uy + uz * uz) * kMvv2e;
-    double KE = Ki;
+    double Ki, KE;
     int32_t nj = 1;
-    for (int32_t q = 0; q < si.width; ++q) {
-        int32_t j = col[base + (int64_t)q * kWave];
-        if (j == slot) continue;
-        int32_t l = j - atom_off;
-        double wx = vx[l] - vc[0], wy = vy[l] - vc[1], wz = vz[l] - vc[2];
-        KE += 0.5 * ms[l] * (wx * wx + wy * wy + wz * wz) * kMvv2e;
-        ++nj;
+    if (global_com) {
+        const double vc[3] = {gmom[0] / gmom[3], gmom[1] / gmom[3], gmom[2] / gmom[3]};
+        const double ux = vx[k] - vc[0], uy = vy[k] - vc[1], uz = vz[k] - vc[2];
+        Ki = 0.5 * ms[k] * (ux * ux + uy * uy + uz * uz) * kMvv2e;
+        KE = Ki;
+        for (int32_t q = 0; q < si.width; ++q) {
+            const int32_t j = col[base + (int64_t)q * kWave];
+            if (j == slot) continue;
+            const int32_t l = j - atom_off;
+            const double wx = vx[l] - vc[0], wy = vy[l] - vc[1], wz = vz[l] - vc[2];
+            KE += 0.5 * ms[l] * (wx * wx + wy * wy + wz * wz) * kMvv2e;
+            ++nj;
+        }
+    } else {
+        const double xi = vx[k], yi = vy[k], zi = vz[k];
+        double M = ms[k], P[3] = {0.0, 0.0, 0.0}, Q = 0.0;
+        for (int32_t q = 0; q < si.width; ++q) {
+            const int32_t j = col[base + (int64_t)q * kWave];
+            if (j == slot) continue;
+            const int32_t l = j - atom_off;
+            const double m = ms[l];
+            const double ux = vx[l] - xi, uy = vy[l] - yi, uz = vz[l] - zi;
+            M += m;
+            P[0] += m * ux;
+            P[1] += m * uy;
+            P[2] += m * uz;
+            Q += m * (ux * ux + uy * uy + uz * uz);
+            ++nj;
+        }
+        const double P2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+        // v_i - v_com = -P / M
+        Ki = 0.5 * ms[k] * (P2 / (M * M)) * kMvv2e;
+        KE = 0.5 * fmax(Q - P2 / M, 0.0) * kMvv2e;
     }
     double T = KE / (1.5 * kBoltzmann * (double)nj);
     bool gated = Ki < ke_eps;

@@ -116,6 +116,23 @@ def test_lattice_temperature_and_gate_equal_oracle(precision):
     assert np.array_equal(nb, np.diff(row).astype(np.float64))
 
 
+def test_lattice_temperature_is_unchanged_by_a_common_drift():
+    """Eq. 4 takes velocities relative to the local centre of mass, so a
+    common drift of every atom (0.5 A/fs, ~250 x the thermal speed) leaves
+    T^lat and the gate unchanged up to rounding."""
+    w = W.c3(n_cells=8, n_substeps=1)
+    sy = w.systems[0]
+    out = []
+    for drift in (0.0, 0.5):
+        sy.vel = sy.vel + np.array([[drift], [-0.3 * drift], [0.7 * drift]])
+        ctx = gpu_context(w, L.L2T_FP64)
+        out.append((ctx.get(0, L.L2T_FIELD_TL), ctx.get(0, L.L2T_FIELD_GATE)))
+        ctx.close()
+    (T0, g0), (T1, g1) = out
+    assert np.array_equal(g0, g1)
+    assert max_rel(T1, T0) < 1e-9
+
+
 # -------------------------------------------------------------- C1: FP64 plain ----
 @pytest.fixture(scope="module")
 def c1_oracle():
