@@ -315,6 +315,129 @@ __global__ void k_neighbors(int32_t n, const int32_t *pos_slot, const double *cx
     }
 }
 
+// Neighbour rows in one search, one wave per cell.  The wave takes the
+// cell's own atoms (cell-order positions k0..k0+na-1 of its system, na <= 64)
+// and, for every distinct cell of the 3x3x3 stencil in the fixed order, its
+// candidates T = 64 / na at a time: lane L pairs own atom L mod na with
+// candidate L / na of the chunk, so the lanes of one candidate read the same
+// position.  Atom i's lanes are i, i + na, ...; its accepted candidates keep
+// the row order of the thread-per-atom search (stencil cell, then cell order),
+// and a lane's place in the row is the atom's running length plus the
+// accepted lanes of the same atom below it (a popcount of the ballot).  Every
+// lane of an atom carries its running length, so no shared memory is used.
+// Rows go to a temporary table in cell order, wcap entries per atom: the
+// global cell-order index of the neighbour and its offset in the brick's halo
+// list (-1 for a neighbour of the atom's own brick, whose tile place follows
+// the count order).  cnt[slot] receives the full count; a row longer than
+// wcap raises *overflow and the caller falls back to the thread-per-atom fill.
+__global__ __launch_bounds__(256) void k_cell_rows(
+    int32_t ncell, int64_t caller_off, const int32_t *__restrict__ pos_slot /*all systems*/,
+    const double *__restrict__ cx, const double *__restrict__ cy,
+    const double *__restrict__ cz /*this system, cell order*/,
+    const int32_t *__restrict__ start, const int32_t *__restrict__ rank_of_cell,
+    const int32_t *__restrict__ cell_of_rank, const int32_t *__restrict__ brick_of_rank,
+    const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ shell, Grid g, double rc2,
+    int32_t wcap, int32_t *__restrict__ cnt, int32_t *__restrict__ tq,
+    int16_t *__restrict__ th, unsigned *__restrict__ overflow) {
+    // the cell, its atoms and its stencil are wave-uniform: scalar registers and loads
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
+    const int32_t r = blockIdx.x * (blockDim.x / kWave) + wave;   // cell rank in this system
+    if (r >= ncell) return;
+    const int32_t k0 = start[r], na = start[r + 1] - k0;
+    if (na == 0 || na > kWave) return;
+    const int32_t il = lane % na, tl = lane / na;   // the lane's atom and candidate slot
+    const int32_t T = kWave / na;                    // candidates per chunk
+    uint64_t pat = 0;                                // lanes 0, na, 2 na, ... of atom 0
+    for (int32_t t = 0; t < T; ++t) pat |= 1ull << (t * na);
+    const uint64_t mine = pat << il;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int32_t k = k0 + il;
+    const double xk = cx[k], yk = cy[k], zk = cz[k];
+    const int32_t cell0 = cell_of_rank[r];
+    const int32_t ic[3] = {cell0 / (g.nc[1] * g.nc[2]), (cell0 / g.nc[2]) % g.nc[1], cell0 % g.nc[2]};
+    int32_t sx[3], sy[3], sz[3], ox[3], oy[3], oz[3];
+    const int mx = axis_cells(ic[0], g.nc[0], g.periodic[0], sx, ox);
+    const int my = axis_cells(ic[1], g.nc[1], g.periodic[1], sy, oy);
+    const int mz = axis_cells(ic[2], g.nc[2], g.periodic[2], sz, oz);
+    const BrickInfo bi = bricks[brick_of_rank[r]];
+    const int64_t row = (caller_off + k) * (int64_t)wcap;
+    int32_t len = 0;
+    for (int a = 0; a < mx; ++a)
+        for (int b = 0; b < my; ++b)
+            for (int e = 0; e < mz; ++e) {
+                const int32_t cell = (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[e];
+                const int32_t rk = rank_of_cell[cell];
+                const int32_t q0 = start[rk], ms = start[rk + 1] - q0;
+                const int32_t p0c = ic[0] - bi.o[0] + ox[a] + 1;
+                const int32_t p1c = ic[1] - bi.o[1] + oy[b] + 1;
+                const int32_t p2c = ic[2] - bi.o[2] + oz[e] + 1;
+                const int32_t hcell = shell[bi.shell_off + (p0c * bi.sh[1] + p1c) * bi.sh[2] + p2c];
+                for (int32_t c0 = 0; c0 < ms; c0 += T) {
+                    const int32_t jq = c0 + tl;
+                    const int32_t q = q0 + jq;
+                    bool acc = false;
+                    if (tl < T && jq < ms && q != k) {
+                        const double dx = min_image(cx[q] - xk, g.len[0], g.periodic[0]);
+                        const double dy = min_image(cy[q] - yk, g.len[1], g.periodic[1]);
+                        const double dz = min_image(cz[q] - zk, g.len[2], g.periodic[2]);
+                        acc = dx * dx + dy * dy + dz * dz <= rc2;
+                    }
+                    const uint64_t mask = __ballot(acc);
+                    if (acc) {
+                        const int32_t m = len + __popcll(mask & mine & below);
+                        if (m < wcap) {
+                            tq[row + m] = (int32_t)(caller_off + q);
+                            th[row + m] = (int16_t)(hcell == -1 ? -1 : hcell + jq);
+                        }
+                    }
+                    len += __popcll(mask & mine);
+                }
+            }
+    if (tl == 0) {
+        cnt[pos_slot[caller_off + k]] = len;
+        if (len > wcap) atomicOr(overflow, 1u);
+    }
+}
+
+// slot -> global cell-order index (the inverse of pos_slot)
+__global__ void k_cell_index(const int32_t *pos_slot, int64_t n_tot, int32_t *kof) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tot) kof[pos_slot[t]] = (int32_t)t;
+}
+
+// Both neighbour tables from the temporary rows, one thread per slot, so the
+// writes of a slice's lanes are coalesced: col the global slot, col16 the LDS
+// byte offset (own brick: the neighbour's slot after the count order; halo:
+// after the brick's own slots).  Entries past the count point at the slot.
+__global__ void k_rows_fill(int32_t n_int, const int32_t *__restrict__ perm,
+                            const int32_t *__restrict__ kof, const int32_t *__restrict__ cnt,
+                            const SliceInfo *__restrict__ slices, const BrickInfo *__restrict__ bricks,
+                            const int32_t *__restrict__ pos_slot, const int32_t *__restrict__ tq,
+                            const int16_t *__restrict__ th, int32_t wcap, int32_t *__restrict__ col,
+                            uint16_t *__restrict__ colh) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_int || perm[s] < 0) return;
+    const SliceInfo si = slices[s / kWave];
+    const BrickInfo &bi = bricks[si.brick];
+    const int64_t base = (int64_t)si.col_base64 * kWave + (s & (kWave - 1));
+    const int64_t basew = (int64_t)si.colw_base64 * kWave + (s & (kWave - 1));
+    const int32_t width = si.width, slot0 = bi.slot0, own_pad = bi.n_own_pad;
+    const int32_t m_n = min(cnt[s], width);
+    const int64_t row = (int64_t)kof[s] * wcap;
+#pragma unroll 4
+    for (int32_t m = 0; m < m_n; ++m) {
+        const int32_t j = pos_slot[tq[row + m]];
+        const int32_t h = th[row + m];
+        col[base + (int64_t)m * kWave] = j;
+        colh[2 * (basew + (int64_t)(m >> 1) * kWave) + (m & 1)] =
+            (uint16_t)(4 * (h < 0 ? j - slot0 : own_pad + h));
+    }
+    for (int32_t m = m_n; m < width; ++m) col[base + (int64_t)m * kWave] = s;
+    for (int32_t m = m_n; m < (width + 1) / 2 * 2; ++m)
+        colh[2 * (basew + (int64_t)(m >> 1) * kWave) + (m & 1)] = (uint16_t)(4 * (s - slot0));
+}
+
 // Within each brick, order the atoms by neighbour count (descending, ties in
 // cell order) so the 64 lanes of a slice carry rows of nearly equal length;
 // the brick kernel reads its tile from LDS, so the order inside a brick costs
@@ -1006,6 +1129,29 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     double *cpos = tmp_of<double>(c, 12, 3 * c->n_tot);
     if (!cpos) return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
     double *csx = cpos, *csy = cpos + c->n_tot, *csz = cpos + 2 * c->n_tot;
+    // one search pass (wave per cell, rows into a temporary table) when no cell
+    // holds more atoms than a wave has lanes; else the thread-per-atom count and fill
+    int32_t occ_max = 0;
+    for (int s = 0; s < S; ++s) {
+        const int32_t *start = h_start.data() + cstart_off[s];
+        for (int64_t r = 0; r < c->sys[s].ncell; ++r)
+            occ_max = std::max(occ_max, start[r + 1] - start[r]);
+    }
+    const bool rows_path = occ_max > 0 && occ_max <= kWave;
+    // temporary row width: the widest row of the previous build plus a margin
+    const int32_t wcap =
+        c->max_nbrs > 0 ? std::min<int32_t>(96, (c->max_nbrs + 8 + 7) / 8 * 8) : 48;
+    int32_t *tq = nullptr, *kof = nullptr;
+    int16_t *th = nullptr;
+    if (rows_path) {
+        tq = tmp_of<int32_t>(c, 13, c->n_tot * (int64_t)wcap);
+        th = tmp_of<int16_t>(c, 14, c->n_tot * (int64_t)wcap);
+        kof = tmp_of<int32_t>(c, 15, c->n_int + 1);   // + the overflow flag
+        if (!tq || !th || !kof)
+            return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
+        L2T_HIP(c, hipMemsetAsync(kof + c->n_int, 0, sizeof(int32_t), st_));
+    }
+    unsigned *row_overflow = rows_path ? reinterpret_cast<unsigned *>(kof + c->n_int) : nullptr;
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
         const int32_t n = st.desc.n_atoms;
@@ -1019,12 +1165,23 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                            grids[s], c->perm, c->inv, c->cell_int, c->pos_slot + st.caller_off,
                            qx, qy, qz, csx + st.caller_off, csy + st.caller_off,
                            csz + st.caller_off);
-        hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
-                           c->pos_slot + st.caller_off, csx + st.caller_off, csy + st.caller_off,
-                           csz + st.caller_off, c->cell_int,
-                           d_start + cstart_off[s], d_rank + ro, d_cell + ro,
-                           d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, nullptr,
-                           nullptr, nullptr);
+        if (rows_path) {
+            const int wpb = 4;
+            hipLaunchKernelGGL(k_cell_rows, dim3(nblk(st.ncell, wpb)), dim3(wpb * kWave), 0, st_,
+                               (int32_t)st.ncell,
+                               st.caller_off, c->pos_slot, csx + st.caller_off,
+                               csy + st.caller_off, csz + st.caller_off,
+                               d_start + cstart_off[s], d_rank + ro, d_cell + ro, d_brick + ro,
+                               c->bricks, c->shell, grids[s], rc2, wcap, c->cnt, tq, th,
+                               row_overflow);
+        } else {
+            hipLaunchKernelGGL(k_neighbors<false>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
+                               c->pos_slot + st.caller_off, csx + st.caller_off,
+                               csy + st.caller_off, csz + st.caller_off, c->cell_int,
+                               d_start + cstart_off[s], d_rank + ro, d_cell + ro,
+                               d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, nullptr,
+                               nullptr, nullptr);
+        }
     }
     L2T_HIP(c, hipGetLastError());
     // ---- count order inside every brick --------------------------------------------
@@ -1074,6 +1231,10 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     if (!hw.empty())
         L2T_HIP(c, hipMemcpyAsync(hw.data(), dw, sizeof(int32_t) * hw.size(),
                                   hipMemcpyDeviceToHost, st_));
+    unsigned h_overflow = 0;
+    if (rows_path)
+        L2T_HIP(c, hipMemcpyAsync(&h_overflow, row_overflow, sizeof(unsigned),
+                                  hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
     std::vector<SliceInfo> hs(c->n_slices);
     int64_t total64 = 0, totalw64 = 0;
@@ -1121,16 +1282,24 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         L2T_HIP(c, hipMemcpyAsync(c->slices, hs.data(), sizeof(SliceInfo) * hs.size(),
                                   hipMemcpyHostToDevice, st_));
     // ---- tables and halo lists (device) ----------------------------------------------
-    for (int s = 0; s < S; ++s) {
-        SystemState &st = c->sys[s];
-        const int32_t n = st.desc.n_atoms;
-        const int64_t ro = lay[s].rank_off;
-        hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
-                           c->pos_slot + st.caller_off, csx + st.caller_off, csy + st.caller_off,
-                           csz + st.caller_off, c->cell_int,
-                           d_start + cstart_off[s], d_rank + ro, d_cell + ro,
-                           d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt, c->slices,
+    if (rows_path && h_overflow == 0) {
+        hipLaunchKernelGGL(k_cell_index, dim3(nblk(c->n_tot, 256)), dim3(256), 0, st_,
+                           c->pos_slot, c->n_tot, kof);
+        hipLaunchKernelGGL(k_rows_fill, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->n_int,
+                           c->perm, kof, c->cnt, c->slices, c->bricks, c->pos_slot, tq, th, wcap,
                            c->col, (uint16_t *)c->colw);
+    } else {
+        for (int s = 0; s < S; ++s) {
+            SystemState &st = c->sys[s];
+            const int32_t n = st.desc.n_atoms;
+            const int64_t ro = lay[s].rank_off;
+            hipLaunchKernelGGL(k_neighbors<true>, dim3(nblk(n, 128)), dim3(128), 0, st_, n,
+                               c->pos_slot + st.caller_off, csx + st.caller_off,
+                               csy + st.caller_off, csz + st.caller_off, c->cell_int,
+                               d_start + cstart_off[s], d_rank + ro, d_cell + ro,
+                               d_brick + ro, c->bricks, c->shell, grids[s], rc2, c->cnt,
+                               c->slices, c->col, (uint16_t *)c->colw);
+        }
     }
     hipLaunchKernelGGL(k_pad_rows, dim3(nblk(c->n_int, 256)), dim3(256), 0, st_, c->perm,
                        c->slices, c->bricks, c->n_int, c->col, (uint16_t *)c->colw);

@@ -117,7 +117,7 @@ struct GraphKey {
 constexpr int32_t kGraphChunk = 256;
 
 // grow-only temporary buffers of the neighbour build (tmp_buf slots)
-constexpr int kTmpSlots = 13;
+constexpr int kTmpSlots = 16;
 
 constexpr int kKernelSliced = 0;   // global gathers through the int32 table
 constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table

@@ -91,6 +91,44 @@ def test_neighbor_sets_equal_oracle(case):
     assert mean == pytest.approx(tot / sum(sy.n for sy in systems))
 
 
+def _rows_equal_oracle(ctx, systems, rc):
+    for s, sy in enumerate(systems):
+        row, col = L.l2t_get_neighbors(ctx.h, s, sy.n)
+        r0, c0 = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, rc)
+        assert np.array_equal(row, r0) and np.array_equal(col, c0)
+
+
+def test_neighbor_rows_past_the_learned_width_and_dense_cells():
+    """The one-search build writes rows into a table as wide as the previous
+    build's widest row plus a margin: a rebuild with a much larger cut-off
+    overflows it and takes the two-pass fill.  Cells of more than 64 atoms
+    take the thread-per-atom search.  Both give the oracle's sets, and the
+    brick tables drive the FP32C sub-steps to the oracle's trajectory."""
+    sy = W.c1(n_cells=6, n_substeps=50).systems[0]
+    ctx = L.Context([sy], L.L2T_FP32C)
+    L.l2t_set_positions(ctx.h, 0, sy.pos.reshape(-1))
+    for rc in (0.8 * W.A_LAT, 1.5 * W.A_LAT, 2.7 * W.A_LAT, 1.1 * W.A_LAT):
+        mx, _ = L.l2t_build_neighbors(ctx.h, rc)
+        _rows_equal_oracle(ctx, [sy], rc)
+    assert mx == 18
+    p = dict(sy.params, K=0.05)
+    L.l2t_set_params(ctx.h, 0, p)
+    L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TE, sy.T_e0)
+    L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_TL, sy.T_l)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, 1)
+    ctx.advance(50)
+    row, col = oracle_neighbors(sy, 1.1 * W.A_LAT)
+    T, _, _ = oracle.run(row, col, sy.T_e0, sy.T_l, p, 50)
+    assert max_rel(ctx.get(0), T) < 1e-5
+    ctx.close()
+    # dense: every cell of a 2.7a cut-off holds 108 atoms
+    ctx = L.Context([sy], L.L2T_FP64)
+    L.l2t_set_positions(ctx.h, 0, sy.pos.reshape(-1))
+    L.l2t_build_neighbors(ctx.h, 2.7 * W.A_LAT)
+    _rows_equal_oracle(ctx, [sy], 2.7 * W.A_LAT)
+    ctx.close()
+
+
 # ------------------------------------------------------------ lattice temperature ----
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_lattice_temperature_and_gate_equal_oracle(precision):
