@@ -70,6 +70,26 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Rank maps of one system's cells.  Bricks are ordered X, Y, Z and the cells
+// inside a brick x, y, z; a brick's extents are clipped at the grid's end, and
+// bc0 holds the first rank of every brick.
+__global__ void k_rank_maps(int64_t ncell, int32_t nc1, int32_t nc2, int32_t b0, int32_t b1,
+                            int32_t b2, int32_t nb1, int32_t nb2, const int32_t *bc0,
+                            int32_t brick0, int32_t *rank_of_cell, int32_t *cell_of_rank,
+                            int32_t *brick_of_rank) {
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= ncell) return;
+    const int32_t x = (int32_t)(cell / ((int64_t)nc1 * nc2));
+    const int32_t y = (int32_t)((cell / nc2) % nc1), z = (int32_t)(cell % nc2);
+    const int32_t X = x / b0, Y = y / b1, Z = z / b2;
+    const int32_t e1 = min(b1, nc1 - Y * b1), e2 = min(b2, nc2 - Z * b2);
+    const int32_t bidx = (X * nb1 + Y) * nb2 + Z;
+    const int32_t r = bc0[bidx] + ((x - X * b0) * e1 + (y - Y * b1)) * e2 + (z - Z * b2);
+    rank_of_cell[cell] = r;
+    cell_of_rank[r] = (int32_t)cell;
+    brick_of_rank[r] = brick0 + bidx;
+}
+
 // bin the atoms of one system (caller order); cell_of receives the cell's
 // rank in brick order
 __global__ void k_bin(const double *px, const double *py, const double *pz, int32_t n, Grid g,
@@ -397,6 +417,36 @@ __global__ __launch_bounds__(256) void k_cell_rows(
     if (tl == 0) {
         cnt[pos_slot[caller_off + k]] = len;
         if (len > wcap) atomicOr(overflow, 1u);
+    }
+}
+
+// sum and largest value of the per-slot neighbour counts (padding slots hold 0)
+__global__ __launch_bounds__(256) void k_count_stats(const int32_t *__restrict__ cnt, int64_t n,
+                                                     unsigned long long *__restrict__ sum,
+                                                     int32_t *__restrict__ mx) {
+    __shared__ unsigned long long bs[256];
+    __shared__ int32_t bm[256];
+    unsigned long long a = 0;
+    int32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = cnt[i];
+        a += (unsigned long long)v;
+        m = max(m, v);
+    }
+    bs[threadIdx.x] = a;
+    bm[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            bs[threadIdx.x] += bs[threadIdx.x + w];
+            bm[threadIdx.x] = max(bm[threadIdx.x], bm[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(sum, bs[0]);
+        atomicMax(mx, bm[0]);
     }
 }
 
@@ -760,8 +810,18 @@ struct SysLayout {
     int32_t b[3] = {1, 1, 1}, nb[3] = {1, 1, 1};
     int32_t nbrick = 0, brick0 = 0;
     int64_t rank_off = 0;                 // into the rank maps (sum of ncell)
-    std::vector<int32_t> rank_of_cell, cell_of_rank, brick_cell0;
+    std::vector<int32_t> brick_cell0;   // first rank of every brick (+ the total)
 };
+
+// rank of cell (x, y, z) in brick order (the formula of k_rank_maps)
+inline int32_t rank_of(const SysLayout &L, const int32_t nc[3], int32_t x, int32_t y, int32_t z) {
+    const int32_t X = x / L.b[0], Y = y / L.b[1], Z = z / L.b[2];
+    const int32_t e1 = std::min(L.b[1], nc[1] - Y * L.b[1]);
+    const int32_t e2 = std::min(L.b[2], nc[2] - Z * L.b[2]);
+    const int32_t bidx = (X * L.nb[1] + Y) * L.nb[2] + Z;
+    return L.brick_cell0[bidx] + ((x - X * L.b[0]) * e1 + (y - Y * L.b[1])) * e2 +
+           (z - Z * L.b[2]);
+}
 
 // Brick edge (cells), one for all systems of the context; along an axis with
 // fewer cells than the edge a brick spans the whole axis.  A brick's own
@@ -858,40 +918,23 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         cstart_off[s] = cells_total;
         st.cell_off = cells_total;
         cells_total += st.ncell + 1;
-        L.rank_of_cell.assign(st.ncell, 0);
-        L.cell_of_rank.assign(st.ncell, 0);
         L.brick_cell0.assign(L.nbrick + 1, 0);
         int32_t r = 0, bidx = 0;
         for (int32_t X = 0; X < L.nb[0]; ++X)
             for (int32_t Y = 0; Y < L.nb[1]; ++Y)
                 for (int32_t Z = 0; Z < L.nb[2]; ++Z, ++bidx) {
                     L.brick_cell0[bidx] = r;
-                    const int32_t o[3] = {X * L.b[0], Y * L.b[1], Z * L.b[2]};
-                    const int32_t e[3] = {std::min(L.b[0], st.nc[0] - o[0]),
-                                          std::min(L.b[1], st.nc[1] - o[1]),
-                                          std::min(L.b[2], st.nc[2] - o[2])};
-                    for (int32_t a = 0; a < e[0]; ++a)
-                        for (int32_t b2 = 0; b2 < e[1]; ++b2)
-                            for (int32_t z = 0; z < e[2]; ++z) {
-                                const int32_t cell =
-                                    ((o[0] + a) * st.nc[1] + (o[1] + b2)) * st.nc[2] + (o[2] + z);
-                                L.rank_of_cell[cell] = r;
-                                L.cell_of_rank[r] = cell;
-                                ++r;
-                            }
+                    r += std::min(L.b[0], st.nc[0] - X * L.b[0]) *
+                         std::min(L.b[1], st.nc[1] - Y * L.b[1]) *
+                         std::min(L.b[2], st.nc[2] - Z * L.b[2]);
                 }
         L.brick_cell0[L.nbrick] = r;
     }
-    // device copies of the rank maps
-    std::vector<int32_t> h_rank(ranks_total), h_cell(ranks_total), h_brick(ranks_total);
-    for (int s = 0; s < S; ++s) {
-        const SysLayout &L = lay[s];
-        std::copy(L.rank_of_cell.begin(), L.rank_of_cell.end(), h_rank.begin() + L.rank_off);
-        std::copy(L.cell_of_rank.begin(), L.cell_of_rank.end(), h_cell.begin() + L.rank_off);
-        for (int32_t b = 0; b < L.nbrick; ++b)
-            for (int32_t r = L.brick_cell0[b]; r < L.brick_cell0[b + 1]; ++r)
-                h_brick[L.rank_off + r] = L.brick0 + b;
-    }
+    // first ranks of every brick, for the device rank maps (system s at brick0 + s)
+    std::vector<int32_t> h_bc0((size_t)nbricks + S);
+    for (int s = 0; s < S; ++s)
+        std::copy(lay[s].brick_cell0.begin(), lay[s].brick_cell0.end(),
+                  h_bc0.begin() + lay[s].brick0 + s);
     // grow-only temporaries owned by the context (kept for the next build)
     int32_t *d_rank = tmp_of<int32_t>(c, 0, ranks_total);
     int32_t *d_cell = tmp_of<int32_t>(c, 1, ranks_total);
@@ -900,12 +943,19 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     int32_t *d_start = tmp_of<int32_t>(c, 4, cells_total);
     if (!d_rank || !d_cell || !d_brick || !d_count || !d_start)
         return fail(c, L2T_ENOMEM, "neighbour build scratch allocation failed");
-    L2T_HIP(c, hipMemcpyAsync(d_rank, h_rank.data(), sizeof(int32_t) * ranks_total,
+    // the brick starts go through d_count, which binning clears and reuses after
+    // the rank maps are written (cells_total >= nbricks + S)
+    L2T_HIP(c, hipMemcpyAsync(d_count, h_bc0.data(), sizeof(int32_t) * h_bc0.size(),
                               hipMemcpyHostToDevice, st_));
-    L2T_HIP(c, hipMemcpyAsync(d_cell, h_cell.data(), sizeof(int32_t) * ranks_total,
-                              hipMemcpyHostToDevice, st_));
-    L2T_HIP(c, hipMemcpyAsync(d_brick, h_brick.data(), sizeof(int32_t) * ranks_total,
-                              hipMemcpyHostToDevice, st_));
+    for (int s = 0; s < S; ++s) {
+        const SystemState &st = c->sys[s];
+        const SysLayout &L = lay[s];
+        hipLaunchKernelGGL(k_rank_maps, dim3(nblk(st.ncell, 256)), dim3(256), 0, st_,
+                           (int64_t)st.ncell, st.nc[1], st.nc[2], L.b[0], L.b[1], L.b[2], L.nb[1],
+                           L.nb[2], d_count + L.brick0 + s, L.brick0, d_rank + L.rank_off,
+                           d_cell + L.rank_off, d_brick + L.rank_off);
+    }
+    L2T_HIP(c, hipGetLastError());
     L2T_HIP(c, hipMemsetAsync(c->derr, 0, sizeof(unsigned), st_));
     // ---- binning in brick order (device) -------------------------------------------
     std::vector<Grid> grids(S);
@@ -1068,7 +1118,7 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                             seen.push_back(cell);
                             seen.push_back(bi.n_halo);
                         }
-                        const int32_t rk = L.rank_of_cell[cell];
+                        const int32_t rk = rank_of(L, st.nc, cv[0][p0], cv[1][p1], cv[2][p2]);
                         HaloCell h;
                         h.brick = gb;
                         h.start_index = (int32_t)(cstart_off[s] + rk);
@@ -1222,7 +1272,9 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         L2T_HIP(c, hipStreamSynchronize(st_));
     }
     // ---- slice widths -> column offsets (host scan) -------------------------------
-    int32_t *dw = tmp_of<int32_t>(c, 10, 2 * (int64_t)c->n_slices + 2);
+    // slice widths and valid lanes, then (8-byte aligned) the count statistics
+    const int64_t stat_at = (2 * (int64_t)c->n_slices + 1) / 2 * 2;
+    int32_t *dw = tmp_of<int32_t>(c, 10, stat_at + 4);
     if (!dw) return fail(c, L2T_ENOMEM, "slice width allocation failed");
     hipLaunchKernelGGL(k_slice_width, dim3(nblk(c->n_slices, 256)), dim3(256), 0, st_, c->cnt,
                        c->perm, c->n_slices, dw, dw + c->n_slices);
@@ -1309,17 +1361,19 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
                            c->pos_slot, c->halo);
     L2T_HIP(c, hipGetLastError());
     // ---- statistics ----------------------------------------------------------------------
-    std::vector<int32_t> hc(c->n_int);
-    if (!hc.empty())
-        L2T_HIP(c, hipMemcpyAsync(hc.data(), c->cnt, sizeof(int32_t) * hc.size(),
-                                  hipMemcpyDeviceToHost, st_));
+    unsigned long long *dsum = reinterpret_cast<unsigned long long *>(dw + stat_at);
+    int32_t *dmax = dw + stat_at + 2;
+    L2T_HIP(c, hipMemsetAsync(dw + stat_at, 0, 4 * sizeof(int32_t), st_));
+    hipLaunchKernelGGL(k_count_stats, dim3(std::max<unsigned>(1, std::min<unsigned>(1024, nblk(c->n_int, 256)))),
+                       dim3(256), 0, st_, c->cnt, (int64_t)c->n_int, dsum, dmax);
+    L2T_HIP(c, hipGetLastError());
+    int32_t hstat[4] = {0, 0, 0, 0};
+    L2T_HIP(c, hipMemcpyAsync(hstat, dw + stat_at, sizeof hstat, hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
-    int64_t sum = 0;
-    int32_t mx = 0;
-    for (int32_t v : hc) {
-        sum += v;
-        mx = std::max(mx, v);
-    }
+    unsigned long long usum = 0;
+    std::memcpy(&usum, hstat, sizeof usum);
+    const int64_t sum = (int64_t)usum;
+    const int32_t mx = hstat[2];
     c->max_nbrs = mx;
     c->mean_nbrs = c->n_tot > 0 ? (double)sum / (double)c->n_tot : 0.0;
     c->mean_width = c->n_tot > 0 ? (double)total64 * kWave / (double)c->n_tot : 0.0;
