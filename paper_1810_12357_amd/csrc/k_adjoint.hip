@@ -31,33 +31,41 @@ namespace {
 using namespace dev;
 
 // f and d1f of one pair from FP32 temperatures.  With d = theta_j - theta_k,
-// m = (theta_k + theta_j)/2, u = d^2, C(u) = cosh d and Q(u) = sinh(d)/d,
-//   f   = d [C - (u/2 + 2m(1-m)) Q]                 (the pair term of Eq. 2)
-//   d1f = -[(1 - 2m(1-m) - u/2) C + (1 - 2m) d Q]    (its derivative in theta_k)
-// so both come from one evaluation of C and Q.  f is returned in temperature
-// units (span * f), as the forward sums it.  The series run to u^5 (the
-// dropped terms are below 3e-9 for |d| <= 1); one straight-line form for
-// every pair measured faster than branching to shorter series for small u.
-__device__ __forceinline__ void pair_adj(float Tk, float Tj, const PairK &pk, float inv_span,
-                                         float &f, float &d1) {
+// u = d^2, s = 1 - 2m = 1 - theta_k - theta_j, C(u) = cosh d and
+// Q(u) = sinh(d)/d, and since 2m(1-m) = (1 - s^2)/2, e = u - s^2 gives
+//   f   = d [C - (u/2 + 2m(1-m)) Q]                 = d [C - (1 + e)/2 Q]
+//   d1f = -[(1 - 2m(1-m) - u/2) C + (1 - 2m) d Q]   = -[(1 - e)/2 C + s d Q]
+// (f is the pair term of Eq. 2, d1f its derivative in theta_k), so both come
+// from one evaluation of C and Q.  f is returned in temperature units
+// (span * f), as the forward sums it.  sk = s + T_j/span is the lane's own
+// part of s.  C runs to u^5 and Q to u^4: for |d| <= 1 the dropped terms are
+// below 3e-9 and 3e-8 (half an FP32 ulp of Q >= 1 is 6e-8).  One
+// straight-line form for every pair measured faster than branching to shorter
+// series for small u.
+__device__ __forceinline__ float adj_sk(float Tk, const PairK &pk, float inv_span) {
+    // theta = T/span + moff with moff = -T_min/span, so
+    // s + T_j/span = 1 - 2 moff - T_k/span
+    return fmaf(Tk, -inv_span, fmaf(-2.0f, pk.moff, 1.0f));
+}
+
+__device__ __forceinline__ void pair_adj(float Tk, float Tj, float sk, float inv_span, float &f,
+                                         float &d1) {
     const float dT = Tj - Tk;
-    const float m = fmaf(Tk + Tj, pk.hinv, pk.moff);
-    const float a = fmaf(-m, m, m);
     const float d = dT * inv_span;
     const float u = d * d;
+    const float s = fmaf(Tj, -inv_span, sk);
+    const float e = fmaf(-s, s, u);
     float C = fmaf(u, 1.0f / 3628800.0f, 1.0f / 40320.0f);
     C = fmaf(u, C, 1.0f / 720.0f);
     C = fmaf(u, C, 1.0f / 24.0f);
     C = fmaf(u, C, 0.5f);
     C = fmaf(u, C, 1.0f);
-    float Q = fmaf(u, 1.0f / 39916800.0f, 1.0f / 362880.0f);
-    Q = fmaf(u, Q, 1.0f / 5040.0f);
+    float Q = fmaf(u, 1.0f / 362880.0f, 1.0f / 5040.0f);
     Q = fmaf(u, Q, 1.0f / 120.0f);
     Q = fmaf(u, Q, 1.0f / 6.0f);
     Q = fmaf(u, Q, 1.0f);
-    const float hu = 0.5f * u;
-    f = dT * fmaf(-fmaf(2.0f, a, hu), Q, C);
-    d1 = -fmaf(fmaf(-2.0f, a, 1.0f) - hu, C, fmaf(-2.0f, m, 1.0f) * (d * Q));
+    f = dT * fmaf(-fmaf(e, 0.5f, 0.5f), Q, C);
+    d1 = -fmaf(fmaf(e, -0.5f, 0.5f), C, (s * d) * Q);
 }
 
 struct AdjGrad {
@@ -117,11 +125,12 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
     const float lk = lam[slot];
     const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
     const PairK pk = pair_consts(p);
+    const float sk = adj_sk(Tk, pk, p.f_inv_span);
     double S = 0.0, D = 0.0;
     for (int32_t q = 0; q < si.width; ++q) {
         const int32_t j = cp[q * kWave];
         float f, d1;
-        pair_adj(Tk, Thi[j], pk, p.f_inv_span, f, d1);
+        pair_adj(Tk, Thi[j], sk, p.f_inv_span, f, d1);
         S += (double)f;
         D += (double)(d1 * (lk - lam[j]));
     }
@@ -135,16 +144,18 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
 }
 
 // LDS-brick form: one workgroup per brick stages T^n and lambda^{n+1} of the
-// brick's slots and of its halo list in two tiles of tile_max floats; the
-// slices then read both through the uint16 table (the byte offset of atom j
-// in the T tile; lambda_j sits tile_max floats further).  Same terms in the
-// same order as k_adjoint_step, so lambda is bitwise equal; the gradient
-// terms are summed per lane over the wave's slices and added once per wave
-// to the row of its first slice.
+// brick's slots and of its halo list in two tiles; the slices then read both
+// through the uint16 table (the byte offset of atom j in the T tile; lambda_j
+// sits LAM floats further, a constant multiple of 64 floats, so the two reads
+// of a neighbour are one two-address LDS instruction on one vector address).
+// Same terms in the same order as k_adjoint_step, so lambda is bitwise equal;
+// the gradient terms are summed per lane over the wave's slices and added
+// once per wave to the row of its first slice.
+template <int LAM>
 __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
     const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
     const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
-    const int32_t *__restrict__ halo, int32_t tile_max, const float *__restrict__ Thi,
+    const int32_t *__restrict__ halo, const float *__restrict__ Thi,
     const float *__restrict__ Tl, const float *__restrict__ srcw, const DevParams *__restrict__ P,
     const int64_t *__restrict__ dstep, int32_t rel, const float *__restrict__ lam,
     float *__restrict__ lam_n, float *__restrict__ lam_lo, double *__restrict__ grad) {
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
     const BrickInfo bi = bricks[list[logical]];
-    float *lt = tile + tile_max;
+    float *lt = tile + LAM;
     const int32_t B = blockDim.x;
     constexpr int U = 8;
     for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
@@ -199,7 +210,6 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
     const int64_t step = dstep[bi.sys] + rel;
     const PairK pk = pair_consts(p);
     const char *tb = reinterpret_cast<const char *>(tile);
-    const char *lb = reinterpret_cast<const char *>(lt);
     double gK = 0.0, gG = 0.0;
     for (int32_t q = wave; q < ns; q += nw) {
         const int32_t sl = bi.slice0 + q;
@@ -209,13 +219,14 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
         const int32_t slot = sl * kWave + lane;
         const float Tk = tile[q * kWave + lane];
         const float lk = lt[q * kWave + lane];
+        const float sk = adj_sk(Tk, pk, p.f_inv_span);
         const uint32_t *row = colw + (int64_t)base * kWave + lane;
         double S = 0.0, D = 0.0;
         auto term = [&](uint32_t off) {
             const float Tj = *reinterpret_cast<const float *>(tb + off);
-            const float lj = *reinterpret_cast<const float *>(lb + off);
+            const float lj = *reinterpret_cast<const float *>(tb + off + 4 * LAM);
             float f, d1;
-            pair_adj(Tk, Tj, pk, p.f_inv_span, f, d1);
+            pair_adj(Tk, Tj, sk, p.f_inv_span, f, d1);
             S += (double)f;
             D += (double)(d1 * (lk - lj));
         };
@@ -354,12 +365,14 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
     hipLaunchKernelGGL(k_zero_d, dim3(nblk(3 * NS, 256)), dim3(256), 0, s_, led, (int64_t)(3 * NS));
     const dim3 g(nblk(NS, 4)), b(256);
     // the brick forms when the tuned forward is the brick kernel and both
-    // tiles of the reverse step fit in 64 KB of LDS
+    // tiles of the reverse step fit in 64 KB of LDS: the lambda tile starts
+    // 4096 or 8192 floats after the T tile
     const bool brick = c->tune.kernel == kKernelBrick && c->n_brick_list > 0 &&
                        c->tile_max <= 8192;
+    const bool lam_near = c->tile_max <= 4096;
     const int bblock = std::min(std::max(c->tune.block, kWave), kBrickBlockMax);
     const unsigned bgrid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
-    const size_t blds = 2 * sizeof(float) * (size_t)c->tile_max;
+    const size_t blds = sizeof(float) * ((lam_near ? 4096 : 8192) + (size_t)c->tile_max);
     std::vector<int64_t> htab(nck * S);
     for (size_t k = 0; k < nck; ++k)
         for (size_t q = 0; q < S; ++q) htab[k * S + q] = r.step0[q] + (int64_t)k * C;
@@ -388,10 +401,11 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
         for (int32_t m = L - 1; m >= 0; --m) {
             const float *Tst = seg + (size_t)m * 2 * NI;
             if (brick)
-                hipLaunchKernelGGL(k_adjoint_brick, dim3(bgrid), dim3(bblock), blds, c->stream,
-                                   c->bricks, c->brick_list, c->n_brick_list, c->slices, c->colw,
-                                   c->halo, c->tile_max, Tst, c->Tl32, c->srcw32, c->dparams, dst,
-                                   m, lam[lc2], lam[lc2 ^ 1], lamlo, grad);
+                hipLaunchKernelGGL(lam_near ? k_adjoint_brick<4096> : k_adjoint_brick<8192>,
+                                   dim3(bgrid), dim3(bblock), blds, c->stream, c->bricks,
+                                   c->brick_list, c->n_brick_list, c->slices, c->colw, c->halo,
+                                   Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc2],
+                                   lam[lc2 ^ 1], lamlo, grad);
             else
                 hipLaunchKernelGGL(k_adjoint_step, g, b, 0, c->stream, c->slices, c->n_slices,
                                    c->col, Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc2],
