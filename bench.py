@@ -353,17 +353,31 @@ def bench_c3_fp64(L, torch, w, n_sub=100):
     return dict(substeps=n_sub, substep_us=us, atom_substeps_per_s=sy.n / (us * 1e-6))
 
 
-def cpu_baseline(sy, r_cut, n_steps):
+def cpu_baseline(L, torch, w, n_steps):
+    """The FP64 oracle on the host cores over the first n_steps sub-steps of
+    the 4M-atom system, and the FP32C library's T_e error against it after the
+    same sub-steps (a fresh context from the same initial state)."""
     import oracle
-    row, col = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, r_cut)
+    sy = w.systems[0]
+    row, col = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, w.r_cut)
     Tl, gated = oracle.lattice_temperature(row, col, sy.vel, sy.mass, sy.params["ke_eps"])
     t0 = time.perf_counter()
-    oracle.run(row, col, sy.T_e0, Tl, sy.params, n_steps, gated=gated)
+    T_ref, _, _ = oracle.run(row, col, sy.T_e0, Tl, sy.params, n_steps, gated=gated)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    ctx = L.Context(w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.setup(w.r_cut)
+    ctx.advance(n_steps)
+    T = ctx.get(0)
+    ctx.close()
+    rel = np.abs(T - T_ref) / np.abs(T_ref)
+    log(f"  FP32C vs FP64 oracle after {n_steps} sub-steps: max rel {rel.max():.2e}")
     return dict(value=sy.n * n_steps / dt, unit="atom-substeps/s", cores=cores, kind="oracle",
                 sample=f"FP64 oracle, same 4,000,000-atom system, {n_steps} sub-steps "
-                       f"({dt:.1f} s), neighbour build not timed")
+                       f"({dt:.1f} s), neighbour build not timed",
+                fp32c_vs_oracle=dict(substeps=n_steps, max_rel_err=float(rel.max()),
+                                     mean_rel_err=float(rel.mean()), tolerance=1e-5,
+                                     T_e_changed_max=float(np.max(np.abs(T_ref - sy.T_e0)))))
 
 
 def main():
@@ -506,7 +520,7 @@ def main():
         out["adjoint"] = bench_adjoint(L, torch)
     if not args.no_cpu:
         log("CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(sy, w.r_cut, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(L, torch, w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 
