@@ -38,7 +38,10 @@ __global__ __launch_bounds__(256) void k_step_fp64(const SliceInfo *slices, int3
                                                    const DevParams *P,
                                                    const int64_t *dstep, int32_t rel,
                                                    double *ledger, double *eatom, unsigned *err) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // the wave index is uniform: slice record, row width and loop bounds sit in
+    // scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
     const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
     if (q >= n_slices) return;
     const int32_t sl = slice0 + q;

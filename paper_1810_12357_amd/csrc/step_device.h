@@ -147,11 +147,28 @@ __device__ __forceinline__ Fp64Lane lane_step_fp64(const SliceInfo &si, int lane
         r.tl_new = tli + p.dt * (p.K_lat * Lsum + p.g_over_clat * (Ti - tli));
     }
     const double ti = (Ti - p.T_min) * p.inv_span;
+    // the literal pair term of Eq. 2 in theta units
+    auto pair = [&](double Tj) {
+        const double tj = (Tj - p.T_min) * p.inv_span;
+        return tj * (1.0 - ti) * exp(ti - tj) - ti * (1.0 - tj) * exp(tj - ti);
+    };
+    // neighbours in chunks of 8: the chunk's references, then its temperatures,
+    // are requested before any term is evaluated, so 8 loads are in flight
+    // where the plain loop has one; terms are added in row order either way
+    constexpr int kChunk = 8;
     double S = 0.0;
-    for (int32_t k = 0; k < si.width; ++k) {
-        const double tj = (T_of(col[base + (int64_t)k * kWave]) - p.T_min) * p.inv_span;
-        S += tj * (1.0 - ti) * exp(ti - tj) - ti * (1.0 - tj) * exp(tj - ti);
+    int32_t k = 0;
+    for (; k + kChunk <= si.width; k += kChunk) {
+        int32_t j[kChunk];
+        double Tj[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) j[u] = col[base + (int64_t)(k + u) * kWave];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) Tj[u] = T_of(j[u]);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) S += pair(Tj[u]);
     }
+    for (; k < si.width; ++k) S += pair(T_of(col[base + (int64_t)k * kWave]));
     if (valid) {
         const double c = ce64(p, Ti);
         const double coup = (signbit(tl_i) && !p.lat_fd) ? 0.0 : p.g * (Ti - fabs(tl_i));
