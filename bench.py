@@ -113,9 +113,12 @@ def bench_c4_speedup(L, torch, n_sub):
     w = W.c4()
     n_atoms = w.n_atoms
     out = {}
+    edge = 0
     for name, prec in (("fp32c_batched", L.L2T_FP32C), ("fp64_plain", L.L2T_FP64)):
         ctx = L.Context(w.systems, prec)
         ctx.setup(w.r_cut)
+        if prec == L.L2T_FP32C:
+            edge = L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE)
         ctx.advance(2)                 # warm-up (autotune, graph capture)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -130,7 +133,7 @@ def bench_c4_speedup(L, torch, n_sub):
                          f"{n_sub} sub-steps",
                 fp32c_batched_atom_substeps_per_s=out["fp32c_batched"],
                 fp64_plain_atom_substeps_per_s=out["fp64_plain"],
-                speedup=out["fp32c_batched"] / out["fp64_plain"])
+                speedup=out["fp32c_batched"] / out["fp64_plain"], brick_edge=edge)
 
 
 def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):

@@ -12,7 +12,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <string>
 #include <unordered_map>
 #include <thread>
 #include <vector>
@@ -877,7 +880,8 @@ int32_t brick_edge(const l2t_ctx *c, int32_t limit) {
 
 }  // namespace
 
-int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *tile_overflow) {
+int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forced,
+                         bool *tile_overflow) {
     const int S = (int)c->sys.size();
     const hipStream_t st_ = c->stream;
     *tile_overflow = false;
@@ -900,7 +904,8 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
         if (st.ncell > (int64_t)1 << 28) return fail(c, L2T_EINVAL, "cell grid too large");
     }
     const int32_t be = c->tune.brick_edge > 0 ? std::min(c->tune.brick_edge, edge_limit)
-                                              : brick_edge(c, edge_limit);
+                       : forced                 ? edge_limit
+                                                : brick_edge(c, edge_limit);
     c->brick_edge_used = be;
     for (int s = 0; s < S; ++s) {
         SystemState &st = c->sys[s];
@@ -1381,12 +1386,15 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool *til
     return L2T_OK;
 }
 
-int build_neighbors(l2t_ctx *c, double r_cut) {
-    int32_t limit = kMaxBrickEdge;
+namespace {
+
+// one layout at brick edge `force` (0: the edge model's choice)
+int build_layout(l2t_ctx *c, double r_cut, int32_t force) {
+    int32_t limit = force > 0 ? force : kMaxBrickEdge;
     c->brick_edge_used = 0;
     for (int attempt = 0; attempt < 12; ++attempt) {
         bool overflow = false;
-        int rc = build_neighbors_once(c, r_cut, limit, &overflow);
+        int rc = build_neighbors_once(c, r_cut, limit, force > 0, &overflow);
         if (rc != L2T_OK) return rc;
         if (!overflow) return L2T_OK;
         // a tile overflowed its LDS cap: retry below the edge that was used
@@ -1396,6 +1404,82 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         limit = used / 2;
     }
     return fail(c, L2T_EINVAL, "atom density too high for the LDS tile of one cell and its halo");
+}
+
+// measured brick edges, per problem shape (cut-off and every system's atom
+// count, box and boundaries), for the life of the process
+std::map<std::string, int32_t> &edge_cache() {
+    static std::map<std::string, int32_t> m;
+    return m;
+}
+
+std::string edge_key(const l2t_ctx *c, double r_cut) {
+    std::string k;
+    char buf[192];
+    std::snprintf(buf, sizeof buf, "rc=%a cu=%d", r_cut, c->n_cu);
+    k += buf;
+    for (const SystemState &st : c->sys) {
+        std::snprintf(buf, sizeof buf, "|%d %a %a %a %d%d%d", st.desc.n_atoms, st.desc.box_len[0],
+                      st.desc.box_len[1], st.desc.box_len[2], st.desc.periodic[0],
+                      st.desc.periodic[1], st.desc.periodic[2]);
+        k += buf;
+    }
+    return k;
+}
+
+}  // namespace
+
+// The brick edge of an FP32C context with at least as many bricks as the GPU
+// has CUs is measured, not only modelled: the model's edge and its two
+// neighbours are built and each runs a short probe of the brick kernel
+// (brick_probe), and a neighbour replaces the model's edge when it is more
+// than 1 % faster.  The winner is kept per problem shape, so later builds of
+// the same shape build once.  Smaller layouts, FP64 contexts, a pinned edge
+// or launch form and a disabled autotuner keep the model's edge.
+int build_neighbors(l2t_ctx *c, double r_cut) {
+    const bool may_tune = c->precision == L2T_FP32C && c->tune.autotune && !c->tune.pinned &&
+                          c->tune.brick_edge == 0;
+    const std::string key = may_tune ? edge_key(c, r_cut) : std::string();
+    if (may_tune) {
+        auto it = edge_cache().find(key);
+        if (it != edge_cache().end()) return build_layout(c, r_cut, it->second);
+    }
+    int rc = build_layout(c, r_cut, 0);
+    if (rc != L2T_OK || !may_tune) return rc;
+    const int32_t e0 = c->brick_edge_used;
+    if (c->n_brick_list < std::max(1, c->n_cu)) {
+        edge_cache()[key] = e0;
+        return L2T_OK;
+    }
+    // an edge above e0 changes the layout only where some axis is longer than e0
+    bool grows = false;
+    for (const SystemState &st : c->sys)
+        for (int d = 0; d < 3; ++d) grows |= st.nc[d] > e0;
+    constexpr int32_t kProbe = 12;
+    float best_ms = 0.0f;
+    rc = brick_probe(c, kProbe, &best_ms);
+    if (rc != L2T_OK) return rc;
+    int32_t best = e0, built = e0;
+    for (const int32_t e : {e0 - 1, e0 + 1}) {
+        if (e < 1 || (e > e0 && !grows)) continue;
+        rc = build_layout(c, r_cut, e);
+        if (rc != L2T_OK) return rc;
+        built = c->brick_edge_used;
+        if (built != e) continue;   // its tiles overflowed: a smaller edge was built
+        float ms = 0.0f;
+        rc = brick_probe(c, kProbe, &ms);
+        if (rc != L2T_OK) return rc;
+        if (ms < 0.99f * best_ms) {
+            best_ms = ms;
+            best = e;
+        }
+    }
+    if (built != best) {
+        rc = build_layout(c, r_cut, best);
+        if (rc != L2T_OK) return rc;
+    }
+    edge_cache()[key] = best;
+    return L2T_OK;
 }
 
 int permute_in(l2t_ctx *c, int32_t sys, const double *src_dev, int32_t field) {

@@ -300,6 +300,11 @@ __global__ void k_bump(int64_t *dstep, int32_t s0, int32_t s1, int32_t n) {
     if (s < s1) dstep[s] += n;
 }
 
+__global__ void k_fill_f32(float *p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_zero_f64(double *p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
@@ -382,62 +387,65 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+// kernel parameter block of one system (its parameters, layout and modes)
+DevParams dev_params_of(const SystemState &st) {
+    const l2t_params &q = st.params;
+    DevParams p{};
+    p.T_min = q.T_min;
+    p.span = q.T_max - q.T_min;
+    p.inv_span = 1.0 / p.span;
+    p.K = q.K;
+    p.A = p.span * q.K;
+    p.dt = q.dt;
+    p.g = q.g;
+    p.ce_const = q.ce_const;
+    p.gamma = q.gamma;
+    p.ce_cap = q.ce_cap;
+    p.ce_model = q.ce_model;
+    p.laser_on = q.laser_on;
+    p.lp = q.laser_lp;
+    p.t0 = q.laser_t0;
+    p.sigma = q.laser_sigma;
+    p.inv_sigma = q.laser_on ? 1.0 / q.laser_sigma : 0.0;
+    p.x0 = q.laser_x0;
+    p.i0 = q.laser_on ? q.laser_fluence * q.v_atom /
+                            (q.laser_lp * std::sqrt(2.0 * M_PI) * q.laser_sigma)
+                      : 0.0;
+    p.atom_off = st.atom_off;
+    p.n_pad = st.n_pad;
+    p.slice0 = st.slice0;
+    p.n_slices = st.n_slices;
+    p.f_inv_span = (float)p.inv_span;
+    p.f_half_inv_span = (float)(0.5 * p.inv_span);
+    p.f_m_off = (float)(-q.T_min * p.inv_span);
+    p.f_A = (float)p.A;
+    p.f_K = (float)q.K;
+    p.f_dt = (float)q.dt;
+    p.f_g = (float)q.g;
+    p.f_ce_const = (float)q.ce_const;
+    p.f_gamma = (float)q.gamma;
+    p.f_ce_cap = (float)q.ce_cap;
+    p.f_T_min = (float)q.T_min;
+    p.f_T_max = (float)q.T_max;
+    p.f_i0 = (float)p.i0;
+    p.f_inv2 = (float)(p.inv_span * p.inv_span);
+    p.f_c_tiny = (float)(-p.inv_span * p.inv_span / 3.0);
+    p.f_w_tiny = (float)((double)dev::kUTiny * p.span * p.span);
+    p.has_fixed = st.has_fixed ? 1 : 0;
+    p.mean_field = st.mf.on ? 1 : 0;
+    p.n_atoms = st.desc.n_atoms;
+    p.mf_lambda = st.mf.lambda;
+    p.mf_kcoef = st.mf.k_coef;
+    p.lat_fd = st.lf.on ? 1 : 0;
+    p.K_lat = st.lf.K_lat;
+    p.g_over_clat = st.lf.on ? q.g / st.lf.c_lat : 0.0;
+    return p;
+}
+
 int upload_params(l2t_ctx *c) {
     const int S = (int)c->sys.size();
     c->hparams.assign(S, DevParams{});
-    for (int s = 0; s < S; ++s) {
-        const SystemState &st = c->sys[s];
-        const l2t_params &q = st.params;
-        DevParams &p = c->hparams[s];
-        p.T_min = q.T_min;
-        p.span = q.T_max - q.T_min;
-        p.inv_span = 1.0 / p.span;
-        p.K = q.K;
-        p.A = p.span * q.K;
-        p.dt = q.dt;
-        p.g = q.g;
-        p.ce_const = q.ce_const;
-        p.gamma = q.gamma;
-        p.ce_cap = q.ce_cap;
-        p.ce_model = q.ce_model;
-        p.laser_on = q.laser_on;
-        p.lp = q.laser_lp;
-        p.t0 = q.laser_t0;
-        p.sigma = q.laser_sigma;
-        p.inv_sigma = q.laser_on ? 1.0 / q.laser_sigma : 0.0;
-        p.x0 = q.laser_x0;
-        p.i0 = q.laser_on ? q.laser_fluence * q.v_atom /
-                                (q.laser_lp * std::sqrt(2.0 * M_PI) * q.laser_sigma)
-                          : 0.0;
-        p.atom_off = st.atom_off;
-        p.n_pad = st.n_pad;
-        p.slice0 = st.slice0;
-        p.n_slices = st.n_slices;
-        p.f_inv_span = (float)p.inv_span;
-        p.f_half_inv_span = (float)(0.5 * p.inv_span);
-        p.f_m_off = (float)(-q.T_min * p.inv_span);
-        p.f_A = (float)p.A;
-        p.f_K = (float)q.K;
-        p.f_dt = (float)q.dt;
-        p.f_g = (float)q.g;
-        p.f_ce_const = (float)q.ce_const;
-        p.f_gamma = (float)q.gamma;
-        p.f_ce_cap = (float)q.ce_cap;
-        p.f_T_min = (float)q.T_min;
-        p.f_T_max = (float)q.T_max;
-        p.f_i0 = (float)p.i0;
-        p.f_inv2 = (float)(p.inv_span * p.inv_span);
-        p.f_c_tiny = (float)(-p.inv_span * p.inv_span / 3.0);
-        p.f_w_tiny = (float)((double)dev::kUTiny * p.span * p.span);
-        p.has_fixed = st.has_fixed ? 1 : 0;
-        p.mean_field = st.mf.on ? 1 : 0;
-        p.n_atoms = st.desc.n_atoms;
-        p.mf_lambda = st.mf.lambda;
-        p.mf_kcoef = st.mf.k_coef;
-        p.lat_fd = st.lf.on ? 1 : 0;
-        p.K_lat = st.lf.K_lat;
-        p.g_over_clat = st.lf.on ? q.g / st.lf.c_lat : 0.0;
-    }
+    for (int s = 0; s < S; ++s) c->hparams[s] = dev_params_of(c->sys[s]);
     // mean-field chunk table: every system in the mode, in order, its slices in
     // chunks of kMfChunk
     std::vector<MfChunk> &chunks = c->h_mf_chunks;
@@ -802,6 +810,92 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
     hipLaunchKernelGGL(k_bump, dim3(nblk((int64_t)c->sys.size(), 256)), dim3(256), 0, c->stream,
                        c->dstep, 0, (int32_t)c->sys.size(), n);
     L2T_HIP(c, hipGetLastError());
+    return L2T_OK;
+}
+
+// Time n sub-steps of the brick kernel on the current layout from a uniform
+// stand-in state held in scratch memory (1,000 K, no coupling, no source), so
+// the brick edge can be measured before any field of the new layout is
+// written.  The context's state, ledger, step counters and error word are not
+// touched.  *ms receives the faster of two timed runs.
+int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
+    *ms = 0.0f;
+    const size_t NI = (size_t)c->n_int, NS = (size_t)c->n_slices, S = c->sys.size();
+    if (c->n_brick_list == 0 || NI == 0 || n < 1) return L2T_OK;
+    const size_t fb = sizeof(float) * NI;
+    const size_t bytes = 4 * fb + sizeof(DevParams) * S + sizeof(double) * 3 * NS +
+                         sizeof(int64_t) * S + sizeof(unsigned) + 8 * 256;
+    if (ensure_scratch(c, bytes) != L2T_OK) return L2T_ENOMEM;
+    char *q = (char *)c->scratch;
+    auto take = [&](size_t b) {
+        char *r = q;
+        q += (b + 255) / 256 * 256;
+        return r;
+    };
+    float *Ta = (float *)take(fb), *Tb = (float *)take(fb), *zl = (float *)take(fb);
+    float *tl = (float *)take(fb);
+    DevParams *P = (DevParams *)take(sizeof(DevParams) * S);
+    double *led = (double *)take(sizeof(double) * 3 * NS);
+    int64_t *stp = (int64_t *)take(sizeof(int64_t) * S);
+    unsigned *perr = (unsigned *)take(sizeof(unsigned));
+    std::vector<DevParams> hp(S);
+    for (size_t s = 0; s < S; ++s) {
+        SystemState st = c->sys[s];
+        st.params = l2t_params{};
+        st.params.T_min = 0.0;
+        st.params.T_max = 2.0e4;
+        st.params.K = 1.0;
+        st.params.dt = 0.05;
+        st.params.ce_model = L2T_CE_CONST;
+        st.params.ce_const = 1.0e-4;
+        st.has_fixed = false;
+        st.mf.on = 0;
+        st.lf.on = 0;
+        hp[s] = dev_params_of(st);
+    }
+    const hipStream_t s_ = c->stream;
+    L2T_HIP(c, hipMemcpyAsync(P, hp.data(), sizeof(DevParams) * S, hipMemcpyHostToDevice, s_));
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, Ta, (int64_t)NI,
+                       1000.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, zl, (int64_t)NI,
+                       0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, tl, (int64_t)NI,
+                       1000.0f);
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblk((int64_t)(3 * NS), 256)), dim3(256), 0, s_, led,
+                       (int64_t)(3 * NS));
+    L2T_HIP(c, hipMemsetAsync(stp, 0, sizeof(int64_t) * S, s_));
+    L2T_HIP(c, hipMemsetAsync(perr, 0, sizeof(unsigned), s_));
+    L2T_HIP(c, hipGetLastError());
+    hipEvent_t e0, e1;
+    L2T_HIP(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(c, hipErrorOutOfMemory, "hipEventCreate");
+    }
+    const unsigned grid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
+    const size_t lds = sizeof(float) * (size_t)c->tile_max;
+    float best = 1e30f;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        (void)hipEventRecord(e0, s_);
+        // T^lat and the source weight both read the constant 1,000 K buffer
+        // (a positive weight marks no atom as held); T_lo is updated in place
+        for (int32_t k = 0; k < n; ++k)
+            hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(kBrickBlockMax), lds, s_,
+                               c->bricks, c->brick_list, c->n_brick_list, c->slices, c->colw,
+                               c->halo, (k & 1) ? Tb : Ta, (k & 1) ? Ta : Tb, nullptr, zl, tl, tl,
+                               P, stp, k, led, nullptr, perr);
+        (void)hipEventRecord(e1, s_);
+        e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e == hipSuccess) best = std::min(best, t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(c, e, "brick probe");
+    L2T_HIP(c, hipGetLastError());
+    *ms = best;
     return L2T_OK;
 }
 

@@ -273,6 +273,9 @@ int reset_ledger(l2t_ctx *c, int32_t sys);
 int energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out);
 int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream_t s);
 int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom);
+// time n brick-kernel sub-steps of the current layout on a stand-in state in
+// scratch memory (the context's fields are not touched)
+int brick_probe(l2t_ctx *c, int32_t n, float *ms);
 // per-atom record of the energy handed to the lattice (nullptr while off)
 inline double *atom_ledger_ptr(l2t_ctx *c) { return c->atom_ledger ? c->eatom : nullptr; }
 int zero_atom_ledger(l2t_ctx *c, int32_t sys);   // sys < 0: every system
