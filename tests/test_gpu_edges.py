@@ -150,3 +150,30 @@ def test_uniform_temperature_is_stationary_and_g0_conserves(precision):
     assert T.sum() == pytest.approx(hot.T_e0.sum(), rel=1e-13 if precision == L.L2T_FP64 else 1e-9)
     assert ctx.energies(0)["E_e_to_l"] == 0.0
     ctx.close()
+
+
+def test_measured_brick_edge_near_the_model_cached_and_exact():
+    """A layout with more bricks than CUs (64 systems of 32,000 atoms): the
+    build measures the model's brick edge against its neighbours and keeps
+    one of the three; a second build of the same shape reuses it; both layouts
+    give the oracle's trajectory on a sampled system."""
+    w = W.c5(n_substeps=40)
+    ctx_m = L.Context(w.systems, L.L2T_FP32C)
+    L.l2t_set_option(ctx_m.h, L.L2T_OPT_AUTOTUNE, 0)     # the model's edge only
+    ctx_m.setup(w.r_cut)
+    e_m = L.l2t_get_option(ctx_m.h, L.L2T_OPT_BRICK_EDGE)
+    ctx_t = L.Context(w.systems, L.L2T_FP32C)
+    ctx_t.setup(w.r_cut)
+    e_t = L.l2t_get_option(ctx_t.h, L.L2T_OPT_BRICK_EDGE)
+    assert abs(e_t - e_m) <= 1
+    ctx_2 = L.Context(w.systems, L.L2T_FP32C)
+    ctx_2.setup(w.r_cut)
+    assert L.l2t_get_option(ctx_2.h, L.L2T_OPT_BRICK_EDGE) == e_t
+    ctx_2.close()
+    sy = w.systems[5]
+    row, col = oracle_neighbors(sy, w.r_cut)
+    ref, _, _ = oracle.run(row, col, sy.T_e0, sy.T_l, sy.params, w.n_substeps)
+    for ctx in (ctx_m, ctx_t):
+        ctx.advance(w.n_substeps)
+        assert max_rel(ctx.get(5), ref) < 1e-5
+        ctx.close()
