@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -22,6 +23,11 @@ struct Choice {
     int kernel, persistent, block;
 };
 
+// shared by the contexts of all host threads, under a lock
+std::mutex &cache_mutex() {
+    static std::mutex m;
+    return m;
+}
 std::map<std::string, Choice> &mem_cache() {
     static std::map<std::string, Choice> m;
     return m;
@@ -75,9 +81,18 @@ int autotune(l2t_ctx *c) {
     Tuning &t = c->tune;
     const std::string key = shape_key(c);
     Choice best{t.kernel, t.persistent, t.block};
-    auto it = mem_cache().find(key);
-    if (it != mem_cache().end() || file_lookup(key, &best)) {
-        if (it != mem_cache().end()) best = it->second;
+    bool hit = false;
+    {
+        std::lock_guard<std::mutex> g(cache_mutex());
+        auto it = mem_cache().find(key);
+        if (it != mem_cache().end()) {
+            best = it->second;
+            hit = true;
+        } else {
+            hit = file_lookup(key, &best);
+        }
+    }
+    if (hit) {
         t.kernel = best.kernel;
         t.persistent = best.persistent;
         t.block = best.block;
@@ -118,9 +133,17 @@ int autotune(l2t_ctx *c) {
     };
     int rc = save();
     if (rc != L2T_OK) return rc;
-    hipEvent_t e0, e1;
-    L2T_HIP(c, hipEventCreate(&e0));
-    L2T_HIP(c, hipEventCreate(&e1));
+    // the two timing events, destroyed on every way out
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    L2T_HIP(c, hipEventCreate(&ev.e0));
+    L2T_HIP(c, hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     const int probe = 16;   // even: the probe leaves the state in buffer `cur`
     float best_ms = 1e30f;
     // the persistent launch is left out: its grid barrier needs agent-scope
@@ -158,16 +181,17 @@ int autotune(l2t_ctx *c) {
             best = ch;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc != L2T_OK) return rc;
     L2T_HIP(c, hipStreamSynchronize(c->stream));
     t.kernel = best.kernel;
     t.persistent = best.persistent;
     t.block = best.block;
     t.tuned = true;
-    mem_cache()[key] = best;
-    file_store(key, best);
+    {
+        std::lock_guard<std::mutex> g(cache_mutex());
+        mem_cache()[key] = best;
+        file_store(key, best);
+    }
     drop_graphs(c);
     return L2T_OK;
 }

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <thread>
@@ -1407,10 +1408,26 @@ int build_layout(l2t_ctx *c, double r_cut, int32_t force) {
 }
 
 // measured brick edges, per problem shape (cut-off and every system's atom
-// count, box and boundaries), for the life of the process
+// count, box and boundaries), for the life of the process; contexts on
+// different host threads share it under a lock
+std::mutex &edge_mutex() {
+    static std::mutex m;
+    return m;
+}
 std::map<std::string, int32_t> &edge_cache() {
     static std::map<std::string, int32_t> m;
     return m;
+}
+bool edge_lookup(const std::string &key, int32_t *edge) {
+    std::lock_guard<std::mutex> g(edge_mutex());
+    auto it = edge_cache().find(key);
+    if (it == edge_cache().end()) return false;
+    *edge = it->second;
+    return true;
+}
+void edge_store(const std::string &key, int32_t edge) {
+    std::lock_guard<std::mutex> g(edge_mutex());
+    edge_cache()[key] = edge;
 }
 
 std::string edge_key(const l2t_ctx *c, double r_cut) {
@@ -1440,15 +1457,13 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
     const bool may_tune = c->precision == L2T_FP32C && c->tune.autotune && !c->tune.pinned &&
                           c->tune.brick_edge == 0;
     const std::string key = may_tune ? edge_key(c, r_cut) : std::string();
-    if (may_tune) {
-        auto it = edge_cache().find(key);
-        if (it != edge_cache().end()) return build_layout(c, r_cut, it->second);
-    }
+    int32_t cached = 0;
+    if (may_tune && edge_lookup(key, &cached)) return build_layout(c, r_cut, cached);
     int rc = build_layout(c, r_cut, 0);
     if (rc != L2T_OK || !may_tune) return rc;
     const int32_t e0 = c->brick_edge_used;
     if (c->n_brick_list < std::max(1, c->n_cu)) {
-        edge_cache()[key] = e0;
+        edge_store(key, e0);
         return L2T_OK;
     }
     // an edge above e0 changes the layout only where some axis is longer than e0
@@ -1478,7 +1493,7 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         rc = build_layout(c, r_cut, best);
         if (rc != L2T_OK) return rc;
     }
-    edge_cache()[key] = best;
+    edge_store(key, best);
     return L2T_OK;
 }
 

@@ -866,12 +866,16 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
     L2T_HIP(c, hipMemsetAsync(stp, 0, sizeof(int64_t) * S, s_));
     L2T_HIP(c, hipMemsetAsync(perr, 0, sizeof(unsigned), s_));
     L2T_HIP(c, hipGetLastError());
-    hipEvent_t e0, e1;
-    L2T_HIP(c, hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(c, hipErrorOutOfMemory, "hipEventCreate");
-    }
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    L2T_HIP(c, hipEventCreate(&ev.e0));
+    L2T_HIP(c, hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     const unsigned grid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
     float best = 1e30f;
@@ -891,8 +895,6 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
         if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
         if (e == hipSuccess) best = std::min(best, t);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(c, e, "brick probe");
     L2T_HIP(c, hipGetLastError());
     *ms = best;

@@ -177,3 +177,34 @@ def test_checkpoint_resume_is_bitwise(precision):
         for key in ("E_e_to_l", "E_src", "T_ledger_acc"):
             assert e[key] == pytest.approx(eA[s][key], rel=1e-12, abs=1e-12), key
     c.close()
+
+
+def test_two_host_threads_one_context_each():
+    """Contexts on two host threads build, tune (launch form and measured
+    brick edge, both cached process-wide) and advance at the same time; each
+    matches the oracle."""
+    import threading
+    w = W.c5(n_systems=16, n_substeps=30)          # more bricks than CUs
+    out, errs = {}, []
+
+    def work(k):
+        try:
+            ctx = L.Context(w.systems, L.L2T_FP32C)
+            ctx.setup(w.r_cut)
+            ctx.advance(w.n_substeps)
+            out[k] = ctx.get(3)
+            ctx.close()
+        except Exception as e:              # reported by the main thread
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    sy = w.systems[3]
+    traj, _, bad = oracle_trajectory(sy, w.r_cut, [w.n_substeps])
+    assert bad == 0
+    for k in range(2):
+        assert max_rel(out[k], traj[0]) < 1e-5
