@@ -205,6 +205,21 @@ int l2t_create(l2t_ctx **out, int32_t n_systems, const l2t_system_desc *descs,
 /* Release every buffer owned by the context (synchronises its stream). */
 void l2t_destroy(l2t_ctx *ctx);
 
+/* Device memory of the context.  Every device buffer the context allocates
+ * after this call comes from alloc(bytes, user), which returns device memory
+ * of the context's GPU aligned to at least 256 bytes, or NULL (the call that
+ * needed it then fails with ENOMEM), and goes back through free_(ptr, user),
+ * for instance so that PyTorch's caching allocator owns the memory.  The
+ * library synchronises its stream before it hands a block back.  Buffers
+ * allocated before the call stay with the allocator that made them and are
+ * released through it.  alloc = free_ = NULL restores hipMalloc / hipFree.
+ * Buffers grow on demand (neighbour build, recorded advance, adjoint, host
+ * staging), so the allocator can be called from any of those calls and from
+ * l2t_destroy.  Errors: EINVAL (NULL context, or exactly one of alloc and
+ * free_ NULL). */
+int l2t_set_allocator(l2t_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                      void (*free_)(void *ptr, void *user), void *user);
+
 /* ---- geometry --------------------------------------------------------------- */
 
 /* Atom positions of system sys, SoA xyz[3*n]: x[0..n), y[0..n), z[0..n), A.

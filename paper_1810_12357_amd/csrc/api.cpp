@@ -27,15 +27,40 @@ int hip_fail(l2t_ctx *c, hipError_t e, const char *what) {
     return fail(c, L2T_EHIP, m);
 }
 
+hipError_t dev_malloc(l2t_ctx *c, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    if (!c->ualloc) return hipMalloc(p, bytes);
+    void *q = c->ualloc(bytes, c->uarg);
+    if (!q) return hipErrorOutOfMemory;
+    c->user_blocks[q] = l2t_ctx::UserBlock{c->ufree, c->uarg};
+    *p = q;
+    return hipSuccess;
+}
+
+void dev_free(l2t_ctx *c, void *p) {
+    if (!p) return;
+    auto it = c->user_blocks.find(p);
+    if (it == c->user_blocks.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    const l2t_ctx::UserBlock b = it->second;
+    c->user_blocks.erase(it);
+    // the block goes back to the caller: nothing queued on the stream may use it
+    (void)hipStreamSynchronize(c->stream);
+    b.free_(p, b.arg);
+}
+
 int ensure_scratch(l2t_ctx *c, size_t bytes) {
     if (bytes <= c->scratch_bytes) return L2T_OK;
     if (c->scratch) {
         (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->scratch);
+        dev_free(c, c->scratch);
     }
     c->scratch = nullptr;
     c->scratch_bytes = 0;
-    if (hipMalloc(&c->scratch, bytes) != hipSuccess)
+    if (dev_malloc(c, &c->scratch, bytes) != hipSuccess)
         return fail(c, L2T_ENOMEM, "scratch allocation failed");
     c->scratch_bytes = bytes;
     return L2T_OK;
@@ -46,22 +71,21 @@ int ensure_scratch(l2t_ctx *c, size_t bytes) {
 namespace {
 
 template <typename T>
-void dfree(T *&p);
-
-template <typename T>
 int dalloc(l2t_ctx *c, T **p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
-    if (e != hipSuccess) return l2t::hip_fail(c, e, "hipMalloc");
+    void *q = nullptr;
+    hipError_t e = l2t::dev_malloc(c, &q, sizeof(T) * count);
+    if (e != hipSuccess) return l2t::hip_fail(c, e, "device allocation");
+    *p = (T *)q;
     e = hipMemsetAsync(*p, 0, sizeof(T) * count, c->stream);
     if (e != hipSuccess) return l2t::hip_fail(c, e, "hipMemsetAsync");
     return L2T_OK;
 }
 
 template <typename T>
-void dfree(T *&p) {
-    if (p) (void)hipFree((void *)p);
+void dfree(l2t_ctx *c, T *&p) {
+    l2t::dev_free(c, (void *)p);
     p = nullptr;
 }
 
@@ -72,10 +96,10 @@ namespace l2t {
 void *tmp_buf(l2t_ctx *c, int slot, size_t bytes) {
     if (bytes > c->tmp_cap[slot]) {
         (void)hipStreamSynchronize(c->stream);
-        if (c->tmp[slot]) (void)hipFree(c->tmp[slot]);
+        dev_free(c, c->tmp[slot]);
         c->tmp[slot] = nullptr;
         c->tmp_cap[slot] = 0;
-        if (hipMalloc(&c->tmp[slot], bytes) != hipSuccess) return nullptr;
+        if (dev_malloc(c, &c->tmp[slot], bytes) != hipSuccess) return nullptr;
         c->tmp_cap[slot] = bytes;
     }
     return c->tmp[slot];
@@ -98,24 +122,24 @@ int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, 
 #define ALLOC(p, n)                                    \
     if (rc == L2T_OK) rc = dalloc(c, &(p), (size_t)(n));
     if ((size_t)n_int > c->cap_ni) {
-        dfree(c->pos_int);
-        dfree(c->perm);
-        dfree(c->cell_int);
-        dfree(c->cnt);
-        dfree(c->slices);
+        dfree(c, c->pos_int);
+        dfree(c, c->perm);
+        dfree(c, c->cell_int);
+        dfree(c, c->cnt);
+        dfree(c, c->slices);
         for (int b = 0; b < 2; ++b) {
-            dfree(c->T64[b]);
-            dfree(c->Thi[b]);
+            dfree(c, c->T64[b]);
+            dfree(c, c->Thi[b]);
         }
-        dfree(c->Tl64);
-        dfree(c->Tl64b);
-        dfree(c->srcw64);
-        dfree(c->Tlo);
-        dfree(c->Tl32);
-        dfree(c->srcw32);
-        dfree(c->ledger);
-        dfree(c->eatom);
-        dfree(c->slice_red);
+        dfree(c, c->Tl64);
+        dfree(c, c->Tl64b);
+        dfree(c, c->srcw64);
+        dfree(c, c->Tlo);
+        dfree(c, c->Tl32);
+        dfree(c, c->srcw32);
+        dfree(c, c->ledger);
+        dfree(c, c->eatom);
+        dfree(c, c->slice_red);
         c->cap_ni = 0;
         const size_t NI = (size_t)n_int, NS = NI / kWave;
         ALLOC(c->pos_int, 3 * NI);
@@ -143,7 +167,7 @@ int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, 
     }
     auto grow = [&](auto *&p, size_t &cap, size_t n) {
         if (rc != L2T_OK || n <= cap) return;
-        dfree(p);
+        dfree(c, p);
         cap = 0;
         rc = dalloc(c, &p, n);
         if (rc == L2T_OK) cap = n;
@@ -264,49 +288,48 @@ void l2t_destroy(l2t_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     l2t::drop_graphs(c);
-    dfree(c->res);
-    dfree(c->pos);
-    dfree(c->pos_int);
-    dfree(c->perm);
-    dfree(c->inv);
-    dfree(c->cell_start);
-    dfree(c->cell_scratch);
-    dfree(c->cell_of);
-    dfree(c->cell_int);
-    dfree(c->sorted_local);
-    dfree(c->cnt);
-    dfree(c->slices);
-    dfree(c->col);
-    dfree(c->colw);
-    dfree(c->pos_slot);
-    dfree(c->bricks);
-    dfree(c->brick_list);
-    dfree(c->shell);
-    dfree(c->halo);
+    dfree(c, c->res);
+    dfree(c, c->pos);
+    dfree(c, c->pos_int);
+    dfree(c, c->perm);
+    dfree(c, c->inv);
+    dfree(c, c->cell_start);
+    dfree(c, c->cell_scratch);
+    dfree(c, c->cell_of);
+    dfree(c, c->cell_int);
+    dfree(c, c->sorted_local);
+    dfree(c, c->cnt);
+    dfree(c, c->slices);
+    dfree(c, c->col);
+    dfree(c, c->colw);
+    dfree(c, c->pos_slot);
+    dfree(c, c->bricks);
+    dfree(c, c->brick_list);
+    dfree(c, c->shell);
+    dfree(c, c->halo);
     for (int b = 0; b < 2; ++b) {
-        dfree(c->T64[b]);
-        dfree(c->Thi[b]);
+        dfree(c, c->T64[b]);
+        dfree(c, c->Thi[b]);
     }
-    dfree(c->Tl64);
-    dfree(c->Tl64b);
-    dfree(c->srcw64);
-    dfree(c->Tlo);
-    dfree(c->Tl32);
-    dfree(c->srcw32);
-    dfree(c->ledger);
-    dfree(c->eatom);
-    dfree(c->slice_red);
-    dfree(c->energy_out);
-    if (c->mf_chunks) (void)hipFree(c->mf_chunks);
-    dfree(c->dparams);
-    dfree(c->dstep);
-    dfree(c->derr);
-    dfree(c->dbar);
-    dfree(c->stage);
-    if (c->scratch) (void)hipFree(c->scratch);
-    for (void *p : c->tmp)
-        if (p) (void)hipFree(p);
-    if (c->rec.buf) (void)hipFree(c->rec.buf);
+    dfree(c, c->Tl64);
+    dfree(c, c->Tl64b);
+    dfree(c, c->srcw64);
+    dfree(c, c->Tlo);
+    dfree(c, c->Tl32);
+    dfree(c, c->srcw32);
+    dfree(c, c->ledger);
+    dfree(c, c->eatom);
+    dfree(c, c->slice_red);
+    dfree(c, c->energy_out);
+    l2t::dev_free(c, c->mf_chunks);
+    dfree(c, c->dparams);
+    dfree(c, c->dstep);
+    dfree(c, c->derr);
+    dfree(c, c->dbar);
+    dfree(c, c->stage);
+    l2t::dev_free(c, c->scratch);
+    for (void *p : c->tmp) l2t::dev_free(c, p);
+    l2t::dev_free(c, c->rec.buf);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
@@ -586,6 +609,17 @@ int l2t_set_velocities(l2t_ctx *c, int32_t sys, const double *v, const double *m
     return L2T_OK;
 }
 
+int l2t_set_allocator(l2t_ctx *c, void *(*alloc)(size_t, void *), void (*free_)(void *, void *),
+                      void *user) {
+    if (!c) return L2T_EINVAL;
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return l2t::fail(c, L2T_EINVAL, "give both alloc and free_, or neither");
+    c->ualloc = alloc;
+    c->ufree = free_;
+    c->uarg = alloc ? user : nullptr;
+    return L2T_OK;
+}
+
 int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
     if (!c) return L2T_EINVAL;
     l2t::Tuning &t = c->tune;
@@ -710,10 +744,10 @@ int l2t_advance_recorded(l2t_ctx *c, int32_t n, int32_t ckpt_every) {
     r.n_ckpt = (n + ckpt_every - 1) / ckpt_every;
     size_t need = (size_t)r.n_ckpt * 2 * sizeof(float) * (size_t)c->n_int;
     if (need > r.bytes) {
-        if (r.buf) (void)hipFree(r.buf);
+        l2t::dev_free(c, r.buf);
         r.buf = nullptr;
         r.bytes = 0;
-        if (hipMalloc(&r.buf, need) != hipSuccess)
+        if (l2t::dev_malloc(c, &r.buf, need) != hipSuccess)
             return l2t::fail(c, L2T_ENOMEM, "checkpoint allocation failed");
         r.bytes = need;
     }

@@ -1319,19 +1319,19 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forc
     }
     int64_t col_len = std::max<int64_t>(total64 * kWave, 1);
     if (col_len > c->col_len) {
-        if (c->col) (void)hipFree(c->col);
+        dev_free(c, c->col);
         c->col = nullptr;
         c->col_len = 0;
-        if (hipMalloc(&c->col, sizeof(int32_t) * col_len) != hipSuccess)
+        if (dev_malloc(c, (void **)&c->col, sizeof(int32_t) * col_len) != hipSuccess)
             return fail(c, L2T_ENOMEM, "neighbour table allocation failed");
         c->col_len = col_len;
     }
     int64_t colw_len = std::max<int64_t>(totalw64 * kWave, 1);
     if (colw_len > c->colw_len) {
-        if (c->colw) (void)hipFree(c->colw);
+        dev_free(c, c->colw);
         c->colw = nullptr;
         c->colw_len = 0;
-        if (hipMalloc(&c->colw, sizeof(uint32_t) * colw_len) != hipSuccess)
+        if (dev_malloc(c, (void **)&c->colw, sizeof(uint32_t) * colw_len) != hipSuccess)
             return fail(c, L2T_ENOMEM, "neighbour table allocation failed");
         c->colw_len = colw_len;
     }

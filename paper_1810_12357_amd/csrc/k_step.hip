@@ -463,10 +463,10 @@ int upload_params(l2t_ctx *c) {
     if (c->n_mf_chunks > c->mf_chunks_cap) {
         drop_graphs(c);   // captured refreshes hold the old table
         (void)hipStreamSynchronize(c->stream);
-        if (c->mf_chunks) (void)hipFree(c->mf_chunks);
+        dev_free(c, c->mf_chunks);
         c->mf_chunks = nullptr;
         c->mf_chunks_cap = 0;
-        if (hipMalloc(&c->mf_chunks, sizeof(MfChunk) * chunks.size()) != hipSuccess)
+        if (dev_malloc(c, (void **)&c->mf_chunks, sizeof(MfChunk) * chunks.size()) != hipSuccess)
             return fail(c, L2T_ENOMEM, "mean-field chunk table allocation failed");
         c->mf_chunks_cap = c->n_mf_chunks;
     }
@@ -618,10 +618,10 @@ static int resident_fp64(l2t_ctx *c, int32_t n, bool lat, double *eatom) {
             c->h_res[s] = ResidentSys{(int32_t)s, c->sys[s].atom_off, c->sys[s].n_pad,
                                       c->sys[s].slice0};
         if (c->h_res.size() > c->res_cap) {
-            if (c->res) (void)hipFree(c->res);
+            dev_free(c, c->res);
             c->res = nullptr;
             c->res_cap = 0;
-            if (hipMalloc(&c->res, sizeof(ResidentSys) * c->h_res.size()) != hipSuccess)
+            if (dev_malloc(c, (void **)&c->res, sizeof(ResidentSys) * c->h_res.size()) != hipSuccess)
                 return fail(c, L2T_ENOMEM, "resident system table allocation failed");
             c->res_cap = c->h_res.size();
         }

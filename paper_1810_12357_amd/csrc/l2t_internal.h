@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "l2t.h"
@@ -157,6 +158,16 @@ struct Recording {
 struct l2t_ctx {
     int precision = L2T_FP32C;
     hipStream_t stream = nullptr;
+    // the caller's device allocator (l2t_set_allocator); unset: hipMalloc / hipFree
+    void *(*ualloc)(size_t, void *) = nullptr;
+    void (*ufree)(void *, void *) = nullptr;
+    void *uarg = nullptr;
+    // blocks that came from a caller allocator, with the call that releases each
+    struct UserBlock {
+        void (*free_)(void *, void *);
+        void *arg;
+    };
+    std::unordered_map<void *, UserBlock> user_blocks;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     int device = 0;
     int n_cu = 256;
@@ -302,6 +313,10 @@ int autotune(l2t_ctx *c);
 
 // ---- buffers ---------------------------------------------------------------
 int ensure_scratch(l2t_ctx *c, size_t bytes);
+// every device buffer of a context: from the caller's allocator when one is
+// set, else hipMalloc; dev_free releases a block through whichever made it
+hipError_t dev_malloc(l2t_ctx *c, void **p, size_t bytes);
+void dev_free(l2t_ctx *c, void *p);
 // temporary device buffer `slot` of at least n elements (kept for the next call)
 void *tmp_buf(l2t_ctx *c, int slot, size_t bytes);
 template <class T>
@@ -312,23 +327,5 @@ inline T *tmp_of(l2t_ctx *c, int slot, int64_t n) {
 int alloc_internal(l2t_ctx *c, int32_t n_int, int32_t n_bricks, int32_t n_list, int64_t shell_len,
                    int64_t halo_len);
 
-// device buffer released (after a stream sync) when it goes out of scope
-template <class T>
-struct DevBuf {
-    T *p = nullptr;
-    hipStream_t s = nullptr;
-    DevBuf(l2t_ctx *c, int64_t n) : s(c->stream) {
-        if (hipMalloc((void **)&p, sizeof(T) * (size_t)(n > 0 ? n : 1)) != hipSuccess) p = nullptr;
-    }
-    ~DevBuf() {
-        if (p) {
-            (void)hipStreamSynchronize(s);
-            (void)hipFree(p);
-        }
-    }
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    bool ok() const { return p != nullptr; }
-};
 
 }  // namespace l2t

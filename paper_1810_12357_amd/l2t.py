@@ -36,9 +36,14 @@ EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbor
            "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
            "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
            "l2t_coupling", "l2t_damping_step", "l2t_set_mean_field", "l2t_get_params",
-           "l2t_set_lattice_fd", "l2t_set_counters",
+           "l2t_set_lattice_fd", "l2t_set_counters", "l2t_set_allocator",
            "l2t_exchange_rate", "l2t_pair_fp32", "l2t_strerror", "l2t_last_error",
            "l2t_version")
+
+
+# the allocator hook of l2t_set_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class l2t_system_desc(C.Structure):
@@ -100,6 +105,7 @@ def load() -> C.CDLL:
     sig = {
         "l2t_create": (C.c_int, [P(vp), i32, P(l2t_system_desc), i32, vp]),
         "l2t_destroy": (None, [vp]),
+        "l2t_set_allocator": (C.c_int, [vp, ALLOC_FN, FREE_FN, vp]),
         "l2t_set_positions": (C.c_int, [vp, i32, vp, i32]),
         "l2t_build_neighbors": (C.c_int, [vp, d, P(i32), P(d)]),
         "l2t_get_neighbors": (C.c_int, [vp, i32, vp, vp, i64]),
@@ -201,6 +207,33 @@ def l2t_create(descs, precision: int, stream=None):
 
 def l2t_destroy(ctx) -> None:
     load().l2t_destroy(ctx)
+
+
+def l2t_set_allocator(ctx, alloc, free_, user=None) -> int:
+    """alloc, free_: ALLOC_FN / FREE_FN objects (or None for both, which restores
+    hipMalloc / hipFree).  The caller keeps them alive while the context lives."""
+    a = C.cast(None, ALLOC_FN) if alloc is None else alloc
+    f = C.cast(None, FREE_FN) if free_ is None else free_
+    return _check(ctx, load().l2t_set_allocator(ctx, a, f, user))
+
+
+def torch_allocator(device=None):
+    """(alloc, free_) hooks that take the context's device memory from
+    PyTorch's caching allocator on the current stream."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def _alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev,
+                                                      torch.cuda.current_stream(dev))
+        except Exception:
+            return None
+
+    def _free(ptr, _user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
 
 
 def l2t_set_positions(ctx, sys: int, xyz) -> int:
@@ -384,10 +417,17 @@ def desc_of(system) -> l2t_system_desc:
 class Context:
     """Owns one l2t context holding a list of independent systems."""
 
-    def __init__(self, systems, precision: int = L2T_FP32C, stream=None):
+    def __init__(self, systems, precision: int = L2T_FP32C, stream=None,
+                 torch_memory: bool = False):
         self.systems = list(systems)
         self.precision = precision
         self.h = l2t_create([desc_of(s) for s in self.systems], precision, stream)
+        self._hooks = None
+        if torch_memory:
+            # device buffers from PyTorch's caching allocator; the hooks live
+            # as long as the context
+            self._hooks = torch_allocator()
+            l2t_set_allocator(self.h, *self._hooks)
 
     def close(self):
         if self.h:

@@ -56,6 +56,8 @@ def test_argument_validation_without_device():
     assert lib.l2t_coupling(None, 0, L.L2T_XI_INSTANT, 1.0, None, None, None, L.L2T_HOST) == L.L2T_EINVAL
     assert lib.l2t_damping_step(None, 0, 1.0, None, None, None, None, L.L2T_HOST) == L.L2T_EINVAL
     assert lib.l2t_set_counters(None, 0, 0, 0.0, 0.0, 0.0) == L.L2T_EINVAL
+    assert lib.l2t_set_allocator(None, ctypes.cast(None, L.ALLOC_FN),
+                                 ctypes.cast(None, L.FREE_FN), None) == L.L2T_EINVAL
     assert lib.l2t_last_error(None) == b""
 
 

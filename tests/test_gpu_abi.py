@@ -208,3 +208,35 @@ def test_two_host_threads_one_context_each():
     assert bad == 0
     for k in range(2):
         assert max_rel(out[k], traj[0]) < 1e-5
+
+
+def test_torch_caching_allocator_owns_the_device_memory():
+    """With the allocator hook set to PyTorch's caching allocator, the
+    buffers a context allocates from then on (layout, tables, recording,
+    adjoint scratch) come from torch and all go back at l2t_destroy; the
+    states are bitwise those of a context on hipMalloc."""
+    import torch
+    w = W.c4(n_systems=3, n_substeps=200, size_lo=800, size_hi=3000)
+    n = w.n_substeps
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    ref = L.Context(w.systems, L.L2T_FP32C)
+    ref.setup(w.r_cut)
+    ref.advance(n)
+    T_ref = [ref.get(s) for s in range(len(w.systems))]
+    ref.close()
+    assert torch.cuda.memory_allocated() == base
+    ctx = L.Context(w.systems, L.L2T_FP32C, torch_memory=True)
+    ctx.setup(w.r_cut)
+    assert torch.cuda.memory_allocated() > base
+    ctx.advance(n)
+    for s in range(len(w.systems)):
+        assert np.array_equal(ctx.get(s), T_ref[s])
+    L.l2t_advance_recorded(ctx.h, 50, 10)
+    dL = np.full(sum(sy.n for sy in w.systems), 1e-3)
+    dK, dg = L.l2t_adjoint(ctx.h, dL, len(w.systems))
+    assert np.all(np.isfinite(dK)) and np.all(np.isfinite(dg))
+    held = torch.cuda.memory_allocated()
+    ctx.close()
+    torch.cuda.synchronize()
+    assert held > base and torch.cuda.memory_allocated() == base
