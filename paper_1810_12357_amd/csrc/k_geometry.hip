@@ -1473,6 +1473,12 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
     constexpr int32_t kProbe = 12;
     float best_ms = 0.0f;
     rc = brick_probe(c, kProbe, &best_ms);
+    if (rc == L2T_ENOMEM) {
+        // no room for the stand-in state: keep the model's edge
+        c->last_error.clear();
+        edge_store(key, e0);
+        return L2T_OK;
+    }
     if (rc != L2T_OK) return rc;
     int32_t best = e0, built = e0;
     for (const int32_t e : {e0 - 1, e0 + 1}) {
@@ -1483,6 +1489,10 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         if (built != e) continue;   // its tiles overflowed: a smaller edge was built
         float ms = 0.0f;
         rc = brick_probe(c, kProbe, &ms);
+        if (rc == L2T_ENOMEM) {   // a larger layout's stand-in did not fit: skip it
+            c->last_error.clear();
+            continue;
+        }
         if (rc != L2T_OK) return rc;
         if (ms < 0.99f * best_ms) {
             best_ms = ms;
