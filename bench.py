@@ -342,7 +342,7 @@ def bench_c3_fp64(L, torch, w, n_sub=100):
     FP32C / FP64 ratio on this system."""
     sy = w.systems[0]
     ctx = L.Context(w.systems, L.L2T_FP64, stream=torch.cuda.current_stream().cuda_stream)
-    ctx.setup(w.r_cut)
+    _, mean, _ = ctx.setup(w.r_cut)
     ctx.advance(4)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -353,7 +353,14 @@ def bench_c3_fp64(L, torch, w, n_sub=100):
     us = e0.elapsed_time(e1) * 1e3 / n_sub
     ctx.close()
     log(f"  C3 FP64 plain: {us:.1f} us per sub-step")
-    return dict(substeps=n_sub, substep_us=us, atom_substeps_per_s=sy.n / (us * 1e-6))
+    # k_step_fp64 per atom-substep: T read and write (16), T_lat (8), row
+    # offset (4), one int32 index per neighbour (4 n_mean)
+    bytes_per = 28.0 + 4.0 * mean
+    gbps = bytes_per * sy.n / (us * 1e-6) / 1e9
+    return dict(substeps=n_sub, substep_us=us, atom_substeps_per_s=sy.n / (us * 1e-6),
+                kernel="k_step_fp64", algorithmic_bytes_per_atom_substep=bytes_per,
+                achieved_GBps=gbps, frac=gbps / HBM_PEAK_GBS,
+                bound="valu: two FP64 exponentials per pair of the literal pair term")
 
 
 def cpu_baseline(L, torch, w, n_steps):
