@@ -360,7 +360,7 @@ def bench_c3_fp64(L, torch, w, n_sub=100):
     return dict(substeps=n_sub, substep_us=us, atom_substeps_per_s=sy.n / (us * 1e-6),
                 kernel="k_step_fp64", algorithmic_bytes_per_atom_substep=bytes_per,
                 achieved_GBps=gbps, frac=gbps / HBM_PEAK_GBS,
-                bound="valu: two FP64 exponentials per pair of the literal pair term")
+                bound="latency of the neighbour gathers (vector issue is about half the launch)")
 
 
 def cpu_baseline(L, torch, w, n_steps):
