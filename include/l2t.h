@@ -100,9 +100,12 @@ extern "C" {
                                       fits.  0 = the default 1024, -1 = never (one launch per
                                       sub-step).  Results are bitwise equal either way. */
 #define L2T_OPT_GRAPH          3   /* replay the per-sub-step launches of an advance from captured hipGraphs of 256 sub-steps (default 1) */
-#define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance (default 1) */
+#define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance, and let
+                                      l2t_build_neighbors time the brick edge (default 1) */
 #define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
-#define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells (1..1024) for the next l2t_build_neighbors (0 = automatic) */
+#define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells (1..1024) for the next
+                                      l2t_build_neighbors (0 = automatic: a cost model, checked
+                                      by timing on large FP32C layouts, see l2t_build_neighbors) */
 #define L2T_OPT_ATOM_LEDGER    7   /* 1 = record each atom's energy to the lattice during every advance
                                       (L2T_FIELD_ELAT, L2T_XI_LEDGER); costs 16 bytes per atom-substep
                                       of extra traffic while on (default 0) */
@@ -231,7 +234,13 @@ int l2t_set_positions(l2t_ctx *ctx, int32_t sys, const double *xyz, int32_t mem)
  * system (Section 2.1, user-given cut-off; minimum image on periodic axes,
  * distances in FP64, inclusive).  Atoms are binned into cells of edge >=
  * r_cut and reordered by cell.  Synchronises.  Outputs (nullable): the
- * largest and the mean neighbour count over all atoms.
+ * largest and the mean neighbour count over all atoms.  An FP32C context
+ * whose layout has at least one brick per CU also times the brick edge the
+ * first time it builds a given problem shape in the process: the cost
+ * model's edge and its two neighbours are built and each runs a short probe
+ * of the sub-step kernel on stand-in data (the context's fields are not
+ * used), so that first build costs two or three layouts.  L2T_OPT_AUTOTUNE
+ * = 0, L2T_OPT_BRICK_EDGE or a pinned launch form skip the timing.
  * Errors: ESTATE (positions missing), EINVAL (r_cut <= 0, periodic box_len <
  * 2 r_cut, atom outside the box on a free axis). */
 int l2t_build_neighbors(l2t_ctx *ctx, double r_cut, int32_t *max_nbrs, double *mean_nbrs);
