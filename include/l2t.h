@@ -102,7 +102,10 @@ extern "C" {
 #define L2T_OPT_GRAPH          3   /* replay the per-sub-step launches of an advance from captured hipGraphs of 256 sub-steps (default 1) */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance, and let
                                       l2t_build_neighbors time the brick edge (default 1) */
-#define L2T_OPT_KERNEL         5   /* FP32C: 0 = global gathers, 1 = LDS brick tiles (default: autotuned) */
+#define L2T_OPT_KERNEL         5   /* 0 = global gathers, 1 = LDS brick tiles.  FP32C: autotuned by
+                                      default.  FP64: 1 by default; systems in the lattice mode, and
+                                      tiles over 64 KB of FP64 values, take the global gathers.  The
+                                      forms give bitwise-equal states. */
 #define L2T_OPT_BRICK_EDGE     6   /* largest brick edge in cells (1..1024) for the next
                                       l2t_build_neighbors (0 = automatic: a cost model, checked
                                       by timing on large FP32C layouts, see l2t_build_neighbors) */

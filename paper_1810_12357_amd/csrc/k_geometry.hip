@@ -1028,6 +1028,7 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forc
         const SysLayout &L = lay[s];
         const int32_t *start = h_start.data() + cstart_off[s];
         st.atom_off = slot;
+        st.list0 = (int32_t)h_list.size();
         for (int32_t b = 0; b < L.nbrick; ++b) {
             const int32_t gb = L.brick0 + b;
             BrickInfo &bi = hb[gb];
@@ -1055,6 +1056,7 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forc
         st.n_pad = slot - st.atom_off;
         st.slice0 = st.atom_off / kWave;
         st.n_slices = st.n_pad / kWave;
+        st.n_list = (int32_t)h_list.size() - st.list0;
     }
     if (shell_total > INT32_MAX) return fail(c, L2T_ENOMEM, "shell tables too large");
     h_shell.assign((size_t)shell_total, 0);

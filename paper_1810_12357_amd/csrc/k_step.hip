@@ -156,6 +156,88 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
     ledger_add(ledger, bi.slice0 + wave, lane, acc, p.dt);
 }
 
+// LDS-tile FP64 sub-step (the plain form of Eq. 2 with the brick layout):
+// one workgroup per brick stages the FP64 temperatures of the brick's own
+// slots and of its halo atoms in LDS, then its waves run the brick's slices
+// through the uint16 table, whose entries are byte offsets into a 4-byte
+// tile (halved for this 8-byte one).  The rows hold the same neighbours in
+// the same order as the int32 table and the per-lane arithmetic is the same
+// template, so states and per-slice ledger rows are bitwise those of
+// k_step_fp64.  Systems in the lattice mode are not launched here.
+__global__ __launch_bounds__(kBrickBlockMax) void k_brick_fp64(
+    const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
+    const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
+    const int32_t *__restrict__ halo, const double *__restrict__ T, double *__restrict__ Tn,
+    const double *__restrict__ Tl, const double *__restrict__ srcw,
+    const DevParams *__restrict__ P, const int64_t *__restrict__ dstep, int32_t rel,
+    double *__restrict__ ledger, double *__restrict__ eatom, unsigned *__restrict__ err) {
+    extern __shared__ double tile64[];
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+    if ((int32_t)logical >= n_list) return;
+    const BrickInfo bi = bricks[list[logical]];
+    constexpr int U = 4;
+    const int32_t B = blockDim.x;
+    for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = t0 + u * B;
+            v[u] = (t < bi.n_own_pad) ? T[bi.slot0 + t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u * B < bi.n_own_pad) tile64[t0 + u * B] = v[u];
+    }
+    const int32_t *hl = halo + bi.halo_off;
+    double *ht = tile64 + bi.n_own_pad;
+    for (int32_t t0 = threadIdx.x; t0 < bi.n_halo; t0 += U * B) {
+        int32_t id[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = t0 + u * B;
+            id[u] = (t < bi.n_halo) ? hl[t] : bi.slot0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = T[id[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u * B < bi.n_halo) ht[t0 + u * B] = v[u];
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    const int32_t ns = bi.n_own_pad / kWave;
+    if (wave >= ns) return;
+    const DevParams &p = P[bi.sys];
+    const int64_t step = dstep[bi.sys] + rel;
+    const char *tb = reinterpret_cast<const char *>(tile64);
+    for (int32_t q = wave; q < ns; q += nw) {
+        const int32_t sl = bi.slice0 + q;
+        const SliceInfo si = slices[sl];
+        const int32_t slot = sl * kWave + lane;
+        const bool valid = lane < si.n_valid;
+        const double sw = (p.laser_on | (si.flags & kSliceHeld)) ? srcw[slot] : 0.0;
+        const uint32_t *rw = colw + (int64_t)si.colw_base64 * kWave + lane;
+        const Fp64Lane r = lane_step_fp64_refs<false>(
+            si, valid, p,
+            [&](int32_t k) { return (rw[(int64_t)(k >> 1) * kWave] >> (16 * (k & 1))) & 0xffffu; },
+            tile64[q * kWave + lane], Tl[slot], sw,
+            [&](uint32_t off) { return *reinterpret_cast<const double *>(tb + 2 * off); },
+            [&](uint32_t) { return 0.0; }, step, err);
+        if (eatom && valid) eatom[slot] += r.e2l;
+        Tn[slot] = r.Tnew;
+        const double e2l = wave_sum(r.e2l), qv = wave_sum(r.q), lt = wave_sum(r.lt);
+        if (lane == 0) {
+            ledger[3 * (int64_t)sl + 0] += e2l;
+            ledger[3 * (int64_t)sl + 1] += qv;
+            ledger[3 * (int64_t)sl + 2] += lt;
+        }
+    }
+}
+
 // Grid-wide barrier for the persistent kernel.  bar[0] counts arrivals over
 // the whole launch (barrier k completes at k * nblocks arrivals); bar[1] is an
 // abort word raised when a block spins past the limit, so every block leaves
@@ -661,6 +743,32 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
         int rc = resident_fp64(c, n, lat, eatom);
         if (rc != L2T_ENOTIMPL) return rc;
     }
+    // FP64 sub-steps through LDS brick tiles (the kernel choice) when the
+    // launch covers at least one brick per CU, no system is in the lattice
+    // mode and an 8-byte tile fits 64 KB of LDS; otherwise the global-gather
+    // k_step_fp64, whose one wave per slice spreads a small system over more
+    // CUs (one brick is one workgroup).  Both give bitwise-equal states.
+    const int32_t *b_list = c->brick_list + (sys < 0 ? 0 : c->sys[sys].list0);
+    const int32_t b_n = sys < 0 ? c->n_brick_list : c->sys[sys].n_list;
+    const bool brick64 = c->precision == L2T_FP64 && c->tune.kernel == kKernelBrick && !lat &&
+                         b_n >= std::max(1, c->n_cu) &&
+                         (size_t)c->tile_max * sizeof(double) <= 65536;
+    const unsigned b_grid = (unsigned)((b_n + 7) / 8 * 8);
+    const size_t b_lds = sizeof(double) * (size_t)c->tile_max;
+    // one FP64 sub-step from state buffer cu (relative step q within the call)
+    auto step64 = [&](int cu, int32_t q, const double *tl_in, double *tl_out) {
+        if (brick64) {
+            if (b_n > 0)
+                hipLaunchKernelGGL(k_brick_fp64, dim3(b_grid), dim3(kBrickBlockMax), b_lds,
+                                   c->stream, c->bricks, b_list, b_n, c->slices, c->colw, c->halo,
+                                   c->T64[cu], c->T64[cu ^ 1], c->Tl64, c->srcw64, c->dparams,
+                                   c->dstep, q, c->ledger, eatom, c->derr);
+        } else {
+            hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
+                               c->T64[cu], c->T64[cu ^ 1], tl_in, tl_out, c->srcw64, c->dparams,
+                               c->dstep, q, c->ledger, eatom, c->derr);
+        }
+    };
     if (sys < 0 && c->precision == L2T_FP64 && c->tune.graph) {
         // all systems: replays of captured chunks, as in the FP32C advance.
         // A chunk is keyed by its length, the state buffer it starts from,
@@ -668,7 +776,8 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
         for (int32_t left = n; left > 0;) {
             const int32_t k = std::min(left, kGraphChunk);
             const int mode = (1 << 16) | (c->cur << 8) | ((int)lat << 9) |
-                             ((int)(c->Tl64 > c->Tl64b) << 10) | (eatom ? 1 << 12 : 0);
+                             ((int)(c->Tl64 > c->Tl64b) << 10) | (eatom ? 1 << 12 : 0) |
+                             (brick64 ? 1 << 13 : 0);
             GraphKey key{k, mode, 0};
             auto it = c->graphs.find(key);
             if (it == c->graphs.end()) {
@@ -679,14 +788,9 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
                 L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
                 c->stream = c->cap_stream;
                 double *tlb[2] = {c->Tl64, c->Tl64b};
-                for (int32_t q = 0; q < k; ++q) {
-                    const int cu = c->cur ^ (q & 1);
-                    hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns,
-                                       c->col, c->T64[cu], c->T64[cu ^ 1],
-                                       lat ? tlb[q & 1] : c->Tl64, lat ? tlb[(q & 1) ^ 1] : nullptr,
-                                       c->srcw64, c->dparams, c->dstep, q, c->ledger, eatom,
-                                       c->derr);
-                }
+                for (int32_t q = 0; q < k; ++q)
+                    step64(c->cur ^ (q & 1), q, lat ? tlb[q & 1] : c->Tl64,
+                           lat ? tlb[(q & 1) ^ 1] : nullptr);
                 hipLaunchKernelGGL(k_bump, dim3(nblk((int64_t)c->sys.size(), 256)), dim3(256), 0,
                                    c->stream, c->dstep, 0, (int32_t)c->sys.size(), k);
                 const hipError_t el = hipGetLastError();
@@ -716,11 +820,7 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     int cur = c->cur;
     for (int32_t k = 0; k < n; ++k) {
         if (c->precision == L2T_FP64) {
-            const double *tl_in = lat ? tl_buf[k & 1] : c->Tl64;
-            double *tl_out = lat ? tl_buf[(k & 1) ^ 1] : nullptr;
-            hipLaunchKernelGGL(k_step_fp64, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
-                               c->T64[cur], c->T64[cur ^ 1], tl_in, tl_out, c->srcw64, c->dparams,
-                               c->dstep, k, c->ledger, eatom, c->derr);
+            step64(cur, k, lat ? tl_buf[k & 1] : c->Tl64, lat ? tl_buf[(k & 1) ^ 1] : nullptr);
         } else {
             hipLaunchKernelGGL(k_step_fp32c, grid, block, 0, c->stream, c->slices, s0, ns, c->col,
                                c->Thi[cur], c->Thi[cur ^ 1], c->Tlo, c->Tl32, c->srcw32,

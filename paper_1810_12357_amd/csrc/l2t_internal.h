@@ -94,6 +94,7 @@ struct SystemState {
     int32_t atom_off = 0;        // first internal slot
     int32_t n_pad = 0;           // internal slots (multiple of 64)
     int32_t slice0 = 0, n_slices = 0;
+    int32_t list0 = 0, n_list = 0;   // this system's non-empty bricks in the brick list
     int32_t nc[3] = {1, 1, 1};
     int64_t cell_off = 0, ncell = 0;
     int64_t step = 0;            // sub-steps since the last T_e write

@@ -130,21 +130,26 @@ struct Fp64Lane {
 // copy of the system).  tl_new is the lattice temperature after the step
 // (the Section 3.1 Fourier law when the system carries the lattice mode,
 // otherwise tl_i); e2l, q and lt are the lane's ledger terms.
-template <class TOf, class TlOf>
-__device__ __forceinline__ Fp64Lane lane_step_fp64(const SliceInfo &si, int lane, bool valid,
-                                                   const DevParams &p,
-                                                   const int32_t *__restrict__ col, double Ti,
-                                                   double tl_i, double sw, TOf T_of, TlOf Tl_of,
-                                                   int64_t step, unsigned *err) {
+// ref_at(k) returns the lane's k-th neighbour reference (a global slot, or
+// the byte offset of an LDS tile entry), T_of and Tl_of the step-n T and
+// T^lat it refers to.  LAT = false compiles the lattice mode out (for
+// launches that never carry a system in that mode).
+template <bool LAT = true, class RefAt, class TOf, class TlOf>
+__device__ __forceinline__ Fp64Lane lane_step_fp64_refs(const SliceInfo &si, bool valid,
+                                                        const DevParams &p, RefAt ref_at,
+                                                        double Ti, double tl_i, double sw,
+                                                        TOf T_of, TlOf Tl_of, int64_t step,
+                                                        unsigned *err) {
     Fp64Lane r{Ti, tl_i, 0.0, 0.0, 0.0};
-    const int64_t base = (int64_t)si.col_base64 * kWave + lane;
     // two-temperature lattice (Section 3.1): the Fourier law over the same
     // neighbours plus the coupling, from the step-n states
-    if (p.lat_fd && valid) {
-        const double tli = fabs(tl_i);
-        double Lsum = 0.0;
-        for (int32_t k = 0; k < si.width; ++k) Lsum += fabs(Tl_of(col[base + (int64_t)k * kWave])) - tli;
-        r.tl_new = tli + p.dt * (p.K_lat * Lsum + p.g_over_clat * (Ti - tli));
+    if constexpr (LAT) {
+        if (p.lat_fd && valid) {
+            const double tli = fabs(tl_i);
+            double Lsum = 0.0;
+            for (int32_t k = 0; k < si.width; ++k) Lsum += fabs(Tl_of(ref_at(k))) - tli;
+            r.tl_new = tli + p.dt * (p.K_lat * Lsum + p.g_over_clat * (Ti - tli));
+        }
     }
     const double ti = (Ti - p.T_min) * p.inv_span;
     // the literal pair term of Eq. 2 in theta units
@@ -159,16 +164,16 @@ __device__ __forceinline__ Fp64Lane lane_step_fp64(const SliceInfo &si, int lane
     double S = 0.0;
     int32_t k = 0;
     for (; k + kChunk <= si.width; k += kChunk) {
-        int32_t j[kChunk];
+        decltype(ref_at(0)) j[kChunk];
         double Tj[kChunk];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) j[u] = col[base + (int64_t)(k + u) * kWave];
+        for (int u = 0; u < kChunk; ++u) j[u] = ref_at(k + u);
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) Tj[u] = T_of(j[u]);
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) S += pair(Tj[u]);
     }
-    for (; k < si.width; ++k) S += pair(T_of(col[base + (int64_t)k * kWave]));
+    for (; k < si.width; ++k) S += pair(T_of(ref_at(k)));
     if (valid) {
         const double c = ce64(p, Ti);
         const double coup = (signbit(tl_i) && !p.lat_fd) ? 0.0 : p.g * (Ti - fabs(tl_i));
@@ -187,6 +192,19 @@ __device__ __forceinline__ Fp64Lane lane_step_fp64(const SliceInfo &si, int lane
         r.q = q * p.dt;
     }
     return r;
+}
+
+// the same lane with its neighbours through the int32 global-slot table
+template <class TOf, class TlOf>
+__device__ __forceinline__ Fp64Lane lane_step_fp64(const SliceInfo &si, int lane, bool valid,
+                                                   const DevParams &p,
+                                                   const int32_t *__restrict__ col, double Ti,
+                                                   double tl_i, double sw, TOf T_of, TlOf Tl_of,
+                                                   int64_t step, unsigned *err) {
+    const int32_t *__restrict__ cp = col + (int64_t)si.col_base64 * kWave + lane;
+    return lane_step_fp64_refs(
+        si, valid, p, [&](int32_t k) { return cp[(int64_t)k * kWave]; }, Ti, tl_i, sw, T_of,
+        Tl_of, step, err);
 }
 
 // one slice through HBM; Tl_out, when given, receives T^lat after the step

@@ -173,3 +173,41 @@ def test_full_size_held_shell_and_mean_field(c3_full):
     e = ctx.energies(0)
     assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(sy.T_e0.sum(), rel=1e-7)
     ctx.close()
+
+
+def test_fp64_brick_and_global_forms_are_bitwise_equal():
+    """The FP64 sub-step through LDS brick tiles and through global gathers
+    on a 400,000-atom laser slab with held end cells (more bricks than CUs,
+    so the brick form runs), the per-atom record on, two advances of odd
+    length, per-system and batched launches, graphs on and off: states,
+    records and ledgers are bitwise equal, and match the oracle."""
+    sy = W.c4_slab(4.0e5, 0.2)
+    sy.params = dict(sy.params, g=2e-6)
+    x = sy.pos[0]
+    sy.T_e0 = sy.T_e0 + np.linspace(0.0, 800.0, sy.n)
+    fixed = ((x < x.min() + W.A_LAT) | (x > x.max() - W.A_LAT)).astype(np.int32)
+    w = W.Workload("slab_400k_fp64", [sy], r_cut=1.1 * W.A_LAT, n_substeps=300,
+                   precision="fp64")
+    n1, n2 = 137, 163
+    runs = []
+    for kernel, batch, graph in ((1, 0, 1), (0, 0, 1), (1, 1, 1), (0, 1, 0), (1, 1, 0)):
+        ctx = gpu_context(w, L.L2T_FP64)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, graph)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, batch)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_ATOM_LEDGER, 1)
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_FIXED, fixed.astype(np.float64))
+        ctx.advance(n1)
+        ctx.advance(n2)
+        runs.append((ctx.get(0), ctx.get(0, L.L2T_FIELD_ELAT), ctx.energies(0)))
+        ctx.close()
+    for T, E, en in runs[1:]:
+        assert np.array_equal(T, runs[0][0])
+        assert np.array_equal(E, runs[0][1])
+        for k in ("E_e_to_l", "E_src", "T_ledger_acc", "sum_T"):
+            assert en[k] == runs[0][2][k]
+    row, col = oracle_neighbors(sy, w.r_cut)
+    T, _, bad = oracle.run(row, col, sy.T_e0, sy.T_l, sy.params, n1 + n2, x=sy.pos[0],
+                           fixed=fixed)
+    assert bad == 0
+    assert max_rel(runs[0][0], T) < 1e-12
