@@ -351,16 +351,20 @@ def bench_c3_fp64(L, torch, w, n_sub=100):
     e1.record()
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / n_sub
-    ctx.close()
     log(f"  C3 FP64 plain: {us:.1f} us per sub-step")
-    # k_step_fp64 per atom-substep: T read and write (16), T_lat (8), row
-    # offset (4), one int32 index per neighbour (4 n_mean)
-    bytes_per = 28.0 + 4.0 * mean
+    # per atom-substep: T read and write (16), T_lat (8), row offset (4), one
+    # index per neighbour (2 B brick-local in k_brick_fp64, the form a launch
+    # of this many bricks takes; 4 B in the global-gather k_step_fp64)
+    brick = L.l2t_get_option(ctx.h, L.L2T_OPT_KERNEL) == 1
+    ctx.close()
+    bytes_per = 28.0 + (2.0 if brick else 4.0) * mean
     gbps = bytes_per * sy.n / (us * 1e-6) / 1e9
     return dict(substeps=n_sub, substep_us=us, atom_substeps_per_s=sy.n / (us * 1e-6),
-                kernel="k_step_fp64", algorithmic_bytes_per_atom_substep=bytes_per,
+                kernel="k_brick_fp64" if brick else "k_step_fp64",
+                algorithmic_bytes_per_atom_substep=bytes_per,
                 achieved_GBps=gbps, frac=gbps / HBM_PEAK_GBS,
-                bound="latency of the neighbour gathers (vector issue is about half the launch)")
+                bound="vector work: two FP64 exponentials per pair of the literal pair term"
+                      if brick else "latency of the neighbour gathers")
 
 
 def cpu_baseline(L, torch, w, n_steps):
