@@ -336,12 +336,15 @@ def copy_rate(torch, dev, reps=5):
     return gbps
 
 
-def bench_c3_fp64(L, torch, w, n_sub=100):
+def bench_c3_fp64(L, torch, w, n_sub=100, kernel="auto"):
     """The same 4M-atom system in the plain FP64 form (one launch per
     sub-step): a bounded sample of sub-steps timed with HIP events, for the
-    FP32C / FP64 ratio on this system."""
+    FP32C / FP64 ratio on this system.  kernel pins the FP64 launch form as
+    --kernel does for FP32C."""
     sy = w.systems[0]
     ctx = L.Context(w.systems, L.L2T_FP64, stream=torch.cuda.current_stream().cuda_stream)
+    if kernel != "auto":
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, 1 if kernel == "brick" else 0)
     _, mean, _ = ctx.setup(w.r_cut)
     ctx.advance(4)
     torch.cuda.synchronize()
@@ -410,7 +413,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the recorded forward and adjoint timing")
     ap.add_argument("--no-md", action="store_true", help="skip the lattice-side (Eq. 5, 8) timing")
-    ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto")
+    ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto",
+                    help="pin the sub-step launch form (FP32C pass and FP64 sample)")
     ap.add_argument("--brick-edge", type=int, default=0)
     ap.add_argument("--block", type=int, default=0,
                     help="threads per workgroup of the sub-step kernel (0 = autotuned)")
@@ -520,7 +524,7 @@ def main():
     ctx.close()
     if not args.no_fp64:
         log("C3 in plain FP64 ...")
-        f64 = bench_c3_fp64(L, torch, w)
+        f64 = bench_c3_fp64(L, torch, w, kernel=args.kernel)
         f64["fp32c_over_fp64"] = out["advance_only_atom_substeps_per_s"] / f64["atom_substeps_per_s"]
         out["c3_fp64"] = f64
     if not args.no_c4:
