@@ -386,38 +386,53 @@ __global__ __launch_bounds__(256) void k_cell_rows(
     const int mz = axis_cells(ic[2], g.nc[2], g.periodic[2], sz, oz);
     const BrickInfo bi = bricks[brick_of_rank[r]];
     const int64_t row = (caller_off + k) * (int64_t)wcap;
+    // the stencil cells in row order t = (a my + b) mz + e: lane t looks up
+    // cell t's rank, atom range and halo offset, so the wave waits for one
+    // round of these loads instead of one dependent chain per stencil cell
+    const int32_t nst = mx * my * mz;
+    int32_t q0_l = 0, ms_l = 0, hc_l = 0;
+    if (lane < nst) {
+        const int a = lane / (my * mz), b = (lane / mz) % my, e = lane % mz;
+        const int32_t xa = a == 0 ? sx[0] : (a == 1 ? sx[1] : sx[2]);
+        const int32_t yb = b == 0 ? sy[0] : (b == 1 ? sy[1] : sy[2]);
+        const int32_t ze = e == 0 ? sz[0] : (e == 1 ? sz[1] : sz[2]);
+        const int32_t oa = a == 0 ? ox[0] : (a == 1 ? ox[1] : ox[2]);
+        const int32_t ob = b == 0 ? oy[0] : (b == 1 ? oy[1] : oy[2]);
+        const int32_t oe = e == 0 ? oz[0] : (e == 1 ? oz[1] : oz[2]);
+        const int32_t rk = rank_of_cell[(xa * g.nc[1] + yb) * g.nc[2] + ze];
+        const int32_t p0c = ic[0] - bi.o[0] + oa + 1;
+        const int32_t p1c = ic[1] - bi.o[1] + ob + 1;
+        const int32_t p2c = ic[2] - bi.o[2] + oe + 1;
+        hc_l = shell[bi.shell_off + (p0c * bi.sh[1] + p1c) * bi.sh[2] + p2c];
+        q0_l = start[rk];
+        ms_l = start[rk + 1] - q0_l;
+    }
     int32_t len = 0;
-    for (int a = 0; a < mx; ++a)
-        for (int b = 0; b < my; ++b)
-            for (int e = 0; e < mz; ++e) {
-                const int32_t cell = (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[e];
-                const int32_t rk = rank_of_cell[cell];
-                const int32_t q0 = start[rk], ms = start[rk + 1] - q0;
-                const int32_t p0c = ic[0] - bi.o[0] + ox[a] + 1;
-                const int32_t p1c = ic[1] - bi.o[1] + oy[b] + 1;
-                const int32_t p2c = ic[2] - bi.o[2] + oz[e] + 1;
-                const int32_t hcell = shell[bi.shell_off + (p0c * bi.sh[1] + p1c) * bi.sh[2] + p2c];
-                for (int32_t c0 = 0; c0 < ms; c0 += T) {
-                    const int32_t jq = c0 + tl;
-                    const int32_t q = q0 + jq;
-                    bool acc = false;
-                    if (tl < T && jq < ms && q != k) {
-                        const double dx = min_image(cx[q] - xk, g.len[0], g.periodic[0]);
-                        const double dy = min_image(cy[q] - yk, g.len[1], g.periodic[1]);
-                        const double dz = min_image(cz[q] - zk, g.len[2], g.periodic[2]);
-                        acc = dx * dx + dy * dy + dz * dz <= rc2;
-                    }
-                    const uint64_t mask = __ballot(acc);
-                    if (acc) {
-                        const int32_t m = len + __popcll(mask & mine & below);
-                        if (m < wcap) {
-                            tq[row + m] = (int32_t)(caller_off + q);
-                            th[row + m] = (int16_t)(hcell == -1 ? -1 : hcell + jq);
-                        }
-                    }
-                    len += __popcll(mask & mine);
+    for (int32_t t = 0; t < nst; ++t) {
+        const int32_t q0 = __builtin_amdgcn_readlane(q0_l, t);
+        const int32_t ms = __builtin_amdgcn_readlane(ms_l, t);
+        const int32_t hcell = __builtin_amdgcn_readlane(hc_l, t);
+        for (int32_t c0 = 0; c0 < ms; c0 += T) {
+            const int32_t jq = c0 + tl;
+            const int32_t q = q0 + jq;
+            bool acc = false;
+            if (tl < T && jq < ms && q != k) {
+                const double dx = min_image(cx[q] - xk, g.len[0], g.periodic[0]);
+                const double dy = min_image(cy[q] - yk, g.len[1], g.periodic[1]);
+                const double dz = min_image(cz[q] - zk, g.len[2], g.periodic[2]);
+                acc = dx * dx + dy * dy + dz * dz <= rc2;
+            }
+            const uint64_t mask = __ballot(acc);
+            if (acc) {
+                const int32_t m = len + __popcll(mask & mine & below);
+                if (m < wcap) {
+                    tq[row + m] = (int32_t)(caller_off + q);
+                    th[row + m] = (int16_t)(hcell == -1 ? -1 : hcell + jq);
                 }
             }
+            len += __popcll(mask & mine);
+        }
+    }
     if (tl == 0) {
         cnt[pos_slot[caller_off + k]] = len;
         if (len > wcap) atomicOr(overflow, 1u);
