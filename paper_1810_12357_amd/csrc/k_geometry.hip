@@ -774,18 +774,41 @@ __global__ void k_lattice_temp(int32_t atom_off, int32_t n_pad, const int32_t *p
     } else {
         const double xi = vx[k], yi = vy[k], zi = vz[k];
         double M = ms[k], P[3] = {0.0, 0.0, 0.0}, Q = 0.0;
-        for (int32_t q = 0; q < si.width; ++q) {
-            const int32_t j = col[base + (int64_t)q * kWave];
-            if (j == slot) continue;
-            const int32_t l = j - atom_off;
-            const double m = ms[l];
-            const double ux = vx[l] - xi, uy = vy[l] - yi, uz = vz[l] - zi;
+        auto add = [&](int32_t j, double m, double wx, double wy, double wz) {
+            if (j == slot) return;   // row padding
+            const double ux = wx - xi, uy = wy - yi, uz = wz - zi;
             M += m;
             P[0] += m * ux;
             P[1] += m * uy;
             P[2] += m * uz;
             Q += m * (ux * ux + uy * uy + uz * uz);
             ++nj;
+        };
+        // neighbours 8 at a time: the chunk's references, then their
+        // velocities and masses, are requested before any is added; the sums
+        // take the terms in row order either way
+        constexpr int kChunk = 8;
+        int32_t q = 0;
+        for (; q + kChunk <= si.width; q += kChunk) {
+            int32_t j[kChunk];
+            double m[kChunk], wx[kChunk], wy[kChunk], wz[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) j[u] = col[base + (int64_t)(q + u) * kWave];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const int32_t l = j[u] - atom_off;
+                m[u] = ms[l];
+                wx[u] = vx[l];
+                wy[u] = vy[l];
+                wz[u] = vz[l];
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) add(j[u], m[u], wx[u], wy[u], wz[u]);
+        }
+        for (; q < si.width; ++q) {
+            const int32_t j = col[base + (int64_t)q * kWave];
+            const int32_t l = j - atom_off;
+            add(j, ms[l], vx[l], vy[l], vz[l]);
         }
         const double P2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
         // v_i - v_com = -P / M
