@@ -65,8 +65,14 @@ __device__ inline int axis_cells(int32_t c, int32_t nc, int32_t periodic, int32_
     return m;
 }
 
+// Positions on a periodic axis lie in [lo, lo + len), so |d| < len and the
+// nearest image is at most one box length away: the shift of
+// d - len * rint(d / len) without its division, equal to it except where d is
+// within an ulp of half a box length (a tie of measure zero).
 __device__ inline double min_image(double d, double len, int32_t periodic) {
-    return periodic ? d - len * rint(d / len) : d;
+    if (!periodic) return d;
+    const double h = 0.5 * len;
+    return d > h ? d - len : (d < -h ? d + len : d);
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -408,18 +414,36 @@ __global__ __launch_bounds__(256) void k_cell_rows(
         ms_l = start[rk + 1] - q0_l;
     }
     int32_t len = 0;
+    // the first chunk of candidate positions of the next stencil cell is
+    // requested before the current cell is searched
+    double nx = 0.0, ny = 0.0, nz = 0.0;
+    auto first_chunk = [&](int32_t t, double &px, double &py, double &pz) {
+        const int32_t q0 = __builtin_amdgcn_readlane(q0_l, t);
+        const int32_t ms = __builtin_amdgcn_readlane(ms_l, t);
+        if (tl < T && tl < ms) {
+            px = cx[q0 + tl];
+            py = cy[q0 + tl];
+            pz = cz[q0 + tl];
+        }
+    };
+    if (nst > 0) first_chunk(0, nx, ny, nz);
     for (int32_t t = 0; t < nst; ++t) {
         const int32_t q0 = __builtin_amdgcn_readlane(q0_l, t);
         const int32_t ms = __builtin_amdgcn_readlane(ms_l, t);
         const int32_t hcell = __builtin_amdgcn_readlane(hc_l, t);
+        const double fx = nx, fy = ny, fz = nz;
+        if (t + 1 < nst) first_chunk(t + 1, nx, ny, nz);
         for (int32_t c0 = 0; c0 < ms; c0 += T) {
             const int32_t jq = c0 + tl;
             const int32_t q = q0 + jq;
             bool acc = false;
             if (tl < T && jq < ms && q != k) {
-                const double dx = min_image(cx[q] - xk, g.len[0], g.periodic[0]);
-                const double dy = min_image(cy[q] - yk, g.len[1], g.periodic[1]);
-                const double dz = min_image(cz[q] - zk, g.len[2], g.periodic[2]);
+                const double px = c0 == 0 ? fx : cx[q];
+                const double py = c0 == 0 ? fy : cy[q];
+                const double pz = c0 == 0 ? fz : cz[q];
+                const double dx = min_image(px - xk, g.len[0], g.periodic[0]);
+                const double dy = min_image(py - yk, g.len[1], g.periodic[1]);
+                const double dz = min_image(pz - zk, g.len[2], g.periodic[2]);
                 acc = dx * dx + dy * dy + dz * dz <= rc2;
             }
             const uint64_t mask = __ballot(acc);
