@@ -34,7 +34,8 @@
  *   - Every function returns an int status (L2T_OK = 0; negative values are
  *     errors; positive values are warnings).  No C++ exception crosses the
  *     ABI.  After an error, l2t_last_error() holds a message.
- *   - A context owns all device buffers it allocates; the caller owns every
+ *   - A context owns all device buffers it allocates (through hipMalloc, or
+ *     the caller's allocator after l2t_set_allocator); the caller owns every
  *     pointer it passes in.  Caller pointers are borrowed for the duration of
  *     the call only: host buffers are copied before the call returns; device
  *     buffers are read or written in order on the context's stream.
@@ -43,6 +44,7 @@
  *   - mem = L2T_HOST for host pointers, L2T_DEVICE for device pointers on the
  *     context's device.
  *   - A context is not thread-safe: use one context per host thread.
+ *     Contexts on different threads may work at the same time.
  *   - All work runs on the HIP stream passed to l2t_create (0 = the null
  *     stream) and is asynchronous unless the function says it synchronises.
  */
