@@ -237,6 +237,15 @@ def test_torch_caching_allocator_owns_the_device_memory():
     dK, dg = L.l2t_adjoint(ctx.h, dL, len(w.systems))
     assert np.all(np.isfinite(dK)) and np.all(np.isfinite(dg))
     held = torch.cuda.memory_allocated()
+    # one hook without the other is refused; NULL for both restores hipMalloc
+    with pytest.raises(L.L2TError) as e:
+        L.l2t_set_allocator(ctx.h, ctx._hooks[0], None)
+    assert e.value.status == L.L2T_EINVAL
+    L.l2t_set_allocator(ctx.h, None, None)
+    # a larger recording: its old buffer goes back to torch, the new one comes
+    # from hipMalloc
+    L.l2t_advance_recorded(ctx.h, 400, 10)
+    assert base < torch.cuda.memory_allocated() < held
     ctx.close()
     torch.cuda.synchronize()
     assert held > base and torch.cuda.memory_allocated() == base
