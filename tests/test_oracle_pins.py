@@ -306,6 +306,41 @@ def test_energy_ledger_constant_uniform_c():
     assert led[0] > 0 and led[1] > 0
 
 
+@pytest.mark.parametrize("model", ["const", "linear", "capped"])
+def test_electronic_energy_is_the_integral_of_the_heat_capacity(model):
+    """E(T) = integral_0^T c dT' (the electronic energy whose rate of change
+    Eq. 6 balances), checked against adaptive quadrature of c itself.  For the
+    capped model c = min(gamma T, cap) this fixes the gamma T*^2/2 - cap T*
+    offset above T* = cap / gamma, which no energy difference sees."""
+    from scipy.integrate import quad
+    gamma, cap, c0 = 1e-4, 3.0 * W.K_B, W.C_NI
+    c_of = {"const": lambda t: c0, "linear": lambda t: gamma * t,
+            "capped": lambda t: min(gamma * t, cap)}[model]
+    ce = {"const": W.CE_CONST, "linear": W.CE_LINEAR, "capped": W.CE_CAPPED}[model]
+    p = W.default_params(ce_model=ce, ce_const=c0, gamma=gamma, ce_cap=cap)
+    Ts = cap / gamma                                   # 2.585 K: where the cap engages
+    temps = [0.5 * Ts, Ts, 1.5 * Ts, 300.0, 8036.0, 19999.0]
+    for T in temps:
+        pts = [Ts] if (model == "capped" and T > Ts) else None
+        ref, _ = quad(c_of, 0.0, T, points=pts, epsabs=0.0, epsrel=1e-13, limit=200)
+        E, S = oracle.energies(np.array([T]), p)
+        assert S == T
+        assert E == pytest.approx(ref, rel=1e-12), (model, T)
+    if model == "capped":
+        # continuous at T*, slope c on both sides (no kink in E, only in c)
+        h = 1e-7 * Ts
+        lo, _ = oracle.energies(np.array([Ts - h]), p)
+        at, _ = oracle.energies(np.array([Ts]), p)
+        hi, _ = oracle.energies(np.array([Ts + h]), p)
+        assert at == pytest.approx(0.5 * cap * Ts, rel=1e-15)
+        assert (at - lo) / h == pytest.approx(cap, rel=1e-6)
+        assert (hi - at) / h == pytest.approx(cap, rel=1e-6)
+        # the C3 field: every T_e is above T*, so E_e = cap sum T - N cap T*/2
+        s = W.c3(n_cells=4).systems[0]
+        E, S = oracle.energies(s.T_e0, s.params)
+        assert E == pytest.approx(cap * S - s.n * cap * Ts / 2.0, rel=1e-14)
+
+
 def test_temperature_ledger_any_c():
     s = W.c4_slab(3000, 0.4)
     row, col = _nbrs(s, 1.1 * W.A_LAT)
