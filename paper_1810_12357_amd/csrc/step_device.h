@@ -152,10 +152,12 @@ __device__ __forceinline__ Fp64Lane lane_step_fp64_refs(const SliceInfo &si, boo
         }
     }
     const double ti = (Ti - p.T_min) * p.inv_span;
-    // the literal pair term of Eq. 2 in theta units
+    // the literal pair term of Eq. 2 in theta units; its two exponentials are
+    // e and 1/e, so one exponential and one division per pair
     auto pair = [&](double Tj) {
         const double tj = (Tj - p.T_min) * p.inv_span;
-        return tj * (1.0 - ti) * exp(ti - tj) - ti * (1.0 - tj) * exp(tj - ti);
+        const double e = exp(ti - tj);
+        return tj * (1.0 - ti) * e - ti * (1.0 - tj) / e;
     };
     // neighbours in chunks of 8: the chunk's references, then its temperatures,
     // are requested before any term is evaluated, so 8 loads are in flight
