@@ -146,16 +146,51 @@ def _is_torch(a) -> bool:
     return type(a).__module__.startswith("torch")
 
 
-def _ptr(a, dtype=np.float64):
-    """(pointer, mem, keepalive) for a numpy array or a torch tensor."""
+# per context handle: atom count of every system and the HIP device, recorded
+# by l2t_create so that array arguments can be checked before the call
+_CTX_INFO: dict = {}
+
+
+def _sys_n(ctx, sys: int):
+    info = _CTX_INFO.get(getattr(ctx, "value", ctx))
+    if info is None or not (0 <= sys < len(info[0])):
+        return None
+    return info[0][sys]
+
+
+def _ctx_device(ctx):
+    info = _CTX_INFO.get(getattr(ctx, "value", ctx))
+    return None if info is None else info[1]
+
+
+def _ptr(a, dtype=np.float64, n=None, out=False, ctx=None):
+    """(pointer, mem, keepalive) for a numpy array or a torch tensor.
+
+    n: required element count (None = unchecked).  out: the library writes
+    the buffer, so it must already have the dtype and layout (no copy).
+    ctx: a device tensor must live on the context's GPU."""
     if _is_torch(a):
         import torch
         want = {np.float64: torch.float64, np.float32: torch.float32,
                 np.int32: torch.int32, np.int64: torch.int64}[dtype]
         if a.dtype != want or not a.is_contiguous():
             raise TypeError(f"tensor must be contiguous {want}")
+        if n is not None and a.numel() != n:
+            raise ValueError(f"tensor has {a.numel()} elements, expected {n}")
+        if a.is_cuda and ctx is not None:
+            dev = _ctx_device(ctx)
+            if dev is not None and a.device.index != dev:
+                raise ValueError(f"tensor on cuda:{a.device.index}, context on cuda:{dev}")
         return C.c_void_p(a.data_ptr()), (L2T_DEVICE if a.is_cuda else L2T_HOST), a
-    arr = np.ascontiguousarray(a, dtype=dtype)
+    if out:
+        if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous
+                and a.flags.writeable):
+            raise TypeError(f"output must be a writeable contiguous {np.dtype(dtype)} array")
+        arr = a
+    else:
+        arr = np.ascontiguousarray(a, dtype=dtype)
+    if n is not None and arr.size != n:
+        raise ValueError(f"array has {arr.size} elements, expected {n}")
     return C.c_void_p(arr.ctypes.data), L2T_HOST, arr
 
 
@@ -202,10 +237,19 @@ def l2t_create(descs, precision: int, stream=None):
     arr = (l2t_system_desc * len(descs))(*descs)
     h = C.c_void_p()
     _check(None, load().l2t_create(C.byref(h), len(descs), arr, precision, _stream(stream)))
+    dev = None
+    try:
+        import torch
+        if torch.cuda.is_available():
+            dev = torch.cuda.current_device()
+    except Exception:
+        pass
+    _CTX_INFO[h.value] = ([int(d.n_atoms) for d in descs], dev)
     return h
 
 
 def l2t_destroy(ctx) -> None:
+    _CTX_INFO.pop(getattr(ctx, "value", ctx), None)
     load().l2t_destroy(ctx)
 
 
@@ -217,16 +261,21 @@ def l2t_set_allocator(ctx, alloc, free_, user=None) -> int:
     return _check(ctx, load().l2t_set_allocator(ctx, a, f, user))
 
 
-def torch_allocator(device=None):
+def torch_allocator(device=None, stream=None):
     """(alloc, free_) hooks that take the context's device memory from
-    PyTorch's caching allocator on the current stream."""
+    PyTorch's caching allocator on the context's stream (the HIP stream
+    handle given to l2t_create; None or 0 = the device's null stream), so
+    that the caching allocator orders the reuse of a block after the library's
+    work on it."""
     import torch
     dev = torch.cuda.current_device() if device is None else int(device)
+    h = int(stream or 0)
+    s = (torch.cuda.ExternalStream(h, device=dev) if h
+         else torch.cuda.default_stream(dev))
 
     def _alloc(nbytes, _user):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), dev,
-                                                      torch.cuda.current_stream(dev))
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, s)
         except Exception:
             return None
 
@@ -237,7 +286,8 @@ def torch_allocator(device=None):
 
 
 def l2t_set_positions(ctx, sys: int, xyz) -> int:
-    p, mem, keep = _ptr(xyz)
+    n = _sys_n(ctx, sys)
+    p, mem, keep = _ptr(xyz, n=None if n is None else 3 * n, ctx=ctx)
     return _check(ctx, load().l2t_set_positions(ctx, sys, p, mem))
 
 
@@ -263,19 +313,20 @@ def l2t_set_params(ctx, sys: int, params: dict) -> int:
 
 
 def l2t_set_field(ctx, sys: int, field: int, src) -> int:
-    p, mem, keep = _ptr(src)
+    p, mem, keep = _ptr(src, n=_sys_n(ctx, sys), ctx=ctx)
     return _check(ctx, load().l2t_set_field(ctx, sys, field, p, mem))
 
 
 def l2t_get_field(ctx, sys: int, field: int, dst):
-    p, mem, keep = _ptr(dst)
+    p, mem, keep = _ptr(dst, n=_sys_n(ctx, sys), out=True, ctx=ctx)
     _check(ctx, load().l2t_get_field(ctx, sys, field, p, mem))
     return dst
 
 
 def l2t_set_velocities(ctx, sys: int, v, mass, global_com: bool = False) -> int:
-    pv, mem, kv = _ptr(v)
-    pm, mem2, km = _ptr(mass)
+    n = _sys_n(ctx, sys)
+    pv, mem, kv = _ptr(v, n=None if n is None else 3 * n, ctx=ctx)
+    pm, mem2, km = _ptr(mass, n=n, ctx=ctx)
     if mem != mem2:
         raise TypeError("velocities and masses must live in the same memory space")
     return _check(ctx, load().l2t_set_velocities(ctx, sys, pv, pm, mem, int(bool(global_com))))
@@ -294,12 +345,14 @@ def l2t_advance_recorded(ctx, n_substeps: int, ckpt_every: int) -> int:
 
 
 def l2t_adjoint(ctx, dL_dTN, n_systems: int, dL_dT0=None):
-    pw, mem, kw = _ptr(dL_dTN)
+    info = _CTX_INFO.get(getattr(ctx, "value", ctx))
+    N = None if info is None else sum(info[0])
+    pw, mem, kw = _ptr(dL_dTN, n=N, ctx=ctx)
     dK = np.zeros(n_systems)
     dg = np.zeros(n_systems)
     p0 = None
     if dL_dT0 is not None:
-        p0, mem0, k0 = _ptr(dL_dT0)
+        p0, mem0, k0 = _ptr(dL_dT0, n=N, out=True, ctx=ctx)
         if mem0 != mem:
             raise TypeError("dL_dTN and dL_dT0 must live in the same memory space")
     _check(ctx, load().l2t_adjoint(ctx, pw, mem, dK.ctypes.data, dg.ctypes.data, p0))
@@ -327,19 +380,12 @@ def l2t_get_params(ctx, sys: int) -> dict:
     return {k: getattr(p, k) for k, _ in p._fields_}
 
 
-def _out_ptr(a):
-    """Pointer of an output array, which must be written in place."""
-    if not _is_torch(a) and not (isinstance(a, np.ndarray) and a.dtype == np.float64
-                                 and a.flags.c_contiguous):
-        raise TypeError("output must be a contiguous float64 numpy array or torch tensor")
-    return _ptr(a)
-
-
 def l2t_coupling(ctx, sys: int, mode: int, dt_md: float, v, mass, xi):
     """Eq. 8 coupling coefficient into xi (see l2t.h)."""
-    pv, mem, kv = _ptr(v)
-    pm, mem2, km = _ptr(mass)
-    px, mem3, kx = _out_ptr(xi)
+    n = _sys_n(ctx, sys)
+    pv, mem, kv = _ptr(v, n=None if n is None else 3 * n, ctx=ctx)
+    pm, mem2, km = _ptr(mass, n=n, ctx=ctx)
+    px, mem3, kx = _ptr(xi, n=n, out=True, ctx=ctx)
     if not (mem == mem2 == mem3):
         raise TypeError("v, mass and xi must live in the same memory space")
     _check(ctx, load().l2t_coupling(ctx, sys, mode, float(dt_md), pv, pm, px, mem))
@@ -348,12 +394,14 @@ def l2t_coupling(ctx, sys: int, mode: int, dt_md: float, v, mass, xi):
 
 def l2t_damping_step(ctx, sys: int, dt_md: float, xi, force, mass, v):
     """One explicit step of Eq. 5 on v in place (see l2t.h)."""
-    px, mem, kx = _ptr(xi)
-    pm, mem2, km = _ptr(mass)
-    pv, mem3, kv = _out_ptr(v)
+    n = _sys_n(ctx, sys)
+    n3 = None if n is None else 3 * n
+    px, mem, kx = _ptr(xi, n=n, ctx=ctx)
+    pm, mem2, km = _ptr(mass, n=n, ctx=ctx)
+    pv, mem3, kv = _ptr(v, n=n3, out=True, ctx=ctx)
     pf, kf = None, None
     if force is not None:
-        pf, mem4, kf = _ptr(force)
+        pf, mem4, kf = _ptr(force, n=n3, ctx=ctx)
         if mem4 != mem:
             raise TypeError("force must live in the same memory space as v")
     if not (mem == mem2 == mem3):
@@ -421,12 +469,13 @@ class Context:
                  torch_memory: bool = False):
         self.systems = list(systems)
         self.precision = precision
-        self.h = l2t_create([desc_of(s) for s in self.systems], precision, stream)
+        hs = _stream(stream)
+        self.h = l2t_create([desc_of(s) for s in self.systems], precision, hs.value or 0)
         self._hooks = None
         if torch_memory:
-            # device buffers from PyTorch's caching allocator; the hooks live
-            # as long as the context
-            self._hooks = torch_allocator()
+            # device buffers from PyTorch's caching allocator, on the stream
+            # the context works on; the hooks live as long as the context
+            self._hooks = torch_allocator(stream=hs.value or 0)
             l2t_set_allocator(self.h, *self._hooks)
 
     def close(self):

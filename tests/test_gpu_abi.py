@@ -249,3 +249,32 @@ def test_torch_caching_allocator_owns_the_device_memory():
     ctx.close()
     torch.cuda.synchronize()
     assert held > base and torch.cuda.memory_allocated() == base
+
+
+def test_torch_memory_on_a_side_stream_with_a_busy_current_stream():
+    """A context on a side stream takes its blocks from PyTorch's caching
+    allocator on that stream, so blocks that torch work on the (busy) current
+    stream frees are not handed to the library while that work is pending;
+    the trajectory matches the oracle."""
+    import torch
+    from helpers import oracle_trajectory
+    w = W.c1(n_cells=6, n_substeps=300)
+    sy = w.systems[0]
+    side = torch.cuda.Stream()
+    ctx = L.Context(w.systems, L.L2T_FP32C, stream=side.cuda_stream, torch_memory=True)
+    base = torch.cuda.memory_allocated()
+    for k in range(3):
+        x = torch.randn(32 << 20, device="cuda")        # queue work on the current stream
+        for _ in range(8):
+            x = x * 1.0001 + 0.5
+        del x                                            # freed while that work may be pending
+        if k == 0:
+            ctx.setup(w.r_cut)
+            assert torch.cuda.memory_allocated() > base
+        ctx.advance(100)
+    T = ctx.get(0)
+    traj, _, bad = oracle_trajectory(sy, w.r_cut, [300])
+    assert bad == 0
+    assert np.max(np.abs(T - traj[0]) / traj[0]) < 1e-5
+    ctx.close()
+    torch.cuda.synchronize()
