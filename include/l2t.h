@@ -310,6 +310,23 @@ int l2t_get_field(l2t_ctx *ctx, int32_t sys, int32_t field, double *dst, int32_t
 int l2t_set_velocities(l2t_ctx *ctx, int32_t sys, const double *v, const double *mass,
                        int32_t mem, int32_t global_com);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight MD loops, harnesses that forbid hipMalloc): the same Eq. 4
+ * update as l2t_set_velocities, with v[3*n] and mass[n] DEVICE pointers on
+ * the context's device (no host staging), staged through a fixed array that
+ * the library holds on each GPU until the process ends instead of the
+ * context's grow-on-demand buffer.  The call allocates nothing: no hipMalloc,
+ * hipFree or caller allocator.  Limit: 4 doubles per atom slot (atoms of the
+ * system padded to a multiple of 64) + 4 <= 32 MiB, i.e. systems of at most
+ * 1,048,512 atoms; larger systems return EINVAL.  Every context on a GPU
+ * shares that GPU's array, so calls that overlap in time on one GPU (two
+ * host threads, or two contexts on different streams) race: serialise them.
+ * Results are bitwise those of l2t_set_velocities.  Synchronises.
+ * Errors: EINVAL (sys out of range, NULL, system over the limit, a mass not
+ * finite and > 0), ESTATE (neighbours or parameters missing), EHIP. */
+int l2t_set_velocities_noalloc(l2t_ctx *ctx, int32_t sys, const double *v, const double *mass,
+                               int32_t global_com);
+
 /* ---- time stepping ---------------------------------------------------------- */
 
 /* Advance every system by n_substeps explicit forward-Euler sub-steps of

@@ -359,6 +359,10 @@ int l2t_create(l2t_ctx **out, int32_t n_systems, const l2t_system_desc *descs, i
     c->precision = precision;
     c->stream = (hipStream_t)hip_stream;
     c->device = dev;
+    // device address of the allocation-free entry point's staging array on
+    // this device (looked up once per device; a failure is reported by that
+    // entry point, not here)
+    (void)l2t::static_scratch_init(dev);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
         c->n_cu = prop.multiProcessorCount;
@@ -604,6 +608,32 @@ int l2t_set_velocities(l2t_ctx *c, int32_t sys, const double *v, const double *m
     if (rc != L2T_OK) return rc;
     if (!ok) return l2t::fail(c, L2T_EINVAL, "masses must be finite and > 0");
     rc = l2t::lattice_temperature(c, sys, dv, dm, global_com);
+    if (rc != L2T_OK) return rc;
+    st.has_tl = true;
+    return L2T_OK;
+}
+
+int l2t_set_velocities_noalloc(l2t_ctx *c, int32_t sys, const double *v, const double *mass,
+                               int32_t global_com) {
+    if (bad_sys(c, sys) || !v || !mass) return l2t::fail(c, L2T_EINVAL, "bad system index or NULL");
+    SystemState &st = c->sys[sys];
+    if (4 * (size_t)st.n_pad + 4 > l2t::kStaticScratchBytes / sizeof(double))
+        return l2t::fail(c, L2T_EINVAL, "system larger than the static staging array");
+    if (!c->nbrs_built) return l2t::fail(c, L2T_ESTATE, "neighbour sets not built");
+    if (!st.has_params) return l2t::fail(c, L2T_ESTATE, "set parameters before velocities");
+    for (const void *p : {(const void *)v, (const void *)mass}) {
+        hipPointerAttribute_t a{};
+        hipError_t e = hipPointerGetAttributes(&a, p);
+        if (e != hipSuccess) (void)hipGetLastError();
+        if (e != hipSuccess || a.device != c->device ||
+            (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged))
+            return l2t::fail(c, L2T_EINVAL, "v and mass must be device memory of the context's GPU");
+    }
+    bool ok = true;
+    int rc = l2t::check_field_range(c, mass, st.desc.n_atoms, 1e-300, HUGE_VAL, &ok);
+    if (rc != L2T_OK) return rc;
+    if (!ok) return l2t::fail(c, L2T_EINVAL, "masses must be finite and > 0");
+    rc = l2t::lattice_temperature_static(c, sys, v, mass, global_com);
     if (rc != L2T_OK) return rc;
     st.has_tl = true;
     return L2T_OK;

@@ -1612,12 +1612,14 @@ int check_field_range(l2t_ctx *c, const double *src_dev, int64_t n, double lo, d
     return L2T_OK;
 }
 
-int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_dev, const double *m_dev,
-                        int32_t global_com) {
+namespace {
+
+// Eq. 4 for system sys with the velocities and masses gathered into internal
+// order in vm ([4][n_pad] doubles followed by the 4 doubles of the system's
+// momentum and mass); synchronises.
+int lattice_temperature_into(l2t_ctx *c, int32_t sys, const double *v_dev, const double *m_dev,
+                             int32_t global_com, double *vm) {
     const SystemState &st = c->sys[sys];
-    size_t need = sizeof(double) * (4 * (size_t)st.n_pad + 4);
-    if (ensure_scratch(c, need) != L2T_OK) return L2T_ENOMEM;
-    double *vm = (double *)c->scratch;
     double *gm = vm + 4 * (size_t)st.n_pad;
     hipLaunchKernelGGL(k_gather_vm, dim3(nblk(st.n_pad, 256)), dim3(256), 0, c->stream,
                        st.atom_off, st.n_pad, c->perm, st.caller_off, st.desc.n_atoms, v_dev, m_dev,
@@ -1630,6 +1632,56 @@ int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_dev, const doub
     L2T_HIP(c, hipGetLastError());
     L2T_HIP(c, hipStreamSynchronize(c->stream));
     return L2T_OK;
+}
+
+// Staging of the allocation-free Eq. 4 entry point: one array per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it names a stand-in, not device memory); it passes the
+// device address hipGetSymbolAddress returned for the current device.
+constexpr size_t kStaticScratchDoubles = kStaticScratchBytes / sizeof(double);
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+double *g_static_ptr[kMaxDevices] = {};
+hipError_t g_static_err[kMaxDevices] = {};
+bool g_static_done[kMaxDevices] = {};
+
+}  // namespace
+
+int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_dev, const double *m_dev,
+                        int32_t global_com) {
+    const SystemState &st = c->sys[sys];
+    size_t need = sizeof(double) * (4 * (size_t)st.n_pad + 4);
+    if (ensure_scratch(c, need) != L2T_OK) return L2T_ENOMEM;
+    return lattice_temperature_into(c, sys, v_dev, m_dev, global_com, (double *)c->scratch);
+}
+
+int static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return L2T_EINVAL;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_done[device]) {
+        // called with `device` current (l2t_create), once per device
+        void *p = nullptr;
+        g_static_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_static_ptr[device] = g_static_err[device] == hipSuccess ? (double *)p : nullptr;
+        g_static_done[device] = true;
+    }
+    return g_static_ptr[device] ? L2T_OK : L2T_EHIP;
+}
+
+int lattice_temperature_static(l2t_ctx *c, int32_t sys, const double *v_dev, const double *m_dev,
+                               int32_t global_com) {
+    const SystemState &st = c->sys[sys];
+    if (4 * (size_t)st.n_pad + 4 > kStaticScratchDoubles)
+        return fail(c, L2T_EINVAL, "system larger than the static staging array");
+    double *vm = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (c->device >= 0 && c->device < kMaxDevices) vm = g_static_ptr[c->device];
+    }
+    if (!vm) return fail(c, L2T_EHIP, "no device address for the static staging array");
+    return lattice_temperature_into(c, sys, v_dev, m_dev, global_com, vm);
 }
 
 int source_weights(l2t_ctx *c, int32_t sys) {

@@ -272,6 +272,14 @@ int permute_out(l2t_ctx *c, int32_t sys, int32_t field, double *dst_dev);
 int mark_held_slices(l2t_ctx *c, int32_t sys);   // kSliceHeld from the held atoms
 int lattice_temperature(l2t_ctx *c, int32_t sys, const double *v_caller, const double *m_caller,
                         int32_t global_com);
+// Eq. 4 staged through the file-scope device array of k_geometry.hip instead
+// of the context's scratch buffer: allocates nothing.  EINVAL when the system
+// needs more than kStaticScratchBytes (4 doubles per padded slot + 4).
+int lattice_temperature_static(l2t_ctx *c, int32_t sys, const double *v_dev, const double *m_dev,
+                               int32_t global_com);
+// device address of that array on `device` (current), looked up once per device
+int static_scratch_init(int device);
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
 int neighbors_to_host(l2t_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *col, int64_t cap);
 int source_weights(l2t_ctx *c, int32_t sys);
 int check_field_range(l2t_ctx *c, const double *src_dev, int64_t n, double lo, double hi,

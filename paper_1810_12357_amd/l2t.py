@@ -33,7 +33,7 @@ L2T_XI_INSTANT, L2T_XI_LEDGER = 0, 1
 # every symbol the header declares (checked by the CPU test suite)
 EXPORTS = ("l2t_create", "l2t_destroy", "l2t_set_positions", "l2t_build_neighbors",
            "l2t_get_neighbors", "l2t_set_params", "l2t_set_field", "l2t_get_field",
-           "l2t_set_velocities", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
+           "l2t_set_velocities", "l2t_set_velocities_noalloc", "l2t_advance", "l2t_advance_system", "l2t_advance_recorded",
            "l2t_adjoint", "l2t_energies", "l2t_sync", "l2t_set_option", "l2t_get_option",
            "l2t_coupling", "l2t_damping_step", "l2t_set_mean_field", "l2t_get_params",
            "l2t_set_lattice_fd", "l2t_set_counters", "l2t_set_allocator",
@@ -113,6 +113,7 @@ def load() -> C.CDLL:
         "l2t_set_field": (C.c_int, [vp, i32, i32, vp, i32]),
         "l2t_get_field": (C.c_int, [vp, i32, i32, vp, i32]),
         "l2t_set_velocities": (C.c_int, [vp, i32, vp, vp, i32, i32]),
+        "l2t_set_velocities_noalloc": (C.c_int, [vp, i32, vp, vp, i32]),
         "l2t_advance": (C.c_int, [vp, i32]),
         "l2t_advance_system": (C.c_int, [vp, i32, i32]),
         "l2t_advance_recorded": (C.c_int, [vp, i32, i32]),
@@ -330,6 +331,18 @@ def l2t_set_velocities(ctx, sys: int, v, mass, global_com: bool = False) -> int:
     if mem != mem2:
         raise TypeError("velocities and masses must live in the same memory space")
     return _check(ctx, load().l2t_set_velocities(ctx, sys, pv, pm, mem, int(bool(global_com))))
+
+
+def l2t_set_velocities_noalloc(ctx, sys: int, v, mass, global_com: bool = False) -> int:
+    """Eq. 4 as l2t_set_velocities, allocating nothing; v and mass are device
+    tensors (float64, contiguous)."""
+    for t in (v, mass):
+        if not (_is_torch(t) and t.is_cuda):
+            raise TypeError("l2t_set_velocities_noalloc takes device tensors")
+    n = _sys_n(ctx, sys)
+    pv, _, kv = _ptr(v, n=None if n is None else 3 * n, ctx=ctx)
+    pm, _, km = _ptr(mass, n=n, ctx=ctx)
+    return _check(ctx, load().l2t_set_velocities_noalloc(ctx, sys, pv, pm, int(bool(global_com))))
 
 
 def l2t_advance(ctx, n_substeps: int) -> int:
