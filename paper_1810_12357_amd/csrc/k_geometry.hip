@@ -867,8 +867,10 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-// Largest LDS tile (own slots + halo atoms) of one workgroup, in floats.
-constexpr int32_t kTileCapFloats = 16384;
+// Largest LDS tile (own slots + halo atoms) of one workgroup, in floats: 64 KB
+// less 256 bytes, which the FP32C brick kernel keeps beside the tile for its
+// per-wave temperature range.
+constexpr int32_t kTileCapFloats = 16384 - 64;
 
 namespace {
 

@@ -87,14 +87,17 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
     const int64_t *__restrict__ dstep, int32_t rel, double *__restrict__ ledger,
     double *__restrict__ eatom, unsigned *__restrict__ err) {
     extern __shared__ float tile[];
+    __shared__ float wlo[kBrickBlockMax / kWave], whi[kBrickBlockMax / kWave];
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
     const BrickInfo bi = bricks[list[logical]];
     // stage the tile: 8 independent loads in flight per thread (a sweep of
-    // 4..32 on the 4M-atom system: 8 and 6 fastest, 16 1.3 % slower, 32 spills)
+    // 4..32 on the 4M-atom system: 8 and 6 fastest, 16 1.3 % slower, 32 spills),
+    // keeping the range of the staged temperatures (padding slots aside)
     constexpr int U = 8;
     const int32_t B = blockDim.x;
+    float tmin = INFINITY, tmax = -INFINITY;
     for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
         float v[U];
 #pragma unroll
@@ -103,8 +106,14 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
             v[u] = (t < bi.n_own_pad) ? Thi[bi.slot0 + t] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + u * B < bi.n_own_pad) tile[t0 + u * B] = v[u];
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = t0 + u * B;
+            if (t < bi.n_own_pad) tile[t] = v[u];
+            if (t < bi.n_own) {
+                tmin = fminf(tmin, v[u]);
+                tmax = fmaxf(tmax, v[u]);
+            }
+        }
     }
     const int32_t *hl = halo + bi.halo_off;
     float *ht = tile + bi.n_own_pad;
@@ -120,18 +129,40 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         for (int u = 0; u < U; ++u) v[u] = Thi[id[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (t0 + u * B < bi.n_halo) ht[t0 + u * B] = v[u];
+            if (t0 + u * B < bi.n_halo) {
+                ht[t0 + u * B] = v[u];
+                tmin = fminf(tmin, v[u]);
+                tmax = fmaxf(tmax, v[u]);
+            }
     }
-    __syncthreads();
     // wave index, slice records and row widths are wave-uniform (scalar registers)
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
+    tmin = wave_min_f32(tmin);
+    tmax = wave_max_f32(tmax);
+    if (lane == 0) {
+        wlo[wave] = tmin;
+        whi[wave] = tmax;
+    }
+    __syncthreads();
     const int32_t ns = bi.n_own_pad / kWave;
     if (wave >= ns) return;
     // every slice of a brick belongs to the brick's system
     const DevParams &p = P[bi.sys];
-    const int64_t step = dstep[bi.sys] + rel;
+    const float qpulse = source_factor32(p, dstep[bi.sys] + rel);
+    // every row of the brick pairs two staged temperatures, so the FP32
+    // difference of any pair is at most the rounded span of the tile, and
+    // its square at most the span's (rounding is monotone): a span whose
+    // square lies within the lowest tier of the pair term puts every pair
+    // of the brick on that tier
+    float bmin = wlo[0], bmax = whi[0];
+    for (int k = 1; k < nw; ++k) {
+        bmin = fminf(bmin, wlo[k]);
+        bmax = fmaxf(bmax, whi[k]);
+    }
+    const float span = bmax - bmin;
+    const bool one_tier = __builtin_amdgcn_readfirstlane((int)(span * span <= p.f_w_tiny)) != 0;
     // ledger terms summed per lane over the wave's slices, reduced once per wave
     // into the row of the wave's first slice (all rows of a system are summed)
     LedgerTerms acc{0.0f, 0.0f, 0.0f};
@@ -146,9 +177,12 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         const float tl = Tl[slot];
         const float sw = (p.laser_on | held) ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
-        const LedgerTerms t = slice_core_brick(w, slot, lane < nv, p, Ti, lo, tl, sw,
-                                               colw + (int64_t)base * kWave, lane, tile, Thi_n,
-                                               Tlo, eatom, step, err);
+        const uint32_t *row = colw + (int64_t)base * kWave;
+        const LedgerTerms t =
+            one_tier ? slice_core_brick<false>(w, slot, lane < nv, p, Ti, lo, tl, sw, row, lane,
+                                               tile, Thi_n, Tlo, eatom, qpulse, err)
+                     : slice_core_brick<true>(w, slot, lane < nv, p, Ti, lo, tl, sw, row, lane,
+                                              tile, Thi_n, Tlo, eatom, qpulse, err);
         acc.e2l += t.e2l;
         acc.src += t.src;
         acc.lt += t.lt;

@@ -24,6 +24,14 @@ __device__ inline double wave_min(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
     return v;
 }
+__device__ inline float wave_max_f32(float v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ inline float wave_min_f32(float v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
 
 // ---- heat capacity models --------------------------------------------------------
 __device__ inline double ce64(const DevParams &p, double T) {
@@ -51,6 +59,11 @@ __device__ inline double pulse64(const DevParams &p, int64_t step) {
 __device__ inline float pulse32(const DevParams &p, int64_t step) {
     const float x = (float)(((double)step * p.dt - p.t0) * p.inv_sigma);
     return expf(-0.5f * x * x);
+}
+// i_0 times the Gaussian time factor of Eq. 10 at sub-step `step` (0 without the
+// source): the same for every atom of the system, so taken once per wave
+__device__ inline float source_factor32(const DevParams &p, int64_t step) {
+    return p.laser_on ? p.f_i0 * pulse32(p, step) : 0.0f;
 }
 
 // ---- FP32 pair term -------------------------------------------------------------
@@ -88,35 +101,66 @@ __device__ __forceinline__ PairK pair_consts(const DevParams &p) {
     return k;
 }
 
-__device__ __forceinline__ float pair32(float Ti, float Tj, const PairK &k) {
-    const float dT = Tj - Ti;
-    const float m = fmaf(Ti + Tj, k.hinv, k.moff);
-    const float a = fmaf(-m, m, m);
-    const float w = dT * dT;
-    float h;
-    if (w <= k.w_tiny) {
-        h = fmaf(a, fmaf(w, k.c_tiny, -2.0f), 1.0f);
+// h on the two upper tiers (w = dT^2 > w_tiny), a = 2 m (1 - m) / 2
+__device__ __forceinline__ float pair32_h_upper(float a, float w, const PairK &k) {
+    const float u = w * k.inv2;
+    float P, Q2;   // Q2 = -2 Q
+    if (u <= 1.0e-2f) {
+        P = fmaf(u * u, fmaf(u, -1.0f / 360.0f, -1.0f / 24.0f), 1.0f);
+        Q2 = fmaf(u, fmaf(u, -2.0f / 120.0f, -2.0f / 6.0f), -2.0f);
     } else {
-        const float u = w * k.inv2;
-        float P, Q2;   // Q2 = -2 Q
-        if (u <= 1.0e-2f) {
-            P = fmaf(u * u, fmaf(u, -1.0f / 360.0f, -1.0f / 24.0f), 1.0f);
-            Q2 = fmaf(u, fmaf(u, -2.0f / 120.0f, -2.0f / 6.0f), -2.0f);
-        } else {
-            float pp = fmaf(u, -5.0f / 479001600.0f, -4.0f / 3628800.0f);
-            pp = fmaf(u, pp, -3.0f / 40320.0f);
-            pp = fmaf(u, pp, -1.0f / 360.0f);
-            pp = fmaf(u, pp, -1.0f / 24.0f);
-            P = fmaf(u * u, pp, 1.0f);
-            float q = fmaf(u, -2.0f / 39916800.0f, -2.0f / 362880.0f);
-            q = fmaf(u, q, -2.0f / 5040.0f);
-            q = fmaf(u, q, -2.0f / 120.0f);
-            q = fmaf(u, q, -2.0f / 6.0f);
-            Q2 = fmaf(u, q, -2.0f);
-        }
-        h = fmaf(a, Q2, P);
+        float pp = fmaf(u, -5.0f / 479001600.0f, -4.0f / 3628800.0f);
+        pp = fmaf(u, pp, -3.0f / 40320.0f);
+        pp = fmaf(u, pp, -1.0f / 360.0f);
+        pp = fmaf(u, pp, -1.0f / 24.0f);
+        P = fmaf(u * u, pp, 1.0f);
+        float q = fmaf(u, -2.0f / 39916800.0f, -2.0f / 362880.0f);
+        q = fmaf(u, q, -2.0f / 5040.0f);
+        q = fmaf(u, q, -2.0f / 120.0f);
+        q = fmaf(u, q, -2.0f / 6.0f);
+        Q2 = fmaf(u, q, -2.0f);
     }
-    return dT * h;
+    return fmaf(a, Q2, P);
+}
+
+// the parts of one pair term every tier shares, and h on the lowest tier
+struct PairParts {
+    float dT, a, w, h;
+};
+__device__ __forceinline__ PairParts pair32_parts(float Ti, float Tj, const PairK &k) {
+    PairParts r;
+    r.dT = Tj - Ti;
+    const float m = fmaf(Ti + Tj, k.hinv, k.moff);
+    r.a = fmaf(-m, m, m);
+    r.w = r.dT * r.dT;
+    r.h = fmaf(r.a, fmaf(r.w, k.c_tiny, -2.0f), 1.0f);
+    return r;
+}
+
+__device__ __forceinline__ float pair32(float Ti, float Tj, const PairK &k) {
+    PairParts r = pair32_parts(Ti, Tj, k);
+    if (r.w > k.w_tiny) r.h = pair32_h_upper(r.a, r.w, k);
+    return r.dT * r.h;
+}
+
+// Eight pair terms of one lane against Tj[0..8), bitwise equal to pair32 on
+// each: the lowest tier runs straight-line for all eight (so their
+// instructions interleave), and the upper tiers only under a branch the
+// whole wave takes when some lane has a pair above it.
+__device__ __forceinline__ void pair32_x8(float Ti, const float (&Tj)[8], const PairK &k,
+                                          float (&f)[8]) {
+    bool big = false;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const PairParts r = pair32_parts(Ti, Tj[u], k);
+        f[u] = r.dT * r.h;
+        big |= r.w > k.w_tiny;
+    }
+    // rare: the whole wave re-evaluates its eight pairs with the tier test
+    if (__any(big)) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f[u] = pair32(Ti, Tj[u], k);
+    }
 }
 
 // ---- one FP64 plain sub-step --------------------------------------------------------
@@ -275,7 +319,7 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
                                                     float Ti, double S, float lo, float tl,
                                                     float sw, float *__restrict__ Thi_n,
                                                     float *__restrict__ Tlo,
-                                                    double *__restrict__ eatom, int64_t step,
+                                                    double *__restrict__ eatom, float qpulse,
                                                     unsigned *err) {
     float hi_new = Ti;
     LedgerTerms r{0.0f, 0.0f, 0.0f};
@@ -284,7 +328,7 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
         const float invc = 1.0f / c;
         const float coup = signbit(tl) ? 0.0f : p.f_g * (Ti - tl);
         float q = 0.0f;
-        if (p.laser_on) q = (p.f_i0 * pulse32(p, step)) * fabsf(sw);
+        if (p.laser_on) q = qpulse * fabsf(sw);
         const float loc = (q - coup) * invc;
         if (eatom) eatom[slot] += (double)coup * p.dt;
         if (p.has_fixed && signbit(sw)) {
@@ -308,7 +352,7 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
                                                         float tl, float sw, IdxAt idx_at,
                                                         ValOf val_of, float *__restrict__ Thi_n,
                                                         float *__restrict__ Tlo,
-                                                        double *__restrict__ eatom, int64_t step,
+                                                        double *__restrict__ eatom, float qpulse,
                                                         unsigned *err) {
     constexpr int C = 8;
     using Ref = decltype(idx_at(0));
@@ -323,24 +367,28 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
     for (int32_t k0 = 0; k0 < w; k0 += C) {
 #pragma unroll
         for (int u = 0; u < C; ++u) nxt[u] = (k0 + C + u < w) ? idx_at(k0 + C + u) : Ref{};
-        float Tj[C];
+        float Tj[C], f[C];
 #pragma unroll
         for (int u = 0; u < C; ++u) Tj[u] = (k0 + u < w) ? val_of(cur[u]) : Ti;
+        pair32_x8(Ti, Tj, pk, f);
 #pragma unroll
         for (int u = 0; u < C; ++u)
-            if (k0 + u < w) S += (double)pair32(Ti, Tj[u], pk);
+            if (k0 + u < w) S += (double)f[u];
 #pragma unroll
         for (int u = 0; u < C; ++u) cur[u] = nxt[u];
     }
-    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, step, err);
+    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, qpulse, err);
 }
 
-// LDS-tile form for one slice.  w is the slice's row width and row the first
+// LDS-tile form for one slice.  TIERS = false: the caller has shown that every
+// pair of the slice lies on the lowest tier of pair32 (it evaluates exactly
+// that tier, bitwise what pair32 returns there).  w is the slice's row width and row the first
 // word of its packed table (both wave-uniform).  Each word holds the LDS byte
 // offsets of two neighbours; a chunk is 4 words = 8 neighbours.  The words of
 // chunk c + 2 are requested once those of chunk c have been turned into LDS
 // reads, alternating between two buffers.  Same terms in the same order as
 // slice_core_fp32c.
+template <bool TIERS>
 __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot, bool valid,
                                                         const DevParams &p, float Ti, float lo,
                                                         float tl, float sw,
@@ -348,7 +396,7 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
                                                         int lane, const float *tile,
                                                         float *__restrict__ Thi_n,
                                                         float *__restrict__ Tlo,
-                                                        double *__restrict__ eatom, int64_t step,
+                                                        double *__restrict__ eatom, float qpulse,
                                                         unsigned *err) {
     const PairK pk = pair_consts(p);
     const char *tb = reinterpret_cast<const char *>(tile);
@@ -391,13 +439,23 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
             }
         }
         load(c + 2, d);
+        float f[8];
+        if constexpr (TIERS) {
+            pair32_x8(Ti, Tj, pk, f);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const PairParts r = pair32_parts(Ti, Tj[u], pk);
+                f[u] = r.dT * r.h;
+            }
+        }
         if (full) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) S += (double)pair32(Ti, Tj[u], pk);
+            for (int u = 0; u < 8; ++u) S += (double)f[u];
         } else {
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (8 * c + u < w) S += (double)pair32(Ti, Tj[u], pk);
+                if (8 * c + u < w) S += (double)f[u];
         }
     };
     if (nch > 0) {
@@ -411,7 +469,7 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
         }
         if (nch & 1) chunk(nch - 1, A);
     }
-    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, step, err);
+    return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, qpulse, err);
 }
 
 // wave sums of ledger terms, added in FP64 to one ledger row.  A row is
@@ -449,7 +507,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
     const float sw = (p.laser_on | (si.flags & kSliceHeld)) ? srcw[slot] : 0.0f;
     const LedgerTerms t = slice_core_fp32c(
         si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },
-        [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, eatom, step, err);
+        [&](int32_t j) { return Thi[j]; }, Thi_n, Tlo, eatom, source_factor32(p, step), err);
     ledger_add(ledger, sl, lane, t, p.dt);
 }
 
