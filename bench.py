@@ -41,6 +41,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# 0: every context the bench makes launches its sub-steps directly instead of
+# replaying captured hipGraphs (for rocprofv3 counter passes)
+GRAPH = 1
+
+
+def new_context(L, systems, prec, **kw):
+    ctx = L.Context(systems, prec, **kw)
+    if not GRAPH:
+        L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, 0)
+    return ctx
 
 
 def log(msg):
@@ -106,34 +116,68 @@ def one_pass(L, h, sy, d, r_cut, n_sub, timer):
     return e
 
 
-def bench_c4_speedup(L, torch, n_sub):
-    """Batched FP32C (one tuned launch for all systems) vs plain FP64 (systems
-    one after another, one launch per sub-step) on the 256-system batch."""
+def bench_c4_speedup(L, torch, n_sub, n_full):
+    """Batched FP32C (one tuned launch per sub-step for all systems) vs plain
+    FP64 on the 256-system batch.  The plain form runs the systems one after
+    another, one launch per sub-step and system; the batched FP64 form (all
+    systems in one launch per sub-step) is timed beside it.  Every form runs
+    the first n_sub sub-steps from t = 0 (the pulse peaks at 150 fs, sub-step
+    3,000), where the speedup is taken; the batched FP32C form also runs the
+    whole n_full sub-steps of the workload."""
     import workloads as W
     w = W.c4()
     n_atoms = w.n_atoms
     out = {}
-    edge = 0
-    for name, prec in (("fp32c_batched", L.L2T_FP32C), ("fp64_plain", L.L2T_FP64)):
-        ctx = L.Context(w.systems, prec)
-        ctx.setup(w.r_cut)
-        if prec == L.L2T_FP32C:
-            edge = L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE)
+    info = {}
+    forms = (("fp32c_batched", L.L2T_FP32C, 0), ("fp64_plain", L.L2T_FP64, 0),
+             ("fp64_batched", L.L2T_FP64, 1))
+    for name, prec, batch in forms:
+        ctx = new_context(L, w.systems, prec)
+        if batch:
+            L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, 1)
+            L.l2t_set_option(ctx.h, L.L2T_OPT_RESIDENT_MAX, -1)
+        _, mean, _ = ctx.setup(w.r_cut)
         ctx.advance(2)                 # warm-up (autotune, graph capture)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.advance(n_sub)
-        L.l2t_sync(ctx.h)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out[name] = n_atoms * n_sub / dt
+        runs = [n_sub] + ([n_full] if prec == L.L2T_FP32C and n_full > n_sub else [])
+        for n in runs:
+            for s, sy in enumerate(w.systems):
+                L.l2t_set_field(ctx.h, s, L.L2T_FIELD_TE, sy.T_e0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.advance(n)
+            L.l2t_sync(ctx.h)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            key = name if n == n_sub else name + "_full"
+            out[key] = n_atoms * n / dt
+            log(f"  C4 {key}: {n_atoms} atoms x {n} sub-steps in {dt:.3f} s")
+        kernel = L.l2t_get_option(ctx.h, L.L2T_OPT_KERNEL)
+        # algorithmic bytes per atom-substep: the state read and written (FP32C
+        # hi + lo: 16; FP64: 16), T_lat (4 / 8), the source weight of the laser
+        # (4 / 8), a row offset (4) and one index per neighbour (2 B in the
+        # brick forms, 4 B through the global-slot table)
+        per_nbr = 2.0 if kernel == 1 else 4.0
+        fixed = 28.0 if prec == L.L2T_FP32C else 36.0
+        info[name] = dict(kernel=["global-gather", "lds-brick"][kernel], mean_neighbors=mean,
+                          bytes_per_atom_substep=fixed + per_nbr * mean,
+                          brick_edge=L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE))
         ctx.close()
-        log(f"  C4 {name}: {n_atoms} atoms x {n_sub} sub-steps in {dt:.3f} s")
-    return dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms, "
-                         f"{n_sub} sub-steps",
-                fp32c_batched_atom_substeps_per_s=out["fp32c_batched"],
-                fp64_plain_atom_substeps_per_s=out["fp64_plain"],
-                speedup=out["fp32c_batched"] / out["fp64_plain"], brick_edge=edge)
+    res = dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms; the speedup "
+                        f"over the first {n_sub} sub-steps (pulse centre at sub-step 3000), "
+                        f"batched FP32C also over all {n_full}",
+               speedup_substeps=n_sub,
+               fp32c_batched_atom_substeps_per_s=out["fp32c_batched"],
+               fp64_plain_atom_substeps_per_s=out["fp64_plain"],
+               fp64_batched_atom_substeps_per_s=out["fp64_batched"],
+               speedup=out["fp32c_batched"] / out["fp64_plain"],
+               speedup_vs_fp64_batched=out["fp32c_batched"] / out["fp64_batched"],
+               brick_edge=info["fp32c_batched"]["brick_edge"])
+    if "fp32c_batched_full" in out:
+        res["fp32c_batched_full_run_atom_substeps_per_s"] = out["fp32c_batched_full"]
+    for name in ("fp32c_batched", "fp64_plain", "fp64_batched"):
+        gbps = info[name]["bytes_per_atom_substep"] * out[name] / 1e9
+        res[name + "_form"] = dict(info[name], algorithmic_GBps=gbps, frac=gbps / HBM_PEAK_GBS)
+    return res
 
 
 def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):
@@ -233,12 +277,12 @@ def bench_adjoint(L, torch):
     for s, sy in enumerate(tw.systems):
         K, g = tw.extra["target_params"][s]
         sy.params = dict(sy.params, K=K, g=g)
-    ctx_t = L.Context(tw.systems, L.L2T_FP32C)
+    ctx_t = new_context(L, tw.systems, L.L2T_FP32C)
     ctx_t.setup(tw.r_cut)
     ctx_t.advance(n)
     tgt = np.concatenate([ctx_t.get(s) for s in range(len(tw.systems))])
     ctx_t.close()
-    ctx = L.Context(w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
+    ctx = new_context(L, w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
     _, mean, _ = ctx.setup(w.r_cut)
     h, S = ctx.h, len(w.systems)
     N = w.n_atoms
@@ -293,7 +337,7 @@ def bench_bar_batch(L, torch, n_sub=30000):
     launch per sub-step for the whole batch, 3 ps at dt = 0.1 fs."""
     import workloads as W
     w = W.c6(n_substeps=n_sub)
-    ctx = L.Context(w.systems, L.L2T_FP64)
+    ctx = new_context(L, w.systems, L.L2T_FP64)
     ctx.setup(w.r_cut)
     L.l2t_set_option(ctx.h, L.L2T_OPT_BATCH_FP64, 1)
     for s in range(len(w.systems)):
@@ -342,7 +386,7 @@ def bench_c3_fp64(L, torch, w, n_sub=100, kernel="auto"):
     FP32C / FP64 ratio on this system.  kernel pins the FP64 launch form as
     --kernel does for FP32C."""
     sy = w.systems[0]
-    ctx = L.Context(w.systems, L.L2T_FP64, stream=torch.cuda.current_stream().cuda_stream)
+    ctx = new_context(L, w.systems, L.L2T_FP64, stream=torch.cuda.current_stream().cuda_stream)
     if kernel != "auto":
         L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, 1 if kernel == "brick" else 0)
     _, mean, _ = ctx.setup(w.r_cut)
@@ -370,31 +414,67 @@ def bench_c3_fp64(L, torch, w, n_sub=100, kernel="auto"):
                       if brick else "latency of the neighbour gathers")
 
 
-def cpu_baseline(L, torch, w, n_steps):
-    """The FP64 oracle on the host cores over the first n_steps sub-steps of
-    the 4M-atom system, and the FP32C library's T_e error against it after the
-    same sub-steps (a fresh context from the same initial state)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.partition(":")[2].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L, torch, w, n_steps, checkpoints, n_single):
+    """The FP64 oracle on the host cores: timed over the first n_steps
+    sub-steps of the 4M-atom system on all OpenMP threads (the reported
+    value) and over n_single sub-steps on one thread; then continued to each
+    sub-step count in checkpoints, where the FP32C library's T_e (a fresh
+    context advanced from the same initial state) is compared with it on
+    every atom."""
     import oracle
     sy = w.systems[0]
     row, col = oracle.neighbors(sy.pos, sy.box_lo, sy.box_len, sy.periodic, w.r_cut)
     Tl, gated = oracle.lattice_temperature(row, col, sy.vel, sy.mass, sy.params["ke_eps"])
+    cores = oracle.threads()
+    single = None
+    if n_single > 0:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.run(row, col, sy.T_e0, Tl, sy.params, n_single, gated=gated)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        single = dict(value=sy.n * n_single / dt1, threads=1,
+                      sample=f"{n_single} sub-steps ({dt1:.1f} s)")
+        log(f"  oracle on one thread: {sy.n * n_single / dt1 / 1e6:.2f} M atom-substeps/s")
     t0 = time.perf_counter()
     T_ref, _, _ = oracle.run(row, col, sy.T_e0, Tl, sy.params, n_steps, gated=gated)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    ctx = L.Context(w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
+    ctx = new_context(L, w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
     ctx.setup(w.r_cut)
-    ctx.advance(n_steps)
-    T = ctx.get(0)
+    parity = []
+    step = 0
+    for c in sorted(set([n_steps] + [c for c in checkpoints if c > n_steps])):
+        if c > n_steps:
+            T_ref, _, _ = oracle.run(row, col, T_ref, Tl, sy.params, c - max(step, n_steps),
+                                     step0=max(step, n_steps), gated=gated)
+        ctx.advance(c - step)
+        step = c
+        T = ctx.get(0)
+        rel = np.abs(T - T_ref) / np.abs(T_ref)
+        parity.append(dict(substeps=c, max_rel_err=float(rel.max()),
+                           mean_rel_err=float(rel.mean()),
+                           T_e_changed_max=float(np.max(np.abs(T_ref - sy.T_e0)))))
+        log(f"  FP32C vs FP64 oracle after {c} sub-steps, all {sy.n} atoms: max rel "
+            f"{rel.max():.2e}")
     ctx.close()
-    rel = np.abs(T - T_ref) / np.abs(T_ref)
-    log(f"  FP32C vs FP64 oracle after {n_steps} sub-steps: max rel {rel.max():.2e}")
     return dict(value=sy.n * n_steps / dt, unit="atom-substeps/s", cores=cores, kind="oracle",
+                cpu=cpu_model(), logical_cpus=os.cpu_count(),
                 sample=f"FP64 oracle, same 4,000,000-atom system, {n_steps} sub-steps "
-                       f"({dt:.1f} s), neighbour build not timed",
-                fp32c_vs_oracle=dict(substeps=n_steps, max_rel_err=float(rel.max()),
-                                     mean_rel_err=float(rel.mean()), tolerance=1e-5,
-                                     T_e_changed_max=float(np.max(np.abs(T_ref - sy.T_e0)))))
+                       f"({dt:.1f} s) on {cores} OpenMP threads, neighbour build not timed",
+                single_thread=single,
+                fp32c_vs_oracle=dict(tolerance=1e-5, checkpoints=parity,
+                                     max_rel_err=max(p["max_rel_err"] for p in parity)))
 
 
 def main():
@@ -406,7 +486,18 @@ def main():
     ap.add_argument("--cells", type=int, default=100)
     ap.add_argument("--c4-substeps", type=int, default=600)
     ap.add_argument("--no-c4", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=200,
+                    help="oracle sub-steps timed on all host threads")
+    ap.add_argument("--cpu-checkpoints", type=str, default="500,1000",
+                    help="further sub-step counts at which every atom is compared with the oracle")
+    ap.add_argument("--cpu-single-steps", type=int, default=5,
+                    help="oracle sub-steps timed on one thread (0 = skip)")
+    ap.add_argument("--c4-full-substeps", type=int, default=6000)
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
+                    help="0 = launch sub-steps directly instead of replaying hipGraphs "
+                         "(rocprofv3 counter passes)")
+    ap.add_argument("--only", choices=["all", "c3", "c4", "md", "bars", "adjoint", "fp64"],
+                    default="all", help="run one section only (profiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 sample on the 4M-atom system")
@@ -429,6 +520,8 @@ def main():
     import torch
     import workloads as W
     from paper_1810_12357_amd import l2t as L
+    global GRAPH
+    GRAPH = args.graph
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -442,106 +535,118 @@ def main():
         return
     w = W.c3(n_cells=args.cells, n_substeps=args.substeps)
     sy = w.systems[0]
-    log(f"C3: {sy.n} atoms, r_c = {w.r_cut:.4f} A, {args.substeps} sub-steps per step")
-    ctx = L.Context(w.systems, L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
-    h = ctx.h
-    if args.brick_edge:
-        L.l2t_set_option(h, L.L2T_OPT_BRICK_EDGE, args.brick_edge)
-    if args.kernel != "auto":
-        L.l2t_set_option(h, L.L2T_OPT_KERNEL, 1 if args.kernel == "brick" else 0)
-    if args.block:
-        L.l2t_set_option(h, L.L2T_OPT_BLOCK, args.block)
-    d = setup_system(L, h, sy, dev)
-    torch.cuda.synchronize()
-    timer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    for k in range(args.warmup):
-        one_pass(L, h, sy, d, w.r_cut, args.substeps, timer)
-        log(f"warm-up {k + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    adv_ms = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        e = one_pass(L, h, sy, d, w.r_cut, args.substeps, timer)
+    want = lambda sec: args.only in ("all", sec)
+    out = {}
+    if want("c3") or want("md"):
+        log(f"C3: {sy.n} atoms, r_c = {w.r_cut:.4f} A, {args.substeps} sub-steps per step")
+        ctx = new_context(L, w.systems, L.L2T_FP32C,
+                          stream=torch.cuda.current_stream().cuda_stream)
+        h = ctx.h
+        if args.brick_edge:
+            L.l2t_set_option(h, L.L2T_OPT_BRICK_EDGE, args.brick_edge)
+        if args.kernel != "auto":
+            L.l2t_set_option(h, L.L2T_OPT_KERNEL, 1 if args.kernel == "brick" else 0)
+        if args.block:
+            L.l2t_set_option(h, L.L2T_OPT_BLOCK, args.block)
+        d = setup_system(L, h, sy, dev)
         torch.cuda.synchronize()
-        adv_ms.append(timer[0].elapsed_time(timer[1]))
-        log(f"step {k + 1}/{args.steps}: advance {adv_ms[-1]:.1f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    md = bnd = None
-    if not args.no_md:
+        timer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        if not want("c3"):
+            one_pass(L, h, sy, d, w.r_cut, 1, timer)
+    if want("c3"):
+        for k in range(args.warmup):
+            one_pass(L, h, sy, d, w.r_cut, args.substeps, timer)
+            log(f"warm-up {k + 1}/{args.warmup} done")
+        torch.cuda.synchronize()
+        adv_ms = []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            e = one_pass(L, h, sy, d, w.r_cut, args.substeps, timer)
+            torch.cuda.synchronize()
+            adv_ms.append(timer[0].elapsed_time(timer[1]))
+            log(f"step {k + 1}/{args.steps}: advance {adv_ms[-1]:.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n_atom_steps = sy.n * args.substeps * args.steps
+        value = n_atom_steps / wall
+        mx, mean = L.l2t_build_neighbors(h, w.r_cut)
+        persistent = L.l2t_get_option(h, L.L2T_OPT_PERSISTENT)
+        block = L.l2t_get_option(h, L.L2T_OPT_BLOCK)
+        kernel = L.l2t_get_option(h, L.L2T_OPT_KERNEL)
+        adv = float(np.mean(adv_ms))
+        # algorithmic bytes per atom-substep: hi+lo read and write (16), T_lat
+        # (4), row offset (4) and one index per neighbour (4 B global, 2 B
+        # brick-local)
+        bytes_per = 24.0 + (2.0 if kernel == 1 else 4.0) * mean
+        if kernel == 1:
+            launch_ms, units, kname = adv / args.substeps, sy.n, "k_brick_fp32c"
+        elif persistent:
+            launch_ms, units, kname = adv, sy.n * args.substeps, "k_persistent_fp32c"
+        else:
+            launch_ms, units, kname = adv / args.substeps, sy.n, "k_step_fp32c"
+        achieved = bytes_per * units / (launch_ms * 1e-3) / 1e9
+        traffic = measured_traffic(kname, sy.n) if units == sy.n else None
+        copy_gbps = copy_rate(torch, dev)
+        roof = dict(bound="hbm", kernel=kname, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                    traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                 "copy-calibrated)",
+                    algorithmic_bytes_per_atom_substep=bytes_per,
+                    launch_ms=launch_ms, units_per_launch=units,
+                    # measured HBM bytes over the live launch time (the gate's reading)
+                    measured_GBps=None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+                    measured_frac=None if traffic is None else
+                    traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    # a 1 GiB device copy on the same GPU: the practical denominator
+                    copy_GBps=copy_gbps, frac_of_copy=achieved / copy_gbps)
+        # value: the atom-substeps/s half of the metric; the batched-FP32C over
+        # plain-FP64 speedup half is c4_speedup.speedup
+        out = dict(metric="electron atom-substeps/s, 4M-atom FCC; batched FP32 vs plain FP64 "
+                          "speedup",
+                   value=value,
+                   unit="atom-substeps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                   ms_per_step=wall / args.steps * 1e3, higher_is_better=True, scaling="weak",
+                   vs_baseline=None, dtype="f32", data="synthetic",
+                   config=dict(workload=f"c3: FCC {args.cells}^3 cells ({sy.n} atoms), jittered "
+                                        f"0.05 A, r_c 1.2a, {args.substeps} FP32C sub-steps per "
+                                        f"step",
+                               n_atoms=sy.n, substeps=args.substeps, mean_neighbors=mean,
+                               max_neighbors=mx, kernel=["global-gather", "lds-brick"][kernel],
+                               brick_edge=L.l2t_get_option(h, L.L2T_OPT_BRICK_EDGE),
+                               persistent=persistent, block=block),
+                   advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
+                   advance_ms_median=float(np.median(adv_ms)),
+                   roofline=roof,
+                   energy=dict(E_e=e["E_e"], sum_T=e["sum_T"],
+                               T_ledger=e["sum_T"] + e["T_ledger_acc"], T_max=e["T_max_atom"]))
+    if want("md") and not args.no_md:
         log("MD coupling (Eq. 5, Eq. 8) ...")
-        md = bench_md_coupling(L, torch, h, sy, d)
+        out["md_coupling"] = bench_md_coupling(L, torch, h, sy, d)
         log("held atoms and mean-field refresh ...")
-        bnd = bench_boundary_mean_field(L, torch, h, sy)
-    n_atom_steps = sy.n * args.substeps * args.steps
-    value = n_atom_steps / wall
-    mx, mean = L.l2t_build_neighbors(h, w.r_cut)
-    persistent = L.l2t_get_option(h, L.L2T_OPT_PERSISTENT)
-    block = L.l2t_get_option(h, L.L2T_OPT_BLOCK)
-    kernel = L.l2t_get_option(h, L.L2T_OPT_KERNEL)
-    adv = float(np.mean(adv_ms))
-    # algorithmic bytes per atom-substep: hi+lo read and write (16), T_lat (4),
-    # row offset (4) and one index per neighbour (4 B global, 2 B brick-local)
-    bytes_per = 24.0 + (2.0 if kernel == 1 else 4.0) * mean
-    if kernel == 1:
-        launch_ms, units, kname = adv / args.substeps, sy.n, "k_brick_fp32c"
-    elif persistent:
-        launch_ms, units, kname = adv, sy.n * args.substeps, "k_persistent_fp32c"
-    else:
-        launch_ms, units, kname = adv / args.substeps, sy.n, "k_step_fp32c"
-    achieved = bytes_per * units / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(kname, sy.n) if units == sy.n else None
-    copy_gbps = copy_rate(torch, dev)
-    roof = dict(bound="hbm", kernel=kname, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                algorithmic_bytes_per_atom_substep=bytes_per,
-                launch_ms=launch_ms, units_per_launch=units,
-                # measured HBM bytes over the live launch time (the bandwidth gate's reading)
-                measured_GBps=None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
-                measured_frac=None if traffic is None else
-                traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                # a 1 GiB device copy on the same GPU: the practical denominator
-                copy_GBps=copy_gbps, frac_of_copy=achieved / copy_gbps)
-    # value: the atom-substeps/s half of the metric; the batched-FP32C over
-    # plain-FP64 speedup half is c4_speedup.speedup
-    out = dict(metric="electron atom-substeps/s, 4M-atom FCC; batched FP32 vs plain FP64 speedup",
-               value=value,
-               unit="atom-substeps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-               ms_per_step=wall / args.steps * 1e3, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=f"c3: FCC {args.cells}^3 cells ({sy.n} atoms), jittered "
-                                    f"0.05 A, r_c 1.2a, {args.substeps} FP32C sub-steps per step",
-                           n_atoms=sy.n, substeps=args.substeps, mean_neighbors=mean,
-                           max_neighbors=mx, kernel=["global-gather", "lds-brick"][kernel],
-                           brick_edge=L.l2t_get_option(h, L.L2T_OPT_BRICK_EDGE),
-                           persistent=persistent, block=block),
-               advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
-               advance_ms_median=float(np.median(adv_ms)),
-               roofline=roof,
-               energy=dict(E_e=e["E_e"], sum_T=e["sum_T"], T_ledger=e["sum_T"] + e["T_ledger_acc"],
-                           T_max=e["T_max_atom"]))
-    if md is not None:
-        out["md_coupling"] = md
-        out["boundary_mean_field"] = bnd
-    ctx.close()
-    if not args.no_fp64:
+        out["boundary_mean_field"] = bench_boundary_mean_field(L, torch, h, sy)
+    if want("c3") or want("md"):
+        ctx.close()
+    if want("fp64") and not args.no_fp64:
         log("C3 in plain FP64 ...")
         f64 = bench_c3_fp64(L, torch, w, kernel=args.kernel)
-        f64["fp32c_over_fp64"] = out["advance_only_atom_substeps_per_s"] / f64["atom_substeps_per_s"]
+        if "advance_only_atom_substeps_per_s" in out:
+            f64["fp32c_over_fp64"] = (out["advance_only_atom_substeps_per_s"] /
+                                      f64["atom_substeps_per_s"])
         out["c3_fp64"] = f64
-    if not args.no_c4:
+    if want("c4") and not args.no_c4:
         log("C4 batched vs plain ...")
-        out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps)
-    if not args.no_md:
+        out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps, args.c4_full_substeps)
+    if want("bars") and not args.no_md:
         log("two-temperature bars (Section 3.1) ...")
         out["bar_batch"] = bench_bar_batch(L, torch)
-    if not args.no_adjoint:
+    if want("adjoint") and not args.no_adjoint:
         log("adjoint (differentiation workload) ...")
         out["adjoint"] = bench_adjoint(L, torch)
-    if not args.no_cpu:
+    if args.only == "all" and not args.no_cpu:
         log("CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(L, torch, w, args.cpu_steps)
+        cps = [int(c) for c in args.cpu_checkpoints.split(",") if c.strip()]
+        out["cpu_baseline"] = cpu_baseline(L, torch, w, args.cpu_steps, cps,
+                                           args.cpu_single_steps)
     print(json.dumps(out), flush=True)
 
 

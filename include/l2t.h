@@ -230,9 +230,11 @@ int l2t_set_allocator(l2t_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
 
 /* ---- geometry --------------------------------------------------------------- */
 
-/* Atom positions of system sys, SoA xyz[3*n]: x[0..n), y[0..n), z[0..n), A.
- * Positions on periodic axes are wrapped into the box.  Invalidates the
- * neighbour sets.  Errors: EINVAL (sys out of range, NULL). */
+/* Atom positions of system sys, SoA xyz[3*n]: x[0..n), y[0..n), z[0..n), A
+ * (Section 2.1: every atom carries its own electronic temperature, and the
+ * atoms it exchanges heat with are those inside the cut-off around its
+ * position).  Positions on periodic axes are wrapped into the box.
+ * Invalidates the neighbour sets.  Errors: EINVAL (sys out of range, NULL). */
 int l2t_set_positions(l2t_ctx *ctx, int32_t sys, const double *xyz, int32_t mem);
 
 /* Build the neighbour sets N(i) = { j != i : |x_j - x_i| <= r_cut } of every
@@ -288,15 +290,22 @@ int l2t_set_lattice_fd(l2t_ctx *ctx, int32_t sys, const l2t_lattice_fd *lf);
  * mean-field refresh set them.  Synchronises. */
 int l2t_get_params(l2t_ctx *ctx, int32_t sys, l2t_params *out);
 
-/* Write a per-atom field of system sys from src[n] (FP64, caller order).
- * Writing L2T_FIELD_TE restarts the system's ledger and step counter.
+/* Write a per-atom field of system sys from src[n] (FP64, caller order):
+ * the per-atom electronic temperature T_e of Section 2.1, the lattice
+ * temperature T^lat of Eq. 4 (when it is not derived from velocities), the
+ * kinetic-energy gate of the remark after Eq. 8, or the fixed-T_e flag of the
+ * Section 4 boundary.  Writing L2T_FIELD_TE restarts the system's ledger and
+ * step counter.
  * Synchronises.  Errors: ESTATE (neighbours not built), EINVAL (unknown or
  * read-only field, T^lat < 0), ERANGE (a T_e outside [T_min, T_max] or
  * non-finite; nothing is written). */
 int l2t_set_field(l2t_ctx *ctx, int32_t sys, int32_t field, const double *src, int32_t mem);
 
-/* Read a per-atom field of system sys into dst[n] (FP64, caller order).
- * FP32C temperatures are returned as (double)hi + (double)lo.
+/* Read a per-atom field of system sys into dst[n] (FP64, caller order): the
+ * per-atom T_e of Section 2.1, T^lat of Eq. 4, the gate, the neighbour count,
+ * the energy handed to the lattice (Eq. 6 integrated over the last advance)
+ * or the fixed-T_e flag.  FP32C temperatures are returned as (double)hi +
+ * (double)lo.
  * Synchronises when mem == L2T_HOST. */
 int l2t_get_field(l2t_ctx *ctx, int32_t sys, int32_t field, double *dst, int32_t mem);
 
@@ -378,7 +387,12 @@ int l2t_adjoint(l2t_ctx *ctx, const double *dL_dTN, int32_t mem, double *dL_dK,
 int l2t_set_counters(l2t_ctx *ctx, int32_t sys, int64_t step, double E_e_to_l, double E_src,
                      double T_ledger_acc);
 
-/* Per-system ledger (FP64 reductions on the device).  Synchronises; returns
+/* Per-system energy report (FP64 reductions on the device): the electronic
+ * energy sum_i integral_0^{T_i} c dT, the energy handed to the lattice at the
+ * exchange rate of Eq. 6 integrated over the sub-steps, and the energy the
+ * Eq. 10 source deposited, whose balance Section 3.2 examines; also sum T and
+ * the temperature ledger that keeps sum T + ledger invariant.  Synchronises;
+ * returns
  * ERANGE if any sub-step since the last check produced theta outside [0,1]
  * or a non-finite T (the ledger is still written). */
 int l2t_energies(l2t_ctx *ctx, int32_t sys, l2t_energy_report *out);

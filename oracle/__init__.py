@@ -117,6 +117,22 @@ def make_params(p: dict) -> Params:
                   laser_x0=p["laser_x0"], v_atom=p["v_atom"])
 
 
+def _gomp():
+    _load()                      # the oracle library pulls in the OpenMP runtime
+    return C.CDLL("libgomp.so.1")
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_gomp().omp_get_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of the oracle's parallel loops (results do
+    not depend on it: every sum runs serially in a fixed order)."""
+    _gomp().omp_set_num_threads(int(n))
+
+
 def pair(ti, tj):
     """Literal pair term of Eq. 2 for arrays of normalised temperatures."""
     ti = _f64(np.atleast_1d(ti))

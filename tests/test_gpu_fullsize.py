@@ -1,7 +1,9 @@
 """Full-size batch and gradient workloads, launched as the benchmark launches
 them, checked on sampled systems against the FP64 oracle and on every system
 against properties that hold at any size."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -11,6 +13,8 @@ import workloads as W
 from helpers import gpu_context, max_rel, oracle_lattice, oracle_neighbors, oracle_trajectory
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 L = pytest.importorskip("paper_1810_12357_amd.l2t")
 
@@ -49,12 +53,41 @@ def test_c4_full_batch_sampled_systems_and_ledgers():
         assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(sy.T_e0.sum(), rel=1e-7)
         assert e["E_src"] == pytest.approx(_laser_energy_closed_form(sy, w.n_substeps), rel=2e-4)
         assert 300.0 <= e["T_min_atom"] and e["T_max_atom"] < 1000.0
-    # oracle trajectories of the five smallest systems, whole length
-    for s in np.argsort(sizes)[:5]:
+    # oracle trajectories over the whole length: the five smallest systems, the
+    # median one and the largest (200,704 atoms), every atom
+    order = np.argsort(sizes, kind="stable")
+    for s in list(order[:5]) + [order[len(order) // 2], order[-1]]:
         sy = w.systems[int(s)]
         traj, led, bad = oracle_trajectory(sy, w.r_cut, [w.n_substeps])
         assert bad == 0
-        assert max_rel(ctx.get(int(s)), traj[0]) < 1e-5
+        assert max_rel(ctx.get(int(s)), traj[0]) < 1e-5, (int(s), sy.n)
+        e = ctx.energies(int(s))
+        assert e["E_src"] == pytest.approx(led[1], rel=1e-5)
+        assert e["E_e_to_l"] == pytest.approx(led[0], rel=1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_c2_full_size_every_atom_against_the_oracle(precision):
+    """Fourier-limit workload at its full size (200 x 8 x 8 cells, 51,200
+    atoms) over all 5,000 sub-steps, every atom against the oracle at three
+    points, plus the energy of the state (constant c: E_e = c sum T)."""
+    w = W.c2(precision=precision)
+    sy = w.systems[0]
+    cps = [1000, 2500, 5000]
+    traj, led, bad = oracle_trajectory(sy, w.r_cut, cps)
+    assert bad == 0
+    ctx = gpu_context(w, L.L2T_FP64 if precision == "fp64" else L.L2T_FP32C)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    step = 0
+    for c, To in zip(cps, traj):
+        ctx.advance(c - step)
+        step = c
+        assert max_rel(ctx.get(0), To) < tol, c
+    e = ctx.energies(0)
+    E_or, S_or = oracle.energies(traj[-1], sy.params)
+    assert e["E_e"] == pytest.approx(E_or, rel=tol)
+    assert e["sum_T"] == pytest.approx(sy.T_e0.sum(), rel=1e-12 if precision == "fp64" else 1e-8)
+    ctx.close()
 
 
 def test_c5_full_adjoint_sampled_systems():
@@ -64,7 +97,7 @@ def test_c5_full_adjoint_sampled_systems():
     ctx.setup(w.r_cut)
     L.l2t_advance_recorded(ctx.h, n, ck)
     TN = [ctx.get(s) for s in range(len(w.systems))]
-    sampled = (0, 37)
+    sampled = (0, 21, 37, 63)
     N = sum(sy.n for sy in w.systems)
     targets = {}
     for s in sampled:
@@ -89,3 +122,33 @@ def test_c5_full_adjoint_sampled_systems():
         assert np.max(np.abs(seg - lam)) < 1e-4 * np.abs(lam).max()
     # the loss falls along -grad for the sampled systems (sanity of direction)
     assert np.isfinite(dK).all() and np.isfinite(dg).all()
+
+
+def test_c3_full_length_sampled_against_the_stored_oracle_run():
+    """The 4,000,000-atom system over all 10,000 sub-steps of the benchmark, in
+    the benchmark's launch configuration, against the FP64 oracle's states of
+    sampled atoms and its system energy and ledger at 1,000, 2,500, 5,000 and
+    10,000 sub-steps (tests/golden/c3_long.json, written by make_c3_long.py
+    from the oracle alone)."""
+    with open(os.path.join(GOLDEN, "c3_long.json")) as fh:
+        ref = json.load(fh)
+    w = W.c3()
+    ctx = gpu_context(w, L.L2T_FP32C)
+    idx = np.asarray(ref["atoms"], dtype=np.int64)
+    step = 0
+    for cp in ref["checkpoints"]:
+        assert cp["out_of_range"] == 0
+        ctx.advance(cp["step"] - step)
+        step = cp["step"]
+        T = ctx.get(0)
+        To = np.asarray(cp["T"])
+        assert max_rel(T[idx], To) < 1e-5, step
+        e = ctx.energies(0)
+        assert e["E_e"] == pytest.approx(cp["E_e"], rel=1e-5)
+        assert e["sum_T"] == pytest.approx(cp["sum_T"], rel=1e-8)
+        assert e["E_e_to_l"] == pytest.approx(cp["E_e_to_l"], rel=1e-5)
+        assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(cp["sum_T"] + cp["T_ledger"],
+                                                                rel=1e-9)
+        assert e["T_max_atom"] == pytest.approx(cp["T_max"], rel=1e-5)
+        assert e["T_min_atom"] == pytest.approx(cp["T_min"], rel=1e-5)
+    ctx.close()
