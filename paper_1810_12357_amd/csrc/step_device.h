@@ -24,14 +24,7 @@ __device__ inline double wave_min(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
     return v;
 }
-__device__ inline float wave_max_f32(float v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-__device__ inline float wave_min_f32(float v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
+
 
 // ---- heat capacity models --------------------------------------------------------
 __device__ inline double ce64(const DevParams &p, double T) {
@@ -141,26 +134,6 @@ __device__ __forceinline__ float pair32(float Ti, float Tj, const PairK &k) {
     PairParts r = pair32_parts(Ti, Tj, k);
     if (r.w > k.w_tiny) r.h = pair32_h_upper(r.a, r.w, k);
     return r.dT * r.h;
-}
-
-// Eight pair terms of one lane against Tj[0..8), bitwise equal to pair32 on
-// each: the lowest tier runs straight-line for all eight (so their
-// instructions interleave), and the upper tiers only under a branch the
-// whole wave takes when some lane has a pair above it.
-__device__ __forceinline__ void pair32_x8(float Ti, const float (&Tj)[8], const PairK &k,
-                                          float (&f)[8]) {
-    bool big = false;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const PairParts r = pair32_parts(Ti, Tj[u], k);
-        f[u] = r.dT * r.h;
-        big |= r.w > k.w_tiny;
-    }
-    // rare: the whole wave re-evaluates its eight pairs with the tier test
-    if (__any(big)) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) f[u] = pair32(Ti, Tj[u], k);
-    }
 }
 
 // ---- one FP64 plain sub-step --------------------------------------------------------
@@ -298,6 +271,35 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Smallest and largest value over the 64 lanes with DPP moves: a lane whose
+// DPP source lies outside its row keeps the identity (bound_ctrl off), and
+// the result lands in lane 63, broadcast through readlane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_keep_f32(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                      ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_min_f32(float v) {
+    const float I = INFINITY;
+    v = fminf(v, dpp_keep_f32<0x111, 0xf>(I, v));
+    v = fminf(v, dpp_keep_f32<0x112, 0xf>(I, v));
+    v = fminf(v, dpp_keep_f32<0x114, 0xf>(I, v));
+    v = fminf(v, dpp_keep_f32<0x118, 0xf>(I, v));
+    v = fminf(v, dpp_keep_f32<0x142, 0xa>(I, v));
+    v = fminf(v, dpp_keep_f32<0x143, 0xc>(I, v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ float wave_max_f32(float v) {
+    const float I = -INFINITY;
+    v = fmaxf(v, dpp_keep_f32<0x111, 0xf>(I, v));
+    v = fmaxf(v, dpp_keep_f32<0x112, 0xf>(I, v));
+    v = fmaxf(v, dpp_keep_f32<0x114, 0xf>(I, v));
+    v = fmaxf(v, dpp_keep_f32<0x118, 0xf>(I, v));
+    v = fmaxf(v, dpp_keep_f32<0x142, 0xa>(I, v));
+    v = fmaxf(v, dpp_keep_f32<0x143, 0xc>(I, v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // ---- one FP32C sub-step of one slice ------------------------------------------------
 // idx_at(k) loads this lane's k-th neighbour reference, val_of(ref) returns the
 // FP32 hi temperature it refers to.  The global-gather and LDS-tile kernels
@@ -325,7 +327,9 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
     LedgerTerms r{0.0f, 0.0f, 0.0f};
     if (valid) {
         const float c = ce32(p, Ti);
-        const float invc = 1.0f / c;
+        // hardware reciprocal (within 1 ulp): it scales only the local terms,
+        // whose own size is a small fraction of the state's FP32 resolution
+        const float invc = __builtin_amdgcn_rcpf(c);
         const float coup = signbit(tl) ? 0.0f : p.f_g * (Ti - tl);
         float q = 0.0f;
         if (p.laser_on) q = qpulse * fabsf(sw);
@@ -367,13 +371,12 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
     for (int32_t k0 = 0; k0 < w; k0 += C) {
 #pragma unroll
         for (int u = 0; u < C; ++u) nxt[u] = (k0 + C + u < w) ? idx_at(k0 + C + u) : Ref{};
-        float Tj[C], f[C];
+        float Tj[C];
 #pragma unroll
         for (int u = 0; u < C; ++u) Tj[u] = (k0 + u < w) ? val_of(cur[u]) : Ti;
-        pair32_x8(Ti, Tj, pk, f);
 #pragma unroll
         for (int u = 0; u < C; ++u)
-            if (k0 + u < w) S += (double)f[u];
+            if (k0 + u < w) S += (double)pair32(Ti, Tj[u], pk);
 #pragma unroll
         for (int u = 0; u < C; ++u) cur[u] = nxt[u];
     }
@@ -420,54 +423,62 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
         }
     };
     auto at = [&](uint32_t off) { return *reinterpret_cast<const float *>(tb + off); };
-    // LDS reads of chunk c (the offsets are consumed here), then the next request
-    // into the same buffer, then the 8 pair terms
-    auto chunk = [&](int32_t c, uint32_t (&d)[4]) {
-        float Tj[8];
-        const bool full = 8 * c + 8 <= w;
-        if (full) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                Tj[2 * u] = at(d[u] & 0xffffu);
-                Tj[2 * u + 1] = at(d[u] >> 16);
-            }
+    auto term = [&](float Tj) {
+        if constexpr (TIERS) {
+            return pair32(Ti, Tj, pk);
         } else {
+            const PairParts r = pair32_parts(Ti, Tj, pk);
+            return r.dT * r.h;
+        }
+    };
+    auto terms = [&](const float (&Tj)[8], float (&f)[8]) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                Tj[2 * u] = (8 * c + 2 * u < w) ? at(d[u] & 0xffffu) : Ti;
-                Tj[2 * u + 1] = (8 * c + 2 * u + 1 < w) ? at(d[u] >> 16) : Ti;
-            }
+        for (int u = 0; u < 8; ++u) f[u] = term(Tj[u]);
+    };
+    // a full chunk c: LDS reads of its 8 neighbours (the offsets are consumed
+    // here), then the request of chunk c + 2 into the same buffer, then the 8
+    // pair terms; no per-neighbour condition
+    auto full_chunk = [&](int32_t c, uint32_t (&d)[4]) {
+        float Tj[8], f[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            Tj[2 * u] = at(d[u] & 0xffffu);
+            Tj[2 * u + 1] = at(d[u] >> 16);
         }
         load(c + 2, d);
-        float f[8];
-        if constexpr (TIERS) {
-            pair32_x8(Ti, Tj, pk, f);
-        } else {
+        terms(Tj, f);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const PairParts r = pair32_parts(Ti, Tj[u], pk);
-                f[u] = r.dT * r.h;
-            }
-        }
-        if (full) {
+        for (int u = 0; u < 8; ++u) S += (double)f[u];
+    };
+    // the row's last chunk when the width is not a multiple of 8: only its
+    // entries inside the row are read and evaluated (wave-uniform conditions)
+    auto tail_chunk = [&](int32_t c, const uint32_t (&d)[4]) {
+        const int32_t m = w - 8 * c;
+        float Tj[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) S += (double)f[u];
-        } else {
+        for (int u = 0; u < 8; ++u)
+            if (u < m) Tj[u] = at((u & 1) ? (d[u >> 1] >> 16) : (d[u >> 1] & 0xffffu));
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (8 * c + u < w) S += (double)f[u];
-        }
+        for (int u = 0; u < 8; ++u)
+            if (u < m) S += (double)term(Tj[u]);
     };
     if (nch > 0) {
         uint32_t A[4], B[4];
         load(0, A);
         load(1, B);
-        const int32_t n2 = nch >> 1;
-        for (int32_t c = 0; c < 2 * n2; c += 2) {
-            chunk(c, A);
-            chunk(c + 1, B);
+        const int32_t nfull = w >> 3;
+        int32_t c = 0;
+        for (; c + 2 <= nfull; c += 2) {
+            full_chunk(c, A);
+            full_chunk(c + 1, B);
         }
-        if (nch & 1) chunk(nch - 1, A);
+        // chunk c (even) takes buffer A, c + 1 buffer B
+        if (c < nfull) {
+            full_chunk(c, A);
+            if (c + 1 < nch) tail_chunk(c + 1, B);
+        } else if (c < nch) {
+            tail_chunk(c, A);
+        }
     }
     return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, qpulse, err);
 }
