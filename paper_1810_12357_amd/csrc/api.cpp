@@ -670,7 +670,11 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             t.block = (int)value;
             break;
         case L2T_OPT_RESIDENT_MAX: t.resident_max = (int)value; break;
-        case L2T_OPT_GRAPH: t.graph = value ? 1 : 0; break;
+        case L2T_OPT_GRAPH:
+            // how launches are issued, not a launch shape: leaves tuning alone
+            t.graph = value ? 1 : 0;
+            l2t::drop_graphs(c);
+            return L2T_OK;
         case L2T_OPT_BRICK_EDGE:
             if (value < 0 || value > l2t::kMaxBrickEdge)
                 return l2t::fail(c, L2T_EINVAL, "brick edge must be 0..1024");

@@ -94,23 +94,33 @@ __device__ __forceinline__ PairK pair_consts(const DevParams &p) {
     return k;
 }
 
+// Series coefficients of the two upper tiers.  Kept in a device table (read
+// into scalar registers) rather than as literals, which the compiler would
+// otherwise hoist into vector registers for the whole sub-step loop.
+__constant__ float kPairUpper[10] = {
+    -1.0f / 360.0f,      -1.0f / 24.0f,       // P, middle tier
+    -2.0f / 120.0f,      -2.0f / 6.0f,        // Q2, middle tier
+    -5.0f / 479001600.0f, -4.0f / 3628800.0f, -3.0f / 40320.0f,   // P, top tier
+    -2.0f / 39916800.0f, -2.0f / 362880.0f, -2.0f / 5040.0f};     // Q2, top tier
+
 // h on the two upper tiers (w = dT^2 > w_tiny), a = 2 m (1 - m) / 2
 __device__ __forceinline__ float pair32_h_upper(float a, float w, const PairK &k) {
+    const float *c = kPairUpper;
     const float u = w * k.inv2;
     float P, Q2;   // Q2 = -2 Q
     if (u <= 1.0e-2f) {
-        P = fmaf(u * u, fmaf(u, -1.0f / 360.0f, -1.0f / 24.0f), 1.0f);
-        Q2 = fmaf(u, fmaf(u, -2.0f / 120.0f, -2.0f / 6.0f), -2.0f);
+        P = fmaf(u * u, fmaf(u, c[0], c[1]), 1.0f);
+        Q2 = fmaf(u, fmaf(u, c[2], c[3]), -2.0f);
     } else {
-        float pp = fmaf(u, -5.0f / 479001600.0f, -4.0f / 3628800.0f);
-        pp = fmaf(u, pp, -3.0f / 40320.0f);
-        pp = fmaf(u, pp, -1.0f / 360.0f);
-        pp = fmaf(u, pp, -1.0f / 24.0f);
+        float pp = fmaf(u, c[4], c[5]);
+        pp = fmaf(u, pp, c[6]);
+        pp = fmaf(u, pp, c[0]);
+        pp = fmaf(u, pp, c[1]);
         P = fmaf(u * u, pp, 1.0f);
-        float q = fmaf(u, -2.0f / 39916800.0f, -2.0f / 362880.0f);
-        q = fmaf(u, q, -2.0f / 5040.0f);
-        q = fmaf(u, q, -2.0f / 120.0f);
-        q = fmaf(u, q, -2.0f / 6.0f);
+        float q = fmaf(u, c[7], c[8]);
+        q = fmaf(u, q, c[9]);
+        q = fmaf(u, q, c[2]);
+        q = fmaf(u, q, c[3]);
         Q2 = fmaf(u, q, -2.0f);
     }
     return fmaf(a, Q2, P);
