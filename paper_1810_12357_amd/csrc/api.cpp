@@ -33,6 +33,10 @@ hipError_t dev_malloc(l2t_ctx *c, void **p, size_t bytes) {
     if (!c->ualloc) return hipMalloc(p, bytes);
     void *q = c->ualloc(bytes, c->uarg);
     if (!q) return hipErrorOutOfMemory;
+    if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {   // the kernels stage 16-byte vectors
+        c->ufree(q, c->uarg);
+        return hipErrorInvalidValue;
+    }
     c->user_blocks[q] = l2t_ctx::UserBlock{c->ufree, c->uarg};
     *p = q;
     return hipSuccess;
@@ -305,6 +309,7 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c, c->pos_slot);
     dfree(c, c->bricks);
     dfree(c, c->brick_list);
+    dfree(c, c->xcd_list);
     dfree(c, c->shell);
     dfree(c, c->halo);
     for (int b = 0; b < 2; ++b) {

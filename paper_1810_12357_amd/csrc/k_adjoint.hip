@@ -159,46 +159,53 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
     const float *__restrict__ Tl, const float *__restrict__ srcw, const DevParams *__restrict__ P,
     const int64_t *__restrict__ dstep, int32_t rel, const float *__restrict__ lam,
     float *__restrict__ lam_n, float *__restrict__ lam_lo, double *__restrict__ grad) {
-    extern __shared__ float tile[];
+    extern __shared__ __align__(16) float tile[];
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
-    const BrickInfo bi = bricks[list[logical]];
+    const int32_t gb = list[logical];
+    if (gb < 0) return;   // a hole of the XCD launch list
+    const BrickInfo bi = bricks[gb];
     float *lt = tile + LAM;
     const int32_t B = blockDim.x;
-    constexpr int U = 8;
-    for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
-        float v[U], w[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t t = min(t0 + u * B, bi.n_own_pad - 1);
-            v[u] = Thi[bi.slot0 + t];
-            w[u] = lam[bi.slot0 + t];
+    // both tiles four slots at a time, as the forward brick kernel stages its
+    // tile: own slots contiguous and 64-aligned, the halo list 16-byte aligned
+    // and padded to a multiple of 4 with copies of its last entry; the second
+    // quad of a pass is clamped to the last one (the same values again)
+    const char *t_in = reinterpret_cast<const char *>(Thi);
+    const char *l_in = reinterpret_cast<const char *>(lam);
+    auto at = [](const char *base, int32_t slot) {
+        return *reinterpret_cast<const float *>(base + (uint32_t)slot * 4u);
+    };
+    {
+        const int32_t nq = bi.n_own_pad >> 2;
+        const float4 *ts = reinterpret_cast<const float4 *>(Thi + bi.slot0);
+        const float4 *ls = reinterpret_cast<const float4 *>(lam + bi.slot0);
+        float4 *td = reinterpret_cast<float4 *>(tile), *ld = reinterpret_cast<float4 *>(lt);
+        for (int32_t q0 = threadIdx.x; q0 < nq; q0 += 2 * B) {
+            const int32_t q1 = min(q0 + B, nq - 1);
+            const float4 a = ts[q0], c = ts[q1], la = ls[q0], lc = ls[q1];
+            td[q0] = a;
+            td[q1] = c;
+            ld[q0] = la;
+            ld[q1] = lc;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + u * B < bi.n_own_pad) {
-                tile[t0 + u * B] = v[u];
-                lt[t0 + u * B] = w[u];
-            }
-    }
-    const int32_t *hl = halo + bi.halo_off;
-    for (int32_t t0 = threadIdx.x; t0 < bi.n_halo; t0 += U * B) {
-        int32_t id[U];
-        float v[U], w[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) id[u] = hl[min(t0 + u * B, bi.n_halo - 1)];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            v[u] = Thi[id[u]];
-            w[u] = lam[id[u]];
+        const int32_t nh = halo_padded(bi.n_halo) >> 2;
+        const int4 *hl = reinterpret_cast<const int4 *>(halo + bi.halo_off);
+        float4 *th = reinterpret_cast<float4 *>(tile + bi.n_own_pad);
+        float4 *lh = reinterpret_cast<float4 *>(lt + bi.n_own_pad);
+        for (int32_t q0 = threadIdx.x; q0 < nh; q0 += 2 * B) {
+            const int32_t q1 = min(q0 + B, nh - 1);
+            const int4 ia = hl[q0], ic = hl[q1];
+            const float4 a = make_float4(at(t_in, ia.x), at(t_in, ia.y), at(t_in, ia.z), at(t_in, ia.w));
+            const float4 c = make_float4(at(t_in, ic.x), at(t_in, ic.y), at(t_in, ic.z), at(t_in, ic.w));
+            const float4 la = make_float4(at(l_in, ia.x), at(l_in, ia.y), at(l_in, ia.z), at(l_in, ia.w));
+            const float4 lc = make_float4(at(l_in, ic.x), at(l_in, ic.y), at(l_in, ic.z), at(l_in, ic.w));
+            th[q0] = a;
+            th[q1] = c;
+            lh[q0] = la;
+            lh[q1] = lc;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + u * B < bi.n_halo) {
-                tile[bi.n_own_pad + t0 + u * B] = v[u];
-                lt[bi.n_own_pad + t0 + u * B] = w[u];
-            }
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -376,7 +383,7 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
     // 512 threads against 159 ms at 256 on the 64 x 32,000-atom workload)
     const int bblock = std::min(std::max(c->tune.block, kWave), kBrickBlockMax);
     const int rblock = kBrickBlockMax;
-    const unsigned bgrid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
+    const unsigned bgrid = (unsigned)c->n_xcd_list;
     const size_t blds = sizeof(float) * ((lam_near ? 4096 : 8192) + (size_t)c->tile_max);
     std::vector<int64_t> htab(nck * S);
     for (size_t k = 0; k < nck; ++k)
@@ -408,7 +415,7 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
             if (brick)
                 hipLaunchKernelGGL(lam_near ? k_adjoint_brick<4096> : k_adjoint_brick<8192>,
                                    dim3(bgrid), dim3(rblock), blds, c->stream, c->bricks,
-                                   c->brick_list, c->n_brick_list, c->slices, c->colw, c->halo,
+                                   c->xcd_list, c->n_xcd_list, c->slices, c->colw, c->halo,
                                    Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc2],
                                    lam[lc2 ^ 1], lamlo, grad);
             else

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -627,6 +628,31 @@ __global__ void k_halo_expand(const HaloCell *hc, int64_t n_hc, const BrickInfo 
     for (int32_t q = q0; q < q1; ++q) halo[b.halo_off + h.offset + (q - q0)] = pos_slot_all[h.pos_base + q];
 }
 
+// estimated work of every listed brick for the XCD split of the brick
+// launches, in tenths of a vector instruction per wave: per slice 11 per row
+// entry (the pair term, its FP64 sum and the offset) and 140 for the update
+// and the ledgers; 0.1 per staged slot; 400 for the workgroup
+__global__ void k_brick_work(const BrickInfo *bricks, const int32_t *list, int32_t n_list,
+                             const SliceInfo *slices, int32_t *work) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_list) return;
+    const BrickInfo bi = bricks[list[q]];
+    int32_t w = 4000 + bi.n_own_pad + bi.n_halo;
+    for (int32_t k = 0; k < bi.n_own_pad / kWave; ++k) w += 110 * slices[bi.slice0 + k].width + 1400;
+    work[q] = w;
+}
+
+// the padding of every halo list: entries n_halo .. to the next multiple of 4
+// repeat entry n_halo - 1
+__global__ void k_halo_pad(const BrickInfo *bricks, int32_t n_bricks, int32_t *halo) {
+    const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_bricks) return;
+    const BrickInfo bi = bricks[b];
+    if (bi.n_halo <= 0) return;
+    const int32_t last = halo[bi.halo_off + bi.n_halo - 1];
+    for (int32_t k = bi.n_halo; k < halo_padded(bi.n_halo); ++k) halo[bi.halo_off + k] = last;
+}
+
 __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                            const double *src, int32_t field, int32_t precision, double *T64,
                            float *Thi, float *Tlo, double *Tl64, float *Tl32, double *srcw64,
@@ -945,6 +971,59 @@ int32_t brick_edge(const l2t_ctx *c, int32_t limit) {
 
 }  // namespace
 
+// cut the brick list into 8 contiguous ranges of about equal estimated work
+// and write the launch list (range x at x G/8, -1 after its last brick).
+// Splitting by count instead left the XCDs of the 256-slab batch unequal
+// (64.1 G atom-substeps/s; 65.7 by work, 66.8 with no XCD ranges at all,
+// which costs the 4M-atom system 5 % through its L2 reuse).
+int xcd_split(l2t_ctx *c, const std::vector<int32_t> &list, const std::vector<int32_t> &work) {
+    const int32_t n = (int32_t)list.size();
+    int64_t total = 0;
+    for (int32_t w : work) total += w;
+    int32_t cut[9];
+    cut[0] = 0;
+    int64_t acc = 0;
+    int32_t q = 0;
+    for (int x = 1; x < 8; ++x) {
+        const int64_t target = total * x / 8;
+        // advance while taking the next brick brings the sum closer to the target
+        while (q < n && std::llabs(acc + work[q] - target) <= std::llabs(acc - target)) acc += work[q++];
+        cut[x] = q;
+    }
+    cut[8] = n;
+    int32_t per = 0;
+    for (int x = 0; x < 8; ++x) per = std::max(per, cut[x + 1] - cut[x]);
+    per = std::max(per, 1);
+    const int32_t G = 8 * per;
+    c->h_xcd_list.assign((size_t)G, -1);
+    // inside its range an XCD takes the bricks largest first, so the last
+    // workgroups of the launch are small ones (measured on the 4M-atom system,
+    // whose bricks are 6 or 7 cells a side: 49.3-50.5 -> 48.4-49.4 us)
+    std::vector<int32_t> idx;
+    for (int x = 0; x < 8; ++x) {
+        idx.clear();
+        for (int32_t k = cut[x]; k < cut[x + 1]; ++k) idx.push_back(k);
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+        for (size_t k = 0; k < idx.size(); ++k) c->h_xcd_list[(size_t)x * per + k] = list[idx[k]];
+    }
+    if ((size_t)G > c->cap_xl) {
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+        dev_free(c, c->xcd_list);
+        c->xcd_list = nullptr;
+        c->cap_xl = 0;
+        void *m = nullptr;
+        const hipError_t e = dev_malloc(c, &m, sizeof(int32_t) * (size_t)G);
+        if (e != hipSuccess) return hip_fail(c, e, "XCD launch list allocation");
+        c->xcd_list = static_cast<int32_t *>(m);
+        c->cap_xl = (size_t)G;
+    }
+    L2T_HIP(c, hipMemcpyAsync(c->xcd_list, c->h_xcd_list.data(), sizeof(int32_t) * (size_t)G,
+                              hipMemcpyHostToDevice, c->stream));
+    c->n_xcd_list = G;
+    return L2T_OK;
+}
+
 int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forced,
                          bool *tile_overflow) {
     const int S = (int)c->sys.size();
@@ -1213,10 +1292,13 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forc
     for (const auto &v : part) n_cells_halo += v.size();
     h_halo.reserve(n_cells_halo);
     for (const auto &v : part) h_halo.insert(h_halo.end(), v.begin(), v.end());
+    // every list starts on a 16-byte boundary and is padded to whole quads (the
+    // padding repeats the list's last entry), so the brick kernels stage it four
+    // slots at a time; the tile holds the padded list
     for (BrickInfo &bi : hb) {   // empty bricks keep n_halo = 0 and the running offset
         bi.halo_off = (int32_t)std::min<int64_t>(halo_total, INT32_MAX);
-        halo_total += bi.n_halo;
-        if (bi.n_own > 0) tile_max = std::max(tile_max, bi.n_own_pad + bi.n_halo);
+        halo_total += halo_padded(bi.n_halo);
+        if (bi.n_own > 0) tile_max = std::max(tile_max, bi.n_own_pad + halo_padded(bi.n_halo));
     }
     if (tile_max > kTileCapFloats) {
         *tile_overflow = true;
@@ -1431,6 +1513,9 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forc
         hipLaunchKernelGGL(k_halo_expand, dim3(nblk((int64_t)h_halo.size(), 256)), dim3(256), 0,
                            st_, d_halo, (int64_t)h_halo.size(), c->bricks, d_start,
                            c->pos_slot, c->halo);
+    if (!h_halo.empty())
+        hipLaunchKernelGGL(k_halo_pad, dim3(nblk(nbricks, 256)), dim3(256), 0, st_, c->bricks,
+                           nbricks, c->halo);
     L2T_HIP(c, hipGetLastError());
     // ---- statistics ----------------------------------------------------------------------
     unsigned long long *dsum = reinterpret_cast<unsigned long long *>(dw + stat_at);
@@ -1439,9 +1524,25 @@ int build_neighbors_once(l2t_ctx *c, double r_cut, int32_t edge_limit, bool forc
     hipLaunchKernelGGL(k_count_stats, dim3(std::max<unsigned>(1, std::min<unsigned>(1024, nblk(c->n_int, 256)))),
                        dim3(256), 0, st_, c->cnt, (int64_t)c->n_int, dsum, dmax);
     L2T_HIP(c, hipGetLastError());
+    std::vector<int32_t> h_work(h_list.size());
+    if (!h_list.empty()) {
+        int32_t *d_work = tmp_of<int32_t>(c, 16, (int64_t)h_list.size());
+        if (!d_work) return fail(c, L2T_ENOMEM, "brick work allocation failed");
+        hipLaunchKernelGGL(k_brick_work, dim3(nblk((int64_t)h_list.size(), 256)), dim3(256), 0,
+                           st_, c->bricks, c->brick_list, (int32_t)h_list.size(), c->slices,
+                           d_work);
+        L2T_HIP(c, hipMemcpyAsync(h_work.data(), d_work, sizeof(int32_t) * h_list.size(),
+                                  hipMemcpyDeviceToHost, st_));
+    }
     int32_t hstat[4] = {0, 0, 0, 0};
     L2T_HIP(c, hipMemcpyAsync(hstat, dw + stat_at, sizeof hstat, hipMemcpyDeviceToHost, st_));
     L2T_HIP(c, hipStreamSynchronize(st_));
+    if (!h_list.empty()) {
+        const int xrc = xcd_split(c, h_list, h_work);
+        if (xrc != L2T_OK) return xrc;
+    } else {
+        c->n_xcd_list = 0;
+    }
     unsigned long long usum = 0;
     std::memcpy(&usum, hstat, sizeof usum);
     const int64_t sum = (int64_t)usum;

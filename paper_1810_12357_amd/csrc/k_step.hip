@@ -71,9 +71,11 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
 // LDS-tile FP32C sub-step: one workgroup per brick stages the FP32 hi
 // temperatures of the brick's own slots and of its halo atoms in LDS, then its
 // waves run the brick's slices reading neighbours from the tile through the
-// uint16 table.  Workgroup b runs on XCD b mod 8 and takes brick
-// (b mod 8) * (G/8) + b/8, so each XCD sweeps one contiguous range of bricks
-// and its L2 serves the halo loads.
+// uint16 table.  Workgroup b runs on XCD b mod 8 and takes entry
+// (b mod 8) * (G/8) + b/8 of the launch list: with the XCD launch list each
+// XCD sweeps one contiguous range of bricks (its L2 serves the halo loads),
+// the ranges carry equal estimated work, and entries past a range are holes
+// (-1) whose workgroups return at once.
 // LO_IN: read T_lo from lo_in and write the new T_lo to Tlo (two buffers, as
 // the adjoint's recomputation keeps every state of a segment); otherwise T_lo
 // is updated in place and lo_in is unused.
@@ -86,54 +88,68 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
     const float *__restrict__ srcw, const DevParams *__restrict__ P,
     const int64_t *__restrict__ dstep, int32_t rel, double *__restrict__ ledger,
     double *__restrict__ eatom, unsigned *__restrict__ err) {
-    extern __shared__ float tile[];
+    extern __shared__ __align__(16) float tile[];
     __shared__ float wlo[kBrickBlockMax / kWave], whi[kBrickBlockMax / kWave];
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
-    const BrickInfo bi = bricks[list[logical]];
-    // stage the tile: 8 independent loads in flight per thread (a sweep of
-    // 4..32 on the 4M-atom system: 8 and 6 fastest, 16 1.3 % slower, 32 spills),
-    // keeping the range of the staged temperatures (padding slots aside)
-    constexpr int U = 8;
+    const int32_t gb = list[logical];
+    if (gb < 0) return;   // a hole of the XCD launch list
+    const BrickInfo bi = bricks[gb];
+    // stage the tile four slots at a time, keeping the range of the staged
+    // temperatures (padding slots aside): the brick's own slots are contiguous
+    // and 64-aligned (real atoms first), and its halo list is 16-byte aligned
+    // and padded to a multiple of 4 with copies of its last entry, which leave
+    // the range unchanged.  Two quads per thread and pass keep 8 loads in
+    // flight; the second is clamped to the last quad, so a thread past the end
+    // stages that quad again (the same values to the same place).
     const int32_t B = blockDim.x;
+    const char *tb_in = reinterpret_cast<const char *>(Thi);
+    auto hi_at = [&](int32_t slot) {   // 32-bit unsigned byte offset: one address op
+        return *reinterpret_cast<const float *>(tb_in + (uint32_t)slot * 4u);
+    };
     float tmin = INFINITY, tmax = -INFINITY;
-    for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
-        float v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t t = t0 + u * B;
-            v[u] = (t < bi.n_own_pad) ? Thi[bi.slot0 + t] : 0.0f;
+    auto range4 = [&](const float4 &v) {
+        tmin = fminf(tmin, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+        tmax = fmaxf(tmax, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+    };
+    auto range_own = [&](float4 v, int32_t q) {
+        const int32_t i = 4 * q;
+        if (i + 4 > bi.n_own) {      // the quad of the last real slot, or padding only
+            if (i >= bi.n_own) return;
+            if (i + 1 >= bi.n_own) v.y = v.x;
+            if (i + 2 >= bi.n_own) v.z = v.x;
+            v.w = v.x;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t t = t0 + u * B;
-            if (t < bi.n_own_pad) tile[t] = v[u];
-            if (t < bi.n_own) {
-                tmin = fminf(tmin, v[u]);
-                tmax = fmaxf(tmax, v[u]);
-            }
+        range4(v);
+    };
+    {
+        const int32_t nq = bi.n_own_pad >> 2;
+        const float4 *src = reinterpret_cast<const float4 *>(Thi + bi.slot0);
+        float4 *dst = reinterpret_cast<float4 *>(tile);
+        for (int32_t q0 = threadIdx.x; q0 < nq; q0 += 2 * B) {
+            const int32_t q1 = min(q0 + B, nq - 1);
+            const float4 a = src[q0];
+            const float4 c = src[q1];
+            dst[q0] = a;
+            dst[q1] = c;
+            range_own(a, q0);
+            range_own(c, q1);
         }
-    }
-    const int32_t *hl = halo + bi.halo_off;
-    float *ht = tile + bi.n_own_pad;
-    for (int32_t t0 = threadIdx.x; t0 < bi.n_halo; t0 += U * B) {
-        int32_t id[U];
-        float v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t t = t0 + u * B;
-            id[u] = (t < bi.n_halo) ? hl[t] : bi.slot0;
+        const int32_t nh = halo_padded(bi.n_halo) >> 2;
+        const int4 *hl = reinterpret_cast<const int4 *>(halo + bi.halo_off);
+        float4 *ht = reinterpret_cast<float4 *>(tile + bi.n_own_pad);
+        for (int32_t q0 = threadIdx.x; q0 < nh; q0 += 2 * B) {
+            const int32_t q1 = min(q0 + B, nh - 1);
+            const int4 ia = hl[q0];
+            const int4 ic = hl[q1];
+            const float4 a = make_float4(hi_at(ia.x), hi_at(ia.y), hi_at(ia.z), hi_at(ia.w));
+            const float4 c = make_float4(hi_at(ic.x), hi_at(ic.y), hi_at(ic.z), hi_at(ic.w));
+            ht[q0] = a;
+            ht[q1] = c;
+            range4(a);
+            range4(c);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = Thi[id[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + u * B < bi.n_halo) {
-                ht[t0 + u * B] = v[u];
-                tmin = fminf(tmin, v[u]);
-                tmax = fmaxf(tmax, v[u]);
-            }
     }
     // wave index, slice records and row widths are wave-uniform (scalar registers)
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -209,7 +225,9 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_brick_fp64(
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned logical = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
     if ((int32_t)logical >= n_list) return;
-    const BrickInfo bi = bricks[list[logical]];
+    const int32_t gb = list[logical];
+    if (gb < 0) return;   // a hole of the XCD launch list
+    const BrickInfo bi = bricks[gb];
     constexpr int U = 4;
     const int32_t B = blockDim.x;
     for (int32_t t0 = threadIdx.x; t0 < bi.n_own_pad; t0 += U * B) {
@@ -782,10 +800,12 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     // mode and an 8-byte tile fits 64 KB of LDS; otherwise the global-gather
     // k_step_fp64, whose one wave per slice spreads a small system over more
     // CUs (one brick is one workgroup).  Both give bitwise-equal states.
-    const int32_t *b_list = c->brick_list + (sys < 0 ? 0 : c->sys[sys].list0);
-    const int32_t b_n = sys < 0 ? c->n_brick_list : c->sys[sys].n_list;
+    // all systems: the XCD launch list; one system: its range of the brick list
+    const int32_t *b_list = sys < 0 ? c->xcd_list : c->brick_list + c->sys[sys].list0;
+    const int32_t b_n = sys < 0 ? c->n_xcd_list : c->sys[sys].n_list;
+    const int32_t b_bricks = sys < 0 ? c->n_brick_list : c->sys[sys].n_list;
     const bool brick64 = c->precision == L2T_FP64 && c->tune.kernel == kKernelBrick && !lat &&
-                         b_n >= std::max(1, c->n_cu) &&
+                         b_bricks >= std::max(1, c->n_cu) &&
                          (size_t)c->tile_max * sizeof(double) <= 65536;
     const unsigned b_grid = (unsigned)((b_n + 7) / 8 * 8);
     const size_t b_lds = sizeof(double) * (size_t)c->tile_max;
@@ -912,12 +932,13 @@ static int persistent_grid(l2t_ctx *c, int block) {
 int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom) {
     int cur = c->cur;
     if (kernel == kKernelBrick) {
-        const int32_t nl = c->n_brick_list;
-        const unsigned grid = (unsigned)((nl + 7) / 8 * 8);
+        // the XCD launch list: G workgroups, a multiple of 8
+        const int32_t nl = c->n_xcd_list;
+        const unsigned grid = (unsigned)nl;
         const size_t lds = sizeof(float) * (size_t)c->tile_max;
         for (int32_t k = 0; k < n && nl > 0; ++k) {
             hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(block), lds, c->stream,
-                               c->bricks, c->brick_list, nl, c->slices, c->colw, c->halo,
+                               c->bricks, c->xcd_list, nl, c->slices, c->colw, c->halo,
                                c->Thi[cur], c->Thi[cur ^ 1], nullptr, c->Tlo, c->Tl32, c->srcw32,
                                c->dparams, c->dstep, k, c->ledger, eatom, c->derr);
             cur ^= 1;
@@ -1010,7 +1031,7 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
     L2T_HIP(c, hipEventCreate(&ev.e0));
     L2T_HIP(c, hipEventCreate(&ev.e1));
     hipEvent_t e0 = ev.e0, e1 = ev.e1;
-    const unsigned grid = (unsigned)((c->n_brick_list + 7) / 8 * 8);
+    const unsigned grid = (unsigned)c->n_xcd_list;
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
     float best = 1e30f;
     hipError_t e = hipSuccess;
@@ -1020,7 +1041,7 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
         // (a positive weight marks no atom as held); T_lo is updated in place
         for (int32_t k = 0; k < n; ++k)
             hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(kBrickBlockMax), lds, s_,
-                               c->bricks, c->brick_list, c->n_brick_list, c->slices, c->colw,
+                               c->bricks, c->xcd_list, c->n_xcd_list, c->slices, c->colw,
                                c->halo, (k & 1) ? Tb : Ta, (k & 1) ? Ta : Tb, nullptr, zl, tl, tl,
                                P, stp, k, led, nullptr, perr);
         (void)hipEventRecord(e1, s_);
@@ -1040,12 +1061,12 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
 // recomputation between checkpoints)
 int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const float *lo_in,
                      float *Tlo, const int64_t *dstep, int32_t rel, double *ledger) {
-    const int32_t nl = c->n_brick_list;
+    const int32_t nl = c->n_xcd_list;
     if (nl <= 0) return L2T_OK;
-    const unsigned grid = (unsigned)((nl + 7) / 8 * 8);
+    const unsigned grid = (unsigned)nl;
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
     hipLaunchKernelGGL(k_brick_fp32c<true>, dim3(grid), dim3(block), lds, c->stream, c->bricks,
-                       c->brick_list, nl, c->slices, c->colw, c->halo, Thi, Thi_n, lo_in, Tlo,
+                       c->xcd_list, nl, c->slices, c->colw, c->halo, Thi, Thi_n, lo_in, Tlo,
                        c->Tl32, c->srcw32, c->dparams, dstep, rel, ledger, nullptr, c->derr);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;

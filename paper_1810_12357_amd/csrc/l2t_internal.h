@@ -119,11 +119,13 @@ struct GraphKey {
 constexpr int32_t kGraphChunk = 256;
 
 // grow-only temporary buffers of the neighbour build (tmp_buf slots)
-constexpr int kTmpSlots = 16;
+constexpr int kTmpSlots = 17;
 
 constexpr int kKernelSliced = 0;   // global gathers through the int32 table
 constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
 constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
+// entries a brick's halo list takes: its length rounded up to a multiple of 4
+__host__ __device__ constexpr int32_t halo_padded(int32_t n_halo) { return (n_halo + 3) & ~3; }
 constexpr int32_t kMaxBrickEdge = 1024;  // largest brick edge (cells) the layout considers
 constexpr int kSlicedBlockMax = 256;  // threads per workgroup, global-gather kernels
 constexpr int kResidentMaxSlots = 1024;  // largest system one workgroup keeps in LDS
@@ -201,6 +203,14 @@ struct l2t_ctx {
     int32_t *pos_slot = nullptr; // caller layout [n_tot]: cell-order position -> slot
     l2t::BrickInfo *bricks = nullptr;
     int32_t *brick_list = nullptr;   // non-empty bricks
+    // launch list of the all-system brick kernels: the brick list cut into 8
+    // contiguous ranges of equal estimated work, range x at [x G/8, (x+1) G/8)
+    // followed by -1 holes, so that workgroup b (on XCD b mod 8) takes entry
+    // (b mod 8) G/8 + b/8; G = n_xcd_list
+    int32_t *xcd_list = nullptr;
+    int32_t n_xcd_list = 0;
+    size_t cap_xl = 0;
+    std::vector<int32_t> h_xcd_list;   // host copy (the upload reads it asynchronously)
     int32_t *shell = nullptr;
     int32_t *halo = nullptr;
     int32_t n_bricks = 0, n_brick_list = 0, tile_max = 0, brick_edge_used = 0;

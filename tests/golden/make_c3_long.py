@@ -6,7 +6,7 @@ the same points (Eq. 6).
 
 Inputs come from the seeded workload generator and every number written
 comes from the oracle; nothing here touches the GPU library.  Runs for about
-15 minutes on 8 cores:  python tests/golden/make_c3_long.py
+35 minutes on 8 cores:  python tests/golden/make_c3_long.py
 """
 import json
 import os
