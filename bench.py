@@ -11,7 +11,7 @@ timed region starts.
 Also reported:
   * roofline of the dominant kernel (the FP32C sub-step launch), from HIP events
     on the library's stream, against 8 TB/s HBM, with the algorithmic bytes
-    24 + 2 n_mean (brick form) or 24 + 4 n_mean (global gathers) per
+    20 + 2 n_mean (brick form) or 20 + 4 n_mean (global gathers) per
     atom-substep, the HBM traffic rocprofv3 measured for it (and that traffic
     over the live launch time), and a 1 GiB device copy on the same GPU;
   * the same system in the plain FP64 form (a bounded sample of sub-steps);
@@ -59,11 +59,13 @@ def log(msg):
 
 def library_source_hash() -> str:
     """sha256 over the sources the sub-step kernels are compiled from (their
-    translation unit, the device helpers, the internal and the C header)."""
+    translation unit, the device helpers, the state encoding, the internal and
+    the C header)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_12357_amd", "csrc")
-    files = [os.path.join(csrc, f) for f in ("k_step.hip", "step_device.h", "l2t_internal.h")]
+    files = [os.path.join(csrc, f)
+             for f in ("k_step.hip", "step_device.h", "state_fp32c.h", "l2t_internal.h")]
     files.append(os.path.join(ROOT, "include", "l2t.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -154,11 +156,11 @@ def bench_c4_speedup(L, torch, n_sub, n_full):
             log(f"  C4 {key}: {n_atoms} atoms x {n} sub-steps in {dt:.3f} s")
         kernel = L.l2t_get_option(ctx.h, L.L2T_OPT_KERNEL)
         # algorithmic bytes per atom-substep: the state read and written (FP32C
-        # hi + lo: 16; FP64: 16), T_lat (4 / 8), the source weight of the laser
-        # (4 / 8), a row offset (4) and one index per neighbour (2 B in the
-        # brick forms, 4 B through the global-slot table)
+        # hi and its 16-bit low part: 12; FP64: 16), T_lat (4 / 8), the source
+        # weight of the laser (4 / 8), a row offset (4) and one index per
+        # neighbour (2 B in the brick forms, 4 B through the global-slot table)
         per_nbr = 2.0 if kernel == 1 else 4.0
-        fixed = 28.0 if prec == L.L2T_FP32C else 36.0
+        fixed = 24.0 if prec == L.L2T_FP32C else 36.0
         info[name] = dict(kernel=["global-gather", "lds-brick"][kernel], mean_neighbors=mean,
                           bytes_per_atom_substep=fixed + per_nbr * mean,
                           brick_edge=L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE))
@@ -308,14 +310,15 @@ def bench_adjoint(L, torch):
     ctx.close()
     fwd, adj = times[-1]
     # algorithmic bytes per atom-substep, 2 B per neighbour index in the brick
-    # form and 4 B in the global-gather form.  Forward: hi+lo read and write
-    # (16), T_lat (4), row offset (4).  Reverse: T hi (4), lambda hi+lo read
-    # and write (16), T_lat (4), row offset (4).  The recomputation runs the
-    # forward on all but one sub-step per checkpoint (the global-gather form
-    # also copies lo into the next state of the segment, 8 B).
+    # form and 4 B in the global-gather form.  Forward: hi and the 16-bit low
+    # part read and written (12), T_lat (4), row offset (4).  Reverse: T hi (4),
+    # lambda hi+lo read and write (16), T_lat (4), row offset (4).  The
+    # recomputation runs the forward on all but one sub-step per checkpoint
+    # (the global-gather form also copies the low part into the next state of
+    # the segment, 4 B).
     per_nbr = 2.0 if kernel == 1 else 4.0
-    fb = 24.0 + per_nbr * mean
-    ab = (28.0 + per_nbr * mean) + (fb + (0.0 if kernel == 1 else 8.0)) * (ck - 1) / ck
+    fb = 20.0 + per_nbr * mean
+    ab = (28.0 + per_nbr * mean) + (fb + (0.0 if kernel == 1 else 4.0)) * (ck - 1) / ck
     out = dict(workload=f"c5: {S} FCC systems of {w.systems[0].n} atoms, {n} FP32C sub-steps, "
                         f"checkpoint every {ck}",
                kernel=["global-gather", "lds-brick"][kernel], mean_neighbors=mean,
@@ -575,10 +578,10 @@ def main():
         block = L.l2t_get_option(h, L.L2T_OPT_BLOCK)
         kernel = L.l2t_get_option(h, L.L2T_OPT_KERNEL)
         adv = float(np.mean(adv_ms))
-        # algorithmic bytes per atom-substep: hi+lo read and write (16), T_lat
-        # (4), row offset (4) and one index per neighbour (4 B global, 2 B
-        # brick-local)
-        bytes_per = 24.0 + (2.0 if kernel == 1 else 4.0) * mean
+        # algorithmic bytes per atom-substep: hi and its 16-bit low part read
+        # and written (12), T_lat (4), row offset (4) and one index per
+        # neighbour (4 B global, 2 B brick-local)
+        bytes_per = 20.0 + (2.0 if kernel == 1 else 4.0) * mean
         if kernel == 1:
             launch_ms, units, kname = adv / args.substeps, sy.n, "k_brick_fp32c"
         elif persistent:

@@ -70,7 +70,7 @@ extern "C" {
 
 /* ---- precision of the sub-step path ---------------------------------------- */
 #define L2T_FP64   0   /* plain: literal Eq. 2 pair term in FP64, one launch per sub-step per system */
-#define L2T_FP32C  1   /* FP32 pair terms, FP64 neighbour sums, FP32 (hi+lo) state updated in FP64 */
+#define L2T_FP32C  1   /* FP32 pair terms, FP64 neighbour sums, state = FP32 hi + 16-bit low part (39 bits), updated in FP64 */
 
 /* ---- memory space of a caller pointer -------------------------------------- */
 #define L2T_HOST    0

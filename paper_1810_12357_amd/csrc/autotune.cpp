@@ -105,14 +105,14 @@ int autotune(l2t_ctx *c) {
     if (ensure_scratch(c, bytes) != L2T_OK) return L2T_ENOMEM;
     char *p = (char *)c->scratch;
     float *s_hi = (float *)p;
-    float *s_lo = s_hi + NI;
-    double *s_led = (double *)(s_lo + NI);
+    int16_t *s_lo = reinterpret_cast<int16_t *>(s_hi + NI);   // in a region of NI floats
+    double *s_led = (double *)(s_hi + 2 * NI);
     int64_t *s_step = (int64_t *)(s_led + 3 * NS);
     const int cur = c->cur;
     auto save = [&]() -> int {
         L2T_HIP(c, hipMemcpyAsync(s_hi, c->Thi[cur], sizeof(float) * NI, hipMemcpyDeviceToDevice,
                                   c->stream));
-        L2T_HIP(c, hipMemcpyAsync(s_lo, c->Tlo, sizeof(float) * NI, hipMemcpyDeviceToDevice,
+        L2T_HIP(c, hipMemcpyAsync(s_lo, c->Tlo, sizeof(int16_t) * NI, hipMemcpyDeviceToDevice,
                                   c->stream));
         L2T_HIP(c, hipMemcpyAsync(s_led, c->ledger, sizeof(double) * 3 * NS,
                                   hipMemcpyDeviceToDevice, c->stream));
@@ -123,7 +123,7 @@ int autotune(l2t_ctx *c) {
     auto restore = [&]() -> int {
         L2T_HIP(c, hipMemcpyAsync(c->Thi[cur], s_hi, sizeof(float) * NI, hipMemcpyDeviceToDevice,
                                   c->stream));
-        L2T_HIP(c, hipMemcpyAsync(c->Tlo, s_lo, sizeof(float) * NI, hipMemcpyDeviceToDevice,
+        L2T_HIP(c, hipMemcpyAsync(c->Tlo, s_lo, sizeof(int16_t) * NI, hipMemcpyDeviceToDevice,
                                   c->stream));
         L2T_HIP(c, hipMemcpyAsync(c->ledger, s_led, sizeof(double) * 3 * NS,
                                   hipMemcpyDeviceToDevice, c->stream));

@@ -305,7 +305,7 @@ __global__ void k_grad_reduce(const SliceInfo *slices, int32_t n_slices, const d
 }
 
 __global__ void k_forward_step(const SliceInfo *slices, int32_t n_slices, const int32_t *col,
-                               const float *Thi, float *Thi_n, float *Tlo, const float *Tl,
+                               const float *Thi, float *Thi_n, int16_t *Tlo, const float *Tl,
                                const float *srcw, const DevParams *P, const int64_t *dstep,
                                int32_t rel, double *ledger, unsigned *err) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -330,7 +330,7 @@ int record_checkpoint(l2t_ctx *c, int64_t k) {
     float *dst = (float *)c->rec.buf + (size_t)k * 2 * NI;
     L2T_HIP(c, hipMemcpyAsync(dst, c->Thi[c->cur], sizeof(float) * NI, hipMemcpyDeviceToDevice,
                               c->stream));
-    L2T_HIP(c, hipMemcpyAsync(dst + NI, c->Tlo, sizeof(float) * NI, hipMemcpyDeviceToDevice,
+    L2T_HIP(c, hipMemcpyAsync(dst + NI, c->Tlo, sizeof(int16_t) * NI, hipMemcpyDeviceToDevice,
                               c->stream));
     return L2T_OK;
 }
@@ -399,14 +399,17 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
         int lc2 = l0;
         for (int32_t m = 0; m + 1 < L; ++m) {
             float *in = seg + (size_t)m * 2 * NI, *out = seg + (size_t)(m + 1) * 2 * NI;
+            // each state is [hi: NI floats][q: NI int16 in a region of NI floats]
+            int16_t *qin = reinterpret_cast<int16_t *>(in + NI);
+            int16_t *qout = reinterpret_cast<int16_t *>(out + NI);
             if (brick) {
-                int rc = brick_step_fp32c(c, bblock, in, out, in + NI, out + NI, dst, m, led);
+                int rc = brick_step_fp32c(c, bblock, in, out, qin, qout, dst, m, led);
                 if (rc != L2T_OK) return rc;
             } else {
-                L2T_HIP(c, hipMemcpyAsync(out + NI, in + NI, sizeof(float) * NI,
+                L2T_HIP(c, hipMemcpyAsync(qout, qin, sizeof(int16_t) * NI,
                                           hipMemcpyDeviceToDevice, c->stream));
                 hipLaunchKernelGGL(k_forward_step, g, b, 0, c->stream, c->slices, c->n_slices,
-                                   c->col, in, out, out + NI, c->Tl32, c->srcw32, c->dparams, dst,
+                                   c->col, in, out, qout, c->Tl32, c->srcw32, c->dparams, dst,
                                    m, led, c->derr);
             }
         }

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "l2t_internal.h"
+#include "state_fp32c.h"
 
 namespace l2t {
 namespace {
@@ -655,7 +656,7 @@ __global__ void k_halo_pad(const BrickInfo *bricks, int32_t n_bricks, int32_t *h
 
 __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                            const double *src, int32_t field, int32_t precision, double *T64,
-                           float *Thi, float *Tlo, double *Tl64, float *Tl32, double *srcw64,
+                           float *Thi, int16_t *Tlo, double *Tl64, float *Tl32, double *srcw64,
                            float *srcw32) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_pad) return;
@@ -666,9 +667,9 @@ __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm,
         if (precision == L2T_FP64) {
             T64[slot] = v;
         } else {
-            float hi = (float)v;
+            const float hi = (float)v;
             Thi[slot] = hi;
-            Tlo[slot] = (float)(v - (double)hi);
+            Tlo[slot] = state_lo(v, hi);
         }
     } else if (field == L2T_FIELD_TL) {
         if (precision == L2T_FP64) {
@@ -696,7 +697,7 @@ __global__ void k_field_in(int32_t atom_off, int32_t n_pad, const int32_t *perm,
 
 __global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm, int64_t caller_off,
                             int32_t field, int32_t precision, const double *T64, const float *Thi,
-                            const float *Tlo, const double *Tl64, const float *Tl32,
+                            const int16_t *Tlo, const double *Tl64, const float *Tl32,
                             const int32_t *cnt, const double *eatom, const double *srcw64,
                             const float *srcw32, double *dst) {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -706,7 +707,7 @@ __global__ void k_field_out(int32_t atom_off, int32_t n_pad, const int32_t *perm
     if (g < 0) return;
     double v = 0.0;
     if (field == L2T_FIELD_TE) {
-        v = (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+        v = (precision == L2T_FP64) ? T64[slot] : state_value(Thi[slot], Tlo[slot]);
     } else if (field == L2T_FIELD_TL) {
         v = (precision == L2T_FP64) ? fabs(Tl64[slot]) : (double)fabsf(Tl32[slot]);
     } else if (field == L2T_FIELD_GATE) {

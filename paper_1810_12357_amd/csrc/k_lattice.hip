@@ -21,6 +21,7 @@
 #include <cmath>
 
 #include "l2t_internal.h"
+#include "state_fp32c.h"
 
 namespace l2t {
 namespace {
@@ -29,7 +30,7 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 __global__ void k_coupling(int32_t n, int64_t caller_off, const int32_t *__restrict__ inv,
                            int32_t mode, int32_t precision, const double *__restrict__ T64,
-                           const float *__restrict__ Thi, const float *__restrict__ Tlo,
+                           const float *__restrict__ Thi, const int16_t *__restrict__ Tlo,
                            const double *__restrict__ Tl64, const float *__restrict__ Tl32,
                            const double *__restrict__ eatom, double g, double dt_md,
                            double ke_eps, const double *__restrict__ v,
@@ -63,7 +64,7 @@ __global__ void k_coupling(int32_t n, int64_t caller_off, const int32_t *__restr
     double P;
     if (mode == L2T_XI_INSTANT) {
         const double T =
-            (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+            (precision == L2T_FP64) ? T64[slot] : state_value(Thi[slot], Tlo[slot]);
         P = g * (T - tl);
     } else {
         P = eatom[slot] / dt_md;

@@ -11,9 +11,9 @@
 //  * FP32C: cancellation-free product form of the pair term evaluated in
 //    FP32 from the hi part of the neighbour temperatures, per-atom sum of the
 //    terms in FP64 (one conversion and one FP64 add per term, two vector
-//    instructions where a Kahan step takes four), state kept as an
-//    unevaluated FP32 pair hi + lo whose sum with the increment is formed in
-//    FP64 and split again; ledgers in FP64.  One launch per sub-step (global gathers or LDS brick tiles), or
+//    instructions where a Kahan step takes four), state kept as the FP32 hi
+//    that neighbours read and a 16-bit low part (state_fp32c.h) whose sum with
+//    the increment is formed in FP64 and split again; ledgers in FP64.  One launch per sub-step (global gathers or LDS brick tiles), or
 //    a persistent launch that runs all sub-steps with a grid barrier between
 //    them.
 #include <hip/hip_runtime.h>
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_step_fp64(const SliceInfo *slices, int3
 
 __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int32_t slice0,
                                                     int32_t n_slices, const int32_t *col,
-                                                    const float *Thi, float *Thi_n, float *Tlo,
+                                                    const float *Thi, float *Thi_n, int16_t *Tlo,
                                                     const float *Tl, const float *srcw,
                                                     const DevParams *P, const int64_t *dstep,
                                                     int32_t rel, double *ledger, double *eatom,
@@ -76,15 +76,15 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
 // XCD sweeps one contiguous range of bricks (its L2 serves the halo loads),
 // the ranges carry equal estimated work, and entries past a range are holes
 // (-1) whose workgroups return at once.
-// LO_IN: read T_lo from lo_in and write the new T_lo to Tlo (two buffers, as
-// the adjoint's recomputation keeps every state of a segment); otherwise T_lo
-// is updated in place and lo_in is unused.
+// LO_IN: read the low part from lo_in and write the new one to Tlo (two
+// buffers, as the adjoint's recomputation keeps every state of a segment);
+// otherwise the low part is updated in place and lo_in is unused.
 template <bool LO_IN>
 __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(8))) void k_brick_fp32c(
     const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
     const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
     const int32_t *__restrict__ halo, const float *__restrict__ Thi, float *__restrict__ Thi_n,
-    const float *__restrict__ lo_in, float *__restrict__ Tlo, const float *__restrict__ Tl,
+    const int16_t *__restrict__ lo_in, int16_t *__restrict__ Tlo, const float *__restrict__ Tl,
     const float *__restrict__ srcw, const DevParams *__restrict__ P,
     const int64_t *__restrict__ dstep, int32_t rel, double *__restrict__ ledger,
     double *__restrict__ eatom, unsigned *__restrict__ err) {
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         const int32_t base = __builtin_amdgcn_readfirstlane(slices[sl].colw_base64);
         const int32_t held = __builtin_amdgcn_readfirstlane(slices[sl].flags) & kSliceHeld;
         const int32_t slot = sl * kWave + lane;
-        const float lo = LO_IN ? lo_in[slot] : Tlo[slot];
+        const int16_t lo = LO_IN ? lo_in[slot] : Tlo[slot];
         const float tl = Tl[slot];
         const float sw = (p.laser_on | held) ? srcw[slot] : 0.0f;
         const float Ti = tile[q * kWave + lane];
@@ -331,7 +331,7 @@ __device__ inline bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned k,
 // contiguous eighth of the atoms and its L2 serves the neighbour gathers.
 __global__ __launch_bounds__(256) void k_persistent_fp32c(
     const SliceInfo *slices, int32_t n_slices, const int32_t *col, float *Thi0, float *Thi1,
-    float *Tlo, const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep,
+    int16_t *Tlo, const float *Tl, const float *srcw, const DevParams *P, const int64_t *dstep,
     int32_t n_steps, double *ledger, double *eatom, unsigned *err, unsigned *bar) {
     const unsigned G = gridDim.x;
     const unsigned b = blockIdx.x;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_persistent_fp32c(
 __global__ __launch_bounds__(256) void k_mf_chunks(const MfChunk *chunks, int32_t chunk0,
                                                    const SliceInfo *slices, int32_t precision,
                                                    const double *T64, const float *Thi,
-                                                   const float *Tlo, const double *Tl64,
+                                                   const int16_t *Tlo, const double *Tl64,
                                                    const float *Tl32, double *part) {
     const MfChunk ch = chunks[chunk0 + blockIdx.x];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_mf_chunks(const MfChunk *chunks, int32_
     for (int32_t sl = ch.slice_begin + wave; sl < ch.slice_end; sl += 4) {
         if (lane < slices[sl].n_valid) {
             const int32_t slot = sl * kWave + lane;
-            t += (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+            t += (precision == L2T_FP64) ? T64[slot] : state_value(Thi[slot], Tlo[slot]);
             l += (precision == L2T_FP64) ? fabs(Tl64[slot]) : (double)fabsf(Tl32[slot]);
         }
     }
@@ -456,7 +456,7 @@ __global__ void k_copy_range_f32(const float *a, float *b, int64_t n) {
 // per-slice E_e, sum T, max T, min T (one wave per slice)
 __global__ void k_slice_energy(const SliceInfo *slices, int32_t slice0, int32_t n_slices,
                                int32_t precision, const double *T64, const float *Thi,
-                               const float *Tlo, const DevParams *P, double *red) {
+                               const int16_t *Tlo, const DevParams *P, double *red) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t q = blockIdx.x * (blockDim.x / kWave) + wave;
     if (q >= n_slices) return;
@@ -466,7 +466,7 @@ __global__ void k_slice_energy(const SliceInfo *slices, int32_t slice0, int32_t 
     const int32_t slot = sl * kWave + lane;
     const bool valid = lane < si.n_valid;
     double T = 0.0;
-    if (valid) T = (precision == L2T_FP64) ? T64[slot] : (double)Thi[slot] + (double)Tlo[slot];
+    if (valid) T = (precision == L2T_FP64) ? T64[slot] : state_value(Thi[slot], Tlo[slot]);
     double e = valid ? energy_of(p, T) : 0.0;
     double s = valid ? T : 0.0;
     double mx = valid ? T : -INFINITY, mn = valid ? T : INFINITY;
@@ -987,7 +987,8 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
         q += (b + 255) / 256 * 256;
         return r;
     };
-    float *Ta = (float *)take(fb), *Tb = (float *)take(fb), *zl = (float *)take(fb);
+    float *Ta = (float *)take(fb), *Tb = (float *)take(fb), *zf = (float *)take(fb);
+    int16_t *zl = reinterpret_cast<int16_t *>(zf);   // q = 0 (the 0.0f fill clears its bits)
     float *tl = (float *)take(fb);
     DevParams *P = (DevParams *)take(sizeof(DevParams) * S);
     double *led = (double *)take(sizeof(double) * 3 * NS);
@@ -1012,7 +1013,7 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
     L2T_HIP(c, hipMemcpyAsync(P, hp.data(), sizeof(DevParams) * S, hipMemcpyHostToDevice, s_));
     hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, Ta, (int64_t)NI,
                        1000.0f);
-    hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, zl, (int64_t)NI,
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, zf, (int64_t)NI,
                        0.0f);
     hipLaunchKernelGGL(k_fill_f32, dim3(nblk((int64_t)NI, 256)), dim3(256), 0, s_, tl, (int64_t)NI,
                        1000.0f);
@@ -1038,7 +1039,7 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
         (void)hipEventRecord(e0, s_);
         // T^lat and the source weight both read the constant 1,000 K buffer
-        // (a positive weight marks no atom as held); T_lo is updated in place
+        // (a positive weight marks no atom as held); the low part is updated in place
         for (int32_t k = 0; k < n; ++k)
             hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(kBrickBlockMax), lds, s_,
                                c->bricks, c->xcd_list, c->n_xcd_list, c->slices, c->colw,
@@ -1057,10 +1058,10 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
 }
 
 // one FP32C sub-step of all systems in the LDS-brick form on explicit state
-// buffers, T_lo read from lo_in and written to Tlo (the adjoint's
+// buffers, the low part read from lo_in and written to Tlo (the adjoint's
 // recomputation between checkpoints)
-int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const float *lo_in,
-                     float *Tlo, const int64_t *dstep, int32_t rel, double *ledger) {
+int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const int16_t *lo_in,
+                     int16_t *Tlo, const int64_t *dstep, int32_t rel, double *ledger) {
     const int32_t nl = c->n_xcd_list;
     if (nl <= 0) return L2T_OK;
     const unsigned grid = (unsigned)nl;

@@ -126,6 +126,7 @@ constexpr int kKernelBrick = 1;    // LDS tile per brick, uint16 table
 constexpr int kBrickBlockMax = 512;   // threads per workgroup, brick kernel
 // entries a brick's halo list takes: its length rounded up to a multiple of 4
 __host__ __device__ constexpr int32_t halo_padded(int32_t n_halo) { return (n_halo + 3) & ~3; }
+
 constexpr int32_t kMaxBrickEdge = 1024;  // largest brick edge (cells) the layout considers
 constexpr int kSlicedBlockMax = 256;  // threads per workgroup, global-gather kernels
 constexpr int kResidentMaxSlots = 1024;  // largest system one workgroup keeps in LDS
@@ -224,7 +225,7 @@ struct l2t_ctx {
     double *Tl64b = nullptr;     // second T^lat buffer of the two-temperature lattice mode
     double *srcw64 = nullptr;
     float *Thi[2] = {nullptr, nullptr};
-    float *Tlo = nullptr;
+    int16_t *Tlo = nullptr;   // FP32C state: the 16-bit low part q of every slot
     float *Tl32 = nullptr;
     float *srcw32 = nullptr;
     int cur = 0;
@@ -313,8 +314,8 @@ int zero_atom_ledger(l2t_ctx *c, int32_t sys);   // sys < 0: every system
 int mean_field_refresh(l2t_ctx *c, int32_t sys);
 int bump_steps(l2t_ctx *c, int32_t sys, int32_t n);
 void drop_graphs(l2t_ctx *c);
-int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const float *lo_in,
-                     float *Tlo, const int64_t *dstep, int32_t rel, double *ledger);
+int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, const int16_t *lo_in,
+                     int16_t *Tlo, const int64_t *dstep, int32_t rel, double *ledger);
 
 // ---- lattice side (k_lattice.hip) ------------------------------------------
 int coupling(l2t_ctx *c, int32_t sys, int32_t mode, double dt_md, const double *v_dev,

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "l2t_internal.h"
+#include "state_fp32c.h"
 
 namespace l2t {
 namespace dev {
@@ -316,7 +317,7 @@ __device__ __forceinline__ float wave_max_f32(float v) {
 // differ only in these two, so both produce bit-identical states.  The
 // references of the next chunk of 8 are loaded before the current chunk is
 // evaluated; terms are added in neighbour order.  The caller loads the
-// lane's own lo part, T^lat and source weight ahead of the neighbour loop and
+// lane's own low part, T^lat and source weight ahead of the neighbour loop and
 // receives the lane's ledger terms (energy to the lattice, source, temperature
 // ledger, per unit time) for its wave reduction.
 struct LedgerTerms {
@@ -324,13 +325,13 @@ struct LedgerTerms {
 };
 
 // coupling, source and state update of one lane, given the neighbour sum
-// S = span * sum_j f(theta_i, theta_j) accumulated in FP64.  The state is the
-// FP32 pair (hi, lo) with T = hi + lo exact in FP64: the increment is added in
-// FP64 and the sum split back into a rounded hi and its remainder lo.
+// S = span * sum_j f(theta_i, theta_j) accumulated in FP64.  The state is
+// (hi, q) with T = hi + q s(hi) (state_fp32c.h): the increment is added to T
+// in FP64 and the sum split back into a rounded hi and its 16-bit remainder q.
 __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t slot, bool valid,
-                                                    float Ti, double S, float lo, float tl,
+                                                    float Ti, double S, int16_t lo, float tl,
                                                     float sw, float *__restrict__ Thi_n,
-                                                    float *__restrict__ Tlo,
+                                                    int16_t *__restrict__ Tlo,
                                                     double *__restrict__ eatom, float qpulse,
                                                     unsigned *err) {
     float hi_new = Ti;
@@ -349,9 +350,9 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
             // held: the exchange it would receive goes to the temperature ledger
             r = LedgerTerms{coup, q, (float)(p.K * S)};
         } else {
-            const double T = ((double)Ti + (double)lo) + p.dt * (p.K * S + (double)loc);
+            const double T = state_value(Ti, lo) + p.dt * (p.K * S + (double)loc);
             hi_new = (float)T;
-            Tlo[slot] = (float)(T - (double)hi_new);
+            Tlo[slot] = state_lo(T, hi_new);
             r = LedgerTerms{coup, q, -loc};
             if (!(hi_new >= p.f_T_min && hi_new <= p.f_T_max)) atomicOr(err, kErrRange);
         }
@@ -362,10 +363,10 @@ __device__ __forceinline__ LedgerTerms finish_fp32c(const DevParams &p, int32_t 
 
 template <class IdxAt, class ValOf>
 __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int32_t sl, int lane,
-                                                        const DevParams &p, float Ti, float lo,
+                                                        const DevParams &p, float Ti, int16_t lo,
                                                         float tl, float sw, IdxAt idx_at,
                                                         ValOf val_of, float *__restrict__ Thi_n,
-                                                        float *__restrict__ Tlo,
+                                                        int16_t *__restrict__ Tlo,
                                                         double *__restrict__ eatom, float qpulse,
                                                         unsigned *err) {
     constexpr int C = 8;
@@ -403,12 +404,12 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
 // slice_core_fp32c.
 template <bool TIERS>
 __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot, bool valid,
-                                                        const DevParams &p, float Ti, float lo,
+                                                        const DevParams &p, float Ti, int16_t lo,
                                                         float tl, float sw,
                                                         const uint32_t *__restrict__ row,
                                                         int lane, const float *tile,
                                                         float *__restrict__ Thi_n,
-                                                        float *__restrict__ Tlo,
+                                                        int16_t *__restrict__ Tlo,
                                                         double *__restrict__ eatom, float qpulse,
                                                         unsigned *err) {
     const PairK pk = pair_consts(p);
@@ -516,7 +517,7 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
                                                  const int32_t *__restrict__ col,
                                                  const float *__restrict__ Thi,
                                                  float *__restrict__ Thi_n,
-                                                 float *__restrict__ Tlo,
+                                                 int16_t *__restrict__ Tlo,
                                                  const float *__restrict__ Tl,
                                                  const float *__restrict__ srcw, int64_t step,
                                                  double *__restrict__ ledger,
@@ -524,7 +525,8 @@ __device__ __forceinline__ void slice_step_fp32c(const SliceInfo &si, int32_t sl
     const int32_t slot = sl * kWave + lane;
     const int32_t *cp = col + (int64_t)si.col_base64 * kWave + lane;
     const float Ti = Thi[slot];
-    const float lo = Tlo[slot], tl = Tl[slot];
+    const int16_t lo = Tlo[slot];
+    const float tl = Tl[slot];
     const float sw = (p.laser_on | (si.flags & kSliceHeld)) ? srcw[slot] : 0.0f;
     const LedgerTerms t = slice_core_fp32c(
         si, sl, lane, p, Ti, lo, tl, sw, [&](int32_t k) { return cp[k * kWave]; },

@@ -141,7 +141,46 @@ def test_advance_system_and_field_round_trip():
     # caller order survives the internal cell ordering
     vals = np.linspace(300.0, 900.0, w.systems[2].n)
     L.l2t_set_field(ctx.h, 2, L.L2T_FIELD_TE, vals)
-    assert max_rel(ctx.get(2), vals) < 1e-13        # hi + lo keeps ~48 bits
+    # the FP32C state keeps 39 significant bits: a value is rounded by at most
+    # 2^-38 of itself
+    assert max_rel(ctx.get(2), vals) <= 1.001 * 2.0 ** -38
+
+
+def test_fp32c_state_written_back_is_the_same_pair():
+    """T_e values halfway between two FP32 numbers, and a quarter of the low
+    part's step inside halfway, on both sides of FP32 numbers with an odd last
+    bit: written, read back and written to a second context, they give the
+    same stored pairs (the read-back values are equal and so are the next
+    sub-steps, which read the FP32 part), also after sub-steps have rounded
+    the states themselves."""
+    w = W.c4(n_systems=1, n_substeps=10, size_lo=1500, size_hi=1500)
+    sy = w.systems[0]
+    rng = np.random.default_rng(11)
+    f = rng.uniform(300.0, 900.0, sy.n).astype(np.float32)
+    f = (f.view(np.uint32) | np.uint32(1)).view(np.float32)        # odd last bit
+    hi = f.astype(np.float64)
+    ulp = np.spacing(f).astype(np.float64)
+    step = ulp * 2.0 ** -15                                        # the low part's unit
+    kind = rng.integers(0, 3, sy.n)
+    v = np.where(kind == 0, hi + ulp / 2,
+                 np.where(kind == 1, hi + ulp / 2 - step / 4, hi - ulp / 2 + step / 4))
+    a = gpu_context(w, L.L2T_FP32C)
+    L.l2t_set_field(a.h, 0, L.L2T_FIELD_TE, v)
+    g = a.get(0)
+    assert max_rel(g, v) <= 1.001 * 2.0 ** -38
+    b = gpu_context(w, L.L2T_FP32C)
+    L.l2t_set_field(b.h, 0, L.L2T_FIELD_TE, g)
+    assert np.array_equal(b.get(0), g)
+    for k in range(3):
+        a.advance(5)
+        b.advance(5)
+        ga = a.get(0)
+        assert np.array_equal(b.get(0), ga), k
+        L.l2t_set_field(b.h, 0, L.L2T_FIELD_TE, ga)   # restores the step counter to 0
+        L.l2t_set_counters(b.h, 0, a.energies(0)["step"], 0.0, 0.0, 0.0)
+        assert np.array_equal(b.get(0), ga), k
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("precision", [L.L2T_FP64, L.L2T_FP32C])

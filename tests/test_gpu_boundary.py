@@ -44,7 +44,7 @@ def test_held_atoms_match_oracle_and_keep_the_ledger(precision):
         L.l2t_set_field(ctx.h, s, L.L2T_FIELD_FIXED, fixed[s].astype(np.float64))
         assert np.array_equal(ctx.get(s, L.L2T_FIELD_FIXED), fixed[s].astype(np.float64))
     n = w.n_substeps
-    # the stored state (FP64, or the FP32C pair hi + lo) the held atoms keep
+    # the stored state (FP64, or the FP32C hi and its 16-bit low part) the held atoms keep
     start = [ctx.get(s) for s in range(len(w.systems))]
     if precision == L.L2T_FP64:
         for s in range(len(w.systems)):
