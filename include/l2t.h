@@ -295,7 +295,10 @@ int l2t_get_params(l2t_ctx *ctx, int32_t sys, l2t_params *out);
  * temperature T^lat of Eq. 4 (when it is not derived from velocities), the
  * kinetic-energy gate of the remark after Eq. 8, or the fixed-T_e flag of the
  * Section 4 boundary.  Writing L2T_FIELD_TE restarts the system's ledger and
- * step counter.
+ * step counter.  An FP32C context stores T_e as the FP32 value hi = fl32(T)
+ * and a 16-bit low part q with T = hi + q 2^(max(f, -125) - 39) (f the frexp
+ * exponent of hi), rounding T by at most 2^-38 of itself; a value read back
+ * with l2t_get_field and written again gives the same stored pair.
  * Synchronises.  Errors: ESTATE (neighbours not built), EINVAL (unknown or
  * read-only field, T^lat < 0), ERANGE (a T_e outside [T_min, T_max] or
  * non-finite; nothing is written). */
@@ -304,8 +307,8 @@ int l2t_set_field(l2t_ctx *ctx, int32_t sys, int32_t field, const double *src, i
 /* Read a per-atom field of system sys into dst[n] (FP64, caller order): the
  * per-atom T_e of Section 2.1, T^lat of Eq. 4, the gate, the neighbour count,
  * the energy handed to the lattice (Eq. 6 integrated over the last advance)
- * or the fixed-T_e flag.  FP32C temperatures are returned as (double)hi +
- * (double)lo.
+ * or the fixed-T_e flag.  FP32C temperatures are returned as hi + q s, exact
+ * in FP64 (see l2t_set_field).
  * Synchronises when mem == L2T_HOST. */
 int l2t_get_field(l2t_ctx *ctx, int32_t sys, int32_t field, double *dst, int32_t mem);
 
