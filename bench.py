@@ -60,12 +60,13 @@ def log(msg):
 def library_source_hash() -> str:
     """sha256 over the sources the sub-step kernels are compiled from (their
     translation unit, the device helpers, the state encoding, the internal and
-    the C header)."""
+    the C header) and over the layout builder, whose brick order sets the
+    kernel's L2 reuse and so its traffic."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_12357_amd", "csrc")
-    files = [os.path.join(csrc, f)
-             for f in ("k_step.hip", "step_device.h", "state_fp32c.h", "l2t_internal.h")]
+    files = [os.path.join(csrc, f) for f in ("k_step.hip", "step_device.h", "state_fp32c.h",
+                                             "l2t_internal.h", "k_geometry.hip")]
     files.append(os.path.join(ROOT, "include", "l2t.h"))
     for f in files:
         h.update(os.path.basename(f).encode())

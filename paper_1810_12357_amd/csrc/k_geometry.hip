@@ -999,13 +999,19 @@ int xcd_split(l2t_ctx *c, const std::vector<int32_t> &list, const std::vector<in
     c->h_xcd_list.assign((size_t)G, -1);
     // inside its range an XCD takes the bricks largest first, so the last
     // workgroups of the launch are small ones (measured on the 4M-atom system,
-    // whose bricks are 6 or 7 cells a side: 49.3-50.5 -> 48.4-49.4 us)
+    // whose bricks are 6 or 7 cells a side: 49.3-50.5 -> 48.4-49.4 us).  The
+    // order is by 5 % classes of work, in list order inside a class, which
+    // keeps bricks of one size in their spatial order for the L2 (47.7 ->
+    // 47.6 us against an order by exact work)
+    auto size_class = [&](int32_t k) {
+        return (int)std::floor(std::log((double)std::max(work[k], 1)) / std::log(1.05));
+    };
     std::vector<int32_t> idx;
     for (int x = 0; x < 8; ++x) {
         idx.clear();
         for (int32_t k = cut[x]; k < cut[x + 1]; ++k) idx.push_back(k);
         std::stable_sort(idx.begin(), idx.end(),
-                         [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+                         [&](int32_t a, int32_t b) { return size_class(a) > size_class(b); });
         for (size_t k = 0; k < idx.size(); ++k) c->h_xcd_list[(size_t)x * per + k] = list[idx[k]];
     }
     if ((size_t)G > c->cap_xl) {
