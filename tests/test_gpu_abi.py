@@ -183,6 +183,31 @@ def test_fp32c_state_written_back_is_the_same_pair():
     b.close()
 
 
+def test_fp32c_state_across_binades():
+    """The FP32C state's low part scales with the binary exponent of the FP32
+    part: T_e values spread log-uniformly from 1e-3 K to near T_max, values
+    exactly representable in FP32, and zero are stored within 2^-38 of
+    themselves (exactly when representable) and read back and written again
+    as the same pairs."""
+    w = W.c4(n_systems=1, n_substeps=1, size_lo=1500, size_hi=1500)
+    n = w.systems[0].n
+    rng = np.random.default_rng(12)
+    v = 10.0 ** rng.uniform(-3.0, np.log10(1.9e4), n)
+    exact = rng.random(n) < 0.25
+    v[exact] = v[exact].astype(np.float32).astype(np.float64)
+    v[:3] = [0.0, 1.0, 16384.0]
+    exact[:3] = True
+    a = gpu_context(w, L.L2T_FP32C)
+    L.l2t_set_field(a.h, 0, L.L2T_FIELD_TE, v)
+    g = a.get(0)
+    assert np.array_equal(g[exact], v[exact])
+    nz = v > 0
+    assert np.max(np.abs(g[nz] - v[nz]) / v[nz]) <= 1.001 * 2.0 ** -38
+    L.l2t_set_field(a.h, 0, L.L2T_FIELD_TE, g)
+    assert np.array_equal(a.get(0), g)
+    a.close()
+
+
 @pytest.mark.parametrize("precision", [L.L2T_FP64, L.L2T_FP32C])
 def test_checkpoint_resume_is_bitwise(precision):
     """Laser slabs run 300 sub-steps straight, and 137 sub-steps, saved
