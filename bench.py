@@ -164,7 +164,10 @@ def bench_c4_speedup(L, torch, n_sub, n_full):
         fixed = 24.0 if prec == L.L2T_FP32C else 36.0
         info[name] = dict(kernel=["global-gather", "lds-brick"][kernel], mean_neighbors=mean,
                           bytes_per_atom_substep=fixed + per_nbr * mean,
-                          brick_edge=L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE))
+                          brick_edge=L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE),
+                          block=L.l2t_get_option(ctx.h, L.L2T_OPT_BLOCK),
+                          sweep=["fixed", "alternating"][
+                              L.l2t_get_option(ctx.h, L.L2T_OPT_SWEEP) - 1])
         ctx.close()
     res = dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms; the speedup "
                         f"over the first {n_sub} sub-steps (pulse centre at sub-step 3000), "
@@ -618,6 +621,8 @@ def main():
                                n_atoms=sy.n, substeps=args.substeps, mean_neighbors=mean,
                                max_neighbors=mx, kernel=["global-gather", "lds-brick"][kernel],
                                brick_edge=L.l2t_get_option(h, L.L2T_OPT_BRICK_EDGE),
+                               sweep=["fixed", "alternating"][
+                                   L.l2t_get_option(h, L.L2T_OPT_SWEEP) - 1],
                                persistent=persistent, block=block),
                    advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
                    advance_ms_median=float(np.median(adv_ms)),

@@ -117,6 +117,13 @@ extern "C" {
 
 #define L2T_OPT_BATCH_FP64     8   /* FP64: 1 = one launch per sub-step over all systems; 0 = the
                                       systems one after another (default 0) */
+#define L2T_OPT_SWEEP          9   /* order in which the brick launches take the bricks: 1 = the
+                                      same every sub-step, 2 = reversed on every other sub-step, so
+                                      that a sub-step starts with the bricks (and the table rows and
+                                      temperatures) the previous one touched last; 0 = chosen at
+                                      l2t_build_neighbors by timing both on large FP32C layouts
+                                      (default; otherwise 1).  Reading it returns the order in
+                                      effect (1 or 2).  States are bitwise the same either way. */
 
 /* ---- source of the energy rate in the coupling coefficient (l2t_coupling) ------ */
 #define L2T_XI_INSTANT  0   /* P_i = g (T_i - T_i^lat) at the current T_e (Section 2.1 order) */

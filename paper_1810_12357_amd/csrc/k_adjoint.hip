@@ -418,7 +418,7 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
             if (brick)
                 hipLaunchKernelGGL(lam_near ? k_adjoint_brick<4096> : k_adjoint_brick<8192>,
                                    dim3(bgrid), dim3(rblock), blds, c->stream, c->bricks,
-                                   c->xcd_list, c->n_xcd_list, c->slices, c->colw, c->halo,
+                                   xcd_list_for(c, m), c->n_xcd_list, c->slices, c->colw, c->halo,
                                    Tst, c->Tl32, c->srcw32, c->dparams, dst, m, lam[lc2],
                                    lam[lc2 ^ 1], lamlo, grad);
             else

@@ -996,7 +996,7 @@ int xcd_split(l2t_ctx *c, const std::vector<int32_t> &list, const std::vector<in
     for (int x = 0; x < 8; ++x) per = std::max(per, cut[x + 1] - cut[x]);
     per = std::max(per, 1);
     const int32_t G = 8 * per;
-    c->h_xcd_list.assign((size_t)G, -1);
+    c->h_xcd_list.assign((size_t)2 * G, -1);
     // inside its range an XCD takes the bricks largest first, so the last
     // workgroups of the launch are small ones (measured on the 4M-atom system,
     // whose bricks are 6 or 7 cells a side: 49.3-50.5 -> 48.4-49.4 us).  The
@@ -1014,18 +1014,23 @@ int xcd_split(l2t_ctx *c, const std::vector<int32_t> &list, const std::vector<in
                          [&](int32_t a, int32_t b) { return size_class(a) > size_class(b); });
         for (size_t k = 0; k < idx.size(); ++k) c->h_xcd_list[(size_t)x * per + k] = list[idx[k]];
     }
-    if ((size_t)G > c->cap_xl) {
+    // the reversed list: every range backwards (its holes first)
+    for (int x = 0; x < 8; ++x)
+        for (int32_t k = 0; k < per; ++k)
+            c->h_xcd_list[(size_t)G + (size_t)x * per + k] =
+                c->h_xcd_list[(size_t)x * per + (per - 1 - k)];
+    if ((size_t)2 * G > c->cap_xl) {
         L2T_HIP(c, hipStreamSynchronize(c->stream));
         dev_free(c, c->xcd_list);
         c->xcd_list = nullptr;
         c->cap_xl = 0;
         void *m = nullptr;
-        const hipError_t e = dev_malloc(c, &m, sizeof(int32_t) * (size_t)G);
+        const hipError_t e = dev_malloc(c, &m, sizeof(int32_t) * (size_t)2 * G);
         if (e != hipSuccess) return hip_fail(c, e, "XCD launch list allocation");
         c->xcd_list = static_cast<int32_t *>(m);
-        c->cap_xl = (size_t)G;
+        c->cap_xl = (size_t)2 * G;
     }
-    L2T_HIP(c, hipMemcpyAsync(c->xcd_list, c->h_xcd_list.data(), sizeof(int32_t) * (size_t)G,
+    L2T_HIP(c, hipMemcpyAsync(c->xcd_list, c->h_xcd_list.data(), sizeof(int32_t) * (size_t)2 * G,
                               hipMemcpyHostToDevice, c->stream));
     c->n_xcd_list = G;
     return L2T_OK;
@@ -1588,20 +1593,22 @@ std::mutex &edge_mutex() {
     static std::mutex m;
     return m;
 }
-std::map<std::string, int32_t> &edge_cache() {
-    static std::map<std::string, int32_t> m;
+// the measured brick edge and sweep order (1 fixed, 2 alternating) of a shape
+std::map<std::string, std::pair<int32_t, int>> &edge_cache() {
+    static std::map<std::string, std::pair<int32_t, int>> m;
     return m;
 }
-bool edge_lookup(const std::string &key, int32_t *edge) {
+bool edge_lookup(const std::string &key, int32_t *edge, int *sweep) {
     std::lock_guard<std::mutex> g(edge_mutex());
     auto it = edge_cache().find(key);
     if (it == edge_cache().end()) return false;
-    *edge = it->second;
+    *edge = it->second.first;
+    *sweep = it->second.second;
     return true;
 }
-void edge_store(const std::string &key, int32_t edge) {
+void edge_store(const std::string &key, int32_t edge, int sweep) {
     std::lock_guard<std::mutex> g(edge_mutex());
-    edge_cache()[key] = edge;
+    edge_cache()[key] = {edge, sweep};
 }
 
 std::string edge_key(const l2t_ctx *c, double r_cut) {
@@ -1628,16 +1635,25 @@ std::string edge_key(const l2t_ctx *c, double r_cut) {
 // the same shape build once.  Smaller layouts, FP64 contexts, a pinned edge
 // or launch form and a disabled autotuner keep the model's edge.
 int build_neighbors(l2t_ctx *c, double r_cut) {
-    const bool may_tune = c->precision == L2T_FP32C && c->tune.autotune && !c->tune.pinned &&
-                          c->tune.brick_edge == 0;
+    Tuning &t = c->tune;
+    // an explicit sweep order applies as set; otherwise the fixed order unless
+    // the alternating one measures faster below
+    t.sweep_used = t.sweep == 2 ? 2 : 1;
+    const bool may_tune = c->precision == L2T_FP32C && t.autotune && !t.pinned &&
+                          t.brick_edge == 0;
     const std::string key = may_tune ? edge_key(c, r_cut) : std::string();
     int32_t cached = 0;
-    if (may_tune && edge_lookup(key, &cached)) return build_layout(c, r_cut, cached);
+    int cached_sweep = 1;
+    if (may_tune && edge_lookup(key, &cached, &cached_sweep)) {
+        const int rc = build_layout(c, r_cut, cached);
+        if (rc == L2T_OK && t.sweep == 0) t.sweep_used = cached_sweep;
+        return rc;
+    }
     int rc = build_layout(c, r_cut, 0);
     if (rc != L2T_OK || !may_tune) return rc;
     const int32_t e0 = c->brick_edge_used;
     if (c->n_brick_list < std::max(1, c->n_cu)) {
-        edge_store(key, e0);
+        edge_store(key, e0, 1);
         return L2T_OK;
     }
     // an edge above e0 changes the layout only where some axis is longer than e0
@@ -1646,11 +1662,11 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         for (int d = 0; d < 3; ++d) grows |= st.nc[d] > e0;
     constexpr int32_t kProbe = 12;
     float best_ms = 0.0f;
-    rc = brick_probe(c, kProbe, &best_ms);
+    rc = brick_probe(c, kProbe, false, &best_ms);
     if (rc == L2T_ENOMEM) {
         // no room for the stand-in state: keep the model's edge
         c->last_error.clear();
-        edge_store(key, e0);
+        edge_store(key, e0, 1);
         return L2T_OK;
     }
     if (rc != L2T_OK) return rc;
@@ -1662,7 +1678,7 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         built = c->brick_edge_used;
         if (built != e) continue;   // its tiles overflowed: a smaller edge was built
         float ms = 0.0f;
-        rc = brick_probe(c, kProbe, &ms);
+        rc = brick_probe(c, kProbe, false, &ms);
         if (rc == L2T_ENOMEM) {   // a larger layout's stand-in did not fit: skip it
             c->last_error.clear();
             continue;
@@ -1677,7 +1693,23 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         rc = build_layout(c, r_cut, best);
         if (rc != L2T_OK) return rc;
     }
-    edge_store(key, best);
+    // the sweep order on the chosen layout: the alternating one replaces the
+    // fixed one when it is more than 1 % faster
+    int sweep = 1;
+    if (t.sweep == 0) {
+        float fixed_ms = 0.0f, alt_ms = 0.0f;
+        rc = brick_probe(c, kProbe, false, &fixed_ms);
+        if (rc == L2T_OK) rc = brick_probe(c, kProbe, true, &alt_ms);
+        if (rc == L2T_ENOMEM) {
+            c->last_error.clear();
+        } else if (rc != L2T_OK) {
+            return rc;
+        } else if (alt_ms < 0.99f * fixed_ms) {
+            sweep = 2;
+        }
+        t.sweep_used = sweep;
+    }
+    edge_store(key, best, sweep);
     return L2T_OK;
 }
 

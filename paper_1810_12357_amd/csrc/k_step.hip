@@ -801,7 +801,7 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     // k_step_fp64, whose one wave per slice spreads a small system over more
     // CUs (one brick is one workgroup).  Both give bitwise-equal states.
     // all systems: the XCD launch list; one system: its range of the brick list
-    const int32_t *b_list = sys < 0 ? c->xcd_list : c->brick_list + c->sys[sys].list0;
+    const int32_t *b_list0 = sys < 0 ? c->xcd_list : c->brick_list + c->sys[sys].list0;
     const int32_t b_n = sys < 0 ? c->n_xcd_list : c->sys[sys].n_list;
     const int32_t b_bricks = sys < 0 ? c->n_brick_list : c->sys[sys].n_list;
     const bool brick64 = c->precision == L2T_FP64 && c->tune.kernel == kKernelBrick && !lat &&
@@ -812,6 +812,7 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
     // one FP64 sub-step from state buffer cu (relative step q within the call)
     auto step64 = [&](int cu, int32_t q, const double *tl_in, double *tl_out) {
         if (brick64) {
+            const int32_t *b_list = sys < 0 ? xcd_list_for(c, q) : b_list0;
             if (b_n > 0)
                 hipLaunchKernelGGL(k_brick_fp64, dim3(b_grid), dim3(kBrickBlockMax), b_lds,
                                    c->stream, c->bricks, b_list, b_n, c->slices, c->colw, c->halo,
@@ -938,7 +939,7 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
         const size_t lds = sizeof(float) * (size_t)c->tile_max;
         for (int32_t k = 0; k < n && nl > 0; ++k) {
             hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(block), lds, c->stream,
-                               c->bricks, c->xcd_list, nl, c->slices, c->colw, c->halo,
+                               c->bricks, xcd_list_for(c, k), nl, c->slices, c->colw, c->halo,
                                c->Thi[cur], c->Thi[cur ^ 1], nullptr, c->Tlo, c->Tl32, c->srcw32,
                                c->dparams, c->dstep, k, c->ledger, eatom, c->derr);
             cur ^= 1;
@@ -973,7 +974,7 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
 // the brick edge can be measured before any field of the new layout is
 // written.  The context's state, ledger, step counters and error word are not
 // touched.  *ms receives the faster of two timed runs.
-int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
+int brick_probe(l2t_ctx *c, int32_t n, bool alternate, float *ms) {
     *ms = 0.0f;
     const size_t NI = (size_t)c->n_int, NS = (size_t)c->n_slices, S = c->sys.size();
     if (c->n_brick_list == 0 || NI == 0 || n < 1) return L2T_OK;
@@ -1042,7 +1043,9 @@ int brick_probe(l2t_ctx *c, int32_t n, float *ms) {
         // (a positive weight marks no atom as held); the low part is updated in place
         for (int32_t k = 0; k < n; ++k)
             hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(kBrickBlockMax), lds, s_,
-                               c->bricks, c->xcd_list, c->n_xcd_list, c->slices, c->colw,
+                               c->bricks,
+                               c->xcd_list + ((alternate && (k & 1)) ? c->n_xcd_list : 0),
+                               c->n_xcd_list, c->slices, c->colw,
                                c->halo, (k & 1) ? Tb : Ta, (k & 1) ? Ta : Tb, nullptr, zl, tl, tl,
                                P, stp, k, led, nullptr, perr);
         (void)hipEventRecord(e1, s_);
@@ -1067,7 +1070,7 @@ int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, cons
     const unsigned grid = (unsigned)nl;
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
     hipLaunchKernelGGL(k_brick_fp32c<true>, dim3(grid), dim3(block), lds, c->stream, c->bricks,
-                       c->xcd_list, nl, c->slices, c->colw, c->halo, Thi, Thi_n, lo_in, Tlo,
+                       xcd_list_for(c, rel), nl, c->slices, c->colw, c->halo, Thi, Thi_n, lo_in, Tlo,
                        c->Tl32, c->srcw32, c->dparams, dstep, rel, ledger, nullptr, c->derr);
     L2T_HIP(c, hipGetLastError());
     return L2T_OK;

@@ -144,6 +144,8 @@ struct Tuning {
     int graph = 1;
     int autotune = 1;
     int brick_edge = 0;      // 0 = chosen by the layout builder
+    int sweep = 0;           // L2T_OPT_SWEEP as set: 0 = chosen at neighbour build, 1, 2
+    int sweep_used = 1;      // in effect: 1 = fixed order, 2 = reversed on odd sub-steps
     bool tuned = false;
     bool pinned = false;     // an explicit option was set: keep the choice
 };
@@ -207,7 +209,8 @@ struct l2t_ctx {
     // launch list of the all-system brick kernels: the brick list cut into 8
     // contiguous ranges of equal estimated work, range x at [x G/8, (x+1) G/8)
     // followed by -1 holes, so that workgroup b (on XCD b mod 8) takes entry
-    // (b mod 8) G/8 + b/8; G = n_xcd_list
+    // (b mod 8) G/8 + b/8; G = n_xcd_list.  A second list of G entries follows
+    // with every range reversed (the odd sub-steps of the alternating sweep).
     int32_t *xcd_list = nullptr;
     int32_t n_xcd_list = 0;
     size_t cap_xl = 0;
@@ -306,7 +309,12 @@ int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream
 int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom);
 // time n brick-kernel sub-steps of the current layout on a stand-in state in
 // scratch memory (the context's fields are not touched)
-int brick_probe(l2t_ctx *c, int32_t n, float *ms);
+int brick_probe(l2t_ctx *c, int32_t n, bool alternate, float *ms);
+// the launch list of sub-step k of an advance (the reversed one on odd k when
+// the alternating sweep is in effect)
+inline const int32_t *xcd_list_for(const l2t_ctx *c, int64_t k) {
+    return c->xcd_list + ((c->tune.sweep_used == 2 && (k & 1)) ? c->n_xcd_list : 0);
+}
 // per-atom record of the energy handed to the lattice (nullptr while off)
 inline double *atom_ledger_ptr(l2t_ctx *c) { return c->atom_ledger ? c->eatom : nullptr; }
 int zero_atom_ledger(l2t_ctx *c, int32_t sys);   // sys < 0: every system
