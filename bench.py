@@ -120,14 +120,15 @@ def one_pass(L, h, sy, d, r_cut, n_sub, timer):
     return e
 
 
-def bench_c4_speedup(L, torch, n_sub, n_full):
+def bench_c4_speedup(L, torch, n_sub, n_full, only_fp32c=False):
     """Batched FP32C (one tuned launch per sub-step for all systems) vs plain
     FP64 on the 256-system batch.  The plain form runs the systems one after
     another, one launch per sub-step and system; the batched FP64 form (all
     systems in one launch per sub-step) is timed beside it.  Every form runs
     the first n_sub sub-steps from t = 0 (the pulse peaks at 150 fs, sub-step
     3,000), where the speedup is taken; the batched FP32C form also runs the
-    whole n_full sub-steps of the workload."""
+    whole n_full sub-steps of the workload.  only_fp32c times the batched
+    FP32C form alone (for profiling that kernel; no speedup is reported)."""
     import workloads as W
     w = W.c4()
     n_atoms = w.n_atoms
@@ -135,6 +136,8 @@ def bench_c4_speedup(L, torch, n_sub, n_full):
     info = {}
     forms = (("fp32c_batched", L.L2T_FP32C, 0), ("fp64_plain", L.L2T_FP64, 0),
              ("fp64_batched", L.L2T_FP64, 1))
+    if only_fp32c:
+        forms = forms[:1]
     for name, prec, batch in forms:
         ctx = new_context(L, w.systems, prec)
         if batch:
@@ -169,6 +172,11 @@ def bench_c4_speedup(L, torch, n_sub, n_full):
                           sweep=["fixed", "alternating"][
                               L.l2t_get_option(ctx.h, L.L2T_OPT_SWEEP) - 1])
         ctx.close()
+    if only_fp32c:
+        return dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms, "
+                             f"batched FP32C only", substeps=n_sub,
+                    fp32c_batched_atom_substeps_per_s=out["fp32c_batched"],
+                    fp32c_batched_form=info["fp32c_batched"])
     res = dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms; the speedup "
                         f"over the first {n_sub} sub-steps (pulse centre at sub-step 3000), "
                         f"batched FP32C also over all {n_full}",
@@ -501,6 +509,8 @@ def main():
     ap.add_argument("--cpu-single-steps", type=int, default=5,
                     help="oracle sub-steps timed on one thread (0 = skip)")
     ap.add_argument("--c4-full-substeps", type=int, default=6000)
+    ap.add_argument("--c4-fp32c-only", action="store_true",
+                    help="C4: time the batched FP32C form alone (profiling; no speedup)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
                     help="0 = launch sub-steps directly instead of replaying hipGraphs "
                          "(rocprofv3 counter passes)")
@@ -645,7 +655,8 @@ def main():
         out["c3_fp64"] = f64
     if want("c4") and not args.no_c4:
         log("C4 batched vs plain ...")
-        out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps, args.c4_full_substeps)
+        out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps, args.c4_full_substeps,
+                                             only_fp32c=args.c4_fp32c_only)
     if want("bars") and not args.no_md:
         log("two-temperature bars (Section 3.1) ...")
         out["bar_batch"] = bench_bar_batch(L, torch)
