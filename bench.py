@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+XGMI_LINK_GBS = 153.0   # one xGMI link of an MI355X, each direction (AMD public figure)
 # 0: every context the bench makes launches its sub-steps directly instead of
 # replaying captured hipGraphs (for rocprofv3 counter passes)
 GRAPH = 1
@@ -193,6 +194,54 @@ def bench_c4_speedup(L, torch, n_sub, n_full, only_fp32c=False):
         gbps = info[name]["bytes_per_atom_substep"] * out[name] / 1e9
         res[name + "_form"] = dict(info[name], algorithmic_GBps=gbps, frac=gbps / HBM_PEAK_GBS)
     return res
+
+
+def bench_shard(L, torch, w, parts=(2, 4, 8), n_sub=2000, reps=3):
+    """One GPU's share of the 4M-atom system when it is cut into x-slabs over
+    N GPUs (a design study on one GPU): the slab's own atoms plus ghost layers
+    of width r_c from both neighbours, held at their T_e (L2T_FIELD_FIXED)
+    where a multi-GPU run would have the neighbours' exchange write them.
+    The sub-step time of the share is measured with HIP events on the
+    library's stream (median of reps advances of n_sub sub-steps); the
+    exchange (the hi of each ghost face, 4 B per ghost atom, one face per
+    xGMI link) is estimated, not run."""
+    import workloads as W
+    res = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for n in parts:
+        sh, ghost = W.c3_shard(w, n)
+        ctx = new_context(L, [sh], L.L2T_FP32C, stream=torch.cuda.current_stream().cuda_stream)
+        _, mean, _ = ctx.setup(w.r_cut)
+        L.l2t_set_field(ctx.h, 0, L.L2T_FIELD_FIXED, ghost)
+        ctx.advance(2)                     # warm-up (autotune, graph capture)
+        times = []
+        for _ in range(reps):
+            a, b = ev(), ev()
+            a.record()
+            ctx.advance(n_sub)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        n_ghost = int(ghost.sum())
+        n_own = sh.n - n_ghost
+        face_bytes = 4.0 * n_ghost / 2.0
+        res[f"n{n}"] = dict(own_atoms=n_own, ghost_atoms=n_ghost, substeps=n_sub,
+                            substep_us=ms * 1e3 / n_sub,
+                            own_atom_substeps_per_s=n_own * n_sub / (ms * 1e-3),
+                            kernel=["global-gather", "lds-brick"][
+                                L.l2t_get_option(ctx.h, L.L2T_OPT_KERNEL)],
+                            brick_edge=L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE),
+                            block=L.l2t_get_option(ctx.h, L.L2T_OPT_BLOCK),
+                            mean_neighbors=mean,
+                            exchange_bytes_per_face=face_bytes,
+                            exchange_us_per_link_est=face_bytes / XGMI_LINK_GBS / 1e3)
+        log(f"  shard of {n}: {n_own} own + {n_ghost} ghost atoms, "
+            f"{res[f'n{n}']['substep_us']:.2f} us per sub-step")
+        ctx.close()
+    return dict(workload="one x-slab of the 4M-atom system cut over N GPUs, with ghost layers "
+                         "of width r_c held (exchange not run)", xgmi_link_GBps=XGMI_LINK_GBS,
+                **res)
 
 
 def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):
@@ -514,9 +563,12 @@ def main():
     ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
                     help="0 = launch sub-steps directly instead of replaying hipGraphs "
                          "(rocprofv3 counter passes)")
-    ap.add_argument("--only", choices=["all", "c3", "c4", "md", "bars", "adjoint", "fp64"],
+    ap.add_argument("--only", choices=["all", "c3", "c4", "md", "bars", "adjoint", "fp64",
+                                       "shard"],
                     default="all", help="run one section only (profiling)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip the per-GPU share of the 4M-atom system over 2, 4, 8 GPUs")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 sample on the 4M-atom system")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -657,6 +709,9 @@ def main():
         log("C4 batched vs plain ...")
         out["c4_speedup"] = bench_c4_speedup(L, torch, args.c4_substeps, args.c4_full_substeps,
                                              only_fp32c=args.c4_fp32c_only)
+    if want("shard") and not args.no_shard:
+        log("one GPU's share of the 4M-atom system over N GPUs ...")
+        out["c3_shard"] = bench_shard(L, torch, w)
     if want("bars") and not args.no_md:
         log("two-temperature bars (Section 3.1) ...")
         out["bar_batch"] = bench_bar_batch(L, torch)

@@ -1,5 +1,6 @@
-"""Host-side contract of bench.py: one GPU only, and the measured-traffic
-record it reads from the committed profile."""
+"""Host-side contract of bench.py: one GPU only, the measured-traffic record
+it reads from the committed profile, and the per-GPU share of its design
+study of several GPUs."""
 import json
 import os
 import subprocess
@@ -31,3 +32,34 @@ def test_profile_traffic_is_read_only_for_the_current_sources():
     assert bench.measured_traffic("k_brick_fp32c", 4_000_000) == (stored if fresh else None)
     assert bench.measured_traffic("k_brick_fp32c", 1_000_000) is None
     assert bench.measured_traffic("k_no_such_kernel", 4_000_000) is None
+
+
+def test_c3_shard_partitions_the_system_with_ghost_layers():
+    """The per-GPU share of the bench's design study: over N slabs every atom
+    is owned exactly once, and each share's ghosts are the atoms of the other
+    slabs within r_c of its faces (periodic in x), placed inside its free-x box."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import workloads as W
+    w = W.c3(n_cells=12, n_substeps=1)
+    s = w.systems[0]
+    Lx, rc = float(s.box_len[0]), float(w.r_cut)
+    for n in (2, 3, 4):
+        owned = 0
+        for part in range(n):
+            sh, ghost = W.c3_shard(w, n, part)
+            assert sh.pos.shape[1] == ghost.size == sh.T_e0.size == sh.mass.size
+            assert list(sh.periodic) == [0, 1, 1]
+            x = sh.pos[0]
+            assert np.all(x > sh.box_lo[0]) and np.all(x < sh.box_lo[0] + sh.box_len[0])
+            width = Lx / n
+            own = ghost == 0.0
+            assert np.all((x[own] >= 0.0) & (x[own] < width))
+            assert np.all(((x[~own] >= -rc) & (x[~own] < 0.0)) |
+                          ((x[~own] >= width) & (x[~own] < width + rc)))
+            # brute force: the ghosts are exactly the other slabs' atoms within r_c of a face
+            d = np.mod(s.pos[0] - part * width, Lx)
+            want = int(np.count_nonzero(((d >= width) & (d < width + rc)) | (d >= Lx - rc)))
+            assert int(ghost.sum()) == want
+            owned += int(own.sum())
+        assert owned == s.n

@@ -207,6 +207,36 @@ def c3(n_cells: int = 100, n_substeps: int = 10000, seed_pos: int = 3001,
                     n_substeps=n_substeps, precision="fp32c", checkpoint_every=1000)
 
 
+def c3_shard(w: Workload, n_parts: int, part: int | None = None):
+    """One GPU's share of the 4M-atom system cut into n_parts slabs along x:
+    the atoms of slab `part` (default n_parts // 2, whose lower face passes
+    through the hotspot centre) and, as ghosts, the atoms of the neighbouring
+    slabs within r_c of its two faces (x wraps around the periodic box).  The
+    share is one system, free in x (its box spans the ghosts) and periodic in
+    y and z.  Returns the system and the ghost mask (1.0 on ghosts), whose
+    T_e a multi-GPU run would take from the neighbours' exchange."""
+    s = w.systems[0]
+    if part is None:
+        part = n_parts // 2
+    Lx = float(s.box_len[0])
+    rc = float(w.r_cut)
+    width = Lx / n_parts
+    dx = np.mod(s.pos[0] - part * width, Lx)
+    own = dx < width
+    hi = (dx >= width) & (dx < width + rc)
+    lo = dx >= Lx - rc
+    keep = own | hi | lo
+    xs = np.where(lo, dx - Lx, dx)[keep]
+    pos = np.vstack([xs, s.pos[1][keep], s.pos[2][keep]])
+    pad = 1e-3
+    box_lo = np.array([-rc - pad, 0.0, 0.0])
+    box_len = np.array([width + 2.0 * rc + 2.0 * pad, s.box_len[1], s.box_len[2]])
+    sh = System(pos=pos, box_lo=box_lo, box_len=box_len,
+                periodic=np.array([0, 1, 1], np.int32), T_e0=s.T_e0[keep].copy(),
+                params=dict(s.params), vel=s.vel[:, keep].copy(), mass=s.mass[keep].copy())
+    return sh, (~own[keep]).astype(np.float64)
+
+
 def c4_sizes(n_systems: int = 256, lo: float = 500.0, hi: float = 2e5,
              seed: int = 4001) -> np.ndarray:
     rng = np.random.default_rng(seed)
