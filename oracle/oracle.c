@@ -29,6 +29,13 @@
  *   - the discrete adjoint of the forward-Euler map (derived from Eq. 2) and
  *     a complex-step forward run for directional derivatives.
  *
+ * Each of these is pinned, in tests/test_oracle_pins.py, to something other
+ * than itself: closed forms, exact invariants, brute force, a library
+ * routine on a special case, quadrature, complex steps and finite
+ * differences, and the constants the paper prints.  Whole trajectories at
+ * the workload sizes go beyond those pins: there they are parity unpinned,
+ * since the paper prints no worked trajectory.
+ *
  * Built with gcc -O2 -ffp-contract=off -fopenmp: no FMA contraction.  OpenMP
  * parallelises over atoms only; every per-atom sum runs serially in
  * ascending-j order and every global sum runs serially in ascending-i order,
