@@ -542,7 +542,7 @@ def cpu_baseline(L, torch, w, n_steps, checkpoints, n_single):
                                      max_rel_err=max(p["max_rel_err"] for p in parity)))
 
 
-def main():
+def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -581,7 +581,11 @@ def main():
                     help="threads per workgroup of the sub-step kernel (0 = autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU only; splitting the systems over "
                                    "several GPUs is not implemented", "n_gpus": args.gpus}))

@@ -63,3 +63,24 @@ def test_c3_shard_partitions_the_system_with_ghost_layers():
             assert int(ghost.sum()) == want
             owned += int(own.sum())
         assert owned == s.n
+
+
+def test_every_profile_names_a_command_of_the_committed_bench():
+    """Each rocprofv3 summary under profiles/ gives the command that made it;
+    every such command runs bench.py (a committed file) with options that
+    bench.py still accepts."""
+    import glob
+    import shlex
+    sys.path.insert(0, ROOT)
+    import bench
+    files = sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md")))
+    assert files
+    for path in files:
+        cmds = [line.strip() for line in open(path) if line.strip().startswith("rocprofv3 ")]
+        assert cmds, f"{os.path.basename(path)} names no rocprofv3 command"
+        for cmd in cmds:
+            argv = shlex.split(cmd)
+            assert "--" in argv, cmd
+            prog = argv[argv.index("--") + 1:]
+            assert prog[:2] == ["python", "bench.py"], cmd
+            bench.make_parser().parse_args(prog[2:])   # exits (SystemExit) on an unknown option
