@@ -1,6 +1,7 @@
 """Degenerate and ragged inputs through the C ABI against the FP64 oracle:
-atoms without a neighbour inside the cut-off, and one batch of systems of
-1, 2, 63, 64, 65 and 200 atoms beside a lattice, in every launch form."""
+atoms without a neighbour inside the cut-off, one batch of systems of 1, 2,
+63, 64, 65 and 200 atoms beside a lattice, and a temperature step that puts
+the pair term on its top tier, in every launch form."""
 import numpy as np
 import pytest
 
@@ -177,3 +178,64 @@ def test_measured_brick_edge_near_the_model_cached_and_exact():
         ctx.advance(w.n_substeps)
         assert max_rel(ctx.get(5), ref) < 1e-5
         ctx.close()
+
+
+def _step_system(n_cells=10, hot=19000.0, cold=300.0, seed=31):
+    """FCC n^3 cells, periodic, jittered 0.05 A: T_e = hot where x < L/2 and
+    cold beyond, so neighbours across the two planes of the step differ by up
+    to 18,700 K and their pair terms run on the top tier of the FP32 form."""
+    pos, box = W.fcc(n_cells, n_cells, n_cells)
+    per = np.ones(3, np.int32)
+    pos = W.wrap_periodic(W.jitter(pos, 0.05, seed), np.zeros(3), box, per)
+    n = pos.shape[1]
+    p = W.default_params(ce_model=W.CE_LINEAR, gamma=1e-4)
+    return W.System(pos=pos, box_lo=np.zeros(3), box_len=box, periodic=per,
+                    T_e0=np.where(pos[0] < box[0] / 2.0, hot, cold), params=p,
+                    T_l=np.full(n, 300.0))
+
+
+def test_steep_step_on_the_top_tier_in_every_launch_form():
+    """A temperature step of 18,700 K, compared after 7, 37 and 400 sub-steps
+    (the top tier carries the exchange through the first ~40): every FP32C
+    launch form (global gathers, persistent, LDS bricks with and without
+    graphs) gives the same states bit for bit and matches the oracle to
+    1e-5; FP64 to 1e-12."""
+    sy = _step_system()
+    w = W.Workload("step", [sy], 1.1 * W.A_LAT, 400, "fp32c")
+    p = sy.params
+    row, col = oracle_neighbors(sy, w.r_cut)
+    own = np.repeat(np.arange(sy.n), np.diff(row))
+    u = ((sy.T_e0[col] - sy.T_e0[own]) / (p["T_max"] - p["T_min"])) ** 2
+    assert u.max() > 0.8 and np.count_nonzero(u > 1e-2) > 1000   # the top tier is reached
+    checkpoints = (7, 37, 400)
+    want, T, step = [], sy.T_e0, 0
+    for c in checkpoints:
+        T, _, bad = oracle.run(row, col, T, sy.T_l, p, c - step)
+        assert bad == 0
+        want.append(T)
+        step = c
+
+    def states(ctx):
+        out, step = [], 0
+        for c in checkpoints:
+            ctx.advance(c - step)
+            step = c
+            out.append(ctx.get(0))
+        ctx.close()
+        return out
+
+    runs = []
+    for kernel, persistent, graph in ((0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 0, 1)):
+        ctx = gpu_context(w, L.L2T_FP32C, graph=graph)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+        if persistent:
+            L.l2t_set_option(ctx.h, L.L2T_OPT_PERSISTENT, 1)
+        runs.append(states(ctx))
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
+    f64 = states(gpu_context(w, L.L2T_FP64))
+    for c, got, got64, T in zip(checkpoints, runs[0], f64, want):
+        err, err64 = max_rel(got, T), max_rel(got64, T)
+        print(f"step of 18,700 K after {c} sub-steps: FP32C {err:.2e}, FP64 {err64:.2e}")
+        assert err < 1e-5 and err64 < 1e-12
