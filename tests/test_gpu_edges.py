@@ -1,7 +1,8 @@
 """Degenerate and ragged inputs through the C ABI against the FP64 oracle:
 atoms without a neighbour inside the cut-off, one batch of systems of 1, 2,
-63, 64, 65 and 200 atoms beside a lattice, and a temperature step that puts
-the pair term on its top tier, in every launch form."""
+63, 64, 65 and 200 atoms beside a lattice, periodic axes only two or three
+cells long, and a temperature step that puts the pair term on its top tier,
+in every launch form."""
 import numpy as np
 import pytest
 
@@ -239,3 +240,74 @@ def test_steep_step_on_the_top_tier_in_every_launch_form():
         err, err64 = max_rel(got, T), max_rel(got64, T)
         print(f"step of 18,700 K after {c} sub-steps: FP32C {err:.2e}, FP64 {err64:.2e}")
         assert err < 1e-5 and err64 < 1e-12
+
+
+def _short_box(cells, seed):
+    """Atoms uniform at the density of FCC nickel in a box whose periodic x
+    and y axes are only `cells` cells long (the cell stencil and a brick's
+    shell wrap onto themselves) and whose z axis is free and 20 cells long.
+    The exchange rate is lowered to 0.2 / fs: random placement gives up to
+    ~40 neighbours, and forward Euler stays stable for K dt (2 n_max) < 2."""
+    rc = 1.1 * W.A_LAT
+    rng = np.random.default_rng(seed)
+    box = np.array([cells * rc * 1.02, cells * rc * 1.02, 20.0 * rc])
+    n = int(4.0 / W.A_LAT ** 3 * np.prod(box))
+    p = W.default_params(g=5e-6, ce_model=W.CE_CONST, ce_const=W.C_NI, K=0.2)
+    return W.System(pos=rng.uniform(0.0, 1.0, (3, n)) * box[:, None], box_lo=np.zeros(3),
+                    box_len=box, periodic=np.array([1, 1, 0], np.int32),
+                    T_e0=300.0 + 4000.0 * rng.uniform(0, 1, n), params=p,
+                    T_l=300.0 + 100.0 * rng.uniform(0, 1, n))
+
+
+def test_periodic_axes_of_two_and_three_cells_every_launch_form():
+    """Neighbour sets equal the oracle's where a periodic axis is only two or
+    three cells long; after 7, 137 and 300 sub-steps the states of every
+    FP32C launch form are bitwise equal and match the oracle (1e-5), FP64 to
+    1e-12."""
+    systems = [_short_box(2, 52), _short_box(3, 53)]
+    rc = 1.1 * W.A_LAT
+    w = W.Workload("short", systems, rc, 300, "fp32c")
+    checkpoints = (7, 137, 300)
+    want = []
+    for sy in systems:
+        row, col = oracle_neighbors(sy, rc)
+        T, step, states = sy.T_e0, 0, []
+        for c in checkpoints:
+            T, _, bad = oracle.run(row, col, T, sy.T_l, sy.params, c - step)
+            assert bad == 0
+            states.append(T)
+            step = c
+        want.append(states)
+
+    def states(ctx):
+        out, step = [], 0
+        for c in checkpoints:
+            ctx.advance(c - step)
+            step = c
+            out.append([ctx.get(s) for s in range(len(systems))])
+        ctx.close()
+        return out
+
+    runs = []
+    for kernel, persistent, graph in ((0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 0, 1)):
+        ctx = gpu_context(w, L.L2T_FP32C, graph=graph)
+        if not runs:
+            for s, sy in enumerate(systems):
+                r, c = L.l2t_get_neighbors(ctx.h, s, sy.n)
+                r0, c0 = oracle_neighbors(sy, rc)
+                assert np.array_equal(r, r0) and np.array_equal(c, c0)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+        if persistent:
+            L.l2t_set_option(ctx.h, L.L2T_OPT_PERSISTENT, 1)
+        runs.append(states(ctx))
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+    f64 = states(gpu_context(w, L.L2T_FP64))
+    for k, c in enumerate(checkpoints):
+        for s in range(len(systems)):
+            err = max_rel(runs[0][k][s], want[s][k])
+            err64 = max_rel(f64[k][s], want[s][k])
+            print(f"{['two', 'three'][s]} cells, {c} sub-steps: FP32C {err:.2e}, FP64 {err64:.2e}")
+            assert err < 1e-5 and err64 < 1e-12

@@ -98,6 +98,28 @@ def test_neighbours_brute_vs_cells_vs_kdtree():
     assert mine == set(map(tuple, pairs.tolist()))
 
 
+@pytest.mark.parametrize("cells", [2, 3])
+def test_neighbours_in_boxes_of_two_and_three_cells(cells):
+    """Periodic axes only two or three cells long, where the cell stencil
+    wraps onto itself, beside a free axis: the cell list equals brute force,
+    and both equal a k-d tree's pairs (its free axis given a period far
+    beyond the box, so no pair wraps there)."""
+    from scipy.spatial import cKDTree
+    rc = 1.1 * W.A_LAT
+    rng = np.random.default_rng(40 + cells)
+    box = np.array([cells * rc * 1.02, cells * rc * 1.02, 20.0 * rc])
+    n = int(4.0 / W.A_LAT ** 3 * np.prod(box))      # the density of FCC nickel
+    pos = rng.uniform(0.0, 1.0, (3, n)) * box[:, None]
+    per = np.array([1, 1, 0], np.int32)
+    rb, cb = oracle.neighbors(pos, np.zeros(3), box, per, rc, method="brute")
+    rcl, ccl = oracle.neighbors(pos, np.zeros(3), box, per, rc, method="cells")
+    assert np.array_equal(rb, rcl) and np.array_equal(cb, ccl)
+    tree = cKDTree(pos.T, boxsize=np.array([box[0], box[1], 10.0 * box[2]]))
+    pairs = set(map(tuple, tree.query_pairs(rc, output_type="ndarray").tolist()))
+    mine = set((i, int(j)) for i in range(n) for j in cb[rb[i]:rb[i + 1]] if i < j)
+    assert mine == pairs and len(pairs) > n
+
+
 def test_neighbours_free_axis_and_symmetry():
     s = W.c4_slab(900, 0.1)
     row, col = _nbrs(s, 1.1 * W.A_LAT, "cells")
