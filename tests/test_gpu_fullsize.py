@@ -1,6 +1,8 @@
 """Full-size batch and gradient workloads, launched as the benchmark launches
 them, checked on sampled systems against the FP64 oracle and on every system
-against properties that hold at any size."""
+against properties that hold at any size; the large-system recipe over its
+whole length against a stored oracle run, and at eight times its size on
+sampled light cones."""
 import json
 import math
 import os
@@ -152,3 +154,53 @@ def test_c3_full_length_sampled_against_the_stored_oracle_run():
         assert e["T_max_atom"] == pytest.approx(cp["T_max"], rel=1e-5)
         assert e["T_min_atom"] == pytest.approx(cp["T_min"], rel=1e-5)
     ctx.close()
+
+
+def _region(sy, i, radius):
+    """Atoms within `radius` of atom i (minimum image), their positions
+    relative to it (shifted into a free box) and atom i's index among them."""
+    d = sy.pos - sy.pos[:, [i]]
+    for a in range(3):
+        if sy.periodic[a]:
+            d[a] -= sy.box_len[a] * np.rint(d[a] / sy.box_len[a])
+    keep = np.nonzero((d * d).sum(0) <= radius * radius)[0]
+    return keep, d[:, keep] + radius, int(np.searchsorted(keep, i))
+
+
+def test_c3_recipe_at_32M_atoms_sampled_light_cones():
+    """The 4M-atom recipe scaled to 200^3 cells (32,000,000 atoms, 8 times the
+    benchmark's system): after n sub-steps an atom depends only on atoms
+    within n neighbour hops, so for each sampled atom the oracle builds the
+    neighbour sets of the atoms within (n + 2) r_c of it, runs the n + 1-hop
+    light cone and must agree to 1e-5 (T^lat to 1e-6)."""
+    from helpers import light_cone, sub_problem
+    w = W.c3(n_cells=200, n_substeps=8)
+    sy = w.systems[0]
+    assert sy.n == 32_000_000
+    n = 8
+    ctx = gpu_context(w, L.L2T_FP32C)
+    ctx.advance(n)
+    T = ctx.get(0)
+    Tl_gpu = ctx.get(0, L.L2T_FIELD_TL)
+    ctx.close()
+    r2 = ((sy.pos - (sy.box_len / 2)[:, None]) ** 2).sum(0)
+    rng = np.random.default_rng(1)
+    seeds = np.r_[np.argmin(r2), np.argmin(np.abs(np.sqrt(r2) - 15.0)),
+                  np.argmin(np.abs(np.sqrt(r2) - 30.0)), rng.integers(0, sy.n, 3)]
+    p = sy.params
+    radius = (n + 2) * w.r_cut
+    for sd in seeds:
+        keep, rel, i = _region(sy, int(sd), radius)
+        box = np.full(3, 2.0 * radius + 1e-6)
+        row, col = oracle.neighbors(rel, np.zeros(3), box, np.zeros(3, np.int32), w.r_cut)
+        Tl, gated = oracle.lattice_temperature(row, col, sy.vel[:, keep], sy.mass[keep],
+                                               p["ke_eps"])
+        cone = light_cone(row, col, [i], n + 1)
+        r, c = sub_problem(row, col, cone)
+        Tk, _, bad = oracle.run(r, c, sy.T_e0[keep][cone], Tl[cone], p, n, gated=gated[cone])
+        assert bad == 0
+        j = int(np.searchsorted(cone, i))
+        err = abs(T[sd] - Tk[j]) / Tk[j]
+        print(f"32M atoms, atom {int(sd)}: T_e {T[sd]:.3f} K, rel err {err:.2e}")
+        assert err < 1e-5
+        assert abs(Tl_gpu[sd] - Tl[i]) / Tl[i] < 1e-6
