@@ -171,7 +171,9 @@ def bench_c4_speedup(L, torch, n_sub, n_full, only_fp32c=False):
                           brick_edge=L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE),
                           block=L.l2t_get_option(ctx.h, L.L2T_OPT_BLOCK),
                           sweep=["fixed", "alternating"][
-                              L.l2t_get_option(ctx.h, L.L2T_OPT_SWEEP) - 1])
+                              L.l2t_get_option(ctx.h, L.L2T_OPT_SWEEP) - 1],
+                          table_loads=["cached", "streamed"][
+                              L.l2t_get_option(ctx.h, L.L2T_OPT_TABLE_STREAM) - 1])
         ctx.close()
     if only_fp32c:
         return dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms, "
@@ -689,6 +691,8 @@ def main():
                                brick_edge=L.l2t_get_option(h, L.L2T_OPT_BRICK_EDGE),
                                sweep=["fixed", "alternating"][
                                    L.l2t_get_option(h, L.L2T_OPT_SWEEP) - 1],
+                               table_loads=["cached", "streamed"][
+                                   L.l2t_get_option(h, L.L2T_OPT_TABLE_STREAM) - 1],
                                persistent=persistent, block=block),
                    advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
                    advance_ms_median=float(np.median(adv_ms)),

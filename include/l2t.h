@@ -124,6 +124,14 @@ extern "C" {
                                       l2t_build_neighbors by timing both on large FP32C layouts
                                       (default; otherwise 1).  Reading it returns the order in
                                       effect (1 or 2).  States are bitwise the same either way. */
+#define L2T_OPT_TABLE_STREAM  10   /* how the brick kernels load the neighbour table, which each
+                                      sub-step reads once: 1 = cached like other loads, 2 = with
+                                      the non-temporal hint, so that it does not displace from
+                                      L2 the temperatures that neighbouring bricks read again;
+                                      0 = chosen at l2t_build_neighbors by timing both on large
+                                      FP32C layouts (default; otherwise 1).  Reading it returns
+                                      the choice in effect (1 or 2).  States are bitwise the
+                                      same either way. */
 
 /* ---- source of the energy rate in the coupling coefficient (l2t_coupling) ------ */
 #define L2T_XI_INSTANT  0   /* P_i = g (T_i - T_i^lat) at the current T_e (Section 2.1 order) */
@@ -253,8 +261,10 @@ int l2t_set_positions(l2t_ctx *ctx, int32_t sys, const double *xyz, int32_t mem)
  * first time it builds a given problem shape in the process: the cost
  * model's edge and its two neighbours are built and each runs a short probe
  * of the sub-step kernel on stand-in data (the context's fields are not
- * used), so that first build costs two or three layouts.  L2T_OPT_AUTOTUNE
- * = 0, L2T_OPT_BRICK_EDGE or a pinned launch form skip the timing.
+ * used), so that first build costs two or three layouts; the sweep order and
+ * the table-load policy (L2T_OPT_SWEEP, L2T_OPT_TABLE_STREAM, when left at 0)
+ * are timed on the chosen layout.  L2T_OPT_AUTOTUNE = 0, L2T_OPT_BRICK_EDGE
+ * or a pinned launch form skip the timing.
  * Errors: ESTATE (positions missing), EINVAL (r_cut <= 0, periodic box_len <
  * 2 r_cut, atom outside the box on a free axis). */
 int l2t_build_neighbors(l2t_ctx *ctx, double r_cut, int32_t *max_nbrs, double *mean_nbrs);

@@ -701,6 +701,15 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             if (value != 0) t.sweep_used = (int)value;
             l2t::drop_graphs(c);
             return L2T_OK;
+        case L2T_OPT_TABLE_STREAM:
+            // a cache hint of the table loads, not a launch shape: leaves the
+            // tuned form alone; an explicit choice applies at once
+            if (value < 0 || value > 2)
+                return l2t::fail(c, L2T_EINVAL, "table stream must be 0, 1 or 2");
+            t.table = (int)value;
+            if (value != 0) t.table_used = (int)value;
+            l2t::drop_graphs(c);
+            return L2T_OK;
         case L2T_OPT_KERNEL:
             if (value != l2t::kKernelSliced && value != l2t::kKernelBrick)
                 return l2t::fail(c, L2T_EINVAL, "kernel must be 0 (global) or 1 (brick)");
@@ -736,6 +745,7 @@ int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
         case L2T_OPT_BATCH_FP64: *value = c->batch_fp64 ? 1 : 0; break;
         case L2T_OPT_BRICK_EDGE: *value = c->brick_edge_used; break;
         case L2T_OPT_SWEEP: *value = t.sweep_used; break;
+        case L2T_OPT_TABLE_STREAM: *value = t.table_used; break;
         default: return l2t::fail(c, L2T_EINVAL, "unknown option");
     }
     return L2T_OK;

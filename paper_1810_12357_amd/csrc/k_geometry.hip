@@ -1594,21 +1594,26 @@ std::mutex &edge_mutex() {
     return m;
 }
 // the measured brick edge and sweep order (1 fixed, 2 alternating) of a shape
-std::map<std::string, std::pair<int32_t, int>> &edge_cache() {
-    static std::map<std::string, std::pair<int32_t, int>> m;
+// what the build measured for a problem shape: brick edge, sweep order and
+// table-load policy
+struct LayoutChoice {
+    int32_t edge = 0;
+    int sweep = 1, table = 1;
+};
+std::map<std::string, LayoutChoice> &edge_cache() {
+    static std::map<std::string, LayoutChoice> m;
     return m;
 }
-bool edge_lookup(const std::string &key, int32_t *edge, int *sweep) {
+bool edge_lookup(const std::string &key, LayoutChoice *out) {
     std::lock_guard<std::mutex> g(edge_mutex());
     auto it = edge_cache().find(key);
     if (it == edge_cache().end()) return false;
-    *edge = it->second.first;
-    *sweep = it->second.second;
+    *out = it->second;
     return true;
 }
-void edge_store(const std::string &key, int32_t edge, int sweep) {
+void edge_store(const std::string &key, const LayoutChoice &ch) {
     std::lock_guard<std::mutex> g(edge_mutex());
-    edge_cache()[key] = {edge, sweep};
+    edge_cache()[key] = ch;
 }
 
 std::string edge_key(const l2t_ctx *c, double r_cut) {
@@ -1631,29 +1636,32 @@ std::string edge_key(const l2t_ctx *c, double r_cut) {
 // has CUs is measured, not only modelled: the model's edge and its two
 // neighbours are built and each runs a short probe of the brick kernel
 // (brick_probe), and a neighbour replaces the model's edge when it is more
-// than 1 % faster.  The winner is kept per problem shape, so later builds of
-// the same shape build once.  Smaller layouts, FP64 contexts, a pinned edge
-// or launch form and a disabled autotuner keep the model's edge.
+// than 1 % faster; on the chosen layout the sweep order (L2T_OPT_SWEEP) and
+// the table-load policy (L2T_OPT_TABLE_STREAM) are timed the same way.  The
+// choices are kept per problem shape, so later builds of the same shape build
+// once.  Smaller layouts, FP64 contexts, a pinned edge or launch form and a
+// disabled autotuner keep the model's edge, the fixed order and cached loads.
 int build_neighbors(l2t_ctx *c, double r_cut) {
     Tuning &t = c->tune;
-    // an explicit sweep order applies as set; otherwise the fixed order unless
-    // the alternating one measures faster below
+    // an explicit sweep order or table policy applies as set; otherwise the
+    // fixed order and cached table loads unless the others measure faster below
     t.sweep_used = t.sweep == 2 ? 2 : 1;
+    t.table_used = t.table == 2 ? 2 : 1;
     const bool may_tune = c->precision == L2T_FP32C && t.autotune && !t.pinned &&
                           t.brick_edge == 0;
     const std::string key = may_tune ? edge_key(c, r_cut) : std::string();
-    int32_t cached = 0;
-    int cached_sweep = 1;
-    if (may_tune && edge_lookup(key, &cached, &cached_sweep)) {
-        const int rc = build_layout(c, r_cut, cached);
-        if (rc == L2T_OK && t.sweep == 0) t.sweep_used = cached_sweep;
+    LayoutChoice cached;
+    if (may_tune && edge_lookup(key, &cached)) {
+        const int rc = build_layout(c, r_cut, cached.edge);
+        if (rc == L2T_OK && t.sweep == 0) t.sweep_used = cached.sweep;
+        if (rc == L2T_OK && t.table == 0) t.table_used = cached.table;
         return rc;
     }
     int rc = build_layout(c, r_cut, 0);
     if (rc != L2T_OK || !may_tune) return rc;
     const int32_t e0 = c->brick_edge_used;
     if (c->n_brick_list < std::max(1, c->n_cu)) {
-        edge_store(key, e0, 1);
+        edge_store(key, LayoutChoice{e0, 1, 1});
         return L2T_OK;
     }
     // an edge above e0 changes the layout only where some axis is longer than e0
@@ -1662,11 +1670,11 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         for (int d = 0; d < 3; ++d) grows |= st.nc[d] > e0;
     constexpr int32_t kProbe = 12;
     float best_ms = 0.0f;
-    rc = brick_probe(c, kProbe, false, &best_ms);
+    rc = brick_probe(c, kProbe, false, false, &best_ms);
     if (rc == L2T_ENOMEM) {
         // no room for the stand-in state: keep the model's edge
         c->last_error.clear();
-        edge_store(key, e0, 1);
+        edge_store(key, LayoutChoice{e0, 1, 1});
         return L2T_OK;
     }
     if (rc != L2T_OK) return rc;
@@ -1678,7 +1686,7 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         built = c->brick_edge_used;
         if (built != e) continue;   // its tiles overflowed: a smaller edge was built
         float ms = 0.0f;
-        rc = brick_probe(c, kProbe, false, &ms);
+        rc = brick_probe(c, kProbe, false, false, &ms);
         if (rc == L2T_ENOMEM) {   // a larger layout's stand-in did not fit: skip it
             c->last_error.clear();
             continue;
@@ -1693,23 +1701,39 @@ int build_neighbors(l2t_ctx *c, double r_cut) {
         rc = build_layout(c, r_cut, best);
         if (rc != L2T_OK) return rc;
     }
-    // the sweep order on the chosen layout: the alternating one replaces the
-    // fixed one when it is more than 1 % faster
-    int sweep = 1;
+    // on the chosen layout, the sweep order and then the table policy: the
+    // alternating order and the non-temporal table loads each replace the
+    // default when they are more than 1 % faster
+    LayoutChoice ch{best, 1, 1};
+    bool alt = t.sweep == 2;
     if (t.sweep == 0) {
         float fixed_ms = 0.0f, alt_ms = 0.0f;
-        rc = brick_probe(c, kProbe, false, &fixed_ms);
-        if (rc == L2T_OK) rc = brick_probe(c, kProbe, true, &alt_ms);
+        rc = brick_probe(c, kProbe, false, t.table == 2, &fixed_ms);
+        if (rc == L2T_OK) rc = brick_probe(c, kProbe, true, t.table == 2, &alt_ms);
         if (rc == L2T_ENOMEM) {
             c->last_error.clear();
         } else if (rc != L2T_OK) {
             return rc;
         } else if (alt_ms < 0.99f * fixed_ms) {
-            sweep = 2;
+            ch.sweep = 2;
+            alt = true;
         }
-        t.sweep_used = sweep;
+        t.sweep_used = ch.sweep;
     }
-    edge_store(key, best, sweep);
+    if (t.table == 0) {
+        float cached_ms = 0.0f, stream_ms = 0.0f;
+        rc = brick_probe(c, kProbe, alt, false, &cached_ms);
+        if (rc == L2T_OK) rc = brick_probe(c, kProbe, alt, true, &stream_ms);
+        if (rc == L2T_ENOMEM) {
+            c->last_error.clear();
+        } else if (rc != L2T_OK) {
+            return rc;
+        } else if (stream_ms < 0.99f * cached_ms) {
+            ch.table = 2;
+        }
+        t.table_used = ch.table;
+    }
+    edge_store(key, ch);
     return L2T_OK;
 }
 

@@ -78,8 +78,9 @@ __global__ __launch_bounds__(256) void k_step_fp32c(const SliceInfo *slices, int
 // (-1) whose workgroups return at once.
 // LO_IN: read the low part from lo_in and write the new one to Tlo (two
 // buffers, as the adjoint's recomputation keeps every state of a segment);
-// otherwise the low part is updated in place and lo_in is unused.
-template <bool LO_IN>
+// otherwise the low part is updated in place and lo_in is unused.  POLICY:
+// cache policy of the table loads (kTableCached, kTableStream).
+template <bool LO_IN, int POLICY>
 __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(8))) void k_brick_fp32c(
     const BrickInfo *__restrict__ bricks, const int32_t *__restrict__ list, int32_t n_list,
     const SliceInfo *__restrict__ slices, const uint32_t *__restrict__ colw,
@@ -195,15 +196,21 @@ __global__ __launch_bounds__(kBrickBlockMax) __attribute__((amdgpu_waves_per_eu(
         const float Ti = tile[q * kWave + lane];
         const uint32_t *row = colw + (int64_t)base * kWave;
         const LedgerTerms t =
-            one_tier ? slice_core_brick<false>(w, slot, lane < nv, p, Ti, lo, tl, sw, row, lane,
-                                               tile, Thi_n, Tlo, eatom, qpulse, err)
-                     : slice_core_brick<true>(w, slot, lane < nv, p, Ti, lo, tl, sw, row, lane,
-                                              tile, Thi_n, Tlo, eatom, qpulse, err);
+            one_tier ? slice_core_brick<false, POLICY>(w, slot, lane < nv, p, Ti, lo, tl, sw, row,
+                                                       lane, tile, Thi_n, Tlo, eatom, qpulse, err)
+                     : slice_core_brick<true, POLICY>(w, slot, lane < nv, p, Ti, lo, tl, sw, row,
+                                                      lane, tile, Thi_n, Tlo, eatom, qpulse, err);
         acc.e2l += t.e2l;
         acc.src += t.src;
         acc.lt += t.lt;
     }
     ledger_add(ledger, bi.slice0 + wave, lane, acc, p.dt);
+}
+
+// the brick kernel with the table-load policy in effect (1 cached, 2 streamed)
+template <bool LO_IN>
+decltype(&k_brick_fp32c<LO_IN, kTableCached>) brick_kernel(int table) {
+    return table == 2 ? &k_brick_fp32c<LO_IN, kTableStream> : &k_brick_fp32c<LO_IN, kTableCached>;
 }
 
 // LDS-tile FP64 sub-step (the plain form of Eq. 2 with the brick layout):
@@ -937,8 +944,9 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
         const int32_t nl = c->n_xcd_list;
         const unsigned grid = (unsigned)nl;
         const size_t lds = sizeof(float) * (size_t)c->tile_max;
+        const auto kern = brick_kernel<false>(c->tune.table_used);
         for (int32_t k = 0; k < n && nl > 0; ++k) {
-            hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(block), lds, c->stream,
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, c->stream,
                                c->bricks, xcd_list_for(c, k), nl, c->slices, c->colw, c->halo,
                                c->Thi[cur], c->Thi[cur ^ 1], nullptr, c->Tlo, c->Tl32, c->srcw32,
                                c->dparams, c->dstep, k, c->ledger, eatom, c->derr);
@@ -973,8 +981,10 @@ int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, d
 // stand-in state held in scratch memory (1,000 K, no coupling, no source), so
 // the brick edge can be measured before any field of the new layout is
 // written.  The context's state, ledger, step counters and error word are not
-// touched.  *ms receives the faster of two timed runs.
-int brick_probe(l2t_ctx *c, int32_t n, bool alternate, float *ms) {
+// touched.  alternate: the sweep order that reverses the launch list on odd
+// sub-steps; stream: non-temporal table loads.  *ms receives the faster of
+// two timed runs.
+int brick_probe(l2t_ctx *c, int32_t n, bool alternate, bool stream, float *ms) {
     *ms = 0.0f;
     const size_t NI = (size_t)c->n_int, NS = (size_t)c->n_slices, S = c->sys.size();
     if (c->n_brick_list == 0 || NI == 0 || n < 1) return L2T_OK;
@@ -1037,12 +1047,13 @@ int brick_probe(l2t_ctx *c, int32_t n, bool alternate, float *ms) {
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
     float best = 1e30f;
     hipError_t e = hipSuccess;
+    const auto kern = brick_kernel<false>(stream ? 2 : 1);
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
         (void)hipEventRecord(e0, s_);
         // T^lat and the source weight both read the constant 1,000 K buffer
         // (a positive weight marks no atom as held); the low part is updated in place
         for (int32_t k = 0; k < n; ++k)
-            hipLaunchKernelGGL(k_brick_fp32c<false>, dim3(grid), dim3(kBrickBlockMax), lds, s_,
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kBrickBlockMax), lds, s_,
                                c->bricks,
                                c->xcd_list + ((alternate && (k & 1)) ? c->n_xcd_list : 0),
                                c->n_xcd_list, c->slices, c->colw,
@@ -1069,7 +1080,8 @@ int brick_step_fp32c(l2t_ctx *c, int block, const float *Thi, float *Thi_n, cons
     if (nl <= 0) return L2T_OK;
     const unsigned grid = (unsigned)nl;
     const size_t lds = sizeof(float) * (size_t)c->tile_max;
-    hipLaunchKernelGGL(k_brick_fp32c<true>, dim3(grid), dim3(block), lds, c->stream, c->bricks,
+    const auto kern = brick_kernel<true>(c->tune.table_used);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, c->stream, c->bricks,
                        xcd_list_for(c, rel), nl, c->slices, c->colw, c->halo, Thi, Thi_n, lo_in, Tlo,
                        c->Tl32, c->srcw32, c->dparams, dstep, rel, ledger, nullptr, c->derr);
     L2T_HIP(c, hipGetLastError());

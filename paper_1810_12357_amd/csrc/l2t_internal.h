@@ -146,6 +146,8 @@ struct Tuning {
     int brick_edge = 0;      // 0 = chosen by the layout builder
     int sweep = 0;           // L2T_OPT_SWEEP as set: 0 = chosen at neighbour build, 1, 2
     int sweep_used = 1;      // in effect: 1 = fixed order, 2 = reversed on odd sub-steps
+    int table = 0;           // L2T_OPT_TABLE_STREAM as set: 0 = chosen at neighbour build, 1, 2
+    int table_used = 1;      // in effect: 1 = cached table loads, 2 = non-temporal
     bool tuned = false;
     bool pinned = false;     // an explicit option was set: keep the choice
 };
@@ -309,7 +311,7 @@ int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream
 int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom);
 // time n brick-kernel sub-steps of the current layout on a stand-in state in
 // scratch memory (the context's fields are not touched)
-int brick_probe(l2t_ctx *c, int32_t n, bool alternate, float *ms);
+int brick_probe(l2t_ctx *c, int32_t n, bool alternate, bool stream, float *ms);
 // the launch list of sub-step k of an advance (the reversed one on odd k when
 // the alternating sweep is in effect)
 inline const int32_t *xcd_list_for(const l2t_ctx *c, int64_t k) {

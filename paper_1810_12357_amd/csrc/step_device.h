@@ -394,6 +394,10 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
     return finish_fp32c(p, slot, valid, Ti, S, lo, tl, sw, Thi_n, Tlo, eatom, qpulse, err);
 }
 
+// cache policy of the table loads: the default, or the non-temporal hint
+// (the table is read once per sub-step)
+constexpr int kTableCached = 0, kTableStream = 2;
+
 // LDS-tile form for one slice.  TIERS = false: the caller has shown that every
 // pair of the slice lies on the lowest tier of pair32 (it evaluates exactly
 // that tier, bitwise what pair32 returns there).  w is the slice's row width and row the first
@@ -401,8 +405,8 @@ __device__ __forceinline__ LedgerTerms slice_core_fp32c(const SliceInfo &si, int
 // offsets of two neighbours; a chunk is 4 words = 8 neighbours.  The words of
 // chunk c + 2 are requested once those of chunk c have been turned into LDS
 // reads, alternating between two buffers.  Same terms in the same order as
-// slice_core_fp32c.
-template <bool TIERS>
+// slice_core_fp32c.  POLICY: kTableCached or kTableStream for the row loads.
+template <bool TIERS, int POLICY>
 __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot, bool valid,
                                                         const DevParams &p, float Ti, int16_t lo,
                                                         float tl, float sw,
@@ -430,7 +434,7 @@ __device__ __forceinline__ LedgerTerms slice_core_brick(int32_t w, int32_t slot,
         for (int u = 0; u < 4; ++u) {
             const int32_t wi = min(4 * c + u, nwd - 1);
             d[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_off,
-                                                        wi * kWave * (int)sizeof(uint32_t), 0);
+                                                        wi * kWave * (int)sizeof(uint32_t), POLICY);
         }
     };
     auto at = [&](uint32_t off) { return *reinterpret_cast<const float *>(tb + off); };

@@ -29,6 +29,7 @@ L2T_CE_CONST, L2T_CE_LINEAR, L2T_CE_CAPPED = 0, 1, 2
 L2T_OPT_PERSISTENT, L2T_OPT_BLOCK, L2T_OPT_RESIDENT_MAX, L2T_OPT_GRAPH, L2T_OPT_AUTOTUNE = 0, 1, 2, 3, 4
 L2T_OPT_KERNEL, L2T_OPT_BRICK_EDGE, L2T_OPT_ATOM_LEDGER, L2T_OPT_BATCH_FP64 = 5, 6, 7, 8
 L2T_OPT_SWEEP = 9
+L2T_OPT_TABLE_STREAM = 10
 L2T_XI_INSTANT, L2T_XI_LEDGER = 0, 1
 
 # every symbol the header declares (checked by the CPU test suite)

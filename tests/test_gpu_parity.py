@@ -209,21 +209,25 @@ def test_c1_fp32c_matches_oracle(c1_oracle, persistent):
 def test_fp32c_launch_forms_bitwise_equal(case):
     """Global-gather per-step, persistent, LDS-brick per-step (with and without
     hipGraph capture, with the bricks in a fixed order or reversed on every
-    other sub-step) evaluate the same per-atom arithmetic in the same order.
-    The last advance spans two captured 256-sub-step chunks and an odd rest."""
+    other sub-step, with cached or non-temporal table loads) evaluate the
+    same per-atom arithmetic in the same order.  The last advance spans two
+    captured 256-sub-step chunks and an odd rest."""
     if case == "c3_jitter":
         w = W.c3(n_cells=9, n_substeps=1)
     else:
         w = W.c4(n_systems=5, n_substeps=1, size_lo=500, size_hi=4000)
     runs = []
-    # (kernel, persistent, graph, sweep): the brick forms also with the brick
-    # order reversed on every other sub-step
-    forms = ((0, 0, 0, 1), (0, 1, 0, 1), (1, 0, 0, 1), (1, 0, 1, 1), (1, 0, 0, 2), (1, 0, 1, 2))
-    for kernel, persistent, graph, sweep in forms:
+    # (kernel, persistent, graph, sweep, table): the brick forms also with the
+    # brick order reversed on every other sub-step and with streamed table loads
+    forms = ((0, 0, 0, 1, 1), (0, 1, 0, 1, 1), (1, 0, 0, 1, 1), (1, 0, 1, 1, 1), (1, 0, 0, 2, 1),
+             (1, 0, 1, 2, 1), (1, 0, 0, 1, 2), (1, 0, 1, 2, 2))
+    for kernel, persistent, graph, sweep, table in forms:
         ctx = gpu_context(w, L.L2T_FP32C, graph=graph)
         L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
         L.l2t_set_option(ctx.h, L.L2T_OPT_SWEEP, sweep)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_TABLE_STREAM, table)
         assert L.l2t_get_option(ctx.h, L.L2T_OPT_SWEEP) == sweep
+        assert L.l2t_get_option(ctx.h, L.L2T_OPT_TABLE_STREAM) == table
         if persistent:
             L.l2t_set_option(ctx.h, L.L2T_OPT_PERSISTENT, 1)
         ctx.advance(37)
