@@ -45,12 +45,20 @@ XGMI_LINK_GBS = 153.0   # one xGMI link of an MI355X, each direction (AMD public
 # 0: every context the bench makes launches its sub-steps directly instead of
 # replaying captured hipGraphs (for rocprofv3 counter passes)
 GRAPH = 1
+# (option, value) pairs set on every FP32C context the bench makes, from the
+# launch-form options (--kernel, --block, --brick-edge, --sweep,
+# --table-stream).  Counter passes pin the form the timed run chose: the
+# build's and the autotuner's timings are perturbed under the counters.
+FP32C_PINS = []
 
 
 def new_context(L, systems, prec, **kw):
     ctx = L.Context(systems, prec, **kw)
     if not GRAPH:
         L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, 0)
+    if prec == L.L2T_FP32C:
+        for opt, value in FP32C_PINS:
+            L.l2t_set_option(ctx.h, opt, value)
     return ctx
 
 
@@ -562,6 +570,12 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--c4-full-substeps", type=int, default=6000)
     ap.add_argument("--c4-fp32c-only", action="store_true",
                     help="C4: time the batched FP32C form alone (profiling; no speedup)")
+    ap.add_argument("--table-stream", type=int, choices=[0, 1, 2], default=0,
+                    help="table loads of the FP32C brick kernels: 0 = measured at the build, "
+                         "1 = cached, 2 = streamed (every FP32C context; counter passes)")
+    ap.add_argument("--sweep", type=int, choices=[0, 1, 2], default=0,
+                    help="brick order of the FP32C brick kernels: 0 = measured at the build, "
+                         "1 = fixed, 2 = reversed every other sub-step (every FP32C context)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
                     help="0 = launch sub-steps directly instead of replaying hipGraphs "
                          "(rocprofv3 counter passes)")
@@ -577,10 +591,11 @@ def make_parser() -> argparse.ArgumentParser:
                     help="skip the recorded forward and adjoint timing")
     ap.add_argument("--no-md", action="store_true", help="skip the lattice-side (Eq. 5, 8) timing")
     ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto",
-                    help="pin the sub-step launch form (FP32C pass and FP64 sample)")
-    ap.add_argument("--brick-edge", type=int, default=0)
+                    help="pin the sub-step launch form (every FP32C context and the FP64 sample)")
+    ap.add_argument("--brick-edge", type=int, default=0,
+                    help="brick edge in cells of every FP32C context (0 = measured at the build)")
     ap.add_argument("--block", type=int, default=0,
-                    help="threads per workgroup of the sub-step kernel (0 = autotuned)")
+                    help="threads per workgroup of the FP32C sub-step kernel (0 = autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     return ap
@@ -598,6 +613,16 @@ def main():
     from paper_1810_12357_amd import l2t as L
     global GRAPH
     GRAPH = args.graph
+    if args.brick_edge:
+        FP32C_PINS.append((L.L2T_OPT_BRICK_EDGE, args.brick_edge))
+    if args.kernel != "auto":
+        FP32C_PINS.append((L.L2T_OPT_KERNEL, 1 if args.kernel == "brick" else 0))
+    if args.block:
+        FP32C_PINS.append((L.L2T_OPT_BLOCK, args.block))
+    if args.sweep:
+        FP32C_PINS.append((L.L2T_OPT_SWEEP, args.sweep))
+    if args.table_stream:
+        FP32C_PINS.append((L.L2T_OPT_TABLE_STREAM, args.table_stream))
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -618,12 +643,6 @@ def main():
         ctx = new_context(L, w.systems, L.L2T_FP32C,
                           stream=torch.cuda.current_stream().cuda_stream)
         h = ctx.h
-        if args.brick_edge:
-            L.l2t_set_option(h, L.L2T_OPT_BRICK_EDGE, args.brick_edge)
-        if args.kernel != "auto":
-            L.l2t_set_option(h, L.L2T_OPT_KERNEL, 1 if args.kernel == "brick" else 0)
-        if args.block:
-            L.l2t_set_option(h, L.L2T_OPT_BLOCK, args.block)
         d = setup_system(L, h, sy, dev)
         torch.cuda.synchronize()
         timer = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
