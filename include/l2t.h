@@ -256,7 +256,12 @@ int l2t_set_positions(l2t_ctx *ctx, int32_t sys, const double *xyz, int32_t mem)
  * system (Section 2.1, user-given cut-off; minimum image on periodic axes,
  * distances in FP64, inclusive).  Atoms are binned into cells of edge >=
  * r_cut and reordered by cell.  Synchronises.  Outputs (nullable): the
- * largest and the mean neighbour count over all atoms.  An FP32C context
+ * largest and the mean neighbour count over all atoms.  A rebuild (new
+ * positions of the same atoms) keeps each system's T_e (bit for bit), T^lat
+ * and gate, its ledger and its step counter; it clears the per-atom energy
+ * record and the held atoms (L2T_FIELD_FIXED), and recomputes the source
+ * weights from the new positions.  If the build fails, T_e and T^lat must be
+ * written again.  An FP32C context
  * whose layout has at least one brick per CU also times the brick edge the
  * first time it builds a given problem shape in the process: the cost
  * model's edge and its two neighbours are built and each runs a short probe

@@ -333,6 +333,7 @@ void l2t_destroy(l2t_ctx *c) {
     dfree(c, c->dbar);
     dfree(c, c->stage);
     l2t::dev_free(c, c->scratch);
+    l2t::dev_free(c, c->carry);
     for (void *p : c->tmp) l2t::dev_free(c, p);
     l2t::dev_free(c, c->rec.buf);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -431,21 +432,65 @@ int l2t_set_positions(l2t_ctx *c, int32_t sys, const double *xyz, int32_t mem) {
     return L2T_OK;
 }
 
+static int restore_counters(l2t_ctx *c, int32_t sys, int64_t step, double E_e_to_l, double E_src,
+                            double T_ledger_acc);
+
 int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mean_nbrs) {
     if (!c) return L2T_EINVAL;
     if (!(r_cut > 0.0) || !std::isfinite(r_cut)) return l2t::fail(c, L2T_EINVAL, "r_cut <= 0");
     for (size_t s = 0; s < c->sys.size(); ++s)
         if (!c->sys[s].has_pos)
             return l2t::fail(c, L2T_ESTATE, "positions of system " + std::to_string(s) + " not set");
+    // each system's T_e, T^lat and gate leave the old internal order for the
+    // caller's, and come back in the new order after the build (the FP32C
+    // state round-trips through FP64 bit for bit); the ledger and the step
+    // counter run on
+    const int32_t S = (int32_t)c->sys.size();
+    std::vector<char> keep_te(S, 0), keep_tl(S, 0);
+    bool keep = false;
+    for (int32_t s = 0; s < S && c->layout_built; ++s) {
+        keep_te[s] = c->sys[s].has_te;
+        keep_tl[s] = c->sys[s].has_tl;
+        keep |= keep_te[s] || keep_tl[s];
+    }
+    const size_t nt = (size_t)c->n_tot;
+    if (keep && 3 * nt > c->carry_len) {
+        L2T_HIP(c, hipStreamSynchronize(c->stream));
+        l2t::dev_free(c, c->carry);
+        c->carry = nullptr;
+        c->carry_len = 0;
+        void *m = nullptr;
+        if (l2t::dev_malloc(c, &m, sizeof(double) * 3 * nt) != hipSuccess)
+            return l2t::fail(c, L2T_ENOMEM, "field carry buffer allocation failed");
+        c->carry = static_cast<double *>(m);
+        c->carry_len = 3 * nt;
+    }
+    // the ledger rows follow the slices, which the build lays out anew: the
+    // kept systems' totals and step counters go back into their first rows
+    std::vector<l2t_energy_report> kept(S);
+    for (int32_t s = 0; s < S && keep; ++s) {
+        double *base = c->carry + c->sys[s].caller_off;
+        int rc = L2T_OK;
+        if (keep_te[s]) rc = l2t::energies(c, s, &kept[s]);
+        if (rc == L2T_OK && keep_te[s]) rc = l2t::permute_out(c, s, L2T_FIELD_TE, base);
+        if (rc == L2T_OK && keep_tl[s]) rc = l2t::permute_out(c, s, L2T_FIELD_TL, base + nt);
+        if (rc == L2T_OK && keep_tl[s]) rc = l2t::permute_out(c, s, L2T_FIELD_GATE, base + 2 * nt);
+        if (rc != L2T_OK) return rc;
+    }
     l2t::drop_graphs(c);
     c->rec.valid = false;
     int rc = l2t::build_neighbors(c, r_cut);
-    if (rc != L2T_OK) return rc;
+    if (rc != L2T_OK) {
+        for (auto &st : c->sys) st.has_te = st.has_tl = false;   // the fields are lost
+        c->layout_built = false;
+        return rc;
+    }
     c->nbrs_built = true;
+    c->layout_built = true;
     c->res_valid = false;
     if (!c->tune.pinned) c->tune.tuned = false;   // new layout: tune again unless pinned
     for (auto &st : c->sys) {
-        st.has_te = false;   // internal order changed: fields must be written again
+        st.has_te = false;   // internal order changed: written again below where kept
         st.has_tl = false;
         st.eatom_valid = false;
         st.has_fixed = false;
@@ -465,6 +510,23 @@ int l2t_build_neighbors(l2t_ctx *c, double r_cut, int32_t *max_nbrs, double *mea
             rc = l2t::source_weights(c, s);
             if (rc != L2T_OK) return rc;
         }
+    for (int32_t s = 0; s < S && keep; ++s) {
+        const double *base = c->carry + c->sys[s].caller_off;
+        if (keep_te[s]) {
+            rc = l2t::permute_in(c, s, base, L2T_FIELD_TE);
+            if (rc == L2T_OK)
+                rc = restore_counters(c, s, kept[s].step, kept[s].E_e_to_l, kept[s].E_src,
+                                      kept[s].T_ledger_acc);
+            if (rc != L2T_OK) return rc;
+            c->sys[s].has_te = true;
+        }
+        if (keep_tl[s]) {
+            rc = l2t::permute_in(c, s, base + nt, L2T_FIELD_TL);
+            if (rc == L2T_OK) rc = l2t::permute_in(c, s, base + 2 * nt, L2T_FIELD_GATE);
+            if (rc != L2T_OK) return rc;
+            c->sys[s].has_tl = true;
+        }
+    }
     L2T_HIP(c, hipStreamSynchronize(c->stream));
     if (max_nbrs) *max_nbrs = c->max_nbrs;
     if (mean_nbrs) *mean_nbrs = c->mean_nbrs;
@@ -982,6 +1044,23 @@ int l2t_energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out) {
     return check_err(c);
 }
 
+// a system's ledger totals into its first ledger row (the report sums its
+// rows, the others are cleared) and its step counter
+static int restore_counters(l2t_ctx *c, int32_t sys, int64_t step, double E_e_to_l, double E_src,
+                            double T_ledger_acc) {
+    SystemState &st = c->sys[sys];
+    int rc = l2t::reset_ledger(c, sys);
+    if (rc != L2T_OK) return rc;
+    const double row[3] = {E_e_to_l, E_src, T_ledger_acc};
+    L2T_HIP(c, hipMemcpyAsync(c->ledger + 3 * (int64_t)st.slice0, row, sizeof row,
+                              hipMemcpyHostToDevice, c->stream));
+    L2T_HIP(c, hipMemcpyAsync(c->dstep + sys, &step, sizeof step, hipMemcpyHostToDevice,
+                              c->stream));
+    L2T_HIP(c, hipStreamSynchronize(c->stream));   // the sources are locals
+    st.step = step;
+    return L2T_OK;
+}
+
 int l2t_set_counters(l2t_ctx *c, int32_t sys, int64_t step, double E_e_to_l, double E_src,
                      double T_ledger_acc) {
     if (bad_sys(c, sys) || step < 0 || !std::isfinite(E_e_to_l) || !std::isfinite(E_src) ||
@@ -990,16 +1069,8 @@ int l2t_set_counters(l2t_ctx *c, int32_t sys, int64_t step, double E_e_to_l, dou
     SystemState &st = c->sys[sys];
     if (!c->nbrs_built || !st.has_te)
         return l2t::fail(c, L2T_ESTATE, "restore T_e before the counters (writing T_e resets them)");
-    int rc = l2t::reset_ledger(c, sys);
+    const int rc = restore_counters(c, sys, step, E_e_to_l, E_src, T_ledger_acc);
     if (rc != L2T_OK) return rc;
-    // the system's totals go into its first ledger row; the report sums its rows
-    const double row[3] = {E_e_to_l, E_src, T_ledger_acc};
-    L2T_HIP(c, hipMemcpyAsync(c->ledger + 3 * (int64_t)st.slice0, row, sizeof row,
-                              hipMemcpyHostToDevice, c->stream));
-    L2T_HIP(c, hipMemcpyAsync(c->dstep + sys, &step, sizeof step, hipMemcpyHostToDevice,
-                              c->stream));
-    L2T_HIP(c, hipStreamSynchronize(c->stream));   // the sources are locals
-    st.step = step;
     c->rec.valid = false;
     return L2T_OK;
 }

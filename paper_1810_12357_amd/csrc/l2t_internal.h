@@ -187,6 +187,7 @@ struct l2t_ctx {
     int32_t max_n = 0;
     double r_cut = 0.0;
     bool nbrs_built = false;
+    bool layout_built = false;   // an internal order exists (kept by l2t_set_positions)
     int32_t max_nbrs = 0;
     double mean_nbrs = 0.0;
 
@@ -256,6 +257,8 @@ struct l2t_ctx {
     double *stage = nullptr;     // staging [max(n_tot, 3 * max_n)]
     void *scratch = nullptr;     // temporary (autotune snapshot, velocities)
     size_t scratch_bytes = 0;
+    double *carry = nullptr;     // T_e, T^lat and gate in caller order across a rebuild
+    size_t carry_len = 0;
     // grow-only capacities of the internal-order buffers and the brick tables
     size_t cap_ni = 0, cap_nb = 0, cap_nl = 0, cap_sh = 0, cap_ha = 0;
     // grow-only temporaries of the neighbour build, one per use

@@ -1,7 +1,7 @@
 """GPU parity over an MD-like loop: the atoms move between advances, so every
 advance follows a new neighbour build (new cell order, new rows, new brick
-tables), the T_e field is carried across the rebuild by reading it back and
-writing it again, and T^lat is taken afresh from Eq. 4.  The captured graphs
+tables), the T_e field is carried across the rebuild (by the rebuild itself,
+or read back and written again), and T^lat is taken afresh from Eq. 4.  The captured graphs
 of one advance must not be replayed with the tables of the previous build:
 the oracle runs the same sequence from its own neighbour sets.  Tolerances as
 in the other parity tests (FP64 1e-12, FP32C 1e-5, relative)."""
@@ -66,14 +66,13 @@ def test_md_loop_moves_atoms_across_the_cut_off(md_case):
     assert changed > 100
 
 
-@pytest.mark.parametrize("precision,kernel", [("fp64", None), ("fp32c", 0), ("fp32c", 1)])
-def test_md_loop_with_rebuilds_matches_oracle(md_case, precision, kernel):
-    w, states, _ = md_case
-    sy = w.systems[0]
-    prec = L.L2T_FP64 if precision == "fp64" else L.L2T_FP32C
-    tol = 1e-12 if precision == "fp64" else 1e-5
+def _run(sy, w, prec, kernel, carry):
+    """The MD loop through the C ABI: with carry, T_e is written once and
+    the rebuilds keep it (with the ledger and the step counter); without, it
+    is read back before every rebuild and written again after it."""
     ctx = L.Context([sy], prec)
     h = ctx.h
+    out = []
     try:
         if kernel is not None:
             L.l2t_set_option(h, L.L2T_OPT_KERNEL, kernel)
@@ -81,13 +80,65 @@ def test_md_loop_with_rebuilds_matches_oracle(md_case, precision, kernel):
         for k in range(N_MD):
             L.l2t_set_positions(h, 0, _positions(sy, k).reshape(-1))
             L.l2t_build_neighbors(h, w.r_cut)
-            L.l2t_set_params(h, 0, sy.params)
-            L.l2t_set_field(h, 0, L.L2T_FIELD_TE, T)
+            if k == 0:
+                L.l2t_set_params(h, 0, sy.params)
+            if k == 0 or not carry:
+                L.l2t_set_field(h, 0, L.L2T_FIELD_TE, T)
             L.l2t_set_velocities(h, 0, sy.vel.reshape(-1), sy.mass)
             ctx.advance(N_SUB)
             T = ctx.get(0)
-            err = max_rel(T, states[k])
-            print(f"{precision} kernel={kernel} MD step {k}: max rel {err:.2e}")
-            assert err <= tol
+            out.append(T)
+        e = ctx.energies(0)
     finally:
         ctx.close()
+    return out, e
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp64", None), ("fp32c", 0), ("fp32c", 1)])
+def test_md_loop_with_rebuilds_matches_oracle(md_case, precision, kernel):
+    """Both ways of crossing a rebuild give the same states bit for bit and
+    match the oracle; when the rebuilds keep the fields, the ledger and the
+    step counter also run through the whole loop (sum T + ledger = sum T_0)."""
+    w, states, _ = md_case
+    sy = w.systems[0]
+    prec = L.L2T_FP64 if precision == "fp64" else L.L2T_FP32C
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    reset, _ = _run(sy, w, prec, kernel, carry=False)
+    kept, e = _run(sy, w, prec, kernel, carry=True)
+    for k in range(N_MD):
+        assert np.array_equal(reset[k], kept[k])
+        err = max_rel(kept[k], states[k])
+        print(f"{precision} kernel={kernel} MD step {k}: max rel {err:.2e}")
+        assert err <= tol
+    assert e["step"] == N_MD * N_SUB
+    assert e["sum_T"] + e["T_ledger_acc"] == pytest.approx(
+        sy.T_e0.sum(), rel=1e-12 if precision == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_rebuild_on_the_same_positions_keeps_the_state(precision):
+    """A rebuild on unchanged positions keeps T_e bit for bit, the ledger and
+    the step counter: 50 sub-steps, a rebuild, 50 more give the same state as
+    100 without the rebuild."""
+    w = W.c3(n_cells=8, n_substeps=100)
+    sy = w.systems[0]
+    prec = L.L2T_FP64 if precision == "fp64" else L.L2T_FP32C
+    a, b = L.Context([sy], prec), L.Context([sy], prec)
+    try:
+        a.setup(w.r_cut)
+        b.setup(w.r_cut)
+        a.advance(50)
+        T1, e1 = a.get(0), a.energies(0)
+        L.l2t_set_positions(a.h, 0, sy.pos.reshape(-1))
+        L.l2t_build_neighbors(a.h, w.r_cut)
+        assert np.array_equal(a.get(0), T1)
+        e2 = a.energies(0)
+        assert e2["step"] == e1["step"] == 50
+        for key in ("sum_T", "T_ledger_acc", "E_e_to_l"):
+            assert e2[key] == pytest.approx(e1[key], rel=1e-13, abs=1e-300)
+        a.advance(50)
+        b.advance(100)
+        assert np.array_equal(a.get(0), b.get(0))
+    finally:
+        a.close()
+        b.close()
