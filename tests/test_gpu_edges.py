@@ -157,20 +157,28 @@ def test_uniform_temperature_is_stationary_and_g0_conserves(precision):
 def test_measured_brick_edge_near_the_model_cached_and_exact():
     """A layout with more bricks than CUs (64 systems of 32,000 atoms): the
     build measures the model's brick edge against its neighbours and keeps
-    one of the three; a second build of the same shape reuses it; both layouts
-    give the oracle's trajectory on a sampled system."""
+    one of the three, and times the sweep order and the table-load policy; a
+    second build of the same shape reuses all three choices; both layouts
+    give the oracle's trajectory on a sampled system.  Without the autotuner
+    the build keeps the fixed order and cached table loads."""
     w = W.c5(n_substeps=40)
     ctx_m = L.Context(w.systems, L.L2T_FP32C)
     L.l2t_set_option(ctx_m.h, L.L2T_OPT_AUTOTUNE, 0)     # the model's edge only
     ctx_m.setup(w.r_cut)
     e_m = L.l2t_get_option(ctx_m.h, L.L2T_OPT_BRICK_EDGE)
+    assert L.l2t_get_option(ctx_m.h, L.L2T_OPT_SWEEP) == 1
+    assert L.l2t_get_option(ctx_m.h, L.L2T_OPT_TABLE_STREAM) == 1
     ctx_t = L.Context(w.systems, L.L2T_FP32C)
     ctx_t.setup(w.r_cut)
     e_t = L.l2t_get_option(ctx_t.h, L.L2T_OPT_BRICK_EDGE)
     assert abs(e_t - e_m) <= 1
+    choice = [L.l2t_get_option(ctx_t.h, o) for o in (L.L2T_OPT_SWEEP, L.L2T_OPT_TABLE_STREAM)]
+    assert all(v in (1, 2) for v in choice)
     ctx_2 = L.Context(w.systems, L.L2T_FP32C)
     ctx_2.setup(w.r_cut)
     assert L.l2t_get_option(ctx_2.h, L.L2T_OPT_BRICK_EDGE) == e_t
+    assert [L.l2t_get_option(ctx_2.h, o)
+            for o in (L.L2T_OPT_SWEEP, L.L2T_OPT_TABLE_STREAM)] == choice
     ctx_2.close()
     sy = w.systems[5]
     row, col = oracle_neighbors(sy, w.r_cut)
