@@ -65,3 +65,15 @@ def test_parameter_struct_layout_matches_header():
     assert ctypes.sizeof(L.l2t_params) == 8 * 5 + 4 * 2 + 8 * 10
     assert ctypes.sizeof(L.l2t_system_desc) == 4 + 4 * 3 + 8 * 3 * 2
     assert ctypes.sizeof(L.l2t_energy_report) == 8 * 9
+
+
+def test_binding_constants_match_the_header():
+    """Every #define L2T_* value of the header (status codes, precisions,
+    memory kinds, fields, heat-capacity models, options, coupling modes) has
+    the same value under the same name in the Python binding."""
+    src = open(os.path.join(ROOT, "include", "l2t.h")).read()
+    defs = dict(re.findall(r"^#define\s+(L2T_\w+)\s+(-?\d+)\b", src, re.M))
+    assert len(defs) >= 30
+    for name, value in defs.items():
+        assert hasattr(L, name), name
+        assert getattr(L, name) == int(value), name
