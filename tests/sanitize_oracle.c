@@ -1,10 +1,10 @@
 /*
- * Driver for the oracle under AddressSanitizer and UndefinedBehaviorSanitizer
+ * A program that runs the oracle under AddressSanitizer and UndefinedBehaviorSanitizer
  * (built and run by tests/test_oracle_sanitizers.py, on the CPU).  It calls
  * every exported oracle routine on small synthetic systems: a jittered
  * periodic FCC crystal, a slab with a free axis and a laser source, and a
  * chain for the two-temperature bar.  The sanitizers abort on the first
- * invalid access or undefined operation; the driver itself only checks
+ * invalid access or undefined operation; the program itself only checks
  * that the cell list equals brute force and that the results are finite.
  *
  * Test infrastructure: it includes the oracle's source to see its parameter
