@@ -42,9 +42,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 XGMI_LINK_GBS = 153.0   # one xGMI link of an MI355X, each direction (AMD public figure)
-# 0: every context the bench makes launches its sub-steps directly instead of
-# replaying captured hipGraphs (for rocprofv3 counter passes)
-GRAPH = 1
+# L2T_OPT_GRAPH of every context the bench makes: None leaves the library's
+# default (the FP32C advance times direct launches against graph replays in the
+# autotuner); 0 launches every sub-step directly (rocprofv3 counter passes),
+# 1 replays captured hipGraphs
+GRAPH = None
 # (option, value) pairs set on every FP32C context the bench makes, from the
 # launch-form options (--kernel, --block, --brick-edge, --sweep,
 # --table-stream).  Counter passes pin the form the timed run chose: the
@@ -54,8 +56,8 @@ FP32C_PINS = []
 
 def new_context(L, systems, prec, **kw):
     ctx = L.Context(systems, prec, **kw)
-    if not GRAPH:
-        L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, 0)
+    if GRAPH is not None:
+        L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, GRAPH)
     if prec == L.L2T_FP32C:
         for opt, value in FP32C_PINS:
             L.l2t_set_option(ctx.h, opt, value)
@@ -181,7 +183,9 @@ def bench_c4_speedup(L, torch, n_sub, n_full, only_fp32c=False):
                           sweep=["fixed", "alternating"][
                               L.l2t_get_option(ctx.h, L.L2T_OPT_SWEEP) - 1],
                           table_loads=["cached", "streamed"][
-                              L.l2t_get_option(ctx.h, L.L2T_OPT_TABLE_STREAM) - 1])
+                              L.l2t_get_option(ctx.h, L.L2T_OPT_TABLE_STREAM) - 1],
+                          launches=["direct", "graph replays"][
+                              L.l2t_get_option(ctx.h, L.L2T_OPT_GRAPH)])
         ctx.close()
     if only_fp32c:
         res = dict(workload=f"c4 batch of {len(w.systems)} laser slabs, {n_atoms} atoms, "
@@ -579,9 +583,9 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--sweep", type=int, choices=[0, 1, 2], default=0,
                     help="brick order of the FP32C brick kernels: 0 = measured at the build, "
                          "1 = fixed, 2 = reversed every other sub-step (every FP32C context)")
-    ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
-                    help="0 = launch sub-steps directly instead of replaying hipGraphs "
-                         "(rocprofv3 counter passes)")
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=None,
+                    help="0 = launch sub-steps directly (rocprofv3 counter passes), 1 = replay "
+                         "captured hipGraphs (default: the FP32C autotuner times both)")
     ap.add_argument("--only", choices=["all", "c3", "c4", "md", "bars", "adjoint", "fp64",
                                        "shard"],
                     default="all", help="run one section only (profiling)")
@@ -715,6 +719,8 @@ def main():
                                    L.l2t_get_option(h, L.L2T_OPT_SWEEP) - 1],
                                table_loads=["cached", "streamed"][
                                    L.l2t_get_option(h, L.L2T_OPT_TABLE_STREAM) - 1],
+                               launches=["direct", "graph replays"][
+                                   L.l2t_get_option(h, L.L2T_OPT_GRAPH)],
                                persistent=persistent, block=block),
                    advance_only_atom_substeps_per_s=sy.n * args.substeps / (adv * 1e-3),
                    advance_ms_median=float(np.median(adv_ms)),

@@ -101,7 +101,13 @@ extern "C" {
                                       sub-steps of an advance; used when every system of the context
                                       fits.  0 = the default 1024, -1 = never (one launch per
                                       sub-step).  Results are bitwise equal either way. */
-#define L2T_OPT_GRAPH          3   /* replay the per-sub-step launches of an advance from captured hipGraphs of 256 sub-steps (default 1) */
+#define L2T_OPT_GRAPH          3   /* how an advance issues its per-sub-step launches: 0 = one by
+                                      one, 1 = replays of captured hipGraphs of 256 sub-steps,
+                                      2 = FP32C: the autotuner times both on its probe and keeps the
+                                      faster (default; FP64 advances and the adjoint's segments
+                                      replay graphs unless it is 0).  Reading it returns the way in
+                                      effect for the FP32C advance (0 or 1; 1 until timed).  Results
+                                      are bitwise equal either way. */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance, and let
                                       l2t_build_neighbors time the brick edge (default 1) */
 #define L2T_OPT_KERNEL         5   /* 0 = global gathers, 1 = LDS brick tiles.  FP32C: autotuned by

@@ -738,8 +738,18 @@ int l2t_set_option(l2t_ctx *c, int32_t option, int64_t value) {
             break;
         case L2T_OPT_RESIDENT_MAX: t.resident_max = (int)value; break;
         case L2T_OPT_GRAPH:
-            // how launches are issued, not a launch shape: leaves tuning alone
-            t.graph = value ? 1 : 0;
+            // how launches are issued, not a launch shape: leaves the tuned
+            // shape alone; an explicit choice applies at once, 2 has the
+            // autotuner time it at the next advance (if it is on and not pinned)
+            if (value < 0 || value > 2) return l2t::fail(c, L2T_EINVAL, "graph must be 0, 1 or 2");
+            t.graph = (int)value;
+            if (value != 2) {
+                t.graph_used = (int)value;
+            } else if (t.autotune && !t.pinned) {
+                t.tuned = false;
+            } else {
+                t.graph_used = 1;
+            }
             l2t::drop_graphs(c);
             return L2T_OK;
         case L2T_OPT_BRICK_EDGE:
@@ -800,7 +810,7 @@ int l2t_get_option(l2t_ctx *c, int32_t option, int64_t *value) {
         case L2T_OPT_PERSISTENT: *value = t.persistent; break;
         case L2T_OPT_BLOCK: *value = t.block; break;
         case L2T_OPT_RESIDENT_MAX: *value = t.resident_max; break;
-        case L2T_OPT_GRAPH: *value = t.graph; break;
+        case L2T_OPT_GRAPH: *value = t.graph_used; break;
         case L2T_OPT_AUTOTUNE: *value = t.autotune; break;
         case L2T_OPT_KERNEL: *value = t.kernel; break;
         case L2T_OPT_ATOM_LEDGER: *value = c->atom_ledger ? 1 : 0; break;

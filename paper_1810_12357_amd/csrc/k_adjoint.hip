@@ -448,7 +448,7 @@ int adjoint(l2t_ctx *c, const double *w, double *dL_dK, double *dL_dg, double *d
         L2T_HIP(c, hipMemcpyAsync(seg, ck, sizeof(float) * 2 * NI, hipMemcpyDeviceToDevice, s_));
         L2T_HIP(c, hipMemcpyAsync(dst, dtab + (size_t)k * S, sizeof(int64_t) * S,
                                   hipMemcpyDeviceToDevice, s_));
-        if (!c->tune.graph) {
+        if (c->tune.graph == 0) {   // graph replays unless switched off
             int rc = segment(L, lc);
             if (rc != L2T_OK) return rc;
         } else {

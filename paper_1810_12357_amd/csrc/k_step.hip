@@ -831,7 +831,7 @@ int advance_plain(l2t_ctx *c, int32_t sys, int32_t n) {
                                c->dstep, q, c->ledger, eatom, c->derr);
         }
     };
-    if (sys < 0 && c->precision == L2T_FP64 && c->tune.graph) {
+    if (sys < 0 && c->precision == L2T_FP64 && c->tune.graph != 0) {
         // all systems: replays of captured chunks, as in the FP32C advance.
         // A chunk is keyed by its length, the state buffer it starts from,
         // the lattice mode and which lattice buffer holds T^lat.
@@ -1093,20 +1093,49 @@ void drop_graphs(l2t_ctx *c) {
     c->graphs.clear();
 }
 
+// capture k FP32C sub-steps of all systems (from buffer `cur`, the step
+// counters advanced at the end) into an executable hipGraph.  The capture runs
+// on a private stream: the caller's may be the legacy null stream, which
+// cannot be captured; the graph is replayed on the caller's.
+int capture_fp32c(l2t_ctx *c, int32_t k, int kernel, int persistent, int block, double *eatom,
+                  hipGraphExec_t *out) {
+    if (!c->cap_stream)
+        L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipStream_t user = c->stream;
+    L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    c->stream = c->cap_stream;
+    int rc = fp32c_launch(c, k, kernel, persistent, block, eatom);
+    c->stream = user;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc != L2T_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    *out = ge;
+    return L2T_OK;
+}
+
 // FP32C advance of all systems with the tuned configuration.  The mean-field
-// parameters are refreshed from the state at the start of the advance; the
-// sub-steps then run as replays of captured hipGraphs of kGraphChunk
-// sub-steps plus one graph for the remainder, each captured once per
-// (length, buffer parity, configuration).  Every captured chunk ends by
-// advancing the device step counters, so a replay does not depend on where
-// in the advance it runs, and a new neighbour table costs one short capture
-// rather than one node per sub-step of the whole advance.
+// parameters are refreshed from the state at the start of the advance.  The
+// sub-steps are then launched one by one, or run as replays of captured
+// hipGraphs of kGraphChunk sub-steps plus one graph for the remainder, each
+// captured once per (length, buffer parity, configuration); which of the two
+// is the option's, or the autotuner's, timed on its probe.  Every captured
+// chunk ends by advancing the device step counters, so a replay does not
+// depend on where in the advance it runs, and a new neighbour table costs one
+// short capture rather than one node per sub-step of the whole advance.
 int advance_fp32c(l2t_ctx *c, int32_t n) {
     const Tuning &t = c->tune;
     int rc = mean_field_refresh(c, -1);
     if (rc != L2T_OK) return rc;
     double *eatom = atom_ledger_ptr(c);
-    if (!t.graph) {
+    if (!t.graph_used) {
         rc = fp32c_launch(c, n, t.kernel, t.persistent, t.block, eatom);
         if (rc != L2T_OK) return rc;
         if (n & 1) c->cur ^= 1;
@@ -1117,26 +1146,9 @@ int advance_fp32c(l2t_ctx *c, int32_t n) {
                          t.block};
             auto it = c->graphs.find(key);
             if (it == c->graphs.end()) {
-                // capture on a private stream (the caller's may be the legacy
-                // null stream, which cannot be captured), replay on the caller's
-                if (!c->cap_stream)
-                    L2T_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-                hipGraph_t g = nullptr;
-                hipStream_t user = c->stream;
-                L2T_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-                c->stream = c->cap_stream;
-                rc = fp32c_launch(c, k, t.kernel, t.persistent, t.block, eatom);
-                c->stream = user;
-                hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-                if (rc != L2T_OK) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return rc;
-                }
-                if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
                 hipGraphExec_t ge = nullptr;
-                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+                rc = capture_fp32c(c, k, t.kernel, t.persistent, t.block, eatom, &ge);
+                if (rc != L2T_OK) return rc;
                 it = c->graphs.emplace(key, ge).first;
             }
             L2T_HIP(c, hipGraphLaunch(it->second, c->stream));

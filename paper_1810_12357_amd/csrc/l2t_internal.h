@@ -141,7 +141,8 @@ struct Tuning {
     int persistent = 0;
     int block = kBrickBlockMax;
     int resident_max = 0;    // 0 = autotune
-    int graph = 1;
+    int graph = 2;           // L2T_OPT_GRAPH as set: 0 = direct, 1 = graphs, 2 = timed by the autotuner
+    int graph_used = 1;      // FP32C advance, in effect: 0 = direct launches, 1 = graph replays
     int autotune = 1;
     int brick_edge = 0;      // 0 = chosen by the layout builder
     int sweep = 0;           // L2T_OPT_SWEEP as set: 0 = chosen at neighbour build, 1, 2
@@ -312,6 +313,9 @@ int reset_ledger(l2t_ctx *c, int32_t sys);
 int energies(l2t_ctx *c, int32_t sys, l2t_energy_report *out);
 int pair_fp32(const float *ti, const float *tj, float *out, int64_t n, hipStream_t s);
 int fp32c_launch(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom);
+// n FP32C sub-steps of all systems captured into an executable graph (the caller destroys it)
+int capture_fp32c(l2t_ctx *c, int32_t n, int kernel, int persistent, int block, double *eatom,
+                  hipGraphExec_t *out);
 // time n brick-kernel sub-steps of the current layout on a stand-in state in
 // scratch memory (the context's fields are not touched)
 int brick_probe(l2t_ctx *c, int32_t n, bool alternate, bool stream, float *ms);

@@ -189,6 +189,34 @@ def test_measured_brick_edge_near_the_model_cached_and_exact():
         ctx.close()
 
 
+def test_graph_or_direct_launches_timed_cached_and_bitwise_equal():
+    """The FP32C autotuner times the tuned shape's probe as direct launches
+    and as a graph replay and keeps the faster (L2T_OPT_GRAPH = 2, the
+    default): the choice reads back as 0 or 1, a second context of the same
+    shape reuses it, and default, direct and graph-replayed advances give the
+    same states bit for bit.  Without the autotuner the advance replays
+    graphs; values outside 0..2 are refused."""
+    w = W.c5(n_substeps=37)
+    states, choice = [], []
+    for graph in (None, None, 0, 1):
+        ctx = gpu_context(w, L.L2T_FP32C, graph=graph)
+        ctx.advance(w.n_substeps)
+        choice.append(L.l2t_get_option(ctx.h, L.L2T_OPT_GRAPH))
+        states.append(np.concatenate([ctx.get(s) for s in (0, 31, 63)]))
+        ctx.close()
+    assert choice[0] in (0, 1) and choice[1] == choice[0] and choice[2:] == [0, 1]
+    for st in states[1:]:
+        assert np.array_equal(st, states[0])
+    ctx = L.Context(w.systems, L.L2T_FP32C)
+    L.l2t_set_option(ctx.h, L.L2T_OPT_AUTOTUNE, 0)
+    ctx.setup(w.r_cut)
+    ctx.advance(3)
+    assert L.l2t_get_option(ctx.h, L.L2T_OPT_GRAPH) == 1
+    with pytest.raises(L.L2TError):
+        L.l2t_set_option(ctx.h, L.L2T_OPT_GRAPH, 3)
+    ctx.close()
+
+
 def _step_system(n_cells=10, hot=19000.0, cold=300.0, seed=31):
     """FCC n^3 cells, periodic, jittered 0.05 A: T_e = hot where x < L/2 and
     cold beyond, so neighbours across the two planes of the step differ by up
