@@ -270,7 +270,8 @@ def bench_md_coupling(L, torch, h, sy, d, n_sub=10, reps=20):
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def timed(fn, k):
-        fn()                                    # warm-up (graph capture, autotune)
+        for _ in range(10):                     # warm-up (graph capture, autotune, clocks)
+            fn()
         torch.cuda.synchronize()
         a, b = ev(), ev()
         a.record()
@@ -313,7 +314,8 @@ def bench_boundary_mean_field(L, torch, h, sy, n_sub=10, reps=40):
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def per_substep():
-        L.l2t_advance(h, n_sub)                 # warm-up (graph capture)
+        for _ in range(10):                     # warm-up (graph capture, clocks)
+            L.l2t_advance(h, n_sub)
         torch.cuda.synchronize()
         a, b = ev(), ev()
         a.record()
