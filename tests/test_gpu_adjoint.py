@@ -35,8 +35,12 @@ def _oracle_grad(sy, r_cut, n, w, params=None):
     return oracle.adjoint(row, col, sy.T_e0, Tl, p, n, w, gated=gated, x=x)
 
 
-@pytest.mark.parametrize("ckpt", [7, 50])
+@pytest.mark.parametrize("ckpt", [1, 7, 50, 1000])
 def test_adjoint_matches_oracle_reduced_c5(ckpt):
+    """Checkpoints every 7 (a ragged last segment) and every 50 sub-steps, and
+    the two degenerate schedules: every state stored (segments of one reverse
+    sub-step, nothing recomputed) and one checkpoint longer than the run (the
+    whole forward recomputed in one segment)."""
     w = W.c5(n_systems=3, n_cells=7, n_substeps=300)
     n = w.n_substeps
     ctx = L.Context(w.systems, L.L2T_FP32C)
