@@ -64,19 +64,43 @@ __device__ __forceinline__ void pair_adj(float Tk, float Tj, float sk, float inv
     Q = fmaf(u, Q, 1.0f / 120.0f);
     Q = fmaf(u, Q, 1.0f / 6.0f);
     Q = fmaf(u, Q, 1.0f);
-    f = dT * fmaf(-fmaf(e, 0.5f, 0.5f), Q, C);
-    d1 = -fmaf(fmaf(e, -0.5f, 0.5f), C, (s * d) * Q);
+    // with h = (1 + e)/2, (1 - e)/2 = 1 - h: f = dT (C - h Q), d1f = -(C - h C + s d Q)
+    const float h = fmaf(e, 0.5f, 0.5f);
+    f = dT * fmaf(-h, Q, C);
+    d1 = -fmaf(s * d, Q, fmaf(-h, C, C));
+}
+
+// the terms of two consecutive row entries (2m, 2m + 1) added to the lane's
+// FP64 sums S and D: the pair's two f, and its two d1f (lambda_k - lambda_j),
+// are summed in FP32 first, so each FP64 sum takes one addition per two
+// entries.  Every form calls this on the same entry pairs in the same order.
+__device__ __forceinline__ void two_terms(float Tk, float lk, float sk, float inv_span, float Tj0,
+                                          float lj0, float Tj1, float lj1, double &S, double &D) {
+    float f0, d0, f1, d1;
+    pair_adj(Tk, Tj0, sk, inv_span, f0, d0);
+    pair_adj(Tk, Tj1, sk, inv_span, f1, d1);
+    S += (double)(f0 + f1);
+    D += (double)fmaf(d1, lk - lj1, d0 * (lk - lj0));
+}
+
+// the term of a row's last entry when the row length is odd
+__device__ __forceinline__ void one_term(float Tk, float lk, float sk, float inv_span, float Tj,
+                                         float lj, double &S, double &D) {
+    float f, d1;
+    pair_adj(Tk, Tj, sk, inv_span, f, d1);
+    S += (double)f;
+    D += (double)(d1 * (lk - lj));
 }
 
 struct AdjGrad {
     double k, g;
 };
 
-// reverse update of one lane given S = span * sum_j f and D = sum_j d1f (lambda_k -
-// lambda_j), both accumulated in FP64 in row order.  lambda is the FP32 pair
-// (hi, lo) with hi + lo exact in FP64; the increment is added in FP64 and the
-// sum split back, as the forward does with T.  Returns this lane's terms of
-// dL/dK and dL/dg.
+// reverse update of one lane given S = span * sum_j f and D = sum_j d1f
+// (lambda_k - lambda_j), accumulated in FP64 in row order, two entries at a
+// time.  lambda is the FP32 pair (hi, lo) with hi + lo exact in FP64; the
+// increment is added in FP64 and the sum split back, as the forward does with
+// T.  Returns this lane's terms of dL/dK and dL/dg.
 __device__ __forceinline__ AdjGrad adjoint_finish(const DevParams &p, bool valid, int32_t slot,
                                                   float Tk, float lk, double S, double D,
                                                   const float *__restrict__ Tl,
@@ -127,12 +151,14 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
     const PairK pk = pair_consts(p);
     const float sk = adj_sk(Tk, pk, p.f_inv_span);
     double S = 0.0, D = 0.0;
-    for (int32_t q = 0; q < si.width; ++q) {
-        const int32_t j = cp[q * kWave];
-        float f, d1;
-        pair_adj(Tk, Thi[j], sk, p.f_inv_span, f, d1);
-        S += (double)f;
-        D += (double)(d1 * (lk - lam[j]));
+    const int32_t full = si.width >> 1;
+    for (int32_t m = 0; m < full; ++m) {
+        const int32_t j0 = cp[(2 * m) * kWave], j1 = cp[(2 * m + 1) * kWave];
+        two_terms(Tk, lk, sk, p.f_inv_span, Thi[j0], lam[j0], Thi[j1], lam[j1], S, D);
+    }
+    if (si.width & 1) {
+        const int32_t j = cp[(si.width - 1) * kWave];
+        one_term(Tk, lk, sk, p.f_inv_span, Thi[j], lam[j], S, D);
     }
     const AdjGrad g = adjoint_finish(p, lane < si.n_valid, slot, Tk, lk, S, D, Tl, srcw, lam_n,
                                      lam_lo, dstep[si.sys] + rel);
@@ -229,22 +255,19 @@ __global__ __launch_bounds__(kBrickBlockMax) void k_adjoint_brick(
         const float sk = adj_sk(Tk, pk, p.f_inv_span);
         const uint32_t *row = colw + (int64_t)base * kWave + lane;
         double S = 0.0, D = 0.0;
-        auto term = [&](uint32_t off) {
-            const float Tj = *reinterpret_cast<const float *>(tb + off);
-            const float lj = *reinterpret_cast<const float *>(tb + off + 4 * LAM);
-            float f, d1;
-            pair_adj(Tk, Tj, sk, p.f_inv_span, f, d1);
-            S += (double)f;
-            D += (double)(d1 * (lk - lj));
-        };
+        auto Tat = [&](uint32_t off) { return *reinterpret_cast<const float *>(tb + off); };
+        auto lat = [&](uint32_t off) { return *reinterpret_cast<const float *>(tb + off + 4 * LAM); };
         const int32_t full = w >> 1;
 #pragma unroll 2
-        for (int32_t k = 0; k < full; ++k) {
+        for (int32_t k = 0; k < full; ++k) {   // one word: entries 2k and 2k + 1
             const uint32_t wd = row[(int64_t)k * kWave];
-            term(wd & 0xffffu);
-            term(wd >> 16);
+            const uint32_t o0 = wd & 0xffffu, o1 = wd >> 16;
+            two_terms(Tk, lk, sk, p.f_inv_span, Tat(o0), lat(o0), Tat(o1), lat(o1), S, D);
         }
-        if (w & 1) term(row[(int64_t)full * kWave] & 0xffffu);
+        if (w & 1) {
+            const uint32_t o = row[(int64_t)full * kWave] & 0xffffu;
+            one_term(Tk, lk, sk, p.f_inv_span, Tat(o), lat(o), S, D);
+        }
         const AdjGrad g = adjoint_finish(p, lane < nv, slot, Tk, lk, S, D, Tl, srcw, lam_n,
                                          lam_lo, step);
         gK += g.k;
