@@ -109,7 +109,12 @@ extern "C" {
                                       effect for the FP32C advance (0 or 1; 1 until timed).  Results
                                       are bitwise equal either way. */
 #define L2T_OPT_AUTOTUNE       4   /* 1 = run the autotuner at the next advance, and let
-                                      l2t_build_neighbors time the brick edge (default 1) */
+                                      l2t_build_neighbors time the brick edge (default 1).  The
+                                      autotuner's choice is kept per problem shape for the
+                                      process and, when the environment variable
+                                      L2T_AUTOTUNE_CACHE names a file, appended to it as one line
+                                      (shape key|kernel persistent block graph) and read back by
+                                      later processes. */
 #define L2T_OPT_KERNEL         5   /* 0 = global gathers, 1 = LDS brick tiles.  FP32C: autotuned by
                                       default.  FP64: 1 by default; systems in the lattice mode, and
                                       tiles over 64 KB of FP64 values, take the global gathers.  The

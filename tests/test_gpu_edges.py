@@ -217,6 +217,27 @@ def test_graph_or_direct_launches_timed_cached_and_bitwise_equal():
     ctx.close()
 
 
+def test_autotune_cache_file_records_the_timed_choice(tmp_path, monkeypatch):
+    """With L2T_AUTOTUNE_CACHE set, the first tuning of a problem shape
+    appends one line for it: the shape key, then kernel, persistent, block
+    and the timed graph choice; the context uses what the line records."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("L2T_AUTOTUNE_CACHE", str(path))
+    sy = _grid_system(m=9, spacing=2.9, seed=44)   # a shape no other test tunes
+    w = W.Workload("grid9", [sy], 4.4, 10, "fp32c")
+    ctx = gpu_context(w, L.L2T_FP32C)
+    ctx.advance(10)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    key, vals = lines[0].split("|")
+    assert key.startswith("n_int=") and " sys=1 " in key
+    k, pers, block, graph = (int(v) for v in vals.split())
+    assert k == L.l2t_get_option(ctx.h, L.L2T_OPT_KERNEL)
+    assert pers == 0 and block == L.l2t_get_option(ctx.h, L.L2T_OPT_BLOCK)
+    assert graph == L.l2t_get_option(ctx.h, L.L2T_OPT_GRAPH) and graph in (0, 1)
+    ctx.close()
+
+
 def _step_system(n_cells=10, hot=19000.0, cold=300.0, seed=31):
     """FCC n^3 cells, periodic, jittered 0.05 A: T_e = hot where x < L/2 and
     cold beyond, so neighbours across the two planes of the step differ by up
