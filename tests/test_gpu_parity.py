@@ -240,6 +240,37 @@ def test_fp32c_launch_forms_bitwise_equal(case):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["c3_jitter", "c4_small"])
+def test_fp32c_every_workgroup_size_bitwise_equal(case):
+    """Every workgroup size the block option accepts (multiples of 64 up to
+    512 for the LDS bricks, up to 256 for the global gathers) gives the same
+    states bit for bit: the per-atom arithmetic does not depend on how many
+    waves share a brick.  The ledger terms are summed per wave in FP32 over
+    the wave's slices, which do depend on it, so the system ledgers agree to
+    FP32 rounding (1e-5)."""
+    if case == "c3_jitter":
+        w = W.c3(n_cells=9, n_substeps=1)
+    else:
+        w = W.c4(n_systems=5, n_substeps=1, size_lo=500, size_hi=4000)
+    forms = [(1, b) for b in range(64, 513, 64)] + [(0, b) for b in range(64, 257, 64)]
+    runs, ledgers = [], []
+    for kernel, block in forms:
+        ctx = gpu_context(w, L.L2T_FP32C)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, kernel)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_BLOCK, block)
+        ctx.advance(37)
+        ctx.advance(2 * 256 + 3)
+        assert L.l2t_get_option(ctx.h, L.L2T_OPT_BLOCK) == block
+        runs.append([ctx.get(s) for s in range(len(w.systems))])
+        ledgers.append([ctx.energies(s)["E_e_to_l"] for s in range(len(w.systems))])
+        ctx.close()
+    for r, led in zip(runs[1:], ledgers[1:]):
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
+        for a, b in zip(ledgers[0], led):
+            assert b == pytest.approx(a, rel=1e-5)
+
+
 # ---------------------------------------------------------- C2: Fourier limit ----
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_c2_reduced_matches_oracle(precision):
