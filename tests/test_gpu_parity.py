@@ -271,6 +271,33 @@ def test_fp32c_every_workgroup_size_bitwise_equal(case):
             assert b == pytest.approx(a, rel=1e-5)
 
 
+@pytest.mark.parametrize("case", ["c3_jitter", "c4_small"])
+def test_fp32c_every_brick_edge_bitwise_equal(case):
+    """The brick layout (one-cell bricks, small and large ones, one brick per
+    system where it fits) changes which atoms share a tile and the order of
+    the slots, not the neighbour order of any row: every edge gives the same
+    states bit for bit."""
+    if case == "c3_jitter":
+        w = W.c3(n_cells=9, n_substeps=1)
+    else:
+        w = W.c4(n_systems=5, n_substeps=1, size_lo=500, size_hi=4000)
+    runs, used = [], []
+    for edge in (1, 2, 3, 5, 8, 1024):
+        ctx = L.Context(w.systems, L.L2T_FP32C)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_BRICK_EDGE, edge)
+        ctx.setup(w.r_cut)
+        L.l2t_set_option(ctx.h, L.L2T_OPT_KERNEL, 1)
+        used.append(L.l2t_get_option(ctx.h, L.L2T_OPT_BRICK_EDGE))
+        ctx.advance(37)
+        ctx.advance(2 * 256 + 3)
+        runs.append([ctx.get(s) for s in range(len(w.systems))])
+        ctx.close()
+    assert used[0] == 1 and len(set(used)) >= 5
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
+
+
 # ---------------------------------------------------------- C2: Fourier limit ----
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_c2_reduced_matches_oracle(precision):
